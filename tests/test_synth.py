@@ -1,0 +1,42 @@
+"""Seeded input generators: determinism, ranges and the phantom recipe."""
+import numpy as np
+
+import synth
+
+
+def test_phantom_is_seeded_and_has_zero_margin():
+    a = synth.ellipsoid_phantom(32, 1.0, 10, synth.rng_for(0))
+    b = synth.ellipsoid_phantom(32, 1.0, 10, synth.rng_for(0))
+    assert a.dtype == np.float32 and a.shape == (32, 32, 32)
+    np.testing.assert_array_equal(a, b)
+    assert a.min() >= 0 and 0.01 <= a.max() <= 0.5
+    # bounding spheres stop 4 voxels short of the face; smoothing (4 sigma
+    # truncation) may reach at most 4 more voxels, never the outer shell
+    assert np.all(a[0] == 0) and np.all(a[-1] == 0)
+    assert np.all(a[:, 0] == 0) and np.all(a[:, :, -1] == 0)
+
+
+def test_shell_value():
+    v = synth.ellipsoid_phantom(64, 0.8, 5, synth.rng_for(1), shell=True, sigma=0.0)
+    assert np.isclose(v.max(), 0.08) or v.max() > 0.08 - 1e-6
+
+
+def test_poses_ranges():
+    p = synth.random_poses(1000, 10.0, 5.0, synth.rng_for(2))
+    assert p.shape == (1000, 6)
+    assert np.abs(p[:, :3]).max() <= 10.0
+    assert np.abs(p[:, 3:]).max() <= np.deg2rad(5.0)
+
+
+def test_gaussian_smoothing_preserves_mass_inside():
+    v = np.zeros((21, 21, 21))
+    v[10, 10, 10] = 1.0
+    s = synth.gaussian_smooth(v, 1.0)
+    assert abs(s.sum() - 1.0) < 1e-12
+    assert abs(s[10, 10, 11] / s[10, 10, 10] - np.exp(-0.5)) < 1e-3
+
+
+def test_motion_amplitude():
+    m = synth.sinusoidal_motion(360, 3.0, 2.0, synth.rng_for(3))
+    assert np.abs(m[:, :3]).max() <= 3.0 + 1e-12
+    assert np.abs(m[:, 3:]).max() <= np.deg2rad(2.0) + 1e-12
