@@ -1,0 +1,298 @@
+"""Benchmark: forward projection + pose gradient throughput (ray-samples/s).
+
+Workload (one step): 256^3 ellipsoid phantom with a high-attenuation shell
+at 0.8 mm, 64 candidate poses (+-10 mm / +-10 deg) as 64 views of one
+512x512 detector at 0.6 mm (SAD 1000 mm, SDD 1500 mm, 0.5 mm ray steps);
+forward-project all 64 DRRs, form the SSD loss gradient against a target
+DRR at a true pose, and compute the 64 x 6 pose gradients.  Inputs are
+resident in device memory before the timed region.
+
+value = exact in-support sample count of the 64 rays sets / step time.
+Extra legs on the same JSON line: per-kernel timings from HIP events on the
+launch stream, the roofline entry of the dominant kernel, the FP64 oracle
+timed on the host on a bounded sample, and the back-projector at
+512^3 / 360 views (voxel-view updates per second).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-bp]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Exact in-support sample count (the unit of the metric)
+# ---------------------------------------------------------------------------
+
+def _rot(g):
+    cx, sx, cy, sy, cz, sz = (math.cos(g[0]), math.sin(g[0]), math.cos(g[1]), math.sin(g[1]),
+                              math.cos(g[2]), math.sin(g[2]))
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    return Rz @ Ry @ Rx
+
+
+def count_ray_samples(geom, angles, poses) -> int:
+    """Number of samples k >= 0 at arc length k*step from the source whose
+    object-frame continuous voxel index lies in the open box (-1, n)^3,
+    summed over all rays of all views (FP64 interval count per ray)."""
+    total = 0
+    n = np.array([geom.nx, geom.ny, geom.nz], dtype=np.float64)
+    h = np.array([geom.vx, geom.vy, geom.vz])
+    c = (n - 1) / 2
+    cu = (geom.nu - 1) / 2 + geom.off_u
+    cv = (geom.nv - 1) / 2 + geom.off_v
+    A, B = np.meshgrid(np.arange(geom.nu), np.arange(geom.nv))
+    xa = ((A - cu) * geom.du).ravel()
+    yb = ((B - cv) * geom.dv).ravel()
+    for beta, th in zip(np.atleast_1d(angles), np.reshape(poses, (-1, 6))):
+        cb, sb = math.cos(beta), math.sin(beta)
+        src = geom.sad * np.array([cb, sb, 0.0])
+        ew, eu, ev = np.array([-cb, -sb, 0.0]), np.array([-sb, cb, 0.0]), np.array([0.0, 0, 1])
+        d = geom.sdd * ew[None, :] + xa[:, None] * eu[None, :] + yb[:, None] * ev[None, :]
+        u = d / np.linalg.norm(d, axis=1, keepdims=True)
+        R = _rot(th[3:])
+        alpha = (R.T @ (src - th[:3])) / h + c          # index of the source
+        beta_ = (u @ R) / h[None, :]                     # index per mm along the ray
+        lo = np.full(u.shape[0], -np.inf)
+        hi = np.full(u.shape[0], np.inf)
+        empty = np.zeros(u.shape[0], bool)
+        for a in range(3):
+            ba = beta_[:, a]
+            nz = ba != 0
+            t1 = np.where(nz, (-1.0 - alpha[a]) / np.where(nz, ba, 1), -np.inf)
+            t2 = np.where(nz, (n[a] - alpha[a]) / np.where(nz, ba, 1), np.inf)
+            lo = np.maximum(lo, np.where(nz, np.minimum(t1, t2), -np.inf))
+            hi = np.minimum(hi, np.where(nz, np.maximum(t1, t2), np.inf))
+            if not (-1.0 < alpha[a] < n[a]):
+                empty |= ~nz
+        kmin = np.maximum(np.floor(lo / geom.step) + 1, 0)
+        kmax = np.ceil(hi / geom.step) - 1
+        cnt = np.where(empty, 0, np.maximum(kmax - kmin + 1, 0))
+        total += int(cnt.sum())
+    return total
+
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+
+def _kernel_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2508_13304_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_key, src_hash):
+    """HBM bytes per launch measured with rocprofv3 counters (committed under
+    profiles/), valid only while the kernel source is unchanged."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p)).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != src_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_forward(args, dp, torch):
+    dev = torch.device("cuda:0")
+    log("[bench] generating config-2 inputs (256^3 phantom, 64 poses)")
+    c = synth.config2_inputs()
+    g, V = c["geom"], len(c["angles"])
+    T = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)  # noqa: E731
+    vol = T(c["vol"], torch.float32)
+    angles = T(c["angles"], torch.float64)
+    poses = T(c["poses"], torch.float64)
+    # target DRR at the true pose (synthetic input, generated once)
+    y = dp.project_fwd(g, T([0.0], torch.float64), T(c["target_pose"], torch.float64), vol)
+    ws = torch.empty(max(dp.workspace_bytes(g, V, dp.OP_FWD), dp.workspace_bytes(g, V, dp.OP_FWD_GRAD)),
+                     dtype=torch.uint8, device=dev)
+    proj = torch.empty((V, g.nv, g.nu), dtype=torch.float32, device=dev)
+    wgrad = torch.empty_like(proj)
+    gpose = torch.empty((V, 6), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        dp.project_fwd(g, angles, poses, vol, out=proj, ws=ws, stream=stream)
+        torch.sub(proj, y, out=wgrad)
+        wgrad.mul_(2.0)
+        dp.project_fwd_grad_pose(g, angles, poses, vol, wgrad, out=gpose, ws=ws, stream=stream)
+
+    n_samples = count_ray_samples(g, c["angles"], c["poses"])
+    log(f"[bench] in-support samples per step: {n_samples:.4e}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dp.profile_enable(True)
+    dp.profile_collect()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = dp.profile_collect()
+    dp.profile_enable(False)
+    ms_step = dt * 1e3 / args.steps
+    per_kernel = {k: round(v[0] / v[1], 4) for k, v in kern.items()}
+    log(f"[bench] {ms_step:.3f} ms/step; per-kernel avg ms: {per_kernel}")
+    fwd_ms, grad_ms = per_kernel.get("rd_fwd", 0.0), per_kernel.get("rd_grad", 0.0)
+    dominant = "rd_grad" if grad_ms >= fwd_ms else "rd_fwd"
+    dom_ms = max(grad_ms, fwd_ms)
+    # Algorithmic gather bytes per sample: 8 trilinear corners x 16 B
+    # (float4 gradient volume) for the gradient, x 4 B for the forward.
+    bytes_per_sample = 128.0 if dominant == "rd_grad" else 32.0
+    achieved = bytes_per_sample * n_samples / (dom_ms * 1e-3) / 1e9
+    src_hash = _kernel_hash("rd.hip", "dp_internal.h")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _traffic(dominant + "_config2", src_hash),
+                "kernel": dominant, "kernel_ms": dom_ms, "bytes_per_sample": bytes_per_sample,
+                "source_hash": src_hash}
+    return dict(geom=g, V=V, n_samples=n_samples, ms_step=ms_step, per_kernel=per_kernel,
+                roofline=roofline, inputs=c)
+
+
+def run_backproject(args, dp, torch):
+    dev = torch.device("cuda:0")
+    g = synth.geom_c3_recon()
+    m = synth.config3_motion()
+    V = len(m["angles"])
+    rng = np.random.default_rng(3)
+    log("[bench] generating config-3 inputs (360 views 512x384, 512^3 recon)")
+    proj_np = synth.smooth_images(V, g.nv, g.nu, rng, n_blobs=4, signed=True)
+    T = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)  # noqa: E731
+    angles, poses = T(m["angles"], torch.float64), T(m["poses"], torch.float64)
+    proj = T(proj_np, torch.float32)
+    del proj_np
+    vol = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=dev)
+    e = torch.empty_like(vol).normal_(generator=torch.Generator(device=dev).manual_seed(5))
+    gp = torch.empty((V, 6), dtype=torch.float64, device=dev)
+    ws = torch.empty(max(dp.workspace_bytes(g, V, dp.OP_BP), dp.workspace_bytes(g, V, dp.OP_BP_GRAD)),
+                     dtype=torch.uint8, device=dev)
+    reps = max(1, min(args.steps, 5))
+    for _ in range(1):
+        dp.backproject(g, angles, poses, proj, dp.W_FDK, out=vol, ws=ws)
+        dp.backproject_grad_pose(g, angles, poses, proj, e, dp.W_FDK, out=gp, ws=ws)
+    torch.cuda.synchronize()
+    dp.profile_enable(True)
+    dp.profile_collect()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dp.backproject(g, angles, poses, proj, dp.W_FDK, out=vol, ws=ws)
+    torch.cuda.synchronize()
+    t_bp = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dp.backproject_grad_pose(g, angles, poses, proj, e, dp.W_FDK, out=gp, ws=ws)
+    torch.cuda.synchronize()
+    t_bpg = (time.perf_counter() - t0) / reps
+    kern = dp.profile_collect()
+    dp.profile_enable(False)
+    upd = float(g.nx) * g.ny * g.nz * V
+    per_kernel = {k: round(v[0] / v[1], 4) for k, v in kern.items()}
+    log(f"[bench] BP {t_bp * 1e3:.2f} ms, BP-grad {t_bpg * 1e3:.2f} ms; kernels {per_kernel}")
+    return {"workload": "512^3 recon at 0.375 mm, 360 views 512x384 at 0.776 mm, FDK weight, "
+                        "sinusoidal motion 3 mm / 2 deg",
+            "voxel_view_updates": upd,
+            "backproject_updates_per_s": upd / t_bp,
+            "backproject_grad_updates_per_s": upd / t_bpg,
+            "backproject_ms": round(t_bp * 1e3, 3), "backproject_grad_ms": round(t_bpg * 1e3, 3),
+            "kernels_ms": per_kernel}
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the same workload
+# ---------------------------------------------------------------------------
+
+def run_cpu_baseline(fw, n_poses=2):
+    import oracle
+    c = fw["inputs"]
+    g = c["geom"]
+    angles, poses = c["angles"][:n_poses], c["poses"][:n_poses]
+    y = oracle.project_fwd(g, [0.0], c["target_pose"], c["vol"])
+    n = count_ray_samples(g, angles, poses)
+    t0 = time.perf_counter()
+    l = oracle.project_fwd(g, angles, poses, c["vol"])
+    w = 2.0 * (l - y)
+    oracle.project_fwd_grad_pose(g, angles, poses, c["vol"], w)
+    dt = time.perf_counter() - t0
+    log(f"[bench] oracle: {n_poses} poses in {dt:.2f} s ({oracle.num_threads()} threads)")
+    return {"value": n / dt, "unit": "ray-samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {n_poses} of 64 poses, all 512x512 rays, forward + SSD pose gradient "
+                      f"({n:.3e} samples, {dt:.1f} s); plain FP64 oracle, not a tuned CPU projector"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-bp", action="store_true", help="skip the back-projector leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the projector shards by view / voxel slab across GPUs, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2508_13304_amd as dp
+    dp.load()
+    fw = run_forward(args, dp, torch)
+    bp = None if args.no_bp else run_backproject(args, dp, torch)
+    cpu = None if args.no_cpu else run_cpu_baseline(fw)
+    value = fw["n_samples"] / (fw["ms_step"] * 1e-3)
+    rec = {
+        "metric": "fwd+pose-grad ray-samples/s",
+        "value": value,
+        "unit": "ray-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fw["ms_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config 2: 256^3 ellipsoid+shell phantom at 0.8 mm, 64 candidate poses "
+                               "(+-10 mm/+-10 deg) x one 512x512 view at 0.6 mm, SAD/SDD 1000/1500 mm, "
+                               "0.5 mm trilinear march; forward + SSD loss gradient + 64x6 pose gradient",
+                   "samples_per_step": fw["n_samples"], "views": fw["V"]},
+        "roofline": fw["roofline"],
+        "cpu_baseline": cpu,
+        "kernels_ms": fw["per_kernel"],
+        "backprojector": bp,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * diffproj.h -- C ABI of the MI355X (gfx950) differentiable cone-beam
+ * projector library `libdiffproj.so`.
+ *
+ * Method: arXiv 2508.13304, "Differentiable Forward and Back-Projector for
+ * Rigid Motion Estimation in X-ray Imaging".  The library computes
+ *   - the ray-driven forward projection l(d, theta) of a rigidly moved
+ *     volume (Eq. forward, Sec. II-A), discretised as a trilinear march;
+ *   - its pose gradient dL/dtheta given dL/dl, obtained by projecting the
+ *     per-voxel matrix G_f = grad'mu^T grad_M r' with the same weights
+ *     (Eqs. final_forward, for_int, dis_forward, Sec. II-B/C);
+ *   - the voxel-driven back-projection mu(r', theta) (Eq. back);
+ *   - its pose gradient dL/dtheta given dL/dmu, obtained by back-projecting
+ *     G_b = grad_d l^T grad_r p grad_M r with the same weights
+ *     (Eqs. final_back, back_int, dis_back);
+ *   - the chain rule dL/dtheta = grad_theta M . dL/dM (Sec. II-B).
+ *
+ * Geometry (all lengths mm, angles rad):
+ *   - volume voxel (i,j,k) has object-frame centre
+ *       p = ((i-(nx-1)/2) vx, (j-(ny-1)/2) vy, (k-(nz-1)/2) vz);
+ *     memory order [nz][ny][nx], x fastest, float32;
+ *   - rigid motion theta = (tx,ty,tz,gx,gy,gz): r = R p + t with
+ *     R = Rz(gz) Ry(gy) Rx(gx) (right-handed elemental rotations);
+ *   - view v has gantry angle beta: source s = SAD (cos b, sin b, 0),
+ *     e_w = (-cos b, -sin b, 0) (source -> isocentre), detector axes
+ *     e_u = (-sin b, cos b, 0) (columns) and e_v = (0,0,1) (rows); pixel
+ *     (a, b) centre = s + SDD e_w + (a-cu) du e_u + (b-cv) dv e_v with
+ *     cu = (nu-1)/2 + off_u, cv = (nv-1)/2 + off_v; images [V][nv][nu];
+ *   - forward: l[v][b][a] = step * sum_{k>=0} mu~(R^T(s + k step u_ab - t)),
+ *     mu~ the zero-extended trilinear interpolant, u_ab the unit direction
+ *     from the source to the pixel centre;
+ *   - back: mu[j] = sum_v W_v(j) l~_v(p_v(R_v p_j + t_v)), l~ the
+ *     zero-extended bilinear interpolant on pixel centres, W = 1
+ *     (DP_W_NONE) or (SAD / depth)^2 (DP_W_FDK, depth = e_w.r + SAD);
+ *   - spatial gradients of mu and l are central differences on grid points,
+ *     zero outside the grid.
+ *
+ * Conventions for every entry point:
+ *   - all array pointers are DEVICE pointers owned by the caller; `g` is a
+ *     host pointer; `stream` is a hipStream_t (NULL = default stream);
+ *   - calls are asynchronous on `stream`, never synchronise and never
+ *     allocate device memory: scratch space comes from the caller's
+ *     workspace `ws` of `ws_bytes` bytes (query dp_workspace_bytes);
+ *   - outputs are overwritten, not accumulated;
+ *   - arguments are validated before any launch; on error nothing is
+ *     launched, outputs are untouched and the return value is negative;
+ *     dp_last_error() then describes the failure (thread-local).
+ *   - results are deterministic: reductions use fixed-order per-block
+ *     partials; FP64 is used only for per-view setup and the final
+ *     cross-block sum of the pose gradient.
+ */
+#ifndef DIFFPROJ_H
+#define DIFFPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Acquisition geometry and voxel grid (host struct, passed by pointer). */
+typedef struct dp_geom {
+    int32_t nx, ny, nz;   /* volume size in voxels                                */
+    double  vx, vy, vz;   /* voxel size (mm)                                      */
+    int32_t nu, nv;       /* detector columns (u, fastest) and rows (v)           */
+    double  du, dv;       /* pixel pitch (mm)                                     */
+    double  off_u, off_v; /* detector-centre offset (pixels)                      */
+    double  sad, sdd;     /* source-to-axis and source-to-detector distance (mm)  */
+    double  step;         /* ray-march step (mm)                                  */
+} dp_geom;
+
+enum {
+    DP_OK = 0,
+    DP_ERR_ARG = -1,         /* null pointer, non-positive size, sdd <= sad, ...    */
+    DP_ERR_WORKSPACE = -2,   /* ws_bytes smaller than dp_workspace_bytes()          */
+    DP_ERR_HIP = -3,         /* a HIP launch reported an error                      */
+    DP_ERR_UNSUPPORTED = -4  /* sizes beyond the kernels' index ranges              */
+};
+
+enum { DP_W_NONE = 0, DP_W_FDK = 1 };
+
+enum { DP_OP_FWD = 0, DP_OP_FWD_GRAD = 1, DP_OP_BP = 2, DP_OP_BP_GRAD = 3 };
+
+/* Workspace size (bytes) needed by operation `op` (DP_OP_*) for this
+ * geometry and view count; 0 for invalid arguments. */
+size_t dp_workspace_bytes(const dp_geom* g, int32_t n_views, int32_t op);
+
+/* Forward projection (Eq. forward).
+ *   angles [V] f64 gantry angles, poses [V][6] f64 (tx,ty,tz mm; gx,gy,gz rad),
+ *   vol [nz][ny][nx] f32, proj [V][nv][nu] f32 (overwritten). */
+int dp_project_fwd(const dp_geom* g, int32_t n_views, const double* angles,
+                   const double* poses, const float* vol, float* proj,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Forward-projection pose gradient (Eqs. final_forward, dis_forward).
+ *   grad_proj [V][nv][nu] f32 = dL/dl; grad_pose [V][6] f64 = dL/dtheta
+ *   (overwritten; per mm and per rad).  Ray samples are recomputed, never
+ *   stored. */
+int dp_project_fwd_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
+                             const double* poses, const float* vol,
+                             const float* grad_proj, double* grad_pose,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Voxel-driven back-projection (Eq. back), weight_mode DP_W_NONE | DP_W_FDK.
+ *   proj [V][nv][nu] f32 (already filtered by the caller if FDK is meant),
+ *   vol [nz][ny][nx] f32 (overwritten).  No angular scale is applied. */
+int dp_backproject(const dp_geom* g, int32_t n_views, const double* angles,
+                   const double* poses, const float* proj, float* vol,
+                   int32_t weight_mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Back-projection pose gradient (Eqs. final_back, back_int, dis_back).
+ *   grad_vol [nz][ny][nx] f32 = dL/dmu; grad_pose [V][6] f64 (overwritten).
+ *   With DP_W_FDK the product-rule term l~ grad_r W is included. */
+int dp_backproject_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
+                             const double* poses, const float* proj,
+                             const float* grad_vol, double* grad_pose,
+                             int32_t weight_mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Thread-local description of the last non-zero return. */
+const char* dp_last_error(void);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t dp_version(void);
+
+/* Optional per-kernel timing with HIP events recorded on the caller's
+ * stream around every launch (for benchmarks; adds two event records per
+ * launch).  Not thread-safe: enable, run, collect from one thread.
+ *   dp_profile_enable(1) starts recording (creates the event pool),
+ *   dp_profile_enable(0) stops;
+ *   dp_profile_collect() waits for the recorded events and accumulates
+ *   their durations per kernel;
+ *   dp_profile_read(k, &ms, &n) returns the accumulated time and launch
+ *   count of kernel k (DP_K_*) and resets them. */
+enum {
+    DP_K_SETUP = 0, DP_K_VOL_PREP = 1, DP_K_RD_FWD = 2, DP_K_RD_GRAD = 3,
+    DP_K_DET_PREP = 4, DP_K_VD_BP = 5, DP_K_VD_GRAD = 6, DP_K_FINALIZE = 7,
+    DP_K_COUNT = 8
+};
+int dp_profile_enable(int32_t on);
+int dp_profile_collect(void);
+int dp_profile_read(int32_t kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIFFPROJ_H */

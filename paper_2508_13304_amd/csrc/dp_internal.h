@@ -1,0 +1,99 @@
+// Internal definitions shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "diffproj.h"
+
+namespace dp {
+
+// Zero border added around internal copies of the volume and of detector
+// images: every trilinear / bilinear tap of an in-support sample lands
+// inside the padded buffer, so the hot loops carry no per-tap bounds test.
+constexpr int kPadV = 2;
+constexpr int kPadD = 2;
+
+// Ray-driven launch shape: one block = 16x16 detector pixels = 4 wavefronts,
+// each wavefront an 8x8 pixel tile (compact footprint in the volume).
+constexpr int kRdTile = 16;
+constexpr int kRdThreads = 256;
+constexpr int kRdChannels = 9;   // B (3) and T (6) accumulators of the pose gradient
+
+// Voxel-driven launch shape: 64 (x) x 4 (y) threads, each thread owns a
+// column of kVdCol voxels along z.
+constexpr int kVdBx = 64;
+constexpr int kVdBy = 4;
+constexpr int kVdCol = 16;
+constexpr int kVdGradCol = 32;
+constexpr int kVdChannels = 12;  // A (3), QX (3), QY (3), QZ (3)
+
+// Per-view parameters, produced on the device by the setup kernel from the
+// gantry angles and the (device-resident) poses.
+struct alignas(16) ViewGeo {
+    // Ray-driven: object-frame basis in padded voxel-index units.
+    double EU[3], EV[3], EW[3];  // R^T e_{u,v,w} / h  (index units per mm)
+    double OT[3];                // padded index of the world isocentre: R^T(-t)/h + c + pad
+    // Voxel-driven: (U, V, W) = rows . (i, j, k, 1) with original voxel
+    // indices; a = U / W + cu, b = V / W + cv, W = depth (mm).  FP64 rows
+    // anchor each voxel column; the FP32 copies of the z coefficients
+    // evaluate the small in-column offsets.
+    double PUd[4], PVd[4], PWd[4];
+    float PU[4], PV[4], PW[4];
+    // Pose quantities for the final contraction (FP64).
+    double E[9];                 // world frame: (S/du) e_u, (S/dv) e_v, e_w
+    double R[9];                 // rotation, row-major
+    double omega[9];             // generators omega_x, omega_y, omega_z (world)
+};
+
+struct GeoScalars {
+    int nx, ny, nz, nu, nv;
+    double vx, vy, vz, du, dv, cu, cv, sad, sdd, step;
+};
+
+inline GeoScalars make_scalars(const dp_geom& g)
+{
+    GeoScalars s;
+    s.nx = g.nx; s.ny = g.ny; s.nz = g.nz; s.nu = g.nu; s.nv = g.nv;
+    s.vx = g.vx; s.vy = g.vy; s.vz = g.vz; s.du = g.du; s.dv = g.dv;
+    s.cu = 0.5 * (g.nu - 1) + g.off_u;
+    s.cv = 0.5 * (g.nv - 1) + g.off_v;
+    s.sad = g.sad; s.sdd = g.sdd; s.step = g.step;
+    return s;
+}
+
+// Kernel launchers (defined next to their kernels).
+void launch_view_setup(const GeoScalars& s, int V, const double* angles, const double* poses,
+                       ViewGeo* views, hipStream_t st);
+void launch_vol_pad(const GeoScalars& s, const float* vol, float* volp, hipStream_t st);
+void launch_vol_grad(const GeoScalars& s, const float* vol, float4* vol4, hipStream_t st);
+void launch_det_pad(const GeoScalars& s, int V, const float* proj, float* projp, hipStream_t st);
+void launch_det_grad(const GeoScalars& s, int V, const float* proj, float4* proj4, hipStream_t st);
+void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
+                   float* proj, hipStream_t st);
+void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* vol4,
+                    const float* grad_proj, float* partials, hipStream_t st);
+void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
+                  float* vol, int weight_mode, hipStream_t st);
+void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
+                    const float* grad_vol, float* partials, int weight_mode, hipStream_t st);
+void launch_finalize_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* partials,
+                         int n_part, double* grad_pose, hipStream_t st);
+void launch_finalize_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* partials,
+                        int n_part, double* grad_pose, hipStream_t st);
+
+inline int rd_tiles(const GeoScalars& s)
+{
+    return ((s.nu + kRdTile - 1) / kRdTile) * ((s.nv + kRdTile - 1) / kRdTile);
+}
+
+inline int vd_blocks(const GeoScalars& s, int col)
+{
+    return ((s.nx + kVdBx - 1) / kVdBx) * ((s.ny + kVdBy - 1) / kVdBy) * ((s.nz + col - 1) / col);
+}
+
+// Profiling hooks (abi.hip): bracket a launch with events when enabled.
+void prof_begin(int kernel, hipStream_t st);
+void prof_end(int kernel, hipStream_t st);
+
+}  // namespace dp

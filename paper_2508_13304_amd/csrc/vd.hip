@@ -1,0 +1,258 @@
+// Voxel-driven (FDK-style) back-projector and its rigid-motion gradient.
+//
+// Back-projection (Eq. back, Sec. II-A; mu^j = sum_i a^ij l^i, Sec. II-C):
+// every voxel j is moved by M_v, projected with the projective mapping of
+// Eq. projmatrix, and picks up W * bilinear(l_v) at its projection, with
+// W = 1 (plain) or (D / depth)^2 (FDK weight).
+//
+// Gradient (Eqs. back_derive / final_back / back_int / dis_back): per
+// voxel-view, G_b = grad_d l^T grad_r p grad_M r is back-projected with the
+// same bilinear weights and weighted by dL/dmu.  With the Jacobian rows of
+// p(r), (P_k w' - P_3 u'_k) / w'^2, the world-frame gradient of one
+// contribution is
+//   g_r = (W / w') [ l_a (S/du) e_u + l_b (S/dv) e_v - (l_a a' + l_b b' + kappa l) e_w ]
+// (a', b' pixel offsets from the detector centre; kappa = 2 carries the
+// product-rule term l grad_r W of the FDK weight, 0 without weight).  Since
+// grad_M r = [p^T, 1] per row, dL/dM needs only
+//   A_k = sum e c_k      and   Q_k = sum e c_k (I - centre)   (k = u, v, w)
+// with g_r = sum_k c_k E_k; each thread accumulates them over its voxel
+// column and the block reduces them per view (fixed order).
+//
+// Numerics: each thread owns a column of K voxels along z.  Per view, the
+// projection of the column's middle voxel is evaluated in FP64 and split
+// into an integer pixel and a fraction; every voxel of the column is then
+// placed exactly (no incremental accumulation) by the small FP32 offset
+//   a(k) - a(anchor) = dk * N_u / W(k),  N_u = (P_u,z W0 - P_w,z U0) / W0,
+// an algebraic identity of the projective division.  The bilinear weights
+// thus carry errors of ~1e-6 pixel instead of the ~3e-5 pixel that FP32
+// pixel coordinates of magnitude ~500 would carry.
+#include "dp_internal.h"
+
+namespace dp {
+
+__device__ inline float lerp_f(float a, float b, float w) { return fmaf(w, b - a, a); }
+
+// FP64 anchor of one voxel column for one view.
+struct ColumnAnchor {
+    long long off;      // padded-image offset of the anchor pixel (integer part)
+    float a0f, b0f;     // fractional part of the anchor's pixel coordinates
+    float nu, nv;       // N_u, N_v of the offset formula
+    float w0;           // depth of the anchor voxel (mm)
+    float ka;           // anchor position in the column
+    float alo, ahi, blo, bhi;  // safe window of the padded image, relative to the anchor
+    float apc, bpc;     // anchor offsets from the detector centre (pixels)
+};
+
+__device__ inline ColumnAnchor column_anchor(const ViewGeo& g, const GeoScalars& s, int i, int j,
+                                             int kb, int K)
+{
+    ColumnAnchor c;
+    int ka = K / 2;
+    const double fi = i, fj = j;
+    double W0 = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], (double)(kb + ka), g.PWd[3])));
+    if (!(fabs(W0) >= 1.0)) {  // anchor within 1 mm of the source plane: move it
+        ka = 0;
+        W0 = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], (double)kb, g.PWd[3])));
+        if (!(fabs(W0) >= 1.0)) W0 = 1.0;  // whole column at the source plane: no ray reaches it
+    }
+    const double fk = kb + ka;
+    const double U0 = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
+    const double V0 = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
+    const double iw0 = 1.0 / W0;
+    const double ap = U0 * iw0, bp = V0 * iw0;
+    // anchors far outside the detector are pulled in; their voxels still
+    // land in the zero border after the per-voxel window clamp
+    const double a0 = fmin(fmax(ap + s.cu + kPadD, -65536.0), 65536.0);
+    const double b0 = fmin(fmax(bp + s.cv + kPadD, -65536.0), 65536.0);
+    const double A0 = floor(a0), B0 = floor(b0);
+    const int NU = s.nu + 2 * kPadD;
+    c.off = (long long)B0 * NU + (long long)A0;
+    c.a0f = (float)(a0 - A0);
+    c.b0f = (float)(b0 - B0);
+    c.nu = (float)((g.PUd[2] * W0 - g.PWd[2] * U0) * iw0);
+    c.nv = (float)((g.PVd[2] * W0 - g.PWd[2] * V0) * iw0);
+    c.w0 = (float)W0;
+    c.ka = (float)ka;
+    c.alo = (float)(kPadD - 1.5 - A0);
+    c.ahi = (float)(s.nu + kPadD + 0.5 - A0);
+    c.blo = (float)(kPadD - 1.5 - B0);
+    c.bhi = (float)(s.nv + kPadD + 0.5 - B0);
+    c.apc = (float)ap;
+    c.bpc = (float)bp;
+    return c;
+}
+
+// Window clamp: positions more than half a pixel outside the detector (or
+// behind the source) land in the zero border; all others are unchanged.
+__device__ inline float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
+
+template <int MODE, int K>
+__global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int V,
+                                                              const ViewGeo* __restrict__ views,
+                                                              const float* __restrict__ projp,
+                                                              float* __restrict__ vol)
+{
+    const int i = blockIdx.x * kVdBx + threadIdx.x;
+    const int j = blockIdx.y * kVdBy + threadIdx.y;
+    const int kb = blockIdx.z * K;
+    const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
+    const float D2 = (float)(s.sad * s.sad);
+    float acc[K];
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) acc[kk] = 0.0f;
+    for (int v = 0; v < V; ++v) {
+        const ViewGeo& g = views[v];
+        const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
+        const float pw2 = g.PW[2];
+        const long long img = (long long)v * NU * NV + c.off;  // anchor pixel of this view
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            const float dk = (float)kk - c.ka;
+            const float W = fmaf(dk, pw2, c.w0);
+            const bool front = W > 0.0f;  // voxels at or behind the source get no ray
+            const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
+            float A = fmaf(dk * c.nu, iw, c.a0f);
+            float B = fmaf(dk * c.nv, iw, c.b0f);
+            A = front ? A : -1.0e9f;
+            A = clampf(A, c.alo, c.ahi);
+            B = clampf(B, c.blo, c.bhi);
+            const float fa = floorf(A), fb = floorf(B);
+            const float wa = A - fa, wb = B - fb;
+            const float* p = projp + (img + ((int)fb * NU + (int)fa));
+            const float t0 = lerp_f(p[0], p[1], wa);
+            const float t1 = lerp_f(p[NU], p[NU + 1], wa);
+            const float val = lerp_f(t0, t1, wb);
+            if (MODE == DP_W_FDK)
+                acc[kk] = fmaf(D2 * (iw * iw), val, acc[kk]);
+            else
+                acc[kk] += val;
+        }
+    }
+    if (i < s.nx && j < s.ny) {
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk)
+            if (kb + kk < s.nz) vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] = acc[kk];
+    }
+}
+
+template <int MODE, int K>
+__global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, int V,
+                                                                const ViewGeo* __restrict__ views,
+                                                                const float4* __restrict__ proj4,
+                                                                const float* __restrict__ grad_vol,
+                                                                float* __restrict__ partials)
+{
+    __shared__ float red[kVdBy][kVdChannels];
+    const int i = blockIdx.x * kVdBx + threadIdx.x;
+    const int j = blockIdx.y * kVdBy + threadIdx.y;
+    const int kb = blockIdx.z * K;
+    const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
+    const float D2 = (float)(s.sad * s.sad);
+    const float kappa = MODE == DP_W_FDK ? 2.0f : 0.0f;
+    const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
+    const float pk0 = (float)kb - 0.5f * (s.nz - 1);
+    // dL/dmu of this thread's voxel column, kept in registers for all views.
+    float e[K];
+    const bool active = i < s.nx && j < s.ny;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+        const bool in = active && kb + kk < s.nz;
+        e[kk] = in ? grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
+        if (MODE == DP_W_FDK) e[kk] *= D2;
+    }
+    const int lane = threadIdx.x, wave = threadIdx.y;
+    for (int v = 0; v < V; ++v) {
+        const ViewGeo& g = views[v];
+        const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
+        const float pw2 = g.PW[2];
+        const long long img = (long long)v * NU * NV + c.off;  // anchor pixel of this view
+        float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            const float dk = (float)kk - c.ka;
+            const float W = fmaf(dk, pw2, c.w0);
+            const bool front = W > 0.0f;  // voxels at or behind the source get no ray
+            const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
+            const float da = dk * c.nu * iw, db = dk * c.nv * iw;
+            const float ap = c.apc + da, bp = c.bpc + db;  // offsets from the detector centre
+            float A = c.a0f + da, B = c.b0f + db;
+            A = front ? A : -1.0e9f;
+            A = clampf(A, c.alo, c.ahi);
+            B = clampf(B, c.blo, c.bhi);
+            const float fa = floorf(A), fb = floorf(B);
+            const float wa = A - fa, wb = B - fb;
+            const float4* p = proj4 + (img + ((int)fb * NU + (int)fa));
+            const float4 p00 = p[0], p10 = p[1], p01 = p[NU], p11 = p[NU + 1];
+            const float l = lerp_f(lerp_f(p00.x, p10.x, wa), lerp_f(p01.x, p11.x, wa), wb);
+            const float la = lerp_f(lerp_f(p00.y, p10.y, wa), lerp_f(p01.y, p11.y, wa), wb);
+            const float lb = lerp_f(lerp_f(p00.z, p10.z, wa), lerp_f(p01.z, p11.z, wa), wb);
+            // e * W / w' (FDK: e D^2 / w'^3, with D^2 folded into e)
+            const float ec = MODE == DP_W_FDK ? e[kk] * (iw * iw) * iw : e[kk] * iw;
+            const float c1 = ec * la, c2 = ec * lb;
+            const float c3 = -ec * fmaf(la, ap, fmaf(lb, bp, kappa * l));
+            const float pk = pk0 + (float)kk;
+            A1 += c1; A2 += c2; A3 += c3;
+            Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
+        }
+        float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
+                                pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
+#pragma unroll
+        for (int ch = 0; ch < kVdChannels; ++ch)
+            for (int off = 32; off > 0; off >>= 1) r[ch] += __shfl_xor(r[ch], off);
+        if (lane == 0) {
+#pragma unroll
+            for (int ch = 0; ch < kVdChannels; ++ch) red[wave][ch] = r[ch];
+        }
+        __syncthreads();
+        if (wave == 0 && lane < kVdChannels) {
+            const float sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+            partials[((size_t)v * nblk + blk) * kVdChannels + lane] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+template <int MODE>
+static void vd_bp_dispatch(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
+                           float* vol, hipStream_t st)
+{
+    dim3 block(kVdBx, kVdBy);
+    dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy, (s.nz + kVdCol - 1) / kVdCol);
+    vd_bp_kernel<MODE, kVdCol><<<grid, block, 0, st>>>(s, V, views, projp, vol);
+}
+
+void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp, float* vol,
+                  int weight_mode, hipStream_t st)
+{
+    prof_begin(DP_K_VD_BP, st);
+    if (weight_mode == DP_W_FDK)
+        vd_bp_dispatch<DP_W_FDK>(s, V, views, projp, vol, st);
+    else
+        vd_bp_dispatch<DP_W_NONE>(s, V, views, projp, vol, st);
+    prof_end(DP_K_VD_BP, st);
+}
+
+template <int MODE>
+static void vd_grad_dispatch(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
+                             const float* grad_vol, float* partials, hipStream_t st)
+{
+    dim3 block(kVdBx, kVdBy);
+    dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy,
+              (s.nz + kVdGradCol - 1) / kVdGradCol);
+    vd_grad_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol, partials);
+}
+
+void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
+                    const float* grad_vol, float* partials, int weight_mode, hipStream_t st)
+{
+    prof_begin(DP_K_VD_GRAD, st);
+    if (weight_mode == DP_W_FDK)
+        vd_grad_dispatch<DP_W_FDK>(s, V, views, proj4, grad_vol, partials, st);
+    else
+        vd_grad_dispatch<DP_W_NONE>(s, V, views, proj4, grad_vol, partials, st);
+    prof_end(DP_K_VD_GRAD, st);
+}
+
+}  // namespace dp

@@ -208,14 +208,15 @@ def smooth_images(n_views: int, nv: int, nu: int, rng: np.random.Generator,
                   n_blobs: int = 12, signed: bool = False) -> np.ndarray:
     """[V][nv][nu] float32 smooth random detector images (sums of 2-D Gaussian blobs)."""
     out = np.zeros((n_views, nv, nu), dtype=np.float64)
-    uu = np.arange(nu, dtype=np.float64)[None, :]
-    vv = np.arange(nv, dtype=np.float64)[:, None]
+    uu = np.arange(nu, dtype=np.float64)
+    vv = np.arange(nv, dtype=np.float64)
     for v in range(n_views):
         for _ in range(n_blobs):
             cu, cv = rng.uniform(0.1 * nu, 0.9 * nu), rng.uniform(0.1 * nv, 0.9 * nv)
             su, sv = rng.uniform(0.03, 0.2) * nu, rng.uniform(0.03, 0.2) * nv
             amp = rng.uniform(-1.0, 1.0) if signed else rng.uniform(0.2, 1.0)
-            out[v] += amp * np.exp(-0.5 * (((uu - cu) / su) ** 2 + ((vv - cv) / sv) ** 2))
+            out[v] += amp * np.outer(np.exp(-0.5 * ((vv - cv) / sv) ** 2),
+                                     np.exp(-0.5 * ((uu - cu) / su) ** 2))
     return out.astype(np.float32)
 
 

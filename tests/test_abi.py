@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/*.h, and rejects invalid arguments before any launch."""
+import ctypes as C
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(dp_\w+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2508_13304_amd as m
+    return m.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    import paper_2508_13304_amd as m
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", m.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(dp_\w+)", out))
+    missing = [n for n in declared if n not in exported]
+    assert not missing, missing
+    assert set(m.EXPORTS) <= set(declared)
+    for n in declared:
+        assert hasattr(lib, n)
+
+
+def test_struct_layout_matches_header(lib):
+    import paper_2508_13304_amd as m
+    # int32 x3, double x3, int32 x2, double x7 with natural alignment
+    assert C.sizeof(m.DPGeom) == 4 * 3 + 4 + 8 * 3 + 4 * 2 + 8 * 7
+    assert lib.dp_version() == 10000
+
+
+def test_workspace_query(lib):
+    import paper_2508_13304_amd as m
+    g = synth.geom_c1()
+    for op in range(4):
+        assert m.workspace_bytes(g, 1, op) > 0
+        assert m.workspace_bytes(g, 1, op) % 256 == 0
+    assert m.workspace_bytes(g, 0, 0) == 0
+    assert m.workspace_bytes(g, 1, 7) == 0
+    assert m.workspace_bytes(g.replace(sdd=900.0), 1, 0) == 0
+    # grows with the number of views for the image-sized buffers
+    assert m.workspace_bytes(g, 8, m.OP_BP) > m.workspace_bytes(g, 1, m.OP_BP)
+
+
+def _call_fwd(lib, g, V=1, ws_bytes=None, ptr=1 << 20, ws=None):
+    import paper_2508_13304_amd as m
+    gs = m.geom_struct(g)
+    wsb = ws_bytes if ws_bytes is not None else m.workspace_bytes(g, max(V, 1), 0)
+    wsp = C.c_void_p(ws if ws is not None else 1 << 24)
+    p = C.c_void_p(ptr) if ptr else None
+    return lib.dp_project_fwd(C.byref(gs), V, p, p, p, p, wsp, wsb, None)
+
+
+def test_invalid_arguments_rejected_before_launch(lib):
+    import paper_2508_13304_amd as m
+    g = synth.geom_c1()
+    assert lib.dp_project_fwd(None, 1, None, None, None, None, None, 0, None) == -1
+    assert b"NULL" in lib.dp_last_error()
+    assert _call_fwd(lib, g.replace(nx=0)) == -1
+    assert _call_fwd(lib, g.replace(sdd=1000.0)) == -1
+    assert b"sad" in lib.dp_last_error()
+    assert _call_fwd(lib, g.replace(step=0.0)) == -1
+    assert _call_fwd(lib, g.replace(vx=float("nan"))) == -1
+    assert _call_fwd(lib, g, V=0) == -1
+    assert _call_fwd(lib, g, V=70000) == -4
+    assert _call_fwd(lib, g, ptr=0) == -1
+    assert _call_fwd(lib, g, ws_bytes=16) == -2
+    assert b"workspace" in lib.dp_last_error()
+    assert _call_fwd(lib, g, ws=(1 << 24) + 8) == -1  # misaligned workspace
+    big = g.replace(nx=2000, ny=2000, nz=2000)
+    assert _call_fwd(lib, big) == -4
+    gs = m.geom_struct(g)
+    p = C.c_void_p(1 << 20)
+    ws = m.workspace_bytes(g, 1, m.OP_BP)
+    assert lib.dp_backproject(C.byref(gs), 1, p, p, p, p, 5, p, ws, None) == -1
+    assert b"weight_mode" in lib.dp_last_error()
+    wsg = m.workspace_bytes(g, 1, m.OP_BP_GRAD)
+    assert lib.dp_backproject_grad_pose(C.byref(gs), 1, p, p, p, None, p, 0, C.c_void_p(1 << 24),
+                                        wsg, None) == -1
+    wsf = m.workspace_bytes(g, 1, m.OP_FWD_GRAD)
+    assert lib.dp_project_fwd_grad_pose(C.byref(gs), 1, p, p, p, p, p, C.c_void_p(1 << 24),
+                                        wsf - 1, None) == -2
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import paper_2508_13304_amd as m
+    saved = m._lib
+    try:
+        m._lib = None
+        with pytest.raises(RuntimeError, match="not built"):
+            m.load(str(tmp_path / "missing.so"))
+    finally:
+        m._lib = saved

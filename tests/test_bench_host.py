@@ -1,0 +1,43 @@
+"""Host-side logic of the benchmark (no GPU): the exact sample count that
+defines the ray-samples/s metric equals the oracle's brute-force count."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from synth import Geom
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_interval_count_matches_oracle(oracle, seed):
+    import bench
+    rng = synth.rng_for(300 + seed)
+    g = Geom(19, 23, 17, 1.3, 1.1, 1.6, 29, 21, 2.1, 1.9, off_u=0.5, off_v=-1.0, step=0.5)
+    V = 3
+    angles = rng.uniform(0, 2 * math.pi, V)
+    poses = synth.random_poses(V, 10.0, 30.0, rng)
+    assert bench.count_ray_samples(g, angles, poses) == oracle.count_samples(g, angles, poses)
+
+
+def test_interval_count_axis_aligned_rays(oracle):
+    import bench
+    g = Geom(16, 16, 16, 2.0, 2.0, 2.0, 21, 21, 3.0, 3.0)
+    for beta in (0.0, 0.5 * math.pi):
+        n = bench.count_ray_samples(g, [beta], np.zeros(6))
+        assert n == oracle.count_samples(g, [beta], np.zeros(6))
+
+
+def test_config1_count(oracle):
+    import bench
+    c = synth.config1_inputs()
+    assert bench.count_ray_samples(c["geom"], c["angles"], c["poses"]) == \
+        oracle.count_samples(c["geom"], c["angles"], c["poses"])
+
+
+def test_multi_gpu_request_exits(monkeypatch, capsys):
+    import bench
+    monkeypatch.setattr("sys.argv", ["bench.py", "--gpus", "2"])
+    with pytest.raises(SystemExit) as e:
+        bench.main()
+    assert e.value.code == 2
