@@ -231,7 +231,7 @@ def run_backproject(args, dp, torch):
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
 
-def run_cpu_baseline(fw, n_poses=2):
+def run_cpu_baseline(fw, n_poses=16):
     import oracle
     c = fw["inputs"]
     g = c["geom"]
@@ -256,6 +256,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bp", action="store_true", help="skip the back-projector leg")
+    ap.add_argument("--no-fwd", action="store_true", help="skip the forward leg (profiling runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -263,8 +266,19 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return
     import paper_2508_13304_amd as dp
     dp.load()
+    if args.no_fwd:
+        bp = run_backproject(args, dp, torch)
+        print(json.dumps({"backprojector": bp}), flush=True)
+        return
     fw = run_forward(args, dp, torch)
     bp = None if args.no_bp else run_backproject(args, dp, torch)
     cpu = None if args.no_cpu else run_cpu_baseline(fw)

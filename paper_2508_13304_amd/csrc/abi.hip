@@ -57,7 +57,7 @@ Layout layout(const dp_geom& g, int V, int op)
         off = align_up(off + padded_volume_elems(g) * sizeof(float));
         break;
     case DP_OP_FWD_GRAD:
-        off = align_up(off + padded_volume_elems(g) * sizeof(float4));
+        off = align_up(off + 3 * padded_volume_elems(g) * sizeof(float));
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
@@ -208,12 +208,12 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
-    float4* vol4 = (float4*)(base + L.buf);
+    float* vol3 = (float*)(base + L.buf);
     float* part = (float*)(base + L.partials);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_vol_grad(s, vol, vol4, st);
-    launch_rd_grad(s, V, views, vol4, grad_proj, part, st);
+    launch_vol_grad(s, vol, vol3, st);
+    launch_rd_grad(s, V, views, vol3, grad_proj, part, st);
     launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_project_fwd_grad_pose");
 }

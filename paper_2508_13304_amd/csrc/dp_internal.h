@@ -66,12 +66,12 @@ inline GeoScalars make_scalars(const dp_geom& g)
 void launch_view_setup(const GeoScalars& s, int V, const double* angles, const double* poses,
                        ViewGeo* views, hipStream_t st);
 void launch_vol_pad(const GeoScalars& s, const float* vol, float* volp, hipStream_t st);
-void launch_vol_grad(const GeoScalars& s, const float* vol, float4* vol4, hipStream_t st);
+void launch_vol_grad(const GeoScalars& s, const float* vol, float* vol3, hipStream_t st);
 void launch_det_pad(const GeoScalars& s, int V, const float* proj, float* projp, hipStream_t st);
 void launch_det_grad(const GeoScalars& s, int V, const float* proj, float4* proj4, hipStream_t st);
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
                    float* proj, hipStream_t st);
-void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* vol4,
+void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
                     const float* grad_proj, float* partials, hipStream_t st);
 void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
                   float* vol, int weight_mode, hipStream_t st);

@@ -2,8 +2,8 @@
 //   - zero-padded copy of the volume for the forward march;
 //   - volume gradient field (central differences, Sec. II-C: the volume
 //     gradient in G_f is approximated by a central finite difference),
-//     stored with the volume as float4 (Gx, Gy, Gz, mu) in voxel-index
-//     units, zero outside the grid;
+//     stored as three zero-padded planes Gx, Gy, Gz in voxel-index units
+//     (half the neighbour difference), zero outside the grid;
 //   - zero-padded copy of the detector images for the back-projection;
 //   - detector gradient field (central differences of l, Sec. II-C) stored
 //     as float4 (l, dl/da, dl/db, 0) in pixel-index units, zero outside.
@@ -32,21 +32,24 @@ __global__ __launch_bounds__(256) void vol_pad_kernel(int nx, int ny, int nz,
 
 __global__ __launch_bounds__(256) void vol_grad_kernel(int nx, int ny, int nz,
                                                        const float* __restrict__ vol,
-                                                       float4* __restrict__ vol4)
+                                                       float* __restrict__ vol3)
 {
-    const int NX = nx + 2 * kPadV, NY = ny + 2 * kPadV;
+    const int NX = nx + 2 * kPadV, NY = ny + 2 * kPadV, NZ = nz + 2 * kPadV;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y, K = blockIdx.z;
     if (I >= NX) return;
     const int i = I - kPadV, j = J - kPadV, k = K - kPadV;
-    float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+    float gx = 0.f, gy = 0.f, gz = 0.f;
     if (i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz) {
-        o.x = 0.5f * (vol_at(vol, nx, ny, nz, i + 1, j, k) - vol_at(vol, nx, ny, nz, i - 1, j, k));
-        o.y = 0.5f * (vol_at(vol, nx, ny, nz, i, j + 1, k) - vol_at(vol, nx, ny, nz, i, j - 1, k));
-        o.z = 0.5f * (vol_at(vol, nx, ny, nz, i, j, k + 1) - vol_at(vol, nx, ny, nz, i, j, k - 1));
-        o.w = vol[((size_t)k * ny + j) * nx + i];
+        gx = 0.5f * (vol_at(vol, nx, ny, nz, i + 1, j, k) - vol_at(vol, nx, ny, nz, i - 1, j, k));
+        gy = 0.5f * (vol_at(vol, nx, ny, nz, i, j + 1, k) - vol_at(vol, nx, ny, nz, i, j - 1, k));
+        gz = 0.5f * (vol_at(vol, nx, ny, nz, i, j, k + 1) - vol_at(vol, nx, ny, nz, i, j, k - 1));
     }
-    vol4[((size_t)K * NY + J) * NX + I] = o;
+    const size_t plane = (size_t)NX * NY * NZ;
+    const size_t o = ((size_t)K * NY + J) * NX + I;
+    vol3[o] = gx;
+    vol3[plane + o] = gy;
+    vol3[2 * plane + o] = gz;
 }
 
 __device__ inline float pix_at(const float* __restrict__ img, int nu, int nv, int a, int b)
@@ -93,12 +96,12 @@ void launch_vol_pad(const GeoScalars& s, const float* vol, float* volp, hipStrea
     prof_end(DP_K_VOL_PREP, st);
 }
 
-void launch_vol_grad(const GeoScalars& s, const float* vol, float4* vol4, hipStream_t st)
+void launch_vol_grad(const GeoScalars& s, const float* vol, float* vol3, hipStream_t st)
 {
     const int NX = s.nx + 2 * kPadV;
     dim3 grid((NX + 255) / 256, s.ny + 2 * kPadV, s.nz + 2 * kPadV);
     prof_begin(DP_K_VOL_PREP, st);
-    vol_grad_kernel<<<grid, 256, 0, st>>>(s.nx, s.ny, s.nz, vol, vol4);
+    vol_grad_kernel<<<grid, 256, 0, st>>>(s.nx, s.ny, s.nz, vol, vol3);
     prof_end(DP_K_VOL_PREP, st);
 }
 

@@ -19,26 +19,43 @@
 // from which the finalize kernel forms dL/dt = -R b and dL/dgamma_a =
 // -omega_a . (R tau) with b = B / h and tau = sum phi p x g.
 //
+// Memory: a block owns a 16x16 pixel tile of one view (4 wavefronts of 8x8
+// rays).  Its rays are marched in chunks of M consecutive sample numbers
+// k; the samples of one chunk lie in the convex hull of the tile's four
+// corner rays between the chunk's two arc lengths, so the chunk's
+// axis-aligned bounding box (plus a one-voxel margin) is loaded once,
+// coalesced, into LDS and every trilinear tap is an LDS read.  M halves
+// when the box exceeds the LDS budget; a chunk that does not fit even at
+// M = 1 reads its taps from the padded volume in global memory.
+//
 // Numerics: per-ray setup in FP64; each ray is anchored at its crossing of
 // the iso-plane (a point of small magnitude), and the FP32 march evaluates
-// X(m) = X0 + (f + m*step) * D with one rounding per FMA, so no absolute
-// positions of ~1000 mm are ever formed in FP32.
+// X(k) = X0 + (f + (k - k0) step) D with one rounding per FMA, so no
+// absolute positions of ~1000 mm are ever formed in FP32.
 #include "dp_internal.h"
 
 namespace dp {
 
-struct RayMarch {
+// LDS budgets (elements): forward = one float plane; gradient = three
+// float planes (Gx, Gy, Gz).
+constexpr int kLdsFwd = 8192;
+constexpr int kLdsGrad = 3072;
+constexpr int kChunkFwd = 32;
+constexpr int kChunkGrad = 16;
+
+struct RayState {
     float x0, y0, z0;   // padded voxel index of the iso-plane anchor
     float dx, dy, dz;   // direction in voxel-index units per mm
     float f;            // arc-length offset of sample k0 from the anchor (mm)
-    int m_lo, m_hi;     // sample range relative to k0 (inclusive); empty if m_lo > m_hi
+    int k0;             // sample number of the anchor's nearest sample
+    int klo, khi;       // in-support sample numbers (inclusive); empty if klo > khi
 };
 
 // FP64 per-ray setup: anchor, direction, sample offset and the slab clip of
 // the samples against the support (-1, n) of the trilinear interpolant.
-__device__ inline RayMarch ray_setup(const GeoScalars& s, const ViewGeo& g, int a, int b)
+__device__ inline RayState ray_setup(const GeoScalars& s, const ViewGeo& g, int a, int b)
 {
-    RayMarch r;
+    RayState r;
     const double D = s.sad, S = s.sdd;
     const double xa = (a - s.cu) * s.du, yb = (b - s.cv) * s.dv;
     const double q = D / S;
@@ -57,7 +74,7 @@ __device__ inline RayMarch ray_setup(const GeoScalars& s, const ViewGeo& g, int 
     const double f = (k0 * s.step - D) - D * rho2 / (sq + 1.0);
     const int n[3] = {s.nx, s.ny, s.nz};
     double tlo = -1.0e30, thi = 1.0e30;
-    bool empty = false;
+    bool empty = !(k0 < 1.0e8);  // also false for NaN geometry
     for (int c = 0; c < 3; ++c) {
         const double lo = kPadV - 1.0, hi = (double)n[c] + kPadV;
         if (fabs(Dir[c]) > 1.0e-12) {
@@ -68,14 +85,17 @@ __device__ inline RayMarch ray_setup(const GeoScalars& s, const ViewGeo& g, int 
             empty = true;
         }
     }
-    r.m_lo = 1;
-    r.m_hi = 0;
+    // the anchor geometry stays valid for rays without samples: corner rays
+    // of a tile bound the chunk boxes whether or not they hit the volume
+    r.k0 = k0 < 1.0e8 ? (int)k0 : 0;
+    r.klo = 1;
+    r.khi = 0;
     if (!empty && tlo < thi) {  // false for NaN inputs
         double mlo = ceil((tlo - f) / s.step), mhi = floor((thi - f) / s.step);
         mlo = fmax(mlo, -k0);  // k = k0 + m >= 0: in front of the source
         if (mlo <= mhi && mhi - mlo < 1.0e7) {
-            r.m_lo = (int)mlo;
-            r.m_hi = (int)mhi;
+            r.klo = (int)(k0 + mlo);
+            r.khi = (int)(k0 + mhi);
         }
     }
     r.x0 = (float)X0[0]; r.y0 = (float)X0[1]; r.z0 = (float)X0[2];
@@ -85,13 +105,155 @@ __device__ inline RayMarch ray_setup(const GeoScalars& s, const ViewGeo& g, int 
 }
 
 // Lane -> detector pixel: 4 wavefronts per block, each an 8x8 pixel tile.
-__device__ inline void rd_pixel(const GeoScalars& s, int tile, int& a, int& b)
+__device__ inline void rd_pixel(const GeoScalars& s, int tile, int& a, int& b, int& a0, int& b0)
 {
     const int tiles_u = (s.nu + kRdTile - 1) / kRdTile;
     const int tu = tile % tiles_u, tv = tile / tiles_u;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    a = tu * kRdTile + (wave & 1) * 8 + (lane & 7);
-    b = tv * kRdTile + (wave >> 1) * 8 + (lane >> 3);
+    a0 = tu * kRdTile;
+    b0 = tv * kRdTile;
+    a = a0 + (wave & 1) * 8 + (lane & 7);
+    b = b0 + (wave >> 1) * 8 + (lane >> 3);
+}
+
+__device__ inline float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
+
+struct Corner {
+    float x0, y0, z0, dx, dy, dz, f, k0;
+};
+
+// Block-wide setup shared by both kernels: union of the rays' sample
+// ranges and the geometry of the tile's four corner rays.
+struct TileShared {
+    Corner corner[4];
+    int klo[4], khi[4];
+};
+
+// `active` rays define the sample range; every in-detector corner lane
+// publishes its ray geometry (whether or not it carries samples).
+__device__ inline void tile_setup(const GeoScalars& s, const RayState& r, bool inside, bool active,
+                                  int a, int b, int a0, int b0, TileShared& sh, int& Kmin, int& Kmax)
+{
+    int lo = active && r.klo <= r.khi ? r.klo : INT_MAX;
+    int hi = active && r.klo <= r.khi ? r.khi : INT_MIN;
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh.klo[wave] = lo;
+        sh.khi[wave] = hi;
+    }
+    // corner rays: first / last valid pixel of the tile in each direction
+    const int a1 = min(a0 + kRdTile - 1, s.nu - 1), b1 = min(b0 + kRdTile - 1, s.nv - 1);
+    // a degenerate tile (one column or row) has coincident corners: every
+    // owner writes the same values
+    if (inside && (a == a0 || a == a1) && (b == b0 || b == b1)) {
+        const Corner c = {r.x0, r.y0, r.z0, r.dx, r.dy, r.dz, r.f, (float)r.k0};
+        if (a == a0 && b == b0) sh.corner[0] = c;
+        if (a == a1 && b == b0) sh.corner[1] = c;
+        if (a == a0 && b == b1) sh.corner[2] = c;
+        if (a == a1 && b == b1) sh.corner[3] = c;
+    }
+    __syncthreads();
+    Kmin = min(min(sh.klo[0], sh.klo[1]), min(sh.klo[2], sh.klo[3]));
+    Kmax = max(max(sh.khi[0], sh.khi[1]), max(sh.khi[2], sh.khi[3]));
+}
+
+struct Box {
+    int ox, oy, oz, bx, by, bz;
+    __device__ int vol() const { return bx * by * bz; }
+};
+
+// Bounding box (padded voxel indices, clamped to the padded volume) of all
+// trilinear taps of the samples k in [K, Ke] of every ray of the tile.
+__device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step, int NX, int NY,
+                                int NZ)
+{
+    float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const Corner& q = sh.corner[c];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float t = fmaf((float)(e ? Ke : K) - q.k0, step, q.f);
+            const float p[3] = {fmaf(t, q.dx, q.x0), fmaf(t, q.dy, q.y0), fmaf(t, q.dz, q.z0)};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = fminf(lo[d], p[d]);
+                hi[d] = fmaxf(hi[d], p[d]);
+            }
+        }
+    }
+    // one voxel of margin below; the upper trilinear tap plus one voxel above
+    const float cap[3] = {(float)(NX - 1), (float)(NY - 1), (float)(NZ - 1)};
+    int o[3], e[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        o[d] = (int)fminf(fmaxf(floorf(lo[d]) - 1.0f, 0.0f), cap[d]);
+        e[d] = (int)fminf(fmaxf(floorf(hi[d]) + 2.0f, 0.0f), cap[d]);
+    }
+    Box bx;
+    bx.ox = o[0]; bx.oy = o[1]; bx.oz = o[2];
+    bx.bx = e[0] - o[0] + 1; bx.by = e[1] - o[1] + 1; bx.bz = e[2] - o[2] + 1;
+    return bx;
+}
+
+// Choose the chunk [K, Ke]: the longest prefix (halving from Mmax) whose
+// box fits the LDS budget; fits = false if even a single sample does not.
+__device__ inline Box choose_chunk(const TileShared& sh, int K, int Kmax, int Mmax, int cap,
+                                   float step, int NX, int NY, int NZ, int& Ke, bool& fits)
+{
+    int M = Mmax;
+    Box b;
+    for (;;) {
+        Ke = min(K + M - 1, Kmax);
+        b = chunk_box(sh, K, Ke, step, NX, NY, NZ);
+        fits = b.vol() <= cap;
+        if (fits || M == 1) break;
+        M = (M + 1) >> 1;
+    }
+    return b;
+}
+
+// Cooperative copy of the box from padded global planes into LDS.  The LDS
+// layout is the box's own x-fastest order, so the flat box index e is the
+// LDS index; e -> (x, y, z) uses multiply-high reciprocals, and each thread
+// issues BATCH global loads before writing any of them to LDS.
+template <int C, int BATCH>
+__device__ inline void load_box(const Box& b, const float* const (&src)[C], float* const (&dst)[C],
+                                int NX, int NY)
+{
+    const int vol = b.vol();
+    // q = floor(e / d) = umulhi(e, floor(2^32 / d) + 1), exact for e * d < 2^32
+    const unsigned mx = b.bx > 1 ? 0xFFFFFFFFu / (unsigned)b.bx + 1u : 0u;
+    const unsigned my = b.by > 1 ? 0xFFFFFFFFu / (unsigned)b.by + 1u : 0u;
+    const size_t base = ((size_t)b.oz * NY + b.oy) * NX + b.ox;
+    for (int e0 = threadIdx.x; e0 < vol; e0 += kRdThreads * BATCH) {
+        float val[BATCH][C];
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int e = e0 + i * kRdThreads;
+            if (e < vol) {
+                const unsigned q = b.bx > 1 ? __umulhi((unsigned)e, mx) : (unsigned)e;
+                const int lx = e - (int)q * b.bx;
+                const unsigned lz = b.by > 1 ? __umulhi(q, my) : q;
+                const int ly = (int)q - (int)lz * b.by;
+                const size_t gi = base + ((size_t)lz * NY + ly) * NX + lx;
+#pragma unroll
+                for (int c = 0; c < C; ++c) val[i][c] = src[c][gi];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int e = e0 + i * kRdThreads;
+            if (e < vol) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) dst[c][e] = val[i][c];
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
@@ -99,44 +261,73 @@ __global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
                                                             const float* __restrict__ volp,
                                                             float* __restrict__ proj)
 {
+    __shared__ float lds[kLdsFwd];
+    __shared__ TileShared sh;
     const int v = blockIdx.y;
-    int a, b;
-    rd_pixel(s, blockIdx.x, a, b);
-    if (a >= s.nu || b >= s.nv) return;
+    int a, b, a0, b0;
+    rd_pixel(s, blockIdx.x, a, b, a0, b0);
+    const bool active = a < s.nu && b < s.nv;
     const ViewGeo& g = views[v];
-    const RayMarch r = ray_setup(s, g, a, b);
+    const RayState r = ray_setup(s, g, min(a, s.nu - 1), min(b, s.nv - 1));
+    int Kmin, Kmax;
+    tile_setup(s, r, active, active, a, b, a0, b0, sh, Kmin, Kmax);
     const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
     const int NXY = NX * NY;
-    // Clamp bounds keep every tap inside the padded buffer even for
-    // positions that FP32 rounding pushes across the support boundary.
-    const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
     const float step = (float)s.step;
+    const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
     float acc = 0.0f;
-    for (int m = r.m_lo; m <= r.m_hi; ++m) {
-        const float t = fmaf((float)m, step, r.f);
-        const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
-        const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
-        const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
-        const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-        const float wx = X - fx, wy = Y - fy, wz = Z - fz;
-        const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
-        const float* p = volp + idx;
-        const float c000 = p[0], c100 = p[1];
-        const float c010 = p[NX], c110 = p[NX + 1];
-        const float c001 = p[NXY], c101 = p[NXY + 1];
-        const float c011 = p[NXY + NX], c111 = p[NXY + NX + 1];
-        const float c00 = fmaf(wx, c100 - c000, c000);
-        const float c10 = fmaf(wx, c110 - c010, c010);
-        const float c01 = fmaf(wx, c101 - c001, c001);
-        const float c11 = fmaf(wx, c111 - c011, c011);
-        const float c0 = fmaf(wy, c10 - c00, c00);
-        const float c1 = fmaf(wy, c11 - c01, c01);
-        acc += fmaf(wz, c1 - c0, c0);
+    for (int K = Kmin; K <= Kmax;) {
+        int Ke;
+        bool fits;
+        const Box bx = choose_chunk(sh, K, Kmax, kChunkFwd, kLdsFwd, step, NX, NY, NZ, Ke, fits);
+        const int kb = max(K, klo), ke = min(Ke, khi);
+        if (fits) {
+            __syncthreads();  // the previous chunk's readers are done
+            {
+                const float* src[1] = {volp};
+                float* dst[1] = {lds};
+                load_box<1, 8>(bx, src, dst, NX, NY);
+            }
+            __syncthreads();
+            const float xl = r.x0 - bx.ox, yl = r.y0 - bx.oy, zl = r.z0 - bx.oz;
+            const int BX = bx.bx, BXY = bx.bx * bx.by;
+            const int imax = kLdsFwd - 1 - (BXY + BX + 1);
+            for (int k = kb; k <= ke; ++k) {
+                const float t = fmaf((float)(k - r.k0), step, r.f);
+                const float X = fmaf(t, r.dx, xl), Y = fmaf(t, r.dy, yl), Z = fmaf(t, r.dz, zl);
+                // local coordinates are >= 1 by the box margin: truncation = floor
+                const int ix = (int)X, iy = (int)Y, iz = (int)Z;
+                const float wx = X - (float)ix, wy = Y - (float)iy, wz = Z - (float)iz;
+                const int idx = min(max((iz * bx.by + iy) * BX + ix, 0), imax);
+                const float* p = lds + idx;
+                const float c00 = lerpf(p[0], p[1], wx);
+                const float c10 = lerpf(p[BX], p[BX + 1], wx);
+                const float c01 = lerpf(p[BXY], p[BXY + 1], wx);
+                const float c11 = lerpf(p[BXY + BX], p[BXY + BX + 1], wx);
+                acc += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
+            }
+        } else {
+            // box too large for LDS: taps straight from the padded volume
+            const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
+            for (int k = kb; k <= ke; ++k) {
+                const float t = fmaf((float)(k - r.k0), step, r.f);
+                const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
+                const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
+                const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
+                const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
+                const float wx = X - fx, wy = Y - fy, wz = Z - fz;
+                const float* p = volp + (((int)fz * NY + (int)fy) * NX + (int)fx);
+                const float c00 = lerpf(p[0], p[1], wx);
+                const float c10 = lerpf(p[NX], p[NX + 1], wx);
+                const float c01 = lerpf(p[NXY], p[NXY + 1], wx);
+                const float c11 = lerpf(p[NXY + NX], p[NXY + NX + 1], wx);
+                acc += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
+            }
+        }
+        K = Ke + 1;
     }
-    proj[((size_t)v * s.nv + b) * s.nu + a] = acc * step;
+    if (active) proj[((size_t)v * s.nv + b) * s.nu + a] = acc * step;
 }
-
-__device__ inline float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
 
 // Deterministic block reduction of C channels: butterfly within each
 // wavefront, then a fixed-order sum over the 4 wavefronts.
@@ -159,85 +350,149 @@ __device__ inline void block_reduce_store(float (&v)[C], float* __restrict__ out
     }
 }
 
+// Per-sample gradient accumulation from the 8 corner gradient vectors q_xyz
+// (index units) with trilinear weights (wx, wy, wz) at base corner offset
+// P from the grid centre.
+struct GradAcc {
+    float Bx = 0.f, By = 0.f, Bz = 0.f;
+    float Txy = 0.f, Txz = 0.f, Tyx = 0.f, Tyz = 0.f, Tzx = 0.f, Tzy = 0.f;
+
+    __device__ inline void add(const float3 (&q)[2][2][2], float wx, float wy, float wz, float Px,
+                               float Py, float Pz)
+    {
+        // q[dz][dy][dx]
+        // Channel Gx: lerp along x first; moments along y and z.
+        float Gx, Mxy, Mxz;
+        {
+            const float L00 = lerpf(q[0][0][0].x, q[0][0][1].x, wx), L10 = lerpf(q[0][1][0].x, q[0][1][1].x, wx);
+            const float L01 = lerpf(q[1][0][0].x, q[1][0][1].x, wx), L11 = lerpf(q[1][1][0].x, q[1][1][1].x, wx);
+            const float Y0 = lerpf(L00, L01, wz), Y1 = lerpf(L10, L11, wz);
+            Gx = lerpf(Y0, Y1, wy);
+            Mxy = wy * Y1;
+            Mxz = wz * lerpf(L01, L11, wy);
+        }
+        // Channel Gy: lerp along y first; moments along x and z.
+        float Gy, Myx, Myz;
+        {
+            const float L00 = lerpf(q[0][0][0].y, q[0][1][0].y, wy), L10 = lerpf(q[0][0][1].y, q[0][1][1].y, wy);
+            const float L01 = lerpf(q[1][0][0].y, q[1][1][0].y, wy), L11 = lerpf(q[1][0][1].y, q[1][1][1].y, wy);
+            const float X0 = lerpf(L00, L01, wz), X1 = lerpf(L10, L11, wz);
+            Gy = lerpf(X0, X1, wx);
+            Myx = wx * X1;
+            Myz = wz * lerpf(L01, L11, wx);
+        }
+        // Channel Gz: lerp along z first; moments along x and y.
+        float Gz, Mzx, Mzy;
+        {
+            const float L00 = lerpf(q[0][0][0].z, q[1][0][0].z, wz), L10 = lerpf(q[0][0][1].z, q[1][0][1].z, wz);
+            const float L01 = lerpf(q[0][1][0].z, q[1][1][0].z, wz), L11 = lerpf(q[0][1][1].z, q[1][1][1].z, wz);
+            const float X0 = lerpf(L00, L01, wy), X1 = lerpf(L10, L11, wy);
+            Gz = lerpf(X0, X1, wx);
+            Mzx = wx * X1;
+            Mzy = wy * lerpf(L01, L11, wx);
+        }
+        Bx += Gx; By += Gy; Bz += Gz;
+        // T_a,c += P_a(base) * sum phi G_c + sum phi delta_a G_c
+        Txy += fmaf(Px, Gy, Myx); Txz += fmaf(Px, Gz, Mzx);
+        Tyx += fmaf(Py, Gx, Mxy); Tyz += fmaf(Py, Gz, Mzy);
+        Tzx += fmaf(Pz, Gx, Mxz); Tzy += fmaf(Pz, Gy, Myz);
+    }
+};
+
 __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                                                              const ViewGeo* __restrict__ views,
-                                                             const float4* __restrict__ vol4,
+                                                             const float* __restrict__ gx,
+                                                             const float* __restrict__ gy,
+                                                             const float* __restrict__ gz,
                                                              const float* __restrict__ grad_proj,
                                                              float* __restrict__ partials)
 {
+    __shared__ float lds[3][kLdsGrad];
+    __shared__ TileShared sh;
     const int v = blockIdx.y;
-    int a, b;
-    rd_pixel(s, blockIdx.x, a, b);
-    float acc[kRdChannels];
+    int a, b, a0, b0;
+    rd_pixel(s, blockIdx.x, a, b, a0, b0);
+    const bool inside = a < s.nu && b < s.nv;
+    const float w = inside ? grad_proj[((size_t)v * s.nv + b) * s.nu + a] : 0.0f;
+    const ViewGeo& g = views[v];
+    const RayState r = ray_setup(s, g, min(a, s.nu - 1), min(b, s.nv - 1));
+    // rays with dL/dl = 0 contribute nothing: they only help load the boxes
+    const bool active = inside && w != 0.0f;
+    int Kmin, Kmax;
+    tile_setup(s, r, inside, active, a, b, a0, b0, sh, Kmin, Kmax);
+    const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
+    const int NXY = NX * NY;
+    const float step = (float)s.step;
+    // Padded index of the grid centre: P_a(j) = I_a(j) - centre_a.
+    const float ccx = 0.5f * (s.nx - 1) + kPadV, ccy = 0.5f * (s.ny - 1) + kPadV,
+                ccz = 0.5f * (s.nz - 1) + kPadV;
+    const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
+    GradAcc G;
+    for (int K = Kmin; K <= Kmax;) {
+        int Ke;
+        bool fits;
+        const Box bx = choose_chunk(sh, K, Kmax, kChunkGrad, kLdsGrad, step, NX, NY, NZ, Ke, fits);
+        const int kb = max(K, klo), ke = min(Ke, khi);
+        if (fits) {
+            __syncthreads();
+            {
+                const float* src[3] = {gx, gy, gz};
+                float* dst[3] = {lds[0], lds[1], lds[2]};
+                load_box<3, 4>(bx, src, dst, NX, NY);
+            }
+            __syncthreads();
+            const float xl = r.x0 - bx.ox, yl = r.y0 - bx.oy, zl = r.z0 - bx.oz;
+            const float cxl = ccx - bx.ox, cyl = ccy - bx.oy, czl = ccz - bx.oz;
+            const int BX = bx.bx, BXY = bx.bx * bx.by;
+            const int imax = kLdsGrad - 1 - (BXY + BX + 1);
+            for (int k = kb; k <= ke; ++k) {
+                const float t = fmaf((float)(k - r.k0), step, r.f);
+                const float X = fmaf(t, r.dx, xl), Y = fmaf(t, r.dy, yl), Z = fmaf(t, r.dz, zl);
+                const int ix = (int)X, iy = (int)Y, iz = (int)Z;
+                const float fx = (float)ix, fy = (float)iy, fz = (float)iz;
+                const int idx = min(max((iz * bx.by + iy) * BX + ix, 0), imax);
+                float3 q[2][2][2];
 #pragma unroll
-    for (int c = 0; c < kRdChannels; ++c) acc[c] = 0.0f;
-    const float w = (a < s.nu && b < s.nv) ? grad_proj[((size_t)v * s.nv + b) * s.nu + a] : 0.0f;
-    if (w != 0.0f) {
-        const ViewGeo& g = views[v];
-        const RayMarch r = ray_setup(s, g, a, b);
-        const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
-        const int NXY = NX * NY;
-        const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
-        // Padded index of the grid centre: P_a(j) = I_a(j) - centre_a.
-        const float ccx = 0.5f * (s.nx - 1) + kPadV, ccy = 0.5f * (s.ny - 1) + kPadV,
-                    ccz = 0.5f * (s.nz - 1) + kPadV;
-        const float step = (float)s.step;
-        float Bx = 0.f, By = 0.f, Bz = 0.f;
-        float Txy = 0.f, Txz = 0.f, Tyx = 0.f, Tyz = 0.f, Tzx = 0.f, Tzy = 0.f;
-        for (int m = r.m_lo; m <= r.m_hi; ++m) {
-            const float t = fmaf((float)m, step, r.f);
-            const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
-            const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
-            const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
-            const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-            const float wx = X - fx, wy = Y - fy, wz = Z - fz;
-            const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
-            const float4* p = vol4 + idx;
-            const float4 q000 = p[0], q100 = p[1];
-            const float4 q010 = p[NX], q110 = p[NX + 1];
-            const float4 q001 = p[NXY], q101 = p[NXY + 1];
-            const float4 q011 = p[NXY + NX], q111 = p[NXY + NX + 1];
-            // Channel Gx: lerp along x first; moments along y and z.
-            float Gx, Mxy, Mxz;  // sum phi Gx, sum phi dy Gx, sum phi dz Gx
-            {
-                const float L00 = lerpf(q000.x, q100.x, wx), L10 = lerpf(q010.x, q110.x, wx);
-                const float L01 = lerpf(q001.x, q101.x, wx), L11 = lerpf(q011.x, q111.x, wx);
-                const float Y0 = lerpf(L00, L01, wz), Y1 = lerpf(L10, L11, wz);
-                Gx = lerpf(Y0, Y1, wy);
-                Mxy = wy * Y1;
-                Mxz = wz * lerpf(L01, L11, wy);
+                for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 2; ++dx) {
+                            const int o = idx + dz * BXY + dy * BX + dx;
+                            q[dz][dy][dx] = make_float3(lds[0][o], lds[1][o], lds[2][o]);
+                        }
+                G.add(q, X - fx, Y - fy, Z - fz, fx - cxl, fy - cyl, fz - czl);
             }
-            // Channel Gy: lerp along y first; moments along x and z.
-            float Gy, Myx, Myz;
-            {
-                const float L00 = lerpf(q000.y, q010.y, wy), L10 = lerpf(q100.y, q110.y, wy);
-                const float L01 = lerpf(q001.y, q011.y, wy), L11 = lerpf(q101.y, q111.y, wy);
-                const float X0 = lerpf(L00, L01, wz), X1 = lerpf(L10, L11, wz);
-                Gy = lerpf(X0, X1, wx);
-                Myx = wx * X1;
-                Myz = wz * lerpf(L01, L11, wx);
+        } else {
+            const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
+            for (int k = kb; k <= ke; ++k) {
+                const float t = fmaf((float)(k - r.k0), step, r.f);
+                const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
+                const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
+                const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
+                const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
+                const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
+                float3 q[2][2][2];
+#pragma unroll
+                for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 2; ++dx) {
+                            const size_t o = (size_t)idx + dz * NXY + dy * NX + dx;
+                            q[dz][dy][dx] = make_float3(gx[o], gy[o], gz[o]);
+                        }
+                G.add(q, X - fx, Y - fy, Z - fz, fx - ccx, fy - ccy, fz - ccz);
             }
-            // Channel Gz: lerp along z first; moments along x and y.
-            float Gz, Mzx, Mzy;
-            {
-                const float L00 = lerpf(q000.z, q001.z, wz), L10 = lerpf(q100.z, q101.z, wz);
-                const float L01 = lerpf(q010.z, q011.z, wz), L11 = lerpf(q110.z, q111.z, wz);
-                const float X0 = lerpf(L00, L01, wy), X1 = lerpf(L10, L11, wy);
-                Gz = lerpf(X0, X1, wx);
-                Mzx = wx * X1;
-                Mzy = wy * lerpf(L01, L11, wx);
-            }
-            const float Px = fx - ccx, Py = fy - ccy, Pz = fz - ccz;
-            Bx += Gx; By += Gy; Bz += Gz;
-            // T_a,c += P_a(base) * sum phi G_c + sum phi delta_a G_c
-            Txy += fmaf(Px, Gy, Myx); Txz += fmaf(Px, Gz, Mzx);
-            Tyx += fmaf(Py, Gx, Mxy); Tyz += fmaf(Py, Gz, Mzy);
-            Tzx += fmaf(Pz, Gx, Mxz); Tzy += fmaf(Pz, Gy, Myz);
         }
+        K = Ke + 1;
+    }
+    float acc[kRdChannels] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (active) {
         const float ws = w * step;
-        acc[0] = Bx * ws; acc[1] = By * ws; acc[2] = Bz * ws;
-        acc[3] = Txy * ws; acc[4] = Txz * ws; acc[5] = Tyx * ws;
-        acc[6] = Tyz * ws; acc[7] = Tzx * ws; acc[8] = Tzy * ws;
+        acc[0] = G.Bx * ws; acc[1] = G.By * ws; acc[2] = G.Bz * ws;
+        acc[3] = G.Txy * ws; acc[4] = G.Txz * ws; acc[5] = G.Tyx * ws;
+        acc[6] = G.Tyz * ws; acc[7] = G.Tzx * ws; acc[8] = G.Tzy * ws;
     }
     const int tiles = gridDim.x;
     block_reduce_store<kRdChannels>(acc, partials + ((size_t)v * tiles + blockIdx.x) * kRdChannels);
@@ -252,12 +507,14 @@ void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float
     prof_end(DP_K_RD_FWD, st);
 }
 
-void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* vol4,
+void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
                     const float* grad_proj, float* partials, hipStream_t st)
 {
+    const size_t plane = (size_t)(s.nx + 2 * kPadV) * (s.ny + 2 * kPadV) * (s.nz + 2 * kPadV);
     dim3 grid(rd_tiles(s), V);
     prof_begin(DP_K_RD_GRAD, st);
-    rd_grad_kernel<<<grid, kRdThreads, 0, st>>>(s, views, vol4, grad_proj, partials);
+    rd_grad_kernel<<<grid, kRdThreads, 0, st>>>(s, views, vol3, vol3 + plane, vol3 + 2 * plane,
+                                                 grad_proj, partials);
     prof_end(DP_K_RD_GRAD, st);
 }
 
