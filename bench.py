@@ -33,7 +33,12 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec
+VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec (packed FMA)
+# Algorithmic FP32 operations per in-support sample (FMA counted as 2):
+#   forward : sample position 8, fractions 3, trilinear 7 lerps x 3 = 21, sum 1
+#   gradient: position 8, fractions 3, 3 channels x 8 lerps x 3 = 72, moments 6,
+#             centre offsets 3, accumulation of B (3) and T (6 x 3)
+FLOPS_PER_SAMPLE = {"rd_fwd": 33, "rd_grad": 113}
 
 
 def log(*a):
@@ -165,16 +170,21 @@ def run_forward(args, dp, torch):
     fwd_ms, grad_ms = per_kernel.get("rd_fwd", 0.0), per_kernel.get("rd_grad", 0.0)
     dominant = "rd_grad" if grad_ms >= fwd_ms else "rd_fwd"
     dom_ms = max(grad_ms, fwd_ms)
-    # Algorithmic gather bytes per sample: 8 trilinear corners x 16 B
-    # (float4 gradient volume) for the gradient, x 4 B for the forward.
-    bytes_per_sample = 128.0 if dominant == "rd_grad" else 32.0
-    achieved = bytes_per_sample * n_samples / (dom_ms * 1e-3) / 1e9
+    # Both ray kernels are bound by VALU issue once their taps come from LDS:
+    # roofline = algorithmic FP32 operations per in-support sample (FMA = 2)
+    # against the fp32 vector peak.
+    flops = FLOPS_PER_SAMPLE[dominant]
+    achieved = flops * n_samples / (dom_ms * 1e-3) / 1e12
     src_hash = _kernel_hash("rd.hip", "dp_internal.h")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
                 "traffic": _traffic(dominant + "_config2", src_hash),
-                "kernel": dominant, "kernel_ms": dom_ms, "bytes_per_sample": bytes_per_sample,
-                "source_hash": src_hash}
+                "kernel": dominant, "kernel_ms": dom_ms, "flops_per_sample": flops,
+                "source_hash": src_hash,
+                "other": {k: {"ms": per_kernel.get(k), "flops_per_sample": FLOPS_PER_SAMPLE[k],
+                              "tflops": round(FLOPS_PER_SAMPLE[k] * n_samples /
+                                              (per_kernel[k] * 1e-3) / 1e12, 2)}
+                          for k in FLOPS_PER_SAMPLE if k != dominant and per_kernel.get(k)}}
     return dict(geom=g, V=V, n_samples=n_samples, ms_step=ms_step, per_kernel=per_kernel,
                 roofline=roofline, inputs=c)
 

@@ -360,6 +360,24 @@ def _cos(a, b):
     return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
 
 
+def _triplet_agreement(ga, fd):
+    """(cosine, norm ratio) of the translation and of the rotation triplet."""
+    out = []
+    for sl in (slice(0, 3), slice(3, 6)):
+        out.append((_cos(ga[sl], fd[sl]), np.linalg.norm(ga[sl]) / np.linalg.norm(fd[sl])))
+    return out
+
+
+def _check_triplets(parts, floor):
+    """A scale or sign slip confined to one triplet (translation or rotation)
+    must fail even when the other triplet dominates the full vector."""
+    parts = np.array(parts)  # [n][2 triplets][cos, ratio]
+    for t in range(2):
+        c, r = parts[:, t, 0], parts[:, t, 1]
+        assert np.median(c) >= floor, (t, np.sort(c)[:5])
+        assert abs(np.median(r) - 1.0) < 0.03, (t, np.median(r))
+
+
 def _fd_steps():
     return np.array([1e-2] * 3 + [np.deg2rad(1e-2)] * 3)
 
@@ -374,7 +392,7 @@ def test_forward_grad_vs_central_fd(oracle):
     targets = synth.random_poses(n_real, 10.0, 10.0, rng)
     betas = rng.uniform(0, 2 * math.pi, n_real)
     hs = _fd_steps()
-    cos = []
+    cos, parts = [], []
     for i in range(n_real):
         beta, th = [betas[i]], poses[i]
         y = oracle.project_fwd(g, beta, targets[i], vol)
@@ -390,10 +408,12 @@ def test_forward_grad_vs_central_fd(oracle):
             e[q] = hs[q]
             fd[q] = (L(th + e) - L(th - e)) / (2 * hs[q])
         cos.append(_cos(ga, fd))
+        parts.append(_triplet_agreement(ga, fd))
     cos = np.array(cos)
     floor = GOLD["paper_gradient_accuracy"]["forward_rd_mean_cosine"]
     assert cos.mean() >= floor, cos
     assert np.quantile(cos, 0.05) >= 0.98, np.sort(cos)[:5]
+    _check_triplets(parts, floor)
 
 
 def _bp_setup(seed):
@@ -430,7 +450,7 @@ def test_backproject_grad_vs_central_fd(oracle, mode, loss):
     """O-FD2: analytic back-projection pose gradient vs central FD."""
     g, rng, V, angles, proj = _bp_setup(109)
     hs = _fd_steps()
-    cos = []
+    cos, parts = [], []
     for real in range(6):
         poses = synth.random_poses(V, 5.0, 5.0, rng)
         target = oracle.backproject(g, angles, synth.random_poses(V, 5.0, 5.0, rng), proj, mode)
@@ -452,10 +472,12 @@ def test_backproject_grad_vs_central_fd(oracle, mode, loss):
                 pm[v, q] -= hs[q]
                 fd[v, q] = (L_and_e(pp)[0] - L_and_e(pm)[0]) / (2 * hs[q])
         cos += [_cos(ga[v], fd[v]) for v in range(V)]
+        parts += [_triplet_agreement(ga[v], fd[v]) for v in range(V)]
     cos = np.array(cos)
     gold = GOLD["paper_gradient_accuracy"]
     assert cos.mean() >= gold["backprojector_vd_mean_cosine"], np.sort(cos)[:5]
     assert np.quantile(cos, 0.05) >= gold["backprojector_vd_p95_cosine"], np.sort(cos)[:5]
+    _check_triplets(parts, gold["backprojector_vd_mean_cosine"])
 
 
 def test_count_samples_consistent(oracle):
