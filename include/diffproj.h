@@ -117,6 +117,78 @@ int dp_backproject_grad_pose(const dp_geom* g, int32_t n_views, const double* an
                              const float* grad_vol, double* grad_pose,
                              int32_t weight_mode, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Uneven batches: many independent ray-driven problems (own volume,
+ * detector, views and poses) in ONE forward launch and ONE gradient launch
+ * (plus small per-problem setup / prep / finalize launches), e.g. many
+ * registrations or calibrations of different sizes at once (the paper's
+ * registration and calibration tasks, Sec. II-D, run many such problems).
+ * Problem descriptors travel as kernel arguments, so a batch can be
+ * captured in a graph.  At most 16 problems per call; workspace from
+ * dp_batch_workspace_bytes.  variant = -1 uses the autotuned (or default)
+ * variant of the largest problem.
+ * ------------------------------------------------------------------------- */
+typedef struct dp_problem {
+    dp_geom       geom;
+    int32_t       n_views;
+    const double* angles;     /* device [V]                                     */
+    const double* poses;      /* device [V][6]                                  */
+    const float*  vol;        /* device [nz][ny][nx]                            */
+    float*        proj;       /* device [V][nv][nu]  forward output             */
+    const float*  grad_proj;  /* device [V][nv][nu]  gradient input dL/dl       */
+    double*       grad_pose;  /* device [V][6]       gradient output            */
+} dp_problem;
+
+size_t dp_batch_workspace_bytes(const dp_problem* problems, int32_t n, int32_t op);
+int dp_project_fwd_batch(const dp_problem* problems, int32_t n, void* ws, size_t ws_bytes,
+                         int32_t variant, void* stream);
+int dp_project_fwd_grad_pose_batch(const dp_problem* problems, int32_t n, void* ws,
+                                   size_t ws_bytes, int32_t variant, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel variants of the ray-driven kernels (chunk length and LDS budget:
+ * 0, 1 = default, 2).  dp_autotune times every variant of `op` (DP_OP_FWD
+ * or DP_OP_FWD_GRAD) on the given inputs (reps timed calls each, after one
+ * warm-up; `out` is proj or grad_pose), records the fastest for this shape
+ * class (grid and detector sizes, view-count octave, pixel-to-voxel ratio)
+ * in a process-wide cache used by later calls, and synchronises `stream`.
+ * dp_set_variant forces a variant for `op` (-1 = cached / default).
+ * ------------------------------------------------------------------------- */
+int dp_autotune(int32_t op, const dp_geom* g, int32_t n_views, const double* angles,
+                const double* poses, const float* vol, const float* grad_proj, void* out,
+                void* ws, size_t ws_bytes, void* stream, int32_t reps, int32_t* best,
+                float* ms_per_variant /* [3] or NULL */);
+int dp_set_variant(int32_t op, int32_t variant);
+int32_t dp_get_variant(const dp_geom* g, int32_t n_views, int32_t op);
+
+/* ---------------------------------------------------------------------------
+ * Learned pose proposal (not in the paper; its discussion, Sec. IV, points
+ * to learning-based initialisation): primitives of a strided CNN on BF16
+ * matrix cores with FP32 accumulation.  Activations are NHWC BF16; a 3x3
+ * convolution with padding 1 and stride s maps H x W to
+ * Ho = (H - 1) / s + 1, Wo = (W - 1) / s + 1.  All pointers are device
+ * pointers; calls are asynchronous on `stream`.
+ * ------------------------------------------------------------------------- */
+/* C[M][N] (FP32, row stride ldc) = op(A) op(B) (+ C if accumulate); A is
+ * BF16 [M][K] (trans_a = 0) or [K][M]; B is BF16 [K][N] (trans_b = 0) or [N][K]. */
+int dp_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                 const void* A, int32_t lda, const void* B, int32_t ldb, float* C,
+                 int32_t ldc, int32_t accumulate, void* stream);
+/* col [N Ho Wo][9 C] BF16 from x [N][H][W][C] BF16; K index (ky, kx, c). */
+int dp_im2col3x3_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
+                      const void* x, void* col, void* stream);
+/* dx [N][H][W][C] FP32 = adjoint of im2col applied to dcol [N Ho Wo][9 C] FP32. */
+int dp_col2im3x3(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
+                 const float* dcol, float* dx, void* stream);
+/* y [rows][C] BF16 = act(z + bias), act = ReLU if relu else identity. */
+int dp_bias_act_bf16(int64_t rows, int32_t C, const float* z, const float* bias,
+                     int32_t relu, void* y, void* stream);
+/* dz BF16 = dy * (y > 0) if relu else dy, elementwise (y BF16, dy FP32). */
+int dp_act_bwd_bf16(int64_t total, const float* dy, const void* y, int32_t relu, void* dz,
+                    void* stream);
+/* db[c] = sum over the M rows of dz [M][C] (BF16), FP32 out. */
+int dp_colsum_bf16(int32_t M, int32_t C, const void* dz, float* db, void* stream);
+
 /* Thread-local description of the last non-zero return. */
 const char* dp_last_error(void);
 

@@ -25,7 +25,11 @@ KERNELS = ("setup", "vol_prep", "rd_fwd", "rd_grad", "det_prep", "vd_bp", "vd_gr
 
 EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "dp_backproject",
            "dp_backproject_grad_pose", "dp_last_error", "dp_version", "dp_profile_enable",
-           "dp_profile_collect", "dp_profile_read")
+           "dp_profile_collect", "dp_profile_read", "dp_batch_workspace_bytes",
+           "dp_project_fwd_batch", "dp_project_fwd_grad_pose_batch", "dp_autotune",
+           "dp_set_variant", "dp_get_variant")
+MAX_BATCH = 16
+N_VARIANTS = 3
 
 
 class DPGeom(C.Structure):
@@ -36,6 +40,13 @@ class DPGeom(C.Structure):
                 ("du", C.c_double), ("dv", C.c_double),
                 ("off_u", C.c_double), ("off_v", C.c_double),
                 ("sad", C.c_double), ("sdd", C.c_double), ("step", C.c_double)]
+
+
+class DPProblem(C.Structure):
+    """Mirror of `dp_problem`."""
+    _fields_ = [("geom", DPGeom), ("n_views", C.c_int32), ("angles", C.c_void_p),
+                ("poses", C.c_void_p), ("vol", C.c_void_p), ("proj", C.c_void_p),
+                ("grad_proj", C.c_void_p), ("grad_pose", C.c_void_p)]
 
 
 _lib = None
@@ -66,6 +77,20 @@ def load(path: str | None = None):
     lib.dp_version.restype = i32
     lib.dp_profile_enable.argtypes = [i32]
     lib.dp_profile_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    P = C.POINTER(DPProblem)
+    lib.dp_batch_workspace_bytes.argtypes = [P, i32, i32]
+    lib.dp_batch_workspace_bytes.restype = sz
+    lib.dp_project_fwd_batch.argtypes = [P, i32, vp, sz, i32, vp]
+    lib.dp_project_fwd_grad_pose_batch.argtypes = [P, i32, vp, sz, i32, vp]
+    lib.dp_project_fwd_batch.restype = C.c_int
+    lib.dp_project_fwd_grad_pose_batch.restype = C.c_int
+    lib.dp_autotune.argtypes = [i32, g, i32, vp, vp, vp, vp, vp, vp, sz, vp, i32,
+                                C.POINTER(i32), C.POINTER(C.c_float)]
+    lib.dp_autotune.restype = C.c_int
+    lib.dp_set_variant.argtypes = [i32, i32]
+    lib.dp_set_variant.restype = C.c_int
+    lib.dp_get_variant.argtypes = [g, i32, i32]
+    lib.dp_get_variant.restype = i32
     _lib = lib
     return lib
 
@@ -192,6 +217,89 @@ def backproject_grad_pose(geom, angles, poses, proj, grad_vol, weight_mode=W_NON
         ws.numel(), _stream(stream))
     _check(rc, "dp_backproject_grad_pose")
     return out
+
+
+# --------------------------------------------------------------------------
+# Uneven batches and kernel variants
+# --------------------------------------------------------------------------
+
+def _problems(problems, op):
+    """problems: list of dicts with geom, angles, poses, vol and proj (forward)
+    or grad_proj + grad_pose (gradient), all CUDA tensors."""
+    import torch
+    arr = (DPProblem * len(problems))()
+    for i, q in enumerate(problems):
+        g = q["geom"]
+        V = _views(q["angles"], q["poses"])
+        arr[i].geom = geom_struct(g)
+        arr[i].n_views = V
+        arr[i].angles = q["angles"].data_ptr()
+        arr[i].poses = q["poses"].data_ptr()
+        arr[i].vol = _dev(q["vol"], torch.float32, "vol", (g.nz, g.ny, g.nx)).value
+        if op == OP_FWD:
+            arr[i].proj = _dev(q["proj"], torch.float32, "proj", (V, g.nv, g.nu)).value
+        else:
+            arr[i].grad_proj = _dev(q["grad_proj"], torch.float32, "grad_proj", (V, g.nv, g.nu)).value
+            arr[i].grad_pose = _dev(q["grad_pose"], torch.float64, "grad_pose", (V, 6)).value
+    return arr
+
+
+def batch_workspace_bytes(problems, op) -> int:
+    arr = _problems(problems, op)
+    return int(load().dp_batch_workspace_bytes(arr, len(problems), op))
+
+
+def _run_batch(problems, op, ws, variant, stream):
+    import torch
+    lib = load()
+    for s0 in range(0, len(problems), MAX_BATCH):
+        chunk = problems[s0:s0 + MAX_BATCH]
+        arr = _problems(chunk, op)
+        need = int(lib.dp_batch_workspace_bytes(arr, len(chunk), op))
+        if need == 0:
+            raise ValueError("invalid batch")
+        w = ws if ws is not None and ws.numel() >= need else torch.empty(
+            need, dtype=torch.uint8, device=chunk[0]["vol"].device)
+        f = lib.dp_project_fwd_batch if op == OP_FWD else lib.dp_project_fwd_grad_pose_batch
+        _check(f(arr, len(chunk), C.c_void_p(w.data_ptr()), w.numel(), int(variant),
+                 _stream(stream)), f.__name__)
+
+
+def project_fwd_batch(problems, ws=None, variant=-1, stream=None):
+    """Forward-project an uneven batch of problems (one launch per 16 problems);
+    each problem dict supplies geom, angles, poses, vol and an output `proj`."""
+    _run_batch(problems, OP_FWD, ws, variant, stream)
+
+
+def project_fwd_grad_pose_batch(problems, ws=None, variant=-1, stream=None):
+    """Pose gradients of an uneven batch; each problem supplies grad_proj and grad_pose."""
+    _run_batch(problems, OP_FWD_GRAD, ws, variant, stream)
+
+
+def autotune(op, geom, angles, poses, vol, out, grad_proj=None, ws=None, reps=3, stream=None):
+    """Time every kernel variant of `op` on these inputs, cache the fastest for
+    this shape class and return (best, [ms per variant])."""
+    import torch
+    V = _views(angles, poses)
+    ws = _workspace(geom, V, op, ws, vol.device)
+    best = C.c_int32()
+    ms = (C.c_float * N_VARIANTS)()
+    gp = C.c_void_p(grad_proj.data_ptr()) if grad_proj is not None else None
+    rc = load().dp_autotune(int(op), C.byref(geom_struct(geom)), V,
+                            C.c_void_p(angles.data_ptr()), C.c_void_p(poses.data_ptr()),
+                            _dev(vol, torch.float32, "vol"), gp, C.c_void_p(out.data_ptr()),
+                            C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream), int(reps),
+                            C.byref(best), ms)
+    _check(rc, "dp_autotune")
+    return best.value, list(ms)
+
+
+def set_variant(op, variant):
+    _check(load().dp_set_variant(int(op), int(variant)), "dp_set_variant")
+
+
+def get_variant(geom, n_views, op) -> int:
+    return int(load().dp_get_variant(C.byref(geom_struct(geom)), int(n_views), int(op)))
 
 
 # --------------------------------------------------------------------------

@@ -5,6 +5,10 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <numeric>
 #include <vector>
 
 #include "dp_internal.h"
@@ -127,6 +131,45 @@ int check_launch(const char* what)
 }
 
 // ---------------------------------------------------------------------------
+// Kernel variants: a process-wide cache of autotuned choices per shape class
+// ---------------------------------------------------------------------------
+struct VariantKey {
+    int op, nx, ny, nz, nu, nv, vbucket, ratio;
+    bool operator<(const VariantKey& o) const
+    {
+        const int a[8] = {op, nx, ny, nz, nu, nv, vbucket, ratio};
+        const int b[8] = {o.op, o.nx, o.ny, o.nz, o.nu, o.nv, o.vbucket, o.ratio};
+        return std::lexicographical_compare(a, a + 8, b, b + 8);
+    }
+};
+std::mutex g_var_mu;
+std::map<VariantKey, int> g_var_cache;
+int g_var_force[4] = {-1, -1, -1, -1};
+constexpr int kDefaultVariant = 1;
+
+// Shape class: grid and detector sizes, view-count octave and the ratio of
+// the pixel footprint at the isocentre to the voxel size (in eighths).
+VariantKey variant_key(int op, const dp_geom& g, int V)
+{
+    VariantKey k;
+    k.op = op; k.nx = g.nx; k.ny = g.ny; k.nz = g.nz; k.nu = g.nu; k.nv = g.nv;
+    int vb = 0;
+    while ((1 << vb) < V && vb < 30) ++vb;
+    k.vbucket = vb;
+    const double hmin = std::min(g.vx, std::min(g.vy, g.vz));
+    k.ratio = (int)lround(8.0 * std::min(g.du, g.dv) * g.sad / g.sdd / hmin);
+    return k;
+}
+
+int variant_for(int op, const dp_geom& g, int V)
+{
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    if (g_var_force[op] >= 0) return g_var_force[op];
+    auto it = g_var_cache.find(variant_key(op, g, V));
+    return it == g_var_cache.end() ? kDefaultVariant : it->second;
+}
+
+// ---------------------------------------------------------------------------
 // Profiling (events on the caller's stream around each launch)
 // ---------------------------------------------------------------------------
 struct Prof {
@@ -190,7 +233,7 @@ int dp_project_fwd(const dp_geom* g, int32_t V, const double* angles, const doub
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
     launch_vol_pad(s, vol, volp, st);
-    launch_rd_fwd(s, V, views, volp, proj, st);
+    launch_rd_fwd(s, V, views, volp, proj, variant_for(DP_OP_FWD, *g, V), st);
     return check_launch("dp_project_fwd");
 }
 
@@ -213,7 +256,7 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
     launch_vol_grad(s, vol, vol3, st);
-    launch_rd_grad(s, V, views, vol3, grad_proj, part, st);
+    launch_rd_grad(s, V, views, vol3, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V), st);
     launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_project_fwd_grad_pose");
 }
@@ -266,6 +309,272 @@ int dp_backproject_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     launch_vd_grad(s, V, views, proj4, grad_vol, part, weight_mode, st);
     launch_finalize_bp(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_backproject_grad_pose");
+}
+
+// ---------------------------------------------------------------------------
+// Variant control and autotuning
+// ---------------------------------------------------------------------------
+
+int dp_set_variant(int32_t op, int32_t variant)
+{
+    if (op != DP_OP_FWD && op != DP_OP_FWD_GRAD) return fail(DP_ERR_ARG, "op must be FWD or FWD_GRAD");
+    if (variant < -1 || variant >= kRdVariants) return fail(DP_ERR_ARG, "variant out of range");
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_var_force[op] = variant;
+    return DP_OK;
+}
+
+int32_t dp_get_variant(const dp_geom* g, int32_t n_views, int32_t op)
+{
+    if (!g || (op != DP_OP_FWD && op != DP_OP_FWD_GRAD)) return -1;
+    return variant_for(op, *g, n_views);
+}
+
+int dp_autotune(int32_t op, const dp_geom* g, int32_t V, const double* angles, const double* poses,
+                const float* vol, const float* grad_proj, void* out, void* ws, size_t ws_bytes,
+                void* stream, int32_t reps, int32_t* best, float* ms_per_variant)
+{
+    if (op != DP_OP_FWD && op != DP_OP_FWD_GRAD) return fail(DP_ERR_ARG, "op must be FWD or FWD_GRAD");
+    if (reps <= 0 || reps > 100) return fail(DP_ERR_ARG, "reps must be in [1, 100]");
+    int rc = check_geom(g, V);
+    if (rc) return rc;
+    if (!angles || !poses || !vol || !out || (op == DP_OP_FWD_GRAD && !grad_proj))
+        return fail(DP_ERR_ARG, "NULL array argument");
+    if ((rc = check_ws(g, V, op, ws, ws_bytes))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(DP_ERR_HIP, "hipEventCreate failed");
+    int saved;
+    {
+        std::lock_guard<std::mutex> lk(g_var_mu);
+        saved = g_var_force[op];
+    }
+    float times[kRdVariants];
+    int arg = 0;
+    for (int var = 0; var < kRdVariants && rc == DP_OK; ++var) {
+        dp_set_variant(op, var);
+        for (int r = 0; r <= reps && rc == DP_OK; ++r) {  // first call warms up
+            if (r == 1) hipEventRecord(e0, st);
+            rc = op == DP_OP_FWD
+                     ? dp_project_fwd(g, V, angles, poses, vol, (float*)out, ws, ws_bytes, stream)
+                     : dp_project_fwd_grad_pose(g, V, angles, poses, vol, grad_proj, (double*)out,
+                                                ws, ws_bytes, stream);
+        }
+        hipEventRecord(e1, st);
+        if (rc == DP_OK && hipEventSynchronize(e1) == hipSuccess) {
+            hipEventElapsedTime(&times[var], e0, e1);
+            times[var] /= reps;
+            if (times[var] < times[arg]) arg = var;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_var_mu);
+        g_var_force[op] = saved;
+        if (rc == DP_OK) g_var_cache[variant_key(op, *g, V)] = arg;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    if (best) *best = arg;
+    if (ms_per_variant)
+        for (int v = 0; v < kRdVariants; ++v) ms_per_variant[v] = times[v];
+    return DP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Uneven batches of ray-driven problems
+// ---------------------------------------------------------------------------
+
+static int check_batch(const dp_problem* pr, int32_t n, int op)
+{
+    if (!pr) return fail(DP_ERR_ARG, "problem array is NULL");
+    if (n <= 0) return fail(DP_ERR_ARG, "batch size must be positive");
+    if (n > kRdMaxBatch) return fail(DP_ERR_UNSUPPORTED, "at most %d problems per batch", kRdMaxBatch);
+    for (int i = 0; i < n; ++i) {
+        const int rc = check_geom(&pr[i].geom, pr[i].n_views);
+        if (rc) {
+            char msg[sizeof g_err];
+            snprintf(msg, sizeof msg, "%s", g_err);
+            return fail(rc, "problem %d: %s", i, msg);
+        }
+        const dp_problem& q = pr[i];
+        if (!q.angles || !q.poses || !q.vol) return fail(DP_ERR_ARG, "problem %d: NULL input", i);
+        if (op == DP_OP_FWD && !q.proj) return fail(DP_ERR_ARG, "problem %d: NULL proj", i);
+        if (op == DP_OP_FWD_GRAD && (!q.grad_proj || !q.grad_pose))
+            return fail(DP_ERR_ARG, "problem %d: NULL grad_proj / grad_pose", i);
+    }
+    return DP_OK;
+}
+
+size_t dp_batch_workspace_bytes(const dp_problem* pr, int32_t n, int32_t op)
+{
+    if ((op != DP_OP_FWD && op != DP_OP_FWD_GRAD) || !pr || n <= 0 || n > kRdMaxBatch) return 0;
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (check_geom(&pr[i].geom, pr[i].n_views) != DP_OK) return 0;
+        total += layout(pr[i].geom, pr[i].n_views, op).total;
+    }
+    return total;
+}
+
+static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t ws_bytes,
+                     int32_t variant, void* stream)
+{
+    int rc = check_batch(pr, n, op);
+    if (rc) return rc;
+    if (variant < -1 || variant >= kRdVariants) return fail(DP_ERR_ARG, "variant out of range");
+    const size_t need = dp_batch_workspace_bytes(pr, n, op);
+    if (ws_bytes < need)
+        return fail(DP_ERR_WORKSPACE, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    if (!ws || (uintptr_t)ws % kAlign) return fail(DP_ERR_ARG, "workspace NULL or not 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    // largest problems first: their blocks are dispatched first, shortening the tail
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto work = [&](int i) {
+        const dp_geom& g = pr[i].geom;
+        return (double)pr[i].n_views * g.nu * g.nv * std::max(g.nx, std::max(g.ny, g.nz));
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    RdBatch bt;
+    bt.n = n;
+    size_t off = 0;
+    long long blocks = 0;
+    int big = order[0];
+    std::vector<size_t> offs(n);
+    for (int i = 0; i < n; ++i) {
+        offs[i] = off;
+        off += layout(pr[i].geom, pr[i].n_views, op).total;
+    }
+    (void)hipGetLastError();
+    for (int j = 0; j < n; ++j) {
+        const int i = order[j];
+        const dp_problem& q = pr[i];
+        const Layout L = layout(q.geom, q.n_views, op);
+        const GeoScalars s = make_scalars(q.geom);
+        char* base = (char*)ws + offs[i];
+        ViewGeo* views = (ViewGeo*)(base + L.views);
+        float* buf = (float*)(base + L.buf);
+        launch_view_setup(s, q.n_views, q.angles, q.poses, views, st);
+        if (op == DP_OP_FWD)
+            launch_vol_pad(s, q.vol, buf, st);
+        else
+            launch_vol_grad(s, q.vol, buf, st);
+        RdBatchItem& it = bt.it[j];
+        it.s = s;
+        it.views = views;
+        it.vol = buf;
+        it.gin = op == DP_OP_FWD ? nullptr : q.grad_proj;
+        it.out = op == DP_OP_FWD ? q.proj : (float*)(base + L.partials);
+        it.tiles = rd_tiles(s);
+        it.first = (int)blocks;
+        blocks += (long long)it.tiles * q.n_views;
+    }
+    if (blocks >= (1LL << 31)) return fail(DP_ERR_UNSUPPORTED, "batch too large for one launch");
+    const int var = variant >= 0 ? variant : variant_for(op, pr[big].geom, pr[big].n_views);
+    if (op == DP_OP_FWD) {
+        launch_rd_fwd_batch(bt, (int)blocks, var, st);
+    } else {
+        launch_rd_grad_batch(bt, (int)blocks, var, st);
+        for (int j = 0; j < n; ++j) {
+            const int i = order[j];
+            const Layout L = layout(pr[i].geom, pr[i].n_views, op);
+            char* base = (char*)ws + offs[i];
+            launch_finalize_fwd(make_scalars(pr[i].geom), pr[i].n_views, (ViewGeo*)(base + L.views),
+                                (float*)(base + L.partials), (int)L.n_part, pr[i].grad_pose, st);
+        }
+    }
+    return check_launch(op == DP_OP_FWD ? "dp_project_fwd_batch" : "dp_project_fwd_grad_pose_batch");
+}
+
+int dp_project_fwd_batch(const dp_problem* problems, int32_t n, void* ws, size_t ws_bytes,
+                         int32_t variant, void* stream)
+{
+    return run_batch(problems, n, DP_OP_FWD, ws, ws_bytes, variant, stream);
+}
+
+int dp_project_fwd_grad_pose_batch(const dp_problem* problems, int32_t n, void* ws,
+                                   size_t ws_bytes, int32_t variant, void* stream)
+{
+    return run_batch(problems, n, DP_OP_FWD_GRAD, ws, ws_bytes, variant, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Learned-proposal CNN primitives (BF16 MFMA GEMM and conv helpers)
+// ---------------------------------------------------------------------------
+
+int dp_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K, const void* A,
+                 int32_t lda, const void* B, int32_t ldb, float* C, int32_t ldc,
+                 int32_t accumulate, void* stream)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return fail(DP_ERR_ARG, "gemm sizes must be positive");
+    if (!A || !B || !C) return fail(DP_ERR_ARG, "gemm: NULL operand");
+    if (lda < (trans_a ? M : K) || ldb < (trans_b ? K : N) || ldc < N)
+        return fail(DP_ERR_ARG, "gemm: leading dimension too small");
+    if ((size_t)M * ldc >= ((size_t)1 << 40)) return fail(DP_ERR_UNSUPPORTED, "gemm too large");
+    if ((N + 63) / 64 > 65535) return fail(DP_ERR_UNSUPPORTED, "gemm: N above 65535 tiles of 64");
+    (void)hipGetLastError();
+    launch_gemm_bf16(trans_a != 0, trans_b != 0, M, N, K, A, lda, B, ldb, C, ldc, accumulate != 0,
+                     (hipStream_t)stream);
+    return check_launch("dp_gemm_bf16");
+}
+
+static int conv_dims(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride)
+{
+    if (N <= 0 || H <= 0 || W <= 0 || C <= 0 || stride <= 0)
+        return fail(DP_ERR_ARG, "conv sizes must be positive");
+    return DP_OK;
+}
+
+int dp_im2col3x3_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride, const void* x,
+                      void* col, void* stream)
+{
+    int rc = conv_dims(N, H, W, C, stride);
+    if (rc) return rc;
+    if (!x || !col) return fail(DP_ERR_ARG, "im2col: NULL pointer");
+    const int Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
+    (void)hipGetLastError();
+    launch_im2col(N, H, W, C, stride, Ho, Wo, x, col, (hipStream_t)stream);
+    return check_launch("dp_im2col3x3_bf16");
+}
+
+int dp_col2im3x3(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride, const float* dcol,
+                 float* dx, void* stream)
+{
+    int rc = conv_dims(N, H, W, C, stride);
+    if (rc) return rc;
+    if (!dcol || !dx) return fail(DP_ERR_ARG, "col2im: NULL pointer");
+    const int Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
+    (void)hipGetLastError();
+    launch_col2im(N, H, W, C, stride, Ho, Wo, dcol, dx, (hipStream_t)stream);
+    return check_launch("dp_col2im3x3");
+}
+
+int dp_bias_act_bf16(int64_t rows, int32_t C, const float* z, const float* bias, int32_t relu,
+                     void* y, void* stream)
+{
+    if (rows <= 0 || C <= 0 || !z || !bias || !y) return fail(DP_ERR_ARG, "bias_act: bad argument");
+    (void)hipGetLastError();
+    launch_bias_relu((size_t)rows * C, C, z, bias, relu != 0, y, (hipStream_t)stream);
+    return check_launch("dp_bias_act_bf16");
+}
+
+int dp_act_bwd_bf16(int64_t total, const float* dy, const void* y, int32_t relu, void* dz,
+                    void* stream)
+{
+    if (total <= 0 || !dy || !y || !dz) return fail(DP_ERR_ARG, "act_bwd: bad argument");
+    (void)hipGetLastError();
+    launch_relu_bwd((size_t)total, dy, y, relu != 0, dz, (hipStream_t)stream);
+    return check_launch("dp_act_bwd_bf16");
+}
+
+int dp_colsum_bf16(int32_t M, int32_t C, const void* dz, float* db, void* stream)
+{
+    if (M <= 0 || C <= 0 || !dz || !db) return fail(DP_ERR_ARG, "colsum: bad argument");
+    (void)hipGetLastError();
+    launch_colsum(M, C, dz, db, (hipStream_t)stream);
+    return check_launch("dp_colsum_bf16");
 }
 
 int dp_profile_enable(int32_t on)

@@ -1,0 +1,279 @@
+// Learned pose proposal: the layers of a small strided CNN on BF16 matrix
+// cores (MFMA) with FP32 accumulation.  The network regresses a 6-DoF pose
+// offset from a pair of DRRs rendered by the forward projector; its output
+// initialises the analytic-gradient registration.
+//
+// Layout: activations are NHWC (row m = (n, y, x), column = channel), so a
+// 3x3 strided convolution is
+//   col  = im2col(x)            [M = N Ho Wo][K = 9 Ci], K index (ky, kx, ci)
+//   z    = col . W^T            W [Co][K]                  (GEMM, MFMA)
+//   y    = relu(z + b)          fused epilogue, BF16 out
+// and its backward is
+//   dz   = dy * (y > 0)
+//   dW   = dz^T . col           [Co][K]                    (GEMM, MFMA)
+//   db   = column sums of dz
+//   dcol = dz . W               [M][K]                     (GEMM, MFMA)
+//   dx   = col2im(dcol)         gather of the overlapping windows.
+//
+// GEMM: C[M][N] (FP32) = op(A) op(B) (+ C if accumulate), A/B BF16.  A block
+// computes a 64x64 tile with 4 wavefronts (32x32 each = 2x2 MFMA 16x16x32
+// tiles); K advances by 32 through LDS.  Operand lane layout of
+// v_mfma_f32_16x16x32_bf16: lane l supplies row (l % 16) of A and column
+// (l % 16) of B, each with the 8 consecutive k = 8 (l / 16) .. +7; it receives
+// D rows 4 (l / 16) .. +3 of column (l % 16).
+#include <algorithm>
+
+#include "dp_internal.h"
+
+namespace dp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGT = 64;   // block tile (M and N)
+constexpr int kGK = 32;   // K step
+constexpr int kGPad = 8;  // LDS row padding (bf16 elements) against bank conflicts
+
+__device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// op(A)[m][k]: A stored [M][K] (lda) or, if TA, [K][M] (lda).
+template <bool TA>
+__device__ inline float a_at(const __bf16* A, int lda, int m, int k)
+{
+    return TA ? (float)A[(size_t)k * lda + m] : (float)A[(size_t)m * lda + k];
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
+                                                        const __bf16* __restrict__ A, int lda,
+                                                        const __bf16* __restrict__ B, int ldb,
+                                                        float* __restrict__ C, int ldc,
+                                                        int accumulate)
+{
+    // As[m][k] and Bs[n][k]: both k-contiguous so a lane reads 8 k at once.
+    __shared__ __attribute__((aligned(16))) __bf16 As[kGT][kGK + kGPad];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[kGT][kGK + kGPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT;
+    // split-K: block z covers k in [kbeg, kend); partial sums are added atomically
+    const int ksplit = (K + (int)gridDim.z - 1) / (int)gridDim.z;
+    const int kbeg = (int)blockIdx.z * ((ksplit + kGK - 1) / kGK * kGK);
+    const int kend = min(K, kbeg + (ksplit + kGK - 1) / kGK * kGK);
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kbeg; k0 < kend; k0 += kGK) {
+        // stage: 64 x 32 elements of each operand, 8 per thread
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + e * 256;          // 0 .. 2047
+            int r, c;
+            if (TA) { r = idx & 63; c = idx >> 6; }  // coalesced along m
+            else    { r = idx >> 5; c = idx & 31; }  // coalesced along k
+            const int m = m0 + r, k = k0 + c;
+            As[r][c] = (m < M && k < kend) ? (TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k])
+                                        : to_bf16(0.f);
+            int rb, cb;
+            if (TB) { rb = idx >> 5; cb = idx & 31; }  // B stored [N][K]: coalesced along k
+            else    { rb = idx & 63; cb = idx >> 6; }  // B stored [K][N]: coalesced along n
+            const int n = n0 + rb, kb = k0 + cb;
+            Bs[rb][cb] = (n < N && kb < kend) ? (TB ? B[(size_t)n * ldb + kb] : B[(size_t)kb * ldb + n])
+                                           : to_bf16(0.f);
+        }
+        __syncthreads();
+        const int kq = (lane >> 4) * 8;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][kq];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][kq];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
+                const int n = n0 + wn + j * 16 + (lane & 15);
+                if (m < M && n < N) {
+                    float* c = C + (size_t)m * ldc + n;
+                    if (gridDim.z > 1)
+                        atomicAdd(c, acc[i][j][q]);
+                    else
+                        *c = accumulate ? *c + acc[i][j][q] : acc[i][j][q];
+                }
+            }
+}
+
+__global__ __launch_bounds__(256) void fill_rows_kernel(int M, int N, float* __restrict__ C, int ldc)
+{
+    const size_t total = (size_t)M * N;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x)
+        C[(i / N) * ldc + i % N] = 0.0f;
+}
+
+void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int lda, const void* B,
+                      int ldb, float* C, int ldc, bool accumulate, hipStream_t st)
+{
+    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
+    // few output tiles and a long reduction: split K over up to 64 blocks per tile
+    int splits = 1;
+    if ((long long)tm * tn < 1024 && K > 4096) splits = (int)std::min<long long>(64, K / 4096);
+    if (splits > 1 && !accumulate) {
+        const size_t total = (size_t)M * N;
+        const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+        fill_rows_kernel<<<blocks, 256, 0, st>>>(M, N, C, ldc);
+    }
+    dim3 grid(tm, tn, splits);
+    const __bf16* a = (const __bf16*)A;
+    const __bf16* b = (const __bf16*)B;
+    const int acc = accumulate ? 1 : 0;
+    if (!ta && !tb) gemm_bf16_kernel<false, false><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
+    else if (!ta && tb) gemm_bf16_kernel<false, true><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
+    else if (ta && !tb) gemm_bf16_kernel<true, false><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
+    else gemm_bf16_kernel<true, true><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
+}
+
+// im2col of a 3x3 convolution (stride s, padding 1) on NHWC BF16 input.
+__global__ __launch_bounds__(256) void im2col_kernel(int N, int H, int W, int C, int s, int Ho,
+                                                     int Wo, const __bf16* __restrict__ x,
+                                                     __bf16* __restrict__ col)
+{
+    const size_t K = (size_t)9 * C;
+    const size_t total = (size_t)N * Ho * Wo * K;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t m = i / K;
+        const int k = (int)(i - m * K);
+        const int ci = k % C, kk = k / C, kx = kk % 3, ky = kk / 3;
+        const int xo = (int)(m % Wo), yo = (int)((m / Wo) % Ho), n = (int)(m / ((size_t)Wo * Ho));
+        const int yi = yo * s + ky - 1, xi = xo * s + kx - 1;
+        col[i] = (yi >= 0 && yi < H && xi >= 0 && xi < W)
+                     ? x[(((size_t)n * H + yi) * W + xi) * C + ci] : to_bf16(0.f);
+    }
+}
+
+// dx = col2im(dcol): each input element gathers the window entries that read it.
+__global__ __launch_bounds__(256) void col2im_kernel(int N, int H, int W, int C, int s, int Ho,
+                                                     int Wo, const float* __restrict__ dcol,
+                                                     float* __restrict__ dx)
+{
+    const size_t total = (size_t)N * H * W * C;
+    const int K = 9 * C;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % C);
+        const int xi = (int)((i / C) % W), yi = (int)((i / ((size_t)C * W)) % H);
+        const int n = (int)(i / ((size_t)C * W * H));
+        float acc = 0.f;
+        for (int ky = 0; ky < 3; ++ky) {
+            const int ty = yi + 1 - ky;  // = yo * s
+            if (ty < 0 || ty % s) continue;
+            const int yo = ty / s;
+            if (yo >= Ho) continue;
+            for (int kx = 0; kx < 3; ++kx) {
+                const int tx = xi + 1 - kx;
+                if (tx < 0 || tx % s) continue;
+                const int xo = tx / s;
+                if (xo >= Wo) continue;
+                const size_t m = ((size_t)n * Ho + yo) * Wo + xo;
+                acc += dcol[m * K + (ky * 3 + kx) * C + ci];
+            }
+        }
+        dx[i] = acc;
+    }
+}
+
+// y = relu(z + b) -> BF16 (and FP32 copy for the head); z [M][C] FP32.
+__global__ __launch_bounds__(256) void bias_relu_kernel(size_t total, int C, const float* __restrict__ z,
+                                                        const float* __restrict__ b, int relu,
+                                                        __bf16* __restrict__ y)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float v = z[i] + b[i % C];
+        if (relu) v = fmaxf(v, 0.f);
+        y[i] = to_bf16(v);
+    }
+}
+
+// dz = dy * (y > 0) -> BF16 operand for the GEMMs; y is the layer's BF16 output.
+__global__ __launch_bounds__(256) void relu_bwd_kernel(size_t total, const float* __restrict__ dy,
+                                                       const __bf16* __restrict__ y, int relu,
+                                                       __bf16* __restrict__ dz)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float g = dy[i];
+        dz[i] = to_bf16(relu ? ((float)y[i] > 0.f ? g : 0.f) : g);
+    }
+}
+
+// db[c] = sum over rows of dz (BF16 operand as used by the weight GEMM).
+__global__ __launch_bounds__(256) void colsum_kernel(int M, int C, const __bf16* __restrict__ dz,
+                                                     float* __restrict__ db)
+{
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float acc = 0.f;
+    for (int m = threadIdx.x; m < M; m += 256) acc += (float)dz[(size_t)m * C + c];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[c] = red[0];
+}
+
+static int grid_for(size_t total)
+{
+    const size_t b = (total + 255) / 256;
+    return (int)(b < 65536 ? (b == 0 ? 1 : b) : 65536);
+}
+
+void launch_im2col(int N, int H, int W, int C, int s, int Ho, int Wo, const void* x, void* col,
+                   hipStream_t st)
+{
+    const size_t total = (size_t)N * Ho * Wo * 9 * C;
+    im2col_kernel<<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, (const __bf16*)x,
+                                                   (__bf16*)col);
+}
+
+void launch_col2im(int N, int H, int W, int C, int s, int Ho, int Wo, const float* dcol, float* dx,
+                   hipStream_t st)
+{
+    const size_t total = (size_t)N * H * W * C;
+    col2im_kernel<<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx);
+}
+
+void launch_bias_relu(size_t total, int C, const float* z, const float* b, bool relu, void* y,
+                      hipStream_t st)
+{
+    bias_relu_kernel<<<grid_for(total), 256, 0, st>>>(total, C, z, b, relu ? 1 : 0, (__bf16*)y);
+}
+
+void launch_relu_bwd(size_t total, const float* dy, const void* y, bool relu, void* dz,
+                     hipStream_t st)
+{
+    relu_bwd_kernel<<<grid_for(total), 256, 0, st>>>(total, dy, (const __bf16*)y, relu ? 1 : 0,
+                                                     (__bf16*)dz);
+}
+
+void launch_colsum(int M, int C, const void* dz, float* db, hipStream_t st)
+{
+    colsum_kernel<<<C, 256, 0, st>>>(M, C, (const __bf16*)dz, db);
+}
+
+}  // namespace dp

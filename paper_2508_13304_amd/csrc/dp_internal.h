@@ -70,9 +70,28 @@ void launch_vol_grad(const GeoScalars& s, const float* vol, float* vol3, hipStre
 void launch_det_pad(const GeoScalars& s, int V, const float* proj, float* projp, hipStream_t st);
 void launch_det_grad(const GeoScalars& s, int V, const float* proj, float4* proj4, hipStream_t st);
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
-                   float* proj, hipStream_t st);
+                   float* proj, int variant, hipStream_t st);
 void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
-                    const float* grad_proj, float* partials, hipStream_t st);
+                    const float* grad_proj, float* partials, int variant, hipStream_t st);
+
+// Uneven batches of ray-driven problems in one launch (descriptors by value).
+constexpr int kRdMaxBatch = 16;
+constexpr int kRdVariants = 3;
+struct RdBatchItem {
+    GeoScalars s;
+    const ViewGeo* views;
+    const float* vol;   // padded volume (forward) or gradient planes (gradient)
+    const float* gin;   // dL/dl (gradient only)
+    float* out;         // DRRs (forward) or per-block partials (gradient)
+    int tiles;          // detector tiles per view
+    int first;          // first block of this problem
+};
+struct RdBatch {
+    int n;
+    RdBatchItem it[kRdMaxBatch];
+};
+void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
+void launch_rd_grad_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
 void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
                   float* vol, int weight_mode, hipStream_t st);
 void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
@@ -81,6 +100,19 @@ void launch_finalize_fwd(const GeoScalars& s, int V, const ViewGeo* views, const
                          int n_part, double* grad_pose, hipStream_t st);
 void launch_finalize_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* partials,
                         int n_part, double* grad_pose, hipStream_t st);
+
+// Learned-proposal CNN primitives (cnn.hip).
+void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int lda, const void* B,
+                      int ldb, float* C, int ldc, bool accumulate, hipStream_t st);
+void launch_im2col(int N, int H, int W, int C, int s, int Ho, int Wo, const void* x, void* col,
+                   hipStream_t st);
+void launch_col2im(int N, int H, int W, int C, int s, int Ho, int Wo, const float* dcol, float* dx,
+                   hipStream_t st);
+void launch_bias_relu(size_t total, int C, const float* z, const float* b, bool relu, void* y,
+                      hipStream_t st);
+void launch_relu_bwd(size_t total, const float* dy, const void* y, bool relu, void* dz,
+                     hipStream_t st);
+void launch_colsum(int M, int C, const void* dz, float* db, hipStream_t st);
 
 inline int rd_tiles(const GeoScalars& s)
 {

@@ -21,27 +21,32 @@
 //
 // Memory: a block owns a 16x16 pixel tile of one view (4 wavefronts of 8x8
 // rays).  Its rays are marched in chunks of M consecutive sample numbers
-// k; the samples of one chunk lie in the convex hull of the tile's four
-// corner rays between the chunk's two arc lengths, so the chunk's
-// axis-aligned bounding box (plus a one-voxel margin) is loaded once,
-// coalesced, into LDS and every trilinear tap is an LDS read.  M halves
-// when the box exceeds the LDS budget; a chunk that does not fit even at
-// M = 1 reads its taps from the padded volume in global memory.
+// k.  The samples of one chunk lie in the convex hull of the tile's four
+// corner rays between the chunk's two arc lengths, up to the height of the
+// spherical cap spanned by the tile (bounded per tile), so the chunk's
+// axis-aligned bounding box is loaded once, coalesced, into LDS and every
+// trilinear tap is an LDS read.  All chunk boxes of a tile are planned up
+// front, one per thread; M halves until every box fits the LDS budget, and
+// a tile whose boxes do not fit even at M = 1 reads its taps from the
+// padded volume in global memory.
 //
 // Numerics: per-ray setup in FP64; each ray is anchored at its crossing of
-// the iso-plane (a point of small magnitude), and the FP32 march evaluates
-// X(k) = X0 + (f + (k - k0) step) D with one rounding per FMA, so no
-// absolute positions of ~1000 mm are ever formed in FP32.
+// the iso-plane (a point of small magnitude) and, per chunk, re-anchored at
+// its first sample of the chunk, X(kb) = X0 + (f + (kb - k0) step) D; the
+// chunk's samples are then X(kb) + j (step D) for j < M.  No absolute
+// position of ~1000 mm is ever formed in FP32.
 #include "dp_internal.h"
 
 namespace dp {
 
-// LDS budgets (elements): forward = one float plane; gradient = three
-// float planes (Gx, Gy, Gz).
-constexpr int kLdsFwd = 8192;
-constexpr int kLdsGrad = 3072;
-constexpr int kChunkFwd = 32;
-constexpr int kChunkGrad = 16;
+// LDS budgets: forward = one float per voxel; gradient = (Gx, Gy, Gz)
+// interleaved per voxel, so the x-neighbour pairs of all three channels are
+// reachable from one address with the 8-bit offsets of ds_read2.
+// Compiled variants (chunk length before adaptation, LDS voxels); the
+// autotuner picks one per shape class, variant 1 is the default.
+//   forward : (16, 4096) (32, 8192) (64, 12288)
+//   gradient: ( 8, 2048) (16, 3072) (32, 5120)
+constexpr int kMaxChunks = kRdThreads;  // one chunk box planned per thread
 
 struct RayState {
     float x0, y0, z0;   // padded voxel index of the iso-plane anchor
@@ -122,17 +127,24 @@ struct Corner {
     float x0, y0, z0, dx, dy, dz, f, k0;
 };
 
-// Block-wide setup shared by both kernels: union of the rays' sample
-// ranges and the geometry of the tile's four corner rays.
-struct TileShared {
-    Corner corner[4];
-    int klo[4], khi[4];
+struct Box {
+    int ox, oy, oz, bx, by, bz;
 };
 
+// Block-wide state shared by both kernels.
+struct TileShared {
+    Corner corner[4];
+    int klo[4], khi[4], vmax[4];
+    unsigned short box[kMaxChunks][6];
+};
+
+// Union of the active rays' sample ranges, the tile's four corner rays and
+// the margin that covers the spherical cap between them (voxel units).
 // `active` rays define the sample range; every in-detector corner lane
 // publishes its ray geometry (whether or not it carries samples).
 __device__ inline void tile_setup(const GeoScalars& s, const RayState& r, bool inside, bool active,
-                                  int a, int b, int a0, int b0, TileShared& sh, int& Kmin, int& Kmax)
+                                  int a, int b, int a0, int b0, TileShared& sh, int& Kmin,
+                                  int& Kmax, float& margin)
 {
     int lo = active && r.klo <= r.khi ? r.klo : INT_MAX;
     int hi = active && r.klo <= r.khi ? r.khi : INT_MIN;
@@ -159,17 +171,23 @@ __device__ inline void tile_setup(const GeoScalars& s, const RayState& r, bool i
     __syncthreads();
     Kmin = min(min(sh.klo[0], sh.klo[1]), min(sh.klo[2], sh.klo[3]));
     Kmax = max(max(sh.khi[0], sh.khi[1]), max(sh.khi[2], sh.khi[3]));
+    // Cap height: for unit directions u0, u3 of the diagonal corner rays, the
+    // tile's rays deviate from the corner hull by at most
+    // lambda (1 - cos(theta/2)) <= 0.31 lambda |u0 - u3|^2 (mm).
+    const float S = (float)s.sdd;
+    const float xa0 = (float)((a0 - s.cu) * s.du), xa1 = (float)((a1 - s.cu) * s.du);
+    const float yb0 = (float)((b0 - s.cv) * s.dv), yb1 = (float)((b1 - s.cv) * s.dv);
+    const float n0 = rsqrtf(S * S + xa0 * xa0 + yb0 * yb0), n1 = rsqrtf(S * S + xa1 * xa1 + yb1 * yb1);
+    const float e0 = S * (n0 - n1), e1 = xa0 * n0 - xa1 * n1, e2 = yb0 * n0 - yb1 * n1;
+    const float hmin = (float)fmin(s.vx, fmin(s.vy, s.vz));
+    const float lmax = (float)(fmax((double)Kmax, 0.0) * s.step + s.step);
+    margin = 0.31f * lmax * (e0 * e0 + e1 * e1 + e2 * e2) / hmin + 0.02f;
 }
-
-struct Box {
-    int ox, oy, oz, bx, by, bz;
-    __device__ int vol() const { return bx * by * bz; }
-};
 
 // Bounding box (padded voxel indices, clamped to the padded volume) of all
 // trilinear taps of the samples k in [K, Ke] of every ray of the tile.
-__device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step, int NX, int NY,
-                                int NZ)
+__device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step, float margin,
+                                int NX, int NY, int NZ)
 {
     float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
 #pragma unroll
@@ -186,13 +204,12 @@ __device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step,
             }
         }
     }
-    // one voxel of margin below; the upper trilinear tap plus one voxel above
     const float cap[3] = {(float)(NX - 1), (float)(NY - 1), (float)(NZ - 1)};
     int o[3], e[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        o[d] = (int)fminf(fmaxf(floorf(lo[d]) - 1.0f, 0.0f), cap[d]);
-        e[d] = (int)fminf(fmaxf(floorf(hi[d]) + 2.0f, 0.0f), cap[d]);
+        o[d] = (int)fminf(fmaxf(floorf(lo[d] - margin), 0.0f), cap[d]);
+        e[d] = (int)fminf(fmaxf(floorf(hi[d] + margin) + 1.0f, 0.0f), cap[d]);
     }
     Box bx;
     bx.ox = o[0]; bx.oy = o[1]; bx.oz = o[2];
@@ -200,36 +217,61 @@ __device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step,
     return bx;
 }
 
-// Choose the chunk [K, Ke]: the longest prefix (halving from Mmax) whose
-// box fits the LDS budget; fits = false if even a single sample does not.
-__device__ inline Box choose_chunk(const TileShared& sh, int K, int Kmax, int Mmax, int cap,
-                                   float step, int NX, int NY, int NZ, int& Ke, bool& fits)
+// Plan every chunk of the tile at once (thread i plans chunk i) and return
+// the chunk length M for which all boxes fit `cap` voxels, or 0 if none
+// does (the tile then reads its taps from global memory).
+__device__ inline int plan_chunks(TileShared& sh, int Kmin, int Kmax, int Mmax, int cap,
+                                  float step, float margin, int NX, int NY, int NZ)
 {
-    int M = Mmax;
-    Box b;
-    for (;;) {
-        Ke = min(K + M - 1, Kmax);
-        b = chunk_box(sh, K, Ke, step, NX, NY, NZ);
-        fits = b.vol() <= cap;
-        if (fits || M == 1) break;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int M = Mmax;;) {
+        const int nch = (Kmax - Kmin) / M + 1;
+        if (nch > kMaxChunks) return 0;
+        int vol = 0;
+        if ((int)threadIdx.x < nch) {
+            const int K = Kmin + (int)threadIdx.x * M;
+            const Box b = chunk_box(sh, K, min(K + M - 1, Kmax), step, margin, NX, NY, NZ);
+            unsigned short* q = sh.box[threadIdx.x];
+            q[0] = (unsigned short)b.ox; q[1] = (unsigned short)b.oy; q[2] = (unsigned short)b.oz;
+            q[3] = (unsigned short)b.bx; q[4] = (unsigned short)b.by; q[5] = (unsigned short)b.bz;
+            vol = b.bx * b.by * b.bz;
+        }
+        for (int off = 32; off > 0; off >>= 1) vol = max(vol, __shfl_xor(vol, off));
+        if (lane == 0) sh.vmax[wave] = vol;
+        __syncthreads();
+        const int vmax = max(max(sh.vmax[0], sh.vmax[1]), max(sh.vmax[2], sh.vmax[3]));
+        __syncthreads();
+        if (vmax <= cap) return M;
+        if (M == 1) return 0;
         M = (M + 1) >> 1;
     }
+}
+
+__device__ inline Box planned_box(const TileShared& sh, int i)
+{
+    const unsigned short* q = sh.box[i];
+    Box b;
+    b.ox = q[0]; b.oy = q[1]; b.oz = q[2]; b.bx = q[3]; b.by = q[4]; b.bz = q[5];
     return b;
 }
 
-// Cooperative copy of the box from padded global planes into LDS.  The LDS
-// layout is the box's own x-fastest order, so the flat box index e is the
-// LDS index; e -> (x, y, z) uses multiply-high reciprocals, and each thread
-// issues BATCH global loads before writing any of them to LDS.
+// Cooperative copy of the box from padded global planes into LDS, in the
+// box's own x-fastest order with C channels interleaved per voxel (LDS
+// index = C * flat box index).  e -> (x, y, z) uses multiply-high
+// reciprocals; each thread issues BATCH loads before writing any to LDS.
 template <int C, int BATCH>
-__device__ inline void load_box(const Box& b, const float* const (&src)[C], float* const (&dst)[C],
-                                int NX, int NY)
+__device__ inline void load_box(const Box& b, const float* const (&src)[C], float* dst, int NX,
+                                int NXY)
 {
-    const int vol = b.vol();
+    const int vol = b.bx * b.by * b.bz;
     // q = floor(e / d) = umulhi(e, floor(2^32 / d) + 1), exact for e * d < 2^32
     const unsigned mx = b.bx > 1 ? 0xFFFFFFFFu / (unsigned)b.bx + 1u : 0u;
     const unsigned my = b.by > 1 ? 0xFFFFFFFFu / (unsigned)b.by + 1u : 0u;
-    const size_t base = ((size_t)b.oz * NY + b.oy) * NX + b.ox;
+    // box origin pointers are uniform; element offsets fit 32 bits
+    const size_t base = ((size_t)b.oz * NXY + (size_t)b.oy * NX) + b.ox;
+    const float* sb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) sb[c] = src[c] + base;
     for (int e0 = threadIdx.x; e0 < vol; e0 += kRdThreads * BATCH) {
         float val[BATCH][C];
 #pragma unroll
@@ -237,12 +279,12 @@ __device__ inline void load_box(const Box& b, const float* const (&src)[C], floa
             const int e = e0 + i * kRdThreads;
             if (e < vol) {
                 const unsigned q = b.bx > 1 ? __umulhi((unsigned)e, mx) : (unsigned)e;
-                const int lx = e - (int)q * b.bx;
+                const unsigned lx = (unsigned)e - q * (unsigned)b.bx;
                 const unsigned lz = b.by > 1 ? __umulhi(q, my) : q;
-                const int ly = (int)q - (int)lz * b.by;
-                const size_t gi = base + ((size_t)lz * NY + ly) * NX + lx;
+                const unsigned ly = q - lz * (unsigned)b.by;
+                const unsigned off = lz * (unsigned)NXY + ly * (unsigned)NX + lx;
 #pragma unroll
-                for (int c = 0; c < C; ++c) val[i][c] = src[c][gi];
+                for (int c = 0; c < C; ++c) val[i][c] = sb[c][off];
             }
         }
 #pragma unroll
@@ -250,55 +292,71 @@ __device__ inline void load_box(const Box& b, const float* const (&src)[C], floa
             const int e = e0 + i * kRdThreads;
             if (e < vol) {
 #pragma unroll
-                for (int c = 0; c < C; ++c) dst[c][e] = val[i][c];
+                for (int c = 0; c < C; ++c) dst[C * e + c] = val[i][c];
             }
         }
     }
 }
 
-__global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
-                                                            const ViewGeo* __restrict__ views,
-                                                            const float* __restrict__ volp,
-                                                            float* __restrict__ proj)
+// One chunk of one ray: first local position and per-sample increment.
+struct ChunkRay {
+    float X, Y, Z;     // local box coordinates of sample kb
+    float sx, sy, sz;  // step * direction
+    float n;           // number of samples - 1 (negative: none)
+};
+
+__device__ inline ChunkRay chunk_ray(const RayState& r, int kb, int ke, const Box& bx, float step)
 {
-    __shared__ float lds[kLdsFwd];
-    __shared__ TileShared sh;
-    const int v = blockIdx.y;
+    ChunkRay c;
+    const float tb = fmaf((float)(kb - r.k0), step, r.f);
+    c.X = fmaf(tb, r.dx, r.x0 - (float)bx.ox);
+    c.Y = fmaf(tb, r.dy, r.y0 - (float)bx.oy);
+    c.Z = fmaf(tb, r.dz, r.z0 - (float)bx.oz);
+    c.sx = step * r.dx; c.sy = step * r.dy; c.sz = step * r.dz;
+    c.n = (float)(ke - kb);
+    return c;
+}
+
+template <int MCH, int CAP>
+__device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
+                                   const float* __restrict__ volp, float* __restrict__ proj,
+                                   int v, int tile, float* lds, TileShared& sh)
+{
     int a, b, a0, b0;
-    rd_pixel(s, blockIdx.x, a, b, a0, b0);
+    rd_pixel(s, tile, a, b, a0, b0);
     const bool active = a < s.nu && b < s.nv;
     const ViewGeo& g = views[v];
     const RayState r = ray_setup(s, g, min(a, s.nu - 1), min(b, s.nv - 1));
     int Kmin, Kmax;
-    tile_setup(s, r, active, active, a, b, a0, b0, sh, Kmin, Kmax);
+    float margin;
+    tile_setup(s, r, active, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
     const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
     const int NXY = NX * NY;
     const float step = (float)s.step;
     const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
     float acc = 0.0f;
-    for (int K = Kmin; K <= Kmax;) {
-        int Ke;
-        bool fits;
-        const Box bx = choose_chunk(sh, K, Kmax, kChunkFwd, kLdsFwd, step, NX, NY, NZ, Ke, fits);
-        const int kb = max(K, klo), ke = min(Ke, khi);
-        if (fits) {
+    const int M = Kmin <= Kmax ? plan_chunks(sh, Kmin, Kmax, MCH, CAP, step, margin, NX, NY, NZ)
+                               : 1;
+    if (M > 0) {
+        for (int K = Kmin, ci = 0; K <= Kmax; K += M, ++ci) {
+            const int Ke = min(K + M - 1, Kmax);
+            const Box bx = planned_box(sh, ci);
             __syncthreads();  // the previous chunk's readers are done
             {
                 const float* src[1] = {volp};
-                float* dst[1] = {lds};
-                load_box<1, 8>(bx, src, dst, NX, NY);
+                load_box<1, 8>(bx, src, lds, NX, NXY);
             }
             __syncthreads();
-            const float xl = r.x0 - bx.ox, yl = r.y0 - bx.oy, zl = r.z0 - bx.oz;
+            const int kb = max(K, klo), ke = min(Ke, khi);
+            const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
             const int BX = bx.bx, BXY = bx.bx * bx.by;
-            const int imax = kLdsFwd - 1 - (BXY + BX + 1);
-            for (int k = kb; k <= ke; ++k) {
-                const float t = fmaf((float)(k - r.k0), step, r.f);
-                const float X = fmaf(t, r.dx, xl), Y = fmaf(t, r.dy, yl), Z = fmaf(t, r.dz, zl);
-                // local coordinates are >= 1 by the box margin: truncation = floor
-                const int ix = (int)X, iy = (int)Y, iz = (int)Z;
-                const float wx = X - (float)ix, wy = Y - (float)iy, wz = Z - (float)iz;
-                const int idx = min(max((iz * bx.by + iy) * BX + ix, 0), imax);
+            const float fbx = (float)bx.bx, fby = (float)bx.by;
+            const int imax = CAP - 1 - (BXY + BX + 1);
+            for (float j = 0.0f; j <= c.n; j += 1.0f) {
+                const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
+                const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
+                const float wx = X - fx, wy = Y - fy, wz = Z - fz;
+                const int idx = min(max((int)fmaf(fmaf(fz, fby, fy), fbx, fx), 0), imax);
                 const float* p = lds + idx;
                 const float c00 = lerpf(p[0], p[1], wx);
                 const float c10 = lerpf(p[BX], p[BX + 1], wx);
@@ -306,25 +364,24 @@ __global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
                 const float c11 = lerpf(p[BXY + BX], p[BXY + BX + 1], wx);
                 acc += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
             }
-        } else {
-            // box too large for LDS: taps straight from the padded volume
-            const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
-            for (int k = kb; k <= ke; ++k) {
-                const float t = fmaf((float)(k - r.k0), step, r.f);
-                const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
-                const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
-                const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
-                const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-                const float wx = X - fx, wy = Y - fy, wz = Z - fz;
-                const float* p = volp + (((int)fz * NY + (int)fy) * NX + (int)fx);
-                const float c00 = lerpf(p[0], p[1], wx);
-                const float c10 = lerpf(p[NX], p[NX + 1], wx);
-                const float c01 = lerpf(p[NXY], p[NXY + 1], wx);
-                const float c11 = lerpf(p[NXY + NX], p[NXY + NX + 1], wx);
-                acc += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
-            }
         }
-        K = Ke + 1;
+    } else {
+        // chunk boxes too large for LDS: taps straight from the padded volume
+        const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
+        for (int k = klo; k <= khi; ++k) {
+            const float t = fmaf((float)(k - r.k0), step, r.f);
+            const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
+            const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
+            const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
+            const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
+            const float wx = X - fx, wy = Y - fy, wz = Z - fz;
+            const float* p = volp + (((int)fz * NY + (int)fy) * NX + (int)fx);
+            const float c00 = lerpf(p[0], p[1], wx);
+            const float c10 = lerpf(p[NX], p[NX + 1], wx);
+            const float c01 = lerpf(p[NXY], p[NXY + 1], wx);
+            const float c11 = lerpf(p[NXY + NX], p[NXY + NX + 1], wx);
+            acc += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
+        }
     }
     if (active) proj[((size_t)v * s.nv + b) * s.nu + a] = acc * step;
 }
@@ -350,9 +407,10 @@ __device__ inline void block_reduce_store(float (&v)[C], float* __restrict__ out
     }
 }
 
-// Per-sample gradient accumulation from the 8 corner gradient vectors q_xyz
-// (index units) with trilinear weights (wx, wy, wz) at base corner offset
-// P from the grid centre.
+// Per-ray gradient sums.  add() takes the 8 corner gradient vectors q (index
+// units), the trilinear weights and the base corner's index P in any frame;
+// T accumulates sum phi P_a G_c + sum phi delta_a G_c, so a frame change by
+// c (P -> P - c) is applied later as T_ac -= c_a B_c.
 struct GradAcc {
     float Bx = 0.f, By = 0.f, Bz = 0.f;
     float Txy = 0.f, Txz = 0.f, Tyx = 0.f, Tyz = 0.f, Tzx = 0.f, Tzy = 0.f;
@@ -392,26 +450,34 @@ struct GradAcc {
             Mzy = wy * lerpf(L01, L11, wx);
         }
         Bx += Gx; By += Gy; Bz += Gz;
-        // T_a,c += P_a(base) * sum phi G_c + sum phi delta_a G_c
         Txy += fmaf(Px, Gy, Myx); Txz += fmaf(Px, Gz, Mzx);
         Tyx += fmaf(Py, Gx, Mxy); Tyz += fmaf(Py, Gz, Mzy);
         Tzx += fmaf(Pz, Gx, Mxz); Tzy += fmaf(Pz, Gy, Myz);
     }
+
+    // this += o with o's base-corner frame shifted by -c.
+    __device__ inline void merge(const GradAcc& o, float cx, float cy, float cz)
+    {
+        Bx += o.Bx; By += o.By; Bz += o.Bz;
+        Txy += fmaf(-cx, o.By, o.Txy); Txz += fmaf(-cx, o.Bz, o.Txz);
+        Tyx += fmaf(-cy, o.Bx, o.Tyx); Tyz += fmaf(-cy, o.Bz, o.Tyz);
+        Tzx += fmaf(-cz, o.Bx, o.Tzx); Tzy += fmaf(-cz, o.By, o.Tzy);
+    }
 };
 
-__global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
-                                                             const ViewGeo* __restrict__ views,
-                                                             const float* __restrict__ gx,
-                                                             const float* __restrict__ gy,
-                                                             const float* __restrict__ gz,
-                                                             const float* __restrict__ grad_proj,
-                                                             float* __restrict__ partials)
+template <int MCH, int CAP>
+__device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
+                                    const float* __restrict__ vol3,
+                                    const float* __restrict__ grad_proj,
+                                    float* __restrict__ partials, int v, int tile, int tiles,
+                                    float* lds, TileShared& sh)
 {
-    __shared__ float lds[3][kLdsGrad];
-    __shared__ TileShared sh;
-    const int v = blockIdx.y;
+    const size_t plane = (size_t)(s.nx + 2 * kPadV) * (s.ny + 2 * kPadV) * (s.nz + 2 * kPadV);
+    const float* __restrict__ gx = vol3;
+    const float* __restrict__ gy = vol3 + plane;
+    const float* __restrict__ gz = vol3 + 2 * plane;
     int a, b, a0, b0;
-    rd_pixel(s, blockIdx.x, a, b, a0, b0);
+    rd_pixel(s, tile, a, b, a0, b0);
     const bool inside = a < s.nu && b < s.nv;
     const float w = inside ? grad_proj[((size_t)v * s.nv + b) * s.nu + a] : 0.0f;
     const ViewGeo& g = views[v];
@@ -419,7 +485,8 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
     // rays with dL/dl = 0 contribute nothing: they only help load the boxes
     const bool active = inside && w != 0.0f;
     int Kmin, Kmax;
-    tile_setup(s, r, inside, active, a, b, a0, b0, sh, Kmin, Kmax);
+    float margin;
+    tile_setup(s, r, inside, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
     const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
     const int NXY = NX * NY;
     const float step = (float)s.step;
@@ -428,50 +495,29 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                 ccz = 0.5f * (s.nz - 1) + kPadV;
     const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
     GradAcc G;
-    for (int K = Kmin; K <= Kmax;) {
-        int Ke;
-        bool fits;
-        const Box bx = choose_chunk(sh, K, Kmax, kChunkGrad, kLdsGrad, step, NX, NY, NZ, Ke, fits);
-        const int kb = max(K, klo), ke = min(Ke, khi);
-        if (fits) {
+    const int M = Kmin <= Kmax ? plan_chunks(sh, Kmin, Kmax, MCH, CAP, step, margin, NX, NY, NZ)
+                               : 1;
+    if (M > 0) {
+        for (int K = Kmin, ci = 0; K <= Kmax; K += M, ++ci) {
+            const int Ke = min(K + M - 1, Kmax);
+            const Box bx = planned_box(sh, ci);
             __syncthreads();
             {
                 const float* src[3] = {gx, gy, gz};
-                float* dst[3] = {lds[0], lds[1], lds[2]};
-                load_box<3, 4>(bx, src, dst, NX, NY);
+                load_box<3, 4>(bx, src, lds, NX, NXY);
             }
             __syncthreads();
-            const float xl = r.x0 - bx.ox, yl = r.y0 - bx.oy, zl = r.z0 - bx.oz;
-            const float cxl = ccx - bx.ox, cyl = ccy - bx.oy, czl = ccz - bx.oz;
-            const int BX = bx.bx, BXY = bx.bx * bx.by;
-            const int imax = kLdsGrad - 1 - (BXY + BX + 1);
-            for (int k = kb; k <= ke; ++k) {
-                const float t = fmaf((float)(k - r.k0), step, r.f);
-                const float X = fmaf(t, r.dx, xl), Y = fmaf(t, r.dy, yl), Z = fmaf(t, r.dz, zl);
-                const int ix = (int)X, iy = (int)Y, iz = (int)Z;
-                const float fx = (float)ix, fy = (float)iy, fz = (float)iz;
-                const int idx = min(max((iz * bx.by + iy) * BX + ix, 0), imax);
-                float3 q[2][2][2];
-#pragma unroll
-                for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-                    for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                        for (int dx = 0; dx < 2; ++dx) {
-                            const int o = idx + dz * BXY + dy * BX + dx;
-                            q[dz][dy][dx] = make_float3(lds[0][o], lds[1][o], lds[2][o]);
-                        }
-                G.add(q, X - fx, Y - fy, Z - fz, fx - cxl, fy - cyl, fz - czl);
-            }
-        } else {
-            const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
-            for (int k = kb; k <= ke; ++k) {
-                const float t = fmaf((float)(k - r.k0), step, r.f);
-                const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
-                const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
-                const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
+            const int kb = max(K, klo), ke = min(Ke, khi);
+            const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
+            const int BX3 = 3 * bx.bx, BXY3 = 3 * bx.bx * bx.by;
+            const float fbx = (float)bx.bx, fby = (float)bx.by;
+            const int imax = 3 * CAP - 1 - (BXY3 + BX3 + 5);
+            GradAcc Gc;  // base-corner frame: local box indices
+            for (float j = 0.0f; j <= c.n; j += 1.0f) {
+                const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
                 const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-                const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
+                const int idx = min(max(3 * (int)fmaf(fmaf(fz, fby, fy), fbx, fx), 0), imax);
+                const float* p = lds + idx;
                 float3 q[2][2][2];
 #pragma unroll
                 for (int dz = 0; dz < 2; ++dz)
@@ -479,13 +525,34 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                     for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                         for (int dx = 0; dx < 2; ++dx) {
-                            const size_t o = (size_t)idx + dz * NXY + dy * NX + dx;
-                            q[dz][dy][dx] = make_float3(gx[o], gy[o], gz[o]);
+                            const float* o = p + dz * BXY3 + dy * BX3 + 3 * dx;
+                            q[dz][dy][dx] = make_float3(o[0], o[1], o[2]);
                         }
-                G.add(q, X - fx, Y - fy, Z - fz, fx - ccx, fy - ccy, fz - ccz);
+                Gc.add(q, X - fx, Y - fy, Z - fz, fx, fy, fz);
             }
+            G.merge(Gc, ccx - bx.ox, ccy - bx.oy, ccz - bx.oz);
         }
-        K = Ke + 1;
+    } else {
+        for (int k = klo; k <= khi; ++k) {
+            const float t = fmaf((float)(k - r.k0), step, r.f);
+            const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
+            const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
+            const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
+            const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
+            const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
+            const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
+            float3 q[2][2][2];
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const size_t o = (size_t)idx + dz * NXY + dy * NX + dx;
+                        q[dz][dy][dx] = make_float3(gx[o], gy[o], gz[o]);
+                    }
+            G.add(q, X - fx, Y - fy, Z - fz, fx - ccx, fy - ccy, fz - ccz);
+        }
     }
     float acc[kRdChannels] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (active) {
@@ -494,27 +561,114 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
         acc[3] = G.Txy * ws; acc[4] = G.Txz * ws; acc[5] = G.Tyx * ws;
         acc[6] = G.Tyz * ws; acc[7] = G.Tzx * ws; acc[8] = G.Tzy * ws;
     }
-    const int tiles = gridDim.x;
-    block_reduce_store<kRdChannels>(acc, partials + ((size_t)v * tiles + blockIdx.x) * kRdChannels);
+    block_reduce_store<kRdChannels>(acc, partials + ((size_t)v * tiles + tile) * kRdChannels);
+}
+
+template <int MCH, int CAP>
+__global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
+                                                            const ViewGeo* __restrict__ views,
+                                                            const float* __restrict__ volp,
+                                                            float* __restrict__ proj)
+{
+    __shared__ float lds[CAP];
+    __shared__ TileShared sh;
+    rd_fwd_tile<MCH, CAP>(s, views, volp, proj, blockIdx.y, blockIdx.x, lds, sh);
+}
+
+template <int MCH, int CAP>
+__global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
+                                                             const ViewGeo* __restrict__ views,
+                                                             const float* __restrict__ vol3,
+                                                             const float* __restrict__ grad_proj,
+                                                             float* __restrict__ partials)
+{
+    __shared__ float lds[3 * CAP];
+    __shared__ TileShared sh;
+    rd_grad_tile<MCH, CAP>(s, views, vol3, grad_proj, partials, blockIdx.y, blockIdx.x, gridDim.x,
+                           lds, sh);
+}
+
+// Uneven batch: one launch covers every (problem, view, tile) of up to
+// kRdMaxBatch problems; the descriptors travel as kernel arguments, so the
+// launch needs no device-side table and can be captured in a graph.  Block
+// b belongs to the last problem whose first block is <= b.
+__device__ inline int batch_problem(const RdBatch& bt)
+{
+    int p = 0;
+    for (int q = 1; q < bt.n; ++q)
+        if ((int)blockIdx.x >= bt.it[q].first) p = q;
+    return p;
+}
+
+template <int MCH, int CAP>
+__global__ __launch_bounds__(kRdThreads) void rd_fwd_batch_kernel(RdBatch bt)
+{
+    __shared__ float lds[CAP];
+    __shared__ TileShared sh;
+    const int p = batch_problem(bt);
+    const RdBatchItem& it = bt.it[p];
+    const int local = (int)blockIdx.x - it.first;
+    rd_fwd_tile<MCH, CAP>(it.s, it.views, it.vol, it.out, local / it.tiles, local % it.tiles, lds,
+                          sh);
+}
+
+template <int MCH, int CAP>
+__global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
+{
+    __shared__ float lds[3 * CAP];
+    __shared__ TileShared sh;
+    const int p = batch_problem(bt);
+    const RdBatchItem& it = bt.it[p];
+    const int local = (int)blockIdx.x - it.first;
+    rd_grad_tile<MCH, CAP>(it.s, it.views, it.vol, it.gin, it.out, local / it.tiles,
+                           local % it.tiles, it.tiles, lds, sh);
 }
 
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
-                   float* proj, hipStream_t st)
+                   float* proj, int variant, hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     prof_begin(DP_K_RD_FWD, st);
-    rd_fwd_kernel<<<grid, kRdThreads, 0, st>>>(s, views, volp, proj);
+    switch (variant) {
+    case 0: rd_fwd_kernel<16, 4096><<<grid, kRdThreads, 0, st>>>(s, views, volp, proj); break;
+    case 2: rd_fwd_kernel<64, 12288><<<grid, kRdThreads, 0, st>>>(s, views, volp, proj); break;
+    default: rd_fwd_kernel<32, 8192><<<grid, kRdThreads, 0, st>>>(s, views, volp, proj); break;
+    }
     prof_end(DP_K_RD_FWD, st);
 }
 
 void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
-                    const float* grad_proj, float* partials, hipStream_t st)
+                    const float* grad_proj, float* partials, int variant, hipStream_t st)
 {
-    const size_t plane = (size_t)(s.nx + 2 * kPadV) * (s.ny + 2 * kPadV) * (s.nz + 2 * kPadV);
     dim3 grid(rd_tiles(s), V);
     prof_begin(DP_K_RD_GRAD, st);
-    rd_grad_kernel<<<grid, kRdThreads, 0, st>>>(s, views, vol3, vol3 + plane, vol3 + 2 * plane,
-                                                 grad_proj, partials);
+    switch (variant) {
+    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, vol3, grad_proj, partials); break;
+    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, vol3, grad_proj, partials); break;
+    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, vol3, grad_proj, partials); break;
+    }
+    prof_end(DP_K_RD_GRAD, st);
+}
+
+void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)
+{
+    prof_begin(DP_K_RD_FWD, st);
+    switch (variant) {
+    case 0: rd_fwd_batch_kernel<16, 4096><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    case 2: rd_fwd_batch_kernel<64, 12288><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    default: rd_fwd_batch_kernel<32, 8192><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    }
+    prof_end(DP_K_RD_FWD, st);
+}
+
+void launch_rd_grad_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)
+{
+    prof_begin(DP_K_RD_GRAD, st);
+    switch (variant) {
+    case 0: rd_grad_batch_kernel<8, 2048><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    case 2: rd_grad_batch_kernel<32, 5120><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    default: rd_grad_batch_kernel<16, 3072><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    }
     prof_end(DP_K_RD_GRAD, st);
 }
 

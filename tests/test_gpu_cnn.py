@@ -1,0 +1,110 @@
+"""BF16 MFMA CNN primitives and the proposal network against the FP64 oracle.
+
+Operands are BF16 on both sides (the oracle rounds the same values with
+round-to-nearest-even), so the GEMM differs only by FP32 accumulation order:
+|C_gpu - C_ref| <= 1e-5 * (|A| |B|)_ij elementwise.  For whole-network
+outputs and gradients, intermediate BF16 roundings may fall on the other
+side of a rounding boundary; the normwise bar is 2e-2 (about 8 BF16 ulps).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn as ocnn
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def bf(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV).to(torch.bfloat16)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (70, 45, 33), (128, 64, 96), (5, 300, 129)])
+def test_gemm_all_layouts(dp, ta, tb, M, N, K):
+    from paper_2508_13304_amd import proposal as pr
+    rng = np.random.default_rng(M * 1000 + N * 10 + K)
+    A = ocnn.bf16(rng.standard_normal((K, M) if ta else (M, K)))
+    B = ocnn.bf16(rng.standard_normal((N, K) if tb else (K, N)))
+    C = pr.gemm(bf(A), bf(B), ta=ta, tb=tb).cpu().numpy()
+    Aop, Bop = (A.T if ta else A), (B.T if tb else B)
+    ref = Aop @ Bop
+    bound = np.abs(Aop) @ np.abs(Bop)
+    assert np.all(np.abs(C - ref) <= 1e-5 * bound + 1e-30)
+
+
+def test_gemm_split_k_and_accumulate(dp):
+    from paper_2508_13304_amd import proposal as pr
+    rng = np.random.default_rng(7)
+    M, N, K = 18, 32, 70000  # few output tiles, long reduction: split over K
+    A = ocnn.bf16(rng.standard_normal((K, M)))
+    B = ocnn.bf16(rng.standard_normal((K, N)))
+    C = pr.gemm(bf(A), bf(B), ta=True).cpu().numpy()
+    ref = A.T @ B
+    bound = np.abs(A.T) @ np.abs(B)
+    assert np.all(np.abs(C - ref) <= 1e-5 * bound)
+    C0 = torch.full((M, N), 2.0, device=DEV)
+    pr.gemm(bf(A), bf(B), ta=True, out=C0, accumulate=True)
+    assert np.all(np.abs(C0.cpu().numpy() - (ref + 2.0)) <= 1e-5 * bound + 1e-6)
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_conv_layer_forward_backward(dp, stride):
+    from paper_2508_13304_amd import proposal as pr
+    rng = np.random.default_rng(11 + stride)
+    N, H, W, Ci, Co = 2, 13, 10, 5, 7
+    x = ocnn.bf16(rng.standard_normal((N, H, W, Ci)))
+    Wt = ocnn.bf16(rng.standard_normal((Co, 3, 3, Ci)))
+    b = rng.standard_normal(Co).astype(np.float32).astype(np.float64)
+    col, Ho, Wo = pr.im2col(bf(x), stride)
+    z = pr.gemm(col, bf(Wt.reshape(Co, -1)), tb=True).cpu().numpy().reshape(N, Ho, Wo, Co) + b
+    zref = ocnn.conv3x3_forward(x, Wt, b, stride)
+    assert np.abs(z - zref).max() <= 1e-5 * np.abs(zref).max()
+    dz = ocnn.bf16(rng.standard_normal(zref.shape))
+    dzt = bf(dz.reshape(-1, Co))
+    dW = pr.gemm(dzt, col, ta=True).cpu().numpy().reshape(Co, 3, 3, Ci)
+    dcol = pr.gemm(dzt, bf(Wt.reshape(Co, -1)))
+    dx = pr.col2im(dcol, (N, H, W, Ci), stride).cpu().numpy()
+    db = pr.colsum(dzt).cpu().numpy()
+    dx_r, dW_r, db_r = ocnn.conv3x3_backward(x, Wt, dz, stride)
+    for got, ref in ((dx, dx_r), (dW, dW_r), (db, db_r)):
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_network_forward_backward_against_oracle(dp):
+    from paper_2508_13304_amd import proposal as pr
+    net = pr.ProposalNet(size=64, channels=(8, 16, 16, 32), seed=3)
+    rng = np.random.default_rng(5)
+    x = ocnn.bf16(rng.uniform(0, 1, (3, 64, 64, 2)))
+    out, cache = net.forward(bf(x), keep=True)
+    convs = [(W.cpu().numpy().astype(np.float64).reshape(W.shape[0], 3, 3, -1), b.cpu().numpy(), s)
+             for W, b, s in net.convs]
+    params = (convs, (net.Wfc.cpu().numpy().astype(np.float64), net.bfc.cpu().numpy()))
+    ref, acts = ocnn.network_forward(x, params)
+    got = out.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 2e-2 * np.linalg.norm(ref)
+    dout = rng.standard_normal((3, 6))
+    grads, (dWfc, dbfc) = net.backward(cache, torch.tensor(dout, dtype=torch.float32, device=DEV))
+    rgrads, (rWfc, rbfc) = ocnn.network_backward(params, acts, dout)
+    assert np.linalg.norm(dWfc.cpu().numpy() - rWfc) <= 2e-2 * np.linalg.norm(rWfc)
+    for (dW, db), (rW, rb) in zip(grads, rgrads):
+        rW = rW.reshape(rW.shape[0], -1)
+        assert np.linalg.norm(dW.cpu().numpy() - rW) <= 2e-2 * np.linalg.norm(rW)
+        assert np.linalg.norm(db.cpu().numpy() - rb) <= 2e-2 * np.linalg.norm(rb) + 1e-12
+
+
+def test_training_reduces_loss_on_a_fixed_batch(dp):
+    from paper_2508_13304_amd import proposal as pr
+    torch.manual_seed(0)
+    net = pr.ProposalNet(size=32, channels=(16, 32, 32), seed=1)
+    x = torch.rand((16, 32, 32, 2), device=DEV).to(torch.bfloat16)
+    y = torch.randn((16, 6), device=DEV) * 0.5
+    losses = []
+    for _ in range(60):
+        out, cache = net.forward(x, keep=True)
+        d = out - y
+        losses.append(float((d * d).mean()))
+        grads, head = net.backward(cache, 2.0 * d / d.numel())
+        net.adam_step(grads, head, lr=3e-3)
+    assert losses[-1] < 0.2 * losses[0], losses[::10]
