@@ -254,3 +254,71 @@ def config3_motion(n_views: int = 360):
     angles = circular_angles(n_views)
     motion = sinusoidal_motion(n_views, 3.0, 2.0, rng)
     return dict(angles=angles, poses=motion, rng=rng)
+
+
+# ---------------------------------------------------------------------------
+# Bulk phantoms on the GPU (training-set generation)
+# ---------------------------------------------------------------------------
+
+def draw_ellipsoids(n: int, h: float, n_ell: int, rng: np.random.Generator,
+                    mu_range=(0.01, 0.05)):
+    """The ellipsoid parameters of `ellipsoid_phantom` (same distribution and
+    rejection rule): centres [E][3], semi-axes [E][3], rotations [E][3][3],
+    attenuations [E]."""
+    L = n * h
+    limit = 0.5 * L - 4.0 * h
+    cs, ss, rs, vs = [], [], [], []
+    while len(cs) < n_ell:
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        centre = d * 0.35 * L * rng.uniform() ** (1.0 / 3.0)
+        semi = rng.uniform(0.05, 0.25, size=3) * L
+        rot = _random_rotation(rng)
+        value = rng.uniform(*mu_range)
+        if np.linalg.norm(centre) + semi.max() > limit:
+            continue
+        cs.append(centre), ss.append(semi), rs.append(rot), vs.append(value)
+    return np.array(cs), np.array(ss), np.array(rs), np.array(vs)
+
+
+def ellipsoid_phantom_torch(n: int, h: float, n_ell: int, rng: np.random.Generator,
+                            device, shell: bool = False, sigma: float = 1.0,
+                            mu_range=(0.01, 0.05)):
+    """`ellipsoid_phantom`'s recipe rasterised with torch on `device` (FP32
+    voxel-centre tests, separable zero-padded Gaussian), for generating many
+    phantoms quickly.  Same parameter distribution; voxels on an ellipsoid's
+    boundary may differ from the FP64 numpy rasteriser."""
+    import torch
+    cs, ss, rs, vs = draw_ellipsoids(n, h, n_ell, rng, mu_range)
+    ax = (torch.arange(n, device=device, dtype=torch.float32) - (n - 1) / 2.0) * h
+    Z, Y, X = torch.meshgrid(ax, ax, ax, indexing="ij")
+    P = torch.stack([X, Y, Z], dim=-1)
+    vol = torch.zeros((n, n, n), device=device, dtype=torch.float32)
+    for c, s, r, v in zip(cs, ss, rs, vs):
+        Q = (P - torch.tensor(c, device=device, dtype=torch.float32)) @ \
+            torch.tensor(r, device=device, dtype=torch.float32)
+        q = ((Q / torch.tensor(s, device=device, dtype=torch.float32)) ** 2).sum(-1)
+        vol += float(v) * (q <= 1.0)
+    if shell:
+        outer = torch.tensor([0.45, 0.40, 0.42], device=device) * n * h
+        qo = ((P / outer) ** 2).sum(-1)
+        qi = ((P / (outer - 4.0)) ** 2).sum(-1)
+        vol = torch.where((qo <= 1.0) & (qi > 1.0), torch.full_like(vol, 0.08), vol)
+    if sigma > 0:
+        rad = int(math.floor(4.0 * sigma + 0.5))
+        k = torch.exp(-0.5 * (torch.arange(-rad, rad + 1, dtype=torch.float64) / sigma) ** 2)
+        k = (k / k.sum()).tolist()
+        for dim in range(3):
+            pad = [0, 0, 0, 0, 0, 0]
+            pad[2 * (2 - dim)] = pad[2 * (2 - dim) + 1] = rad
+            vp = torch.nn.functional.pad(vol, pad)
+            out = torch.zeros_like(vol)
+            for j, w in enumerate(k):
+                out += w * vp.narrow(dim, j, n)
+            vol = out
+    return vol.contiguous()
+
+
+def geom_c5() -> Geom:
+    """192^3 at 1 mm; one 256x256 view at 1.2 mm; SAD/SDD 1000/1500; 0.5 mm steps."""
+    return Geom(192, 192, 192, 1.0, 1.0, 1.0, 256, 256, 1.2, 1.2)

@@ -40,3 +40,11 @@ def test_motion_amplitude():
     m = synth.sinusoidal_motion(360, 3.0, 2.0, synth.rng_for(3))
     assert np.abs(m[:, :3]).max() <= 3.0 + 1e-12
     assert np.abs(m[:, 3:]).max() <= np.deg2rad(2.0) + 1e-12
+
+
+def test_torch_phantom_matches_numpy_recipe():
+    """The bulk (torch) phantom generator draws the same ellipsoids as the
+    numpy one and agrees with it to FP32 rounding."""
+    a = synth.ellipsoid_phantom_torch(40, 2.0, 8, synth.rng_for(9, 3), "cpu", shell=True)
+    b = synth.ellipsoid_phantom(40, 2.0, 8, synth.rng_for(9, 3), shell=True)
+    assert np.abs(a.numpy() - b).max() < 1e-6
