@@ -104,3 +104,39 @@ def test_sharpness_gradient_matches_finite_differences():
         assert fd == pytest.approx(g[idx], rel=1e-7, abs=1e-9)
     # invariant under a constant offset, so the gradient sums to zero
     assert abs(g.sum()) < 1e-9
+
+
+def test_gradient_entropy_of_a_ramp_is_log_of_its_support():
+    """A linear ramp along x has equal gradient magnitude on the (nx-1) ny nz
+    voxels with a +x neighbour and (up to sqrt(eps)) zero elsewhere: its
+    gradient entropy is that of a uniform distribution, log((nx-1) ny nz)."""
+    nz, ny, nx = 4, 5, 9
+    vol = np.broadcast_to(np.arange(nx) * 0.01, (nz, ny, nx))
+    assert fdk.gradient_entropy(vol, eps=1e-20) == pytest.approx(math.log((nx - 1) * ny * nz), abs=1e-7)
+
+
+def test_gradient_entropy_invariances_and_sharpening():
+    """GE does not change when the volume is scaled or offset (eps -> 0), and
+    blurring an edge raises it."""
+    rng = np.random.default_rng(3)
+    vol = rng.random((6, 7, 8))
+    ge = fdk.gradient_entropy(vol, eps=1e-24)
+    assert fdk.gradient_entropy(3.0 * vol + 5.0, eps=1e-24) == pytest.approx(ge, rel=1e-10)
+    edge = np.zeros((8, 8, 16))
+    edge[:, :, 8:] = 1.0
+    blurred = edge.copy()
+    blurred[:, :, 7] = 0.25
+    blurred[:, :, 8] = 0.75
+    assert fdk.gradient_entropy(blurred) > fdk.gradient_entropy(edge) + 0.5
+
+
+def test_gradient_entropy_gradient_matches_finite_differences():
+    rng = np.random.default_rng(5)
+    vol = rng.random((4, 5, 6))
+    g = fdk.gradient_entropy_grad(vol)
+    h = 1e-6
+    for idx in [(0, 0, 0), (3, 4, 5), (1, 2, 3), (2, 0, 5), (0, 4, 2), (3, 0, 0)]:
+        e = np.zeros_like(vol)
+        e[idx] = h
+        fd = (fdk.gradient_entropy(vol + e) - fdk.gradient_entropy(vol - e)) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-10)
