@@ -128,7 +128,7 @@ def _traffic(kernel_key, src_hash):
 
 def run_forward(args, dp, torch):
     dev = torch.device("cuda:0")
-    log("[bench] generating config-2 inputs (256^3 phantom, 64 poses)")
+    log("[bench] generating registration-scale inputs (256^3 phantom, 64 poses)")
     c = synth.config2_inputs()
     g, V = c["geom"], len(c["angles"])
     T = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)  # noqa: E731
@@ -195,7 +195,7 @@ def run_backproject(args, dp, torch):
     m = synth.config3_motion()
     V = len(m["angles"])
     rng = np.random.default_rng(3)
-    log("[bench] generating config-3 inputs (360 views 512x384, 512^3 recon)")
+    log("[bench] generating motion-compensated reconstruction inputs (360 views 512x384, 512^3 recon)")
     proj_np = synth.smooth_images(V, g.nv, g.nu, rng, n_blobs=4, signed=True)
     T = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)  # noqa: E731
     angles, poses = T(m["angles"], torch.float64), T(m["poses"], torch.float64)
@@ -237,6 +237,181 @@ def run_backproject(args, dp, torch):
             "kernels_ms": per_kernel}
 
 
+def run_registration(args, dp, torch, fw):
+    """Registrations/s at 0.1 mm / 0.1 deg on the registration-scale workload:
+    64 single-view targets rendered at the 64 candidate poses, each registered
+    from the identity in one batched launch pair per iteration; BFGS with the
+    default kernel variants, BFGS with the autotuned variants, and the Adam
+    driver at the same batch."""
+    from paper_2508_13304_amd import registration as reg
+    dev = torch.device("cuda:0")
+    c = fw["inputs"]
+    g = c["geom"]
+    T = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)  # noqa: E731
+    vol = T(c["vol"], torch.float32)
+    truth = T(c["poses"], torch.float64)
+    angles = T(c["angles"], torch.float64)
+    B = truth.shape[0]
+    targets = dp.project_fwd(g, angles, truth, vol)
+    init = torch.zeros_like(truth)
+    out = {"workload": f"{B} single-view registrations, 256^3 phantom at 0.8 mm, 512x512 at 0.6 mm, "
+                       "truth offsets +-10 mm/+-10 deg, start at identity, SSD loss"}
+
+    def record(name, res):
+        ok = reg.success(res.poses, truth)
+        et, er = reg.pose_errors(res.poses, truth)
+        out[name] = {"registrations_per_s": round(B / res.seconds, 3),
+                     "successful_per_s": round(int(ok.sum()) / res.seconds, 3),
+                     "success_rate": int(ok.sum()) / B, "seconds": round(res.seconds, 3),
+                     "launch_pairs": res.launches,
+                     "mean_iterations": float(res.iterations.double().mean()),
+                     "median_err_mm": float(et.median()), "median_err_deg": float(er.median())}
+        log(f"[bench] registration {name}: {out[name]}")
+
+    reg.register_bfgs(g, vol, angles[:4], targets[:4], init[:4], iters=3)  # warm-up
+    record("bfgs_default_variants", reg.register_bfgs(g, vol, angles, targets, init))
+    out["autotuned_variants"] = {str(k): v for k, v in
+                                 reg.autotune_registration(g, vol, angles, truth, targets).items()}
+    record("bfgs_autotuned", reg.register_bfgs(g, vol, angles, targets, init))
+    record("adam", reg.register(g, vol, angles, targets, init, iters=300, lr_t=3.0, lr_r_deg=2.0,
+                                decay=0.99))
+    return out
+
+
+def run_calibration_batch(args, dp, torch):
+    """Uneven batched geometry calibration: 16 independent problems (cubic
+    phantoms of 128^3-384^3 voxels spanning ~200 mm, 1-8 views each on
+    256^2-768^2 detectors, pose perturbations +-5 mm/+-3 deg), each running
+    forward + SSD pose-gradient iterations.  Three ways to run one iteration
+    of all 16: per-problem sequential launches, the batched launches
+    (variant chosen by timing each compiled variant on this batch), and the
+    batched iteration captured once in a HIP graph and replayed."""
+    dev = torch.device("cuda:0")
+    rng = synth.rng_for(3, 9)
+    probs = []
+    n_samples = 0
+    for i in range(16):
+        n = int(rng.choice([128, 192, 256, 320, 384]))
+        h = 200.0 / n
+        V = int(rng.integers(1, 9))
+        nu = int(rng.choice([256, 384, 512, 640, 768]))
+        du = 1.5 * 240.0 / nu
+        g = synth.Geom(n, n, n, h, h, h, nu, nu, du, du)
+        vol = synth.ellipsoid_phantom_torch(n, h, 20, rng, dev)
+        angles = torch.tensor(rng.uniform(0, 2 * math.pi, V), dtype=torch.float64, device=dev)
+        truth = torch.tensor(synth.random_poses(V, 5.0, 3.0, rng), dtype=torch.float64, device=dev)
+        y = dp.project_fwd(g, angles, truth, vol)
+        poses = torch.zeros_like(truth)
+        n_samples += count_ray_samples(g, angles.cpu().numpy(), poses.cpu().numpy())
+        probs.append(dict(geom=g, angles=angles, poses=poses, vol=vol, target=y,
+                          proj=torch.empty_like(y), grad_proj=torch.empty_like(y),
+                          grad_pose=torch.empty((V, 6), dtype=torch.float64, device=dev)))
+    total_views = sum(p["angles"].numel() for p in probs)
+    log(f"[bench] calibration batch: 16 problems, {total_views} views, {n_samples:.3e} samples/iteration")
+    lr = torch.tensor([0.05] * 3 + [math.radians(0.05)] * 3, dtype=torch.float64, device=dev)
+    ws_f = torch.empty(dp.batch_workspace_bytes(probs, dp.OP_FWD), dtype=torch.uint8, device=dev)
+    ws_g = torch.empty(dp.batch_workspace_bytes(probs, dp.OP_FWD_GRAD), dtype=torch.uint8, device=dev)
+    ws1 = torch.empty(max(max(dp.workspace_bytes(p["geom"], p["angles"].numel(), op) for p in probs)
+                          for op in (dp.OP_FWD, dp.OP_FWD_GRAD)), dtype=torch.uint8, device=dev)
+    init = [p["poses"].clone() for p in probs]
+
+    def residuals():
+        for p in probs:
+            torch.sub(p["proj"], p["target"], out=p["grad_proj"])
+            p["grad_proj"].mul_(2.0)
+
+    def update():
+        for p in probs:
+            p["poses"].sub_(lr * torch.sign(p["grad_pose"]))
+
+    def seq_iter(stream):
+        for p in probs:
+            dp.project_fwd(p["geom"], p["angles"], p["poses"], p["vol"], out=p["proj"], ws=ws1,
+                           stream=stream)
+        residuals()
+        for p in probs:
+            dp.project_fwd_grad_pose(p["geom"], p["angles"], p["poses"], p["vol"], p["grad_proj"],
+                                     out=p["grad_pose"], ws=ws1, stream=stream)
+        update()
+
+    def batch_iter(stream, vf=-1, vg=-1):
+        dp.project_fwd_batch(probs, ws=ws_f, variant=vf, stream=stream)
+        residuals()
+        dp.project_fwd_grad_pose_batch(probs, ws=ws_g, variant=vg, stream=stream)
+        update()
+
+    def reset():
+        for p, p0 in zip(probs, init):
+            p["poses"].copy_(p0)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    reps = max(3, min(args.steps, 10))
+    stream = torch.cuda.current_stream()
+    seq_iter(stream)
+    reset()
+    t_seq = timed(lambda: seq_iter(stream), reps)
+    reset()
+    # batch autotuning: time each compiled variant of both batched kernels
+    ms = {}
+    for op, fn in ((dp.OP_FWD, dp.project_fwd_batch), (dp.OP_FWD_GRAD, dp.project_fwd_grad_pose_batch)):
+        wsx = ws_f if op == dp.OP_FWD else ws_g
+        for var in range(dp.N_VARIANTS):
+            fn(probs, ws=wsx, variant=var, stream=stream)
+            ms[(op, var)] = timed(lambda: fn(probs, ws=wsx, variant=var, stream=stream), 3)
+    vf = min(range(dp.N_VARIANTS), key=lambda v: ms[(dp.OP_FWD, v)])
+    vg = min(range(dp.N_VARIANTS), key=lambda v: ms[(dp.OP_FWD_GRAD, v)])
+    reset()
+    t_batch = timed(lambda: batch_iter(stream, vf, vg), reps)
+    # graph: capture one batched iteration on a side stream, replay
+    reset()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s2):
+        batch_iter(s2, vf, vg)
+    torch.cuda.current_stream().wait_stream(s2)
+    torch.cuda.synchronize()
+    reset()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch_iter(torch.cuda.current_stream(), vf, vg)
+    reset()
+    t_graph = timed(graph.replay, reps)
+    res = {"workload": "16 problems, 128^3-384^3 phantoms (~200 mm), 1-8 views each on 256^2-768^2 "
+                       "detectors, +-5 mm/+-3 deg perturbations; one iteration = forward + SSD "
+                       "residual + pose gradient + pose step for all 16",
+           "views": total_views, "samples_per_iteration": n_samples,
+           "sequential_ms": round(t_seq * 1e3, 3), "batched_ms": round(t_batch * 1e3, 3),
+           "graph_ms": round(t_graph * 1e3, 3),
+           "graph_samples_per_s": n_samples / t_graph,
+           "sequential_samples_per_s": n_samples / t_seq,
+           "batch_variants": {"fwd": vf, "grad": vg,
+                              "ms": {f"{'fwd' if k[0] == dp.OP_FWD else 'grad'}{k[1]}": round(v * 1e3, 3)
+                                     for k, v in ms.items()}}}
+    log(f"[bench] calibration batch: {res}")
+    return res
+
+
+def run_learned(args, dp, torch):
+    """Learned proposal + refinement against the plain registration from the
+    identity on unseen 192^3 phantoms (offsets +-30 mm / +-20 deg)."""
+    from paper_2508_13304_amd import proposal as pr
+    if not os.path.exists(pr.WEIGHTS):
+        log("[bench] no trained proposal weights; learned leg skipped")
+        return None
+    net = pr.ProposalNet.load(pr.WEIGHTS)
+    res = pr.evaluate(net, synth.geom_c5(), n_phantoms=4, per_phantom=16, log=log)
+    res["workload"] = ("4 unseen 192^3 phantoms at 1 mm x 16 offsets (+-30 mm/+-20 deg), one 256x256 "
+                       "view at 1.2 mm, SSD loss; plain = BFGS from identity")
+    return res
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
@@ -267,6 +442,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bp", action="store_true", help="skip the back-projector leg")
     ap.add_argument("--no-fwd", action="store_true", help="skip the forward leg (profiling runs)")
+    ap.add_argument("--no-reg", action="store_true", help="skip the registration legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch calibration leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -291,6 +468,9 @@ def main():
         return
     fw = run_forward(args, dp, torch)
     bp = None if args.no_bp else run_backproject(args, dp, torch)
+    regr = None if args.no_reg else run_registration(args, dp, torch, fw)
+    learned = None if args.no_reg else run_learned(args, dp, torch)
+    calib = None if args.no_batch else run_calibration_batch(args, dp, torch)
     cpu = None if args.no_cpu else run_cpu_baseline(fw)
     value = fw["n_samples"] / (fw["ms_step"] * 1e-3)
     rec = {
@@ -306,7 +486,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "config 2: 256^3 ellipsoid+shell phantom at 0.8 mm, 64 candidate poses "
+        "config": {"workload": "registration scale: 256^3 ellipsoid+shell phantom at 0.8 mm, 64 candidate poses "
                                "(+-10 mm/+-10 deg) x one 512x512 view at 0.6 mm, SAD/SDD 1000/1500 mm, "
                                "0.5 mm trilinear march; forward + SSD loss gradient + 64x6 pose gradient",
                    "samples_per_step": fw["n_samples"], "views": fw["V"]},
@@ -314,6 +494,9 @@ def main():
         "cpu_baseline": cpu,
         "kernels_ms": fw["per_kernel"],
         "backprojector": bp,
+        "registration": regr,
+        "learned_proposal": learned,
+        "calibration_batch": calib,
     }
     print(json.dumps(rec), flush=True)
 

@@ -189,6 +189,47 @@ int dp_act_bwd_bf16(int64_t total, const float* dy, const void* y, int32_t relu,
 /* db[c] = sum over the M rows of dz [M][C] (BF16), FP32 out. */
 int dp_colsum_bf16(int32_t M, int32_t C, const void* dz, float* db, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Motion-compensated FDK reconstruction (Sec. III-B, motion-compensated
+ * analytical reconstruction: FDK-style back-projection of ramp-filtered
+ * projections, motion estimated by maximising image sharpness).
+ *
+ * dp_fdk_filter: out[V][nv][nu] = FDK pre-filtered proj[V][nv][nu] (both
+ * FP32 device arrays; out == proj is allowed).  Detector coordinates are
+ * referred to the isocentre (pitch tau = du * sad / sdd, centre as in the
+ * projector), multiplied by the cosine weight sad / sqrt(sad^2 + u'^2 + v'^2)
+ * and convolved along u with the band-limited ramp kernel (h[0] = 1/(4 tau^2),
+ * h[k] = -1/(pi^2 k^2 tau^2) for odd k, 0 otherwise; rows zero outside the
+ * detector), times scale * tau.  With scale = pi / V for V views over a full
+ * circle, dp_backproject(..., DP_W_FDK) of the result is the FDK
+ * reconstruction.  Only the detector fields of `g` are used (the volume
+ * fields must still be valid).  Errors: DP_ERR_ARG for bad arguments,
+ * DP_ERR_UNSUPPORTED for rows longer than 4000 pixels.
+ *
+ * dp_sharpness: *loss (one FP64 on the device) = S(vol) = -(sum of the
+ * squared forward differences of vol [nz][ny][nx] along x, y and z, over
+ * pairs inside the grid); if grad is not NULL, grad [nz][ny][nx] FP32 =
+ * dS/dvol.  ws: device workspace of dp_sharpness_workspace_bytes(nx, ny,
+ * nz) bytes, 256-byte aligned.  The result is bitwise reproducible.
+ * ------------------------------------------------------------------------- */
+int dp_fdk_filter(const dp_geom* g, int32_t n_views, const float* proj, float* out, double scale,
+                  void* stream);
+size_t dp_sharpness_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
+int dp_sharpness(int32_t nx, int32_t ny, int32_t nz, const float* vol, double* loss, float* grad,
+                 void* ws, size_t ws_bytes, void* stream);
+/* dp_gradient_entropy: the sharpness criterion of the paper's
+ * motion-compensated FBP experiment (Sec. III-B).  With the forward
+ * differences above (zero where the +axis neighbour is outside the grid),
+ * g_j = sqrt(dx_j^2 + dy_j^2 + dz_j^2 + eps), p_j = g_j / sum g and
+ * *loss (device FP64) = GE = -sum p_j log p_j (lower is sharper); grad
+ * (optional, FP32 like vol) = dGE/dvol.  eps > 0 keeps g differentiable at
+ * zero (1e-12 for attenuation volumes in mm^-1).  ws: device workspace of
+ * dp_gradient_entropy_workspace_bytes(nx, ny, nz) bytes, 256-byte aligned.
+ * Bitwise reproducible. */
+size_t dp_gradient_entropy_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
+int dp_gradient_entropy(int32_t nx, int32_t ny, int32_t nz, const float* vol, float eps,
+                        double* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
+
 /* Thread-local description of the last non-zero return. */
 const char* dp_last_error(void);
 
@@ -207,7 +248,8 @@ int32_t dp_version(void);
 enum {
     DP_K_SETUP = 0, DP_K_VOL_PREP = 1, DP_K_RD_FWD = 2, DP_K_RD_GRAD = 3,
     DP_K_DET_PREP = 4, DP_K_VD_BP = 5, DP_K_VD_GRAD = 6, DP_K_FINALIZE = 7,
-    DP_K_COUNT = 8
+    DP_K_FDK_FILTER = 8, DP_K_SHARPNESS = 9,
+    DP_K_COUNT = 10
 };
 int dp_profile_enable(int32_t on);
 int dp_profile_collect(void);

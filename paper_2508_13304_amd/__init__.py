@@ -21,13 +21,17 @@ LIB_PATH = os.path.join(_HERE, "libdiffproj.so")
 W_NONE = 0
 W_FDK = 1
 OP_FWD, OP_FWD_GRAD, OP_BP, OP_BP_GRAD = 0, 1, 2, 3
-KERNELS = ("setup", "vol_prep", "rd_fwd", "rd_grad", "det_prep", "vd_bp", "vd_grad", "finalize")
+KERNELS = ("setup", "vol_prep", "rd_fwd", "rd_grad", "det_prep", "vd_bp", "vd_grad", "finalize",
+           "fdk_filter", "sharpness")
 
 EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "dp_backproject",
            "dp_backproject_grad_pose", "dp_last_error", "dp_version", "dp_profile_enable",
            "dp_profile_collect", "dp_profile_read", "dp_batch_workspace_bytes",
            "dp_project_fwd_batch", "dp_project_fwd_grad_pose_batch", "dp_autotune",
-           "dp_set_variant", "dp_get_variant")
+           "dp_set_variant", "dp_get_variant", "dp_fdk_filter", "dp_sharpness",
+           "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
+           "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
+           "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16")
 MAX_BATCH = 16
 N_VARIANTS = 3
 
@@ -91,6 +95,16 @@ def load(path: str | None = None):
     lib.dp_set_variant.restype = C.c_int
     lib.dp_get_variant.argtypes = [g, i32, i32]
     lib.dp_get_variant.restype = i32
+    lib.dp_fdk_filter.argtypes = [g, i32, vp, vp, C.c_double, vp]
+    lib.dp_fdk_filter.restype = C.c_int
+    lib.dp_sharpness_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.dp_sharpness_workspace_bytes.restype = sz
+    lib.dp_sharpness.argtypes = [i32, i32, i32, vp, vp, vp, vp, sz, vp]
+    lib.dp_sharpness.restype = C.c_int
+    lib.dp_gradient_entropy_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.dp_gradient_entropy_workspace_bytes.restype = sz
+    lib.dp_gradient_entropy.argtypes = [i32, i32, i32, vp, C.c_float, vp, vp, vp, sz, vp]
+    lib.dp_gradient_entropy.restype = C.c_int
     _lib = lib
     return lib
 
@@ -292,6 +306,54 @@ def autotune(op, geom, angles, poses, vol, out, grad_proj=None, ws=None, reps=3,
                             C.byref(best), ms)
     _check(rc, "dp_autotune")
     return best.value, list(ms)
+
+
+def fdk_filter(geom, proj, scale, out=None, stream=None):
+    """FDK pre-filtered projections (cosine weight, ramp along u, times scale);
+    scale = pi / V for V views over a full circle."""
+    import torch
+    V = proj.shape[0]
+    if out is None:
+        out = torch.empty_like(proj)
+    rc = load().dp_fdk_filter(C.byref(geom_struct(geom)), V,
+                              _dev(proj, torch.float32, "proj", (V, geom.nv, geom.nu)),
+                              _dev(out, torch.float32, "out", (V, geom.nv, geom.nu)),
+                              float(scale), _stream(stream))
+    _check(rc, "dp_fdk_filter")
+    return out
+
+
+def sharpness(vol, grad=True, ws=None, stream=None):
+    """(S, dS/dvol): S a 0-d FP64 device tensor, dS/dvol FP32 like vol (or None)."""
+    import torch
+    nz, ny, nx = vol.shape
+    need = load().dp_sharpness_workspace_bytes(nx, ny, nz)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=vol.device)
+    loss = torch.empty((), dtype=torch.float64, device=vol.device)
+    g = torch.empty_like(vol) if grad else None
+    rc = load().dp_sharpness(nx, ny, nz, _dev(vol, torch.float32, "vol"), C.c_void_p(loss.data_ptr()),
+                             C.c_void_p(g.data_ptr()) if grad else None,
+                             C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "dp_sharpness")
+    return loss, g
+
+
+def gradient_entropy(vol, grad=True, eps=1e-12, ws=None, stream=None):
+    """(GE, dGE/dvol): GE a 0-d FP64 device tensor, dGE/dvol FP32 like vol (or None)."""
+    import torch
+    nz, ny, nx = vol.shape
+    need = load().dp_gradient_entropy_workspace_bytes(nx, ny, nz)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=vol.device)
+    loss = torch.empty((), dtype=torch.float64, device=vol.device)
+    g = torch.empty_like(vol) if grad else None
+    rc = load().dp_gradient_entropy(nx, ny, nz, _dev(vol, torch.float32, "vol"), float(eps),
+                                    C.c_void_p(loss.data_ptr()),
+                                    C.c_void_p(g.data_ptr()) if grad else None,
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "dp_gradient_entropy")
+    return loss, g
 
 
 def set_variant(op, variant):

@@ -577,6 +577,79 @@ int dp_colsum_bf16(int32_t M, int32_t C, const void* dz, float* db, void* stream
     return check_launch("dp_colsum_bf16");
 }
 
+int dp_fdk_filter(const dp_geom* g, int32_t n_views, const float* proj, float* out, double scale,
+                  void* stream)
+{
+    int rc = check_geom(g, n_views);
+    if (rc) return rc;
+    if (!proj || !out) return fail(DP_ERR_ARG, "fdk_filter: NULL array argument");
+    if (g->nu > fdk_max_nu())
+        return fail(DP_ERR_UNSUPPORTED, "fdk_filter: detector rows longer than %d pixels (got %d)",
+                    fdk_max_nu(), g->nu);
+    if ((int64_t)n_views * g->nv > INT32_MAX) return fail(DP_ERR_ARG, "fdk_filter: too many rows");
+    if (!std::isfinite(scale)) return fail(DP_ERR_ARG, "fdk_filter: scale must be finite");
+    (void)hipGetLastError();
+    const GeoScalars s = make_scalars(*g);
+    prof_begin(DP_K_FDK_FILTER, (hipStream_t)stream);
+    launch_fdk_filter(s, n_views, proj, out, scale, (hipStream_t)stream);
+    prof_end(DP_K_FDK_FILTER, (hipStream_t)stream);
+    return check_launch("dp_fdk_filter");
+}
+
+size_t dp_sharpness_workspace_bytes(int32_t nx, int32_t ny, int32_t nz)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0) return 0;
+    return (sharpness_partials(nx, ny, nz) * sizeof(double) + kAlign - 1) / kAlign * kAlign;
+}
+
+int dp_sharpness(int32_t nx, int32_t ny, int32_t nz, const float* vol, double* loss, float* grad,
+                 void* ws, size_t ws_bytes, void* stream)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(DP_ERR_ARG, "sharpness: sizes must be positive");
+    if ((int64_t)nx * ny * nz >= ((int64_t)1 << 31) * 256)
+        return fail(DP_ERR_ARG, "sharpness: volume too large");
+    if (!vol || !loss) return fail(DP_ERR_ARG, "sharpness: NULL array argument");
+    const size_t need = dp_sharpness_workspace_bytes(nx, ny, nz);
+    if (!ws) return fail(DP_ERR_ARG, "workspace pointer is NULL");
+    if ((uintptr_t)ws % kAlign != 0) return fail(DP_ERR_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(DP_ERR_WORKSPACE, "sharpness: workspace too small (%zu < %zu bytes)", ws_bytes, need);
+    (void)hipGetLastError();
+    prof_begin(DP_K_SHARPNESS, (hipStream_t)stream);
+    launch_sharpness(nx, ny, nz, vol, grad, loss, (double*)ws, (hipStream_t)stream);
+    prof_end(DP_K_SHARPNESS, (hipStream_t)stream);
+    return check_launch("dp_sharpness");
+}
+
+size_t dp_gradient_entropy_workspace_bytes(int32_t nx, int32_t ny, int32_t nz)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0) return 0;
+    return (gradient_entropy_ws_doubles(nx, ny, nz) * sizeof(double) + kAlign - 1) / kAlign * kAlign;
+}
+
+int dp_gradient_entropy(int32_t nx, int32_t ny, int32_t nz, const float* vol, float eps,
+                        double* loss, float* grad, void* ws, size_t ws_bytes, void* stream)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0)
+        return fail(DP_ERR_ARG, "gradient_entropy: sizes must be positive");
+    if ((int64_t)nx * ny * nz >= ((int64_t)1 << 31) * 256)
+        return fail(DP_ERR_ARG, "gradient_entropy: volume too large");
+    if (!vol || !loss) return fail(DP_ERR_ARG, "gradient_entropy: NULL array argument");
+    if (!(eps > 0.0f) || !std::isfinite(eps))
+        return fail(DP_ERR_ARG, "gradient_entropy: eps must be finite and positive");
+    const size_t need = dp_gradient_entropy_workspace_bytes(nx, ny, nz);
+    if (!ws) return fail(DP_ERR_ARG, "workspace pointer is NULL");
+    if ((uintptr_t)ws % kAlign != 0) return fail(DP_ERR_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(DP_ERR_WORKSPACE, "gradient_entropy: workspace too small (%zu < %zu bytes)",
+                    ws_bytes, need);
+    (void)hipGetLastError();
+    prof_begin(DP_K_SHARPNESS, (hipStream_t)stream);
+    launch_gradient_entropy(nx, ny, nz, eps, vol, grad, loss, (double*)ws, (hipStream_t)stream);
+    prof_end(DP_K_SHARPNESS, (hipStream_t)stream);
+    return check_launch("dp_gradient_entropy");
+}
+
 int dp_profile_enable(int32_t on)
 {
     if (on && g_prof.ev.empty()) {

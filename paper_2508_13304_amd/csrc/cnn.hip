@@ -36,14 +36,53 @@ constexpr int kGPad = 8;  // LDS row padding (bf16 elements) against bank confli
 
 __device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
 
-// op(A)[m][k]: A stored [M][K] (lda) or, if TA, [K][M] (lda).
-template <bool TA>
-__device__ inline float a_at(const __bf16* A, int lda, int m, int k)
+// Stage a 64 x 32 (rows x k) tile of one operand into LDS S[row][k].
+// KC: the operand is stored k-contiguous (element (r, k) at P[r * ld + k]),
+// else row-contiguous (at P[k * ld + r]).  VEC: ld is a multiple of 8 and P
+// 16-byte aligned, so each thread moves 8 contiguous elements with one
+// 16-byte load (ragged edges fall back to guarded element loads).
+template <bool KC, bool VEC>
+__device__ inline void stage_tile(const __bf16* __restrict__ P, int ld, int rows, int row0, int k0,
+                                  int kend, __bf16 (*S)[kGK + kGPad], int tid)
 {
-    return TA ? (float)A[(size_t)k * lda + m] : (float)A[(size_t)m * lda + k];
+    if (VEC) {
+        if (KC) {
+            const int r = tid >> 2, c = (tid & 3) * 8, row = row0 + r, k = k0 + c;
+            if (row < rows && k + 8 <= kend) {
+                *(uint4*)&S[r][c] = *(const uint4*)(P + (size_t)row * ld + k);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    S[r][c + j] = (row < rows && k + j < kend) ? P[(size_t)row * ld + k + j] : to_bf16(0.f);
+            }
+        } else {
+            const int kk = tid >> 3, c = (tid & 7) * 8, k = k0 + kk, row = row0 + c;
+            if (k < kend && row + 8 <= rows) {
+                union { uint4 u; __bf16 h[8]; } v;
+                v.u = *(const uint4*)(P + (size_t)k * ld + row);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) S[c + j][kk] = v.h[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    S[c + j][kk] = (k < kend && row + j < rows) ? P[(size_t)k * ld + row + j] : to_bf16(0.f);
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int idx = tid + e * 256;  // 0 .. 2047
+        int r, c;
+        if (KC) { r = idx >> 5; c = idx & 31; }  // coalesced along k
+        else    { r = idx & 63; c = idx >> 6; }  // coalesced along rows
+        const int row = row0 + r, k = k0 + c;
+        S[r][c] = (row < rows && k < kend) ? (KC ? P[(size_t)row * ld + k] : P[(size_t)k * ld + row])
+                                           : to_bf16(0.f);
+    }
 }
 
-template <bool TA, bool TB>
+template <bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
                                                         const __bf16* __restrict__ A, int lda,
                                                         const __bf16* __restrict__ B, int ldb,
@@ -66,24 +105,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int k0 = kbeg; k0 < kend; k0 += kGK) {
-        // stage: 64 x 32 elements of each operand, 8 per thread
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid + e * 256;          // 0 .. 2047
-            int r, c;
-            if (TA) { r = idx & 63; c = idx >> 6; }  // coalesced along m
-            else    { r = idx >> 5; c = idx & 31; }  // coalesced along k
-            const int m = m0 + r, k = k0 + c;
-            As[r][c] = (m < M && k < kend) ? (TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k])
-                                        : to_bf16(0.f);
-            int rb, cb;
-            if (TB) { rb = idx >> 5; cb = idx & 31; }  // B stored [N][K]: coalesced along k
-            else    { rb = idx & 63; cb = idx >> 6; }  // B stored [K][N]: coalesced along n
-            const int n = n0 + rb, kb = k0 + cb;
-            Bs[rb][cb] = (n < N && kb < kend) ? (TB ? B[(size_t)n * ldb + kb] : B[(size_t)kb * ldb + n])
-                                           : to_bf16(0.f);
-        }
-        __syncthreads();
+        // A stored [M][K] (k-contiguous) unless TA; B stored [N][K] if TB
+        stage_tile<!TA, VEC>(A, lda, M, m0, k0, kend, As, tid);
+        stage_tile<TB, VEC>(B, ldb, N, n0, k0, kend, Bs, tid);
+    __syncthreads();
         const int kq = (lane >> 4) * 8;
         bf16x8 a[2], b[2];
 #pragma unroll
@@ -127,9 +152,12 @@ void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int 
                       int ldb, float* C, int ldc, bool accumulate, hipStream_t st)
 {
     const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
-    // few output tiles and a long reduction: split K over up to 64 blocks per tile
+    // few output tiles and a long reduction (the weight gradients): split K so
+    // that about 1024 blocks run, each reducing at least 1024 rows
     int splits = 1;
-    if ((long long)tm * tn < 1024 && K > 4096) splits = (int)std::min<long long>(64, K / 4096);
+    const long long tiles = (long long)tm * tn;
+    if (tiles < 512 && K >= 2048)
+        splits = (int)std::max<long long>(1, std::min<long long>((1024 + tiles - 1) / tiles, K / 1024));
     if (splits > 1 && !accumulate) {
         const size_t total = (size_t)M * N;
         const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
@@ -139,10 +167,19 @@ void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int 
     const __bf16* a = (const __bf16*)A;
     const __bf16* b = (const __bf16*)B;
     const int acc = accumulate ? 1 : 0;
-    if (!ta && !tb) gemm_bf16_kernel<false, false><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
-    else if (!ta && tb) gemm_bf16_kernel<false, true><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
-    else if (ta && !tb) gemm_bf16_kernel<true, false><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
-    else gemm_bf16_kernel<true, true><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc);
+    const bool vec = lda % 8 == 0 && ldb % 8 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+#define DP_GEMM(TA_, TB_)                                                                          \
+    do {                                                                                           \
+        if (vec)                                                                                   \
+            gemm_bf16_kernel<TA_, TB_, true><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc); \
+        else                                                                                       \
+            gemm_bf16_kernel<TA_, TB_, false><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc); \
+    } while (0)
+    if (!ta && !tb) DP_GEMM(false, false);
+    else if (!ta && tb) DP_GEMM(false, true);
+    else if (ta && !tb) DP_GEMM(true, false);
+    else DP_GEMM(true, true);
+#undef DP_GEMM
 }
 
 // im2col of a 3x3 convolution (stride s, padding 1) on NHWC BF16 input.

@@ -114,6 +114,17 @@ void launch_relu_bwd(size_t total, const float* dy, const void* y, bool relu, vo
                      hipStream_t st);
 void launch_colsum(int M, int C, const void* dz, float* db, hipStream_t st);
 
+// FDK pre-filter and sharpness loss (fdk.hip).
+void launch_fdk_filter(const GeoScalars& s, int V, const float* proj, float* out, double scale,
+                       hipStream_t st);
+int fdk_max_nu();
+size_t sharpness_partials(int nx, int ny, int nz);
+void launch_sharpness(int nx, int ny, int nz, const float* vol, float* grad, double* loss,
+                      double* partial, hipStream_t st);
+size_t gradient_entropy_ws_doubles(int nx, int ny, int nz);
+void launch_gradient_entropy(int nx, int ny, int nz, float eps, const float* vol, float* grad,
+                             double* loss, double* ws, hipStream_t st);
+
 inline int rd_tiles(const GeoScalars& s)
 {
     return ((s.nu + kRdTile - 1) / kRdTile) * ((s.nv + kRdTile - 1) / kRdTile);

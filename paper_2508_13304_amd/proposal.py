@@ -12,14 +12,32 @@ plain form (started from the identity) is the fallback.
 """
 from __future__ import annotations
 
+import argparse
 import ctypes as C
+import dataclasses
+import json
 import math
+import os
+import sys
+import time
 
 import torch
 
 from . import _check, _stream, load
+from . import project_fwd as _project_fwd
 
 CHANNELS = (32, 64, 128, 256, 256, 256)
+# Training range of the pose offset: translations +-30 mm, rotations +-20 deg;
+# the network regresses the offset divided by these (order tx ty tz gx gy gz).
+T_RANGE_MM = 30.0
+R_RANGE_DEG = 20.0
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                       "proposal_192vox_256px.safetensors")
+
+
+def label_scale(device) -> torch.Tensor:
+    return torch.tensor([T_RANGE_MM] * 3 + [math.radians(R_RANGE_DEG)] * 3,
+                        dtype=torch.float64, device=device)
 
 
 def _lib():
@@ -174,13 +192,43 @@ class ProposalNet:
             v.mul_(betas[1]).addcmul_(g, g, value=1 - betas[1])
             p.sub_(lr * (m / c1) / ((v / c2).sqrt() + eps))
 
-    def state_dict(self):
-        return {"convs": [(W.cpu(), b.cpu(), s) for W, b, s in self.convs],
-                "Wfc": self.Wfc.cpu(), "bfc": self.bfc.cpu(), "size": self.size}
+    def tensors(self) -> dict:
+        """Flat name -> FP32 CPU tensor map (safetensors layout)."""
+        out = {}
+        for i, (W, b, s) in enumerate(self.convs):
+            out[f"conv{i}.weight"] = W.detach().cpu().contiguous()
+            out[f"conv{i}.bias"] = b.detach().cpu().contiguous()
+        out["fc.weight"] = self.Wfc.detach().cpu().contiguous()
+        out["fc.bias"] = self.bfc.detach().cpu().contiguous()
+        return out
 
-    def load_state_dict(self, st):
-        self.convs = [[W.to(self.device), b.to(self.device), s] for W, b, s in st["convs"]]
-        self.Wfc, self.bfc = st["Wfc"].to(self.device), st["bfc"].to(self.device)
+    def save(self, path: str, meta: dict | None = None):
+        from safetensors.torch import save_file
+        info = {"size": str(self.size), "channels": ",".join(str(W.shape[0]) for W, _, _ in self.convs)}
+        info.update({k: str(v) for k, v in (meta or {}).items()})
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        save_file(self.tensors(), path, metadata=info)
+
+    @classmethod
+    def load(cls, path: str, device="cuda:0") -> "ProposalNet":
+        from safetensors import safe_open
+        with safe_open(path, framework="pt") as fh:
+            meta = fh.metadata()
+            t = {k: fh.get_tensor(k) for k in fh.keys()}
+        chans = tuple(int(c) for c in meta["channels"].split(","))
+        net = cls(size=int(meta["size"]), channels=chans, device=device)
+        for i, conv in enumerate(net.convs):
+            conv[0] = t[f"conv{i}.weight"].to(net.device).contiguous()
+            conv[1] = t[f"conv{i}.bias"].to(net.device).contiguous()
+        net.Wfc = t["fc.weight"].to(net.device).contiguous()
+        net.bfc = t["fc.bias"].to(net.device).contiguous()
+        net.meta = meta
+        return net
+
+    def predict(self, x, batch=256) -> torch.Tensor:
+        """Pose offsets [N][6] (FP64, mm and rad) for NHWC BF16 pair images."""
+        outs = [self.forward(x[i:i + batch]) for i in range(0, x.shape[0], batch)]
+        return torch.cat(outs).to(torch.float64) * label_scale(x.device)
 
 
 def pair_input(ref, target, size):
@@ -192,3 +240,247 @@ def pair_input(ref, target, size):
         x = torch.nn.functional.adaptive_avg_pool2d(x, (size, size))
     scale = x[:, :1].amax(dim=(1, 2, 3), keepdim=True).clamp_min(1e-6)
     return (x / scale).permute(0, 2, 3, 1).contiguous().to(torch.bfloat16)
+
+
+# ---------------------------------------------------------------------------
+# Training set: DRR pairs rendered by the library's own forward projector
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DRRSet:
+    """Reference DRRs (identity pose) per phantom and target DRRs at random
+    pose offsets, both divided by the reference's maximum and stored BF16."""
+    ref: torch.Tensor      # [P][nv][nu] bf16
+    tgt: torch.Tensor      # [S][nv][nu] bf16
+    pid: torch.Tensor      # [S] int64 phantom of each target
+    poses: torch.Tensor    # [S][6] f64 pose offsets (mm, rad)
+
+    def __len__(self):
+        return self.tgt.shape[0]
+
+    def inputs(self, idx) -> torch.Tensor:
+        return torch.stack([self.ref[self.pid[idx]], self.tgt[idx]], dim=-1).contiguous()
+
+    def labels(self, idx) -> torch.Tensor:
+        return (self.poses[idx] / label_scale(self.poses.device)).to(torch.float32)
+
+
+def phantom(geom, rng, device):
+    """One training/evaluation phantom: 10-40 random ellipsoids, half of them
+    inside a high-attenuation shell, sigma = 1 voxel smoothing."""
+    import synth
+    n_ell = int(rng.integers(10, 41))
+    shell = bool(rng.uniform() < 0.5)
+    return synth.ellipsoid_phantom_torch(geom.nx, geom.vx, n_ell, rng, device, shell=shell)
+
+
+def render_set(geom, n_phantoms, per_phantom, salt, device="cuda:0", log=None) -> DRRSet:
+    """Render per_phantom targets at uniform random offsets (+-30 mm, +-20 deg)
+    and one identity reference for each of n_phantoms phantoms, gantry angle 0."""
+    import synth
+    dev = torch.device(device)
+    S = n_phantoms * per_phantom
+    ref = torch.empty((n_phantoms, geom.nv, geom.nu), dtype=torch.bfloat16, device=dev)
+    tgt = torch.empty((S, geom.nv, geom.nu), dtype=torch.bfloat16, device=dev)
+    poses = torch.empty((S, 6), dtype=torch.float64, device=dev)
+    pid = torch.arange(n_phantoms, device=dev).repeat_interleave(per_phantom)
+    zero_angle = torch.zeros(1, dtype=torch.float64, device=dev)
+    angles = torch.zeros(per_phantom, dtype=torch.float64, device=dev)
+    ident = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    for i in range(n_phantoms):
+        rng = synth.rng_for(4, salt * 1_000_003 + i)
+        vol = phantom(geom, rng, dev)
+        th = torch.tensor(synth.random_poses(per_phantom, T_RANGE_MM, R_RANGE_DEG, rng),
+                          dtype=torch.float64, device=dev)
+        r = _project_fwd(geom, zero_angle, ident, vol)[0]
+        scale = 1.0 / r.max().clamp_min(1e-6)
+        ref[i] = (r * scale).to(torch.bfloat16)
+        sl = slice(i * per_phantom, (i + 1) * per_phantom)
+        tgt[sl] = (_project_fwd(geom, angles, th, vol) * scale).to(torch.bfloat16)
+        poses[sl] = th
+        if log and ((i + 1) % max(1, n_phantoms // 10) == 0 or i + 1 == n_phantoms):
+            torch.cuda.synchronize(dev)
+            log(f"rendered {i + 1}/{n_phantoms} phantoms ({(i + 1) * per_phantom} DRRs) "
+                f"in {time.perf_counter() - t0:.1f} s")
+    return DRRSet(ref, tgt, pid, poses)
+
+
+def pose_error_stats(pred, truth):
+    """Median and 90th-percentile |error| per component (mm, deg)."""
+    d = (pred - truth).abs()
+    d[:, 3:] = torch.rad2deg(d[:, 3:])
+    return d.median(dim=0).values, d.quantile(0.9, dim=0)
+
+
+def train(net, data: DRRSet, val: DRRSet | None = None, epochs=8, batch=256, lr=1e-3,
+          lr_min=2e-5, seed=0, log=print):
+    """Minimise the mean squared error of the normalised pose offset with Adam
+    (cosine learning-rate schedule); every layer's forward and backward runs
+    on the library's BF16 MFMA kernels."""
+    dev = data.tgt.device
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    steps_per_epoch = len(data) // batch
+    total = epochs * steps_per_epoch
+    step = 0
+    t0 = time.perf_counter()
+    history = []
+    for ep in range(epochs):
+        perm = torch.randperm(len(data), generator=gen, device=dev)
+        acc, cnt = torch.zeros((), device=dev), 0
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            x, y = data.inputs(idx), data.labels(idx)
+            out, cache = net.forward(x, keep=True)
+            d = out - y
+            acc += (d * d).mean().detach()
+            cnt += 1
+            grads, head = net.backward(cache, (2.0 / d.numel()) * d)
+            a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(1, total)))
+            net.adam_step(grads, head, lr=a)
+            step += 1
+        msg = f"epoch {ep + 1}/{epochs}: train mse {float(acc) / max(cnt, 1):.5f}"
+        if val is not None:
+            pred = net.predict(val.inputs(torch.arange(len(val), device=dev)))
+            med, p90 = pose_error_stats(pred, val.poses)
+            msg += (f"; val median |err| t {med[:3].cpu().numpy().round(2)} mm, "
+                    f"r {med[3:].cpu().numpy().round(2)} deg; p90 t {p90[:3].cpu().numpy().round(2)}"
+                    f" r {p90[3:].cpu().numpy().round(2)}")
+        torch.cuda.synchronize(dev)
+        msg += f" ({time.perf_counter() - t0:.1f} s)"
+        history.append(msg)
+        log(msg)
+    return history
+
+
+# ---------------------------------------------------------------------------
+# Registration with the learned proposal
+# ---------------------------------------------------------------------------
+
+def register_learned(net, geom, vol, angles, targets, ref, fallback=True, rel_tol=1e-6, **kw):
+    """Propose theta0 with the network from (reference DRR, target), refine
+    with the analytic-gradient BFGS registration, and fall back to the plain
+    registration from the identity for every registration whose refined
+    loss stays above rel_tol * |target|^2 (keeping the lower loss).
+
+    The network was trained at gantry angle 0, so `angles` must be zero;
+    `ref` is the [nv][nu] DRR of `vol` at the identity pose.
+    Returns (RegistrationResult, theta0, number of fallbacks).
+    """
+    from .registration import RegistrationResult, register_bfgs
+    if bool((angles != 0).any()):
+        raise ValueError("the proposal network is trained for gantry angle 0")
+    t0 = time.perf_counter()
+    B = targets.shape[0]
+    x = pair_input(ref.expand(B, -1, -1), targets, net.size)
+    theta0 = net.predict(x)
+    res = register_bfgs(geom, vol, angles, targets, theta0, **kw)
+    poses, its, conv, fl = res.poses.clone(), res.iterations.clone(), res.converged.clone(), \
+        res.final_loss.clone()
+    launches = res.launches
+    n_fb = 0
+    if fallback:
+        energy = (targets.to(torch.float64) ** 2).reshape(B, -1).sum(1)
+        bad = torch.nonzero(fl > rel_tol * energy).flatten()
+        n_fb = int(bad.numel())
+        if n_fb:
+            r2 = register_bfgs(geom, vol, angles[bad], targets[bad], torch.zeros_like(theta0[bad]),
+                               **kw)
+            better = r2.final_loss < fl[bad]
+            sel = bad[better]
+            poses[sel] = r2.poses[better]
+            fl[sel] = r2.final_loss[better]
+            conv[sel] = r2.converged[better]
+            its[bad] += r2.iterations
+            launches += r2.launches
+    torch.cuda.synchronize(targets.device)
+    out = RegistrationResult(poses=poses, iterations=its, converged=conv, final_loss=fl,
+                             seconds=time.perf_counter() - t0, launches=launches)
+    return out, theta0, n_fb
+
+
+def evaluate(net, geom, n_phantoms=8, per_phantom=16, salt=3, device="cuda:0", log=None, **kw):
+    """Plain (identity start) versus learned-proposal registration on unseen
+    phantoms with offsets drawn like the training set.  Returns success
+    rates at 0.1 mm / 0.1 deg, registrations per second and error stats."""
+    import synth
+    from .registration import register_bfgs, success
+    dev = torch.device(device)
+    stats = {"plain_ok": 0, "learned_ok": 0, "n": 0, "plain_s": 0.0, "learned_s": 0.0,
+             "fallbacks": 0, "plain_iters": 0, "learned_iters": 0}
+    prop_err, truths = [], []
+    for i in range(n_phantoms):
+        rng = synth.rng_for(4, salt * 1_000_003 + i)
+        vol = phantom(geom, rng, dev)
+        truth = torch.tensor(synth.random_poses(per_phantom, T_RANGE_MM, R_RANGE_DEG, rng),
+                             dtype=torch.float64, device=dev)
+        angles = torch.zeros(per_phantom, dtype=torch.float64, device=dev)
+        targets = _project_fwd(geom, angles, truth, vol)
+        ref = _project_fwd(geom, angles[:1], torch.zeros_like(truth[:1]), vol)[0]
+        torch.cuda.synchronize(dev)
+        plain = register_bfgs(geom, vol, angles, targets, torch.zeros_like(truth), **kw)
+        learned, theta0, nfb = register_learned(net, geom, vol, angles, targets, ref, **kw)
+        stats["plain_ok"] += int(success(plain.poses, truth).sum())
+        stats["learned_ok"] += int(success(learned.poses, truth).sum())
+        stats["n"] += per_phantom
+        stats["plain_s"] += plain.seconds
+        stats["learned_s"] += learned.seconds
+        stats["fallbacks"] += nfb
+        stats["plain_iters"] += int(plain.iterations.sum())
+        stats["learned_iters"] += int(learned.iterations.sum())
+        prop_err.append(theta0)
+        truths.append(truth)
+        if log:
+            log(f"phantom {i + 1}/{n_phantoms}: plain {stats['plain_ok']}/{stats['n']} "
+                f"learned {stats['learned_ok']}/{stats['n']} fallbacks {stats['fallbacks']}")
+    med, p90 = pose_error_stats(torch.cat(prop_err), torch.cat(truths))
+    n = stats["n"]
+    return {
+        "registrations": n,
+        "plain_success": stats["plain_ok"] / n,
+        "learned_success": stats["learned_ok"] / n,
+        "plain_registrations_per_s": n / stats["plain_s"],
+        "learned_registrations_per_s": n / stats["learned_s"],
+        "plain_successful_per_s": stats["plain_ok"] / stats["plain_s"],
+        "learned_successful_per_s": stats["learned_ok"] / stats["learned_s"],
+        "plain_mean_iterations": stats["plain_iters"] / n,
+        "learned_mean_iterations": stats["learned_iters"] / n,
+        "fallbacks": stats["fallbacks"],
+        "proposal_median_err": med.cpu().tolist(),
+        "proposal_p90_err": p90.cpu().tolist(),
+    }
+
+
+def _main(argv=None):
+    ap = argparse.ArgumentParser(description="Render the DRR training set with the forward "
+                                 "projector and train the pose-proposal network on the GPU.")
+    ap.add_argument("--phantoms", type=int, default=2000)
+    ap.add_argument("--per-phantom", type=int, default=100)
+    ap.add_argument("--val-phantoms", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-phantoms", type=int, default=4)
+    ap.add_argument("--out", default=WEIGHTS)
+    a = ap.parse_args(argv)
+    import synth
+
+    def log(m):
+        print(m, flush=True)
+
+    geom = synth.geom_c5()
+    data = render_set(geom, a.phantoms, a.per_phantom, salt=1, log=log)
+    val = render_set(geom, a.val_phantoms, a.per_phantom, salt=2, log=log)
+    net = ProposalNet(size=geom.nu, seed=0)
+    hist = train(net, data, val, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
+    net.save(a.out, {"phantoms": a.phantoms, "per_phantom": a.per_phantom, "epochs": a.epochs,
+                     "batch": a.batch, "lr": a.lr, "final": hist[-1]})
+    log(f"saved {a.out}")
+    del data
+    if a.eval_phantoms:
+        res = evaluate(net, geom, n_phantoms=a.eval_phantoms, per_phantom=16, log=log)
+        log(json.dumps(res))
+
+
+if __name__ == "__main__":
+    sys.exit(_main())

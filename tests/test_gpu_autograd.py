@@ -94,19 +94,43 @@ def test_volume_gradient_request_is_rejected(dp):
                    torch.zeros(1, dtype=torch.float64, device=DEV))
 
 
-def test_batched_registration_recovers_poses(dp):
-    from paper_2508_13304_amd import registration as reg
+def _registration_case(dp, B=8):
     rng = synth.rng_for(402)
     g = Geom(96, 96, 96, 1.0, 1.0, 1.0, 192, 192, 0.9, 0.9)
     vol = T(synth.ellipsoid_phantom(96, 1.0, 12, rng), torch.float32)
-    B = 8
     truth = T(synth.random_poses(B, 5.0, 5.0, rng))
     angles = T(rng.uniform(0, 2 * math.pi, B))
     targets = dp.project_fwd(g, angles, truth, vol)
-    res = reg.register(g, vol, angles, targets, torch.zeros_like(truth), loss="ssd", iters=400,
-                       lr_t=3.0, lr_r_deg=2.0, decay=0.99)
+    return g, vol, truth, angles, targets
+
+
+def _report(reg, res, truth):
     et, er = reg.pose_errors(res.poses, truth)
     print("translation err (mm)", et.cpu().numpy().round(4), "rotation err (deg)",
           er.cpu().numpy().round(4), "iters", res.iterations.cpu().numpy())
+    return et, er
+
+
+def test_batched_bfgs_registration_reaches_target_accuracy(dp):
+    """Single-view registrations from identity (+-5 mm, +-5 deg) all reach
+    0.1 mm / 0.1 deg with the analytic gradient and BFGS."""
+    from paper_2508_13304_amd import registration as reg
+    g, vol, truth, angles, targets = _registration_case(dp)
+    res = reg.register_bfgs(g, vol, angles, targets, torch.zeros_like(truth), loss="ssd")
+    _report(reg, res, truth)
     ok = reg.success(res.poses, truth)
-    assert ok.sum().item() >= B - 1, ok
+    assert bool(ok.all()), ok
+    assert bool(res.converged.all())
+
+
+def test_batched_adam_registration_reduces_error(dp):
+    """The Adam driver (fixed step sizes) recovers the rotations and shrinks
+    the translation error by an order of magnitude on the same case."""
+    from paper_2508_13304_amd import registration as reg
+    g, vol, truth, angles, targets = _registration_case(dp)
+    res = reg.register(g, vol, angles, targets, torch.zeros_like(truth), loss="ssd", iters=400,
+                       lr_t=3.0, lr_r_deg=2.0, decay=0.99)
+    et, er = _report(reg, res, truth)
+    et0, er0 = reg.pose_errors(torch.zeros_like(truth), truth)
+    assert bool((er < 0.1).all()), er
+    assert float(et.median()) < 0.1 * float(et0.median())
