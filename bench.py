@@ -38,7 +38,8 @@ VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec (packed FMA)
 #   forward : sample position 8, fractions 3, trilinear 7 lerps x 3 = 21, sum 1
 #   gradient: position 8, fractions 3, 3 channels x 8 lerps x 3 = 72, moments 6,
 #             centre offsets 3, accumulation of B (3) and T (6 x 3)
-FLOPS_PER_SAMPLE = {"rd_fwd": 33, "rd_grad": 113}
+#   fused   : the gradient's 113 plus the mu trilinear (21) and its sum (1)
+FLOPS_PER_SAMPLE = {"rd_fwd": 33, "rd_grad": 113, "rd_fused": 135}
 
 
 def log(*a):
@@ -135,16 +136,23 @@ def run_forward(args, dp, torch):
     vol = T(c["vol"], torch.float32)
     angles = T(c["angles"], torch.float64)
     poses = T(c["poses"], torch.float64)
-    # target DRR at the true pose (synthetic input, generated once)
-    y = dp.project_fwd(g, T([0.0], torch.float64), T(c["target_pose"], torch.float64), vol)
-    ws = torch.empty(max(dp.workspace_bytes(g, V, dp.OP_FWD), dp.workspace_bytes(g, V, dp.OP_FWD_GRAD)),
+    # target DRR at the true pose (synthetic input, generated once), one copy per candidate
+    y1 = dp.project_fwd(g, T([0.0], torch.float64), T(c["target_pose"], torch.float64), vol)
+    y = y1.expand(V, -1, -1).contiguous()
+    ws = torch.empty(max(dp.workspace_bytes(g, V, op) for op in (dp.OP_FWD, dp.OP_FWD_GRAD,
+                                                                  dp.OP_FWD_SSD)),
                      dtype=torch.uint8, device=dev)
     proj = torch.empty((V, g.nv, g.nu), dtype=torch.float32, device=dev)
     wgrad = torch.empty_like(proj)
     gpose = torch.empty((V, 6), dtype=torch.float64, device=dev)
+    loss = torch.empty(V, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step():
+    def step():  # one pass: DRRs, per-view SSD and its pose gradient
+        dp.project_fwd_ssd_grad_pose(g, angles, poses, vol, y, proj=proj, loss=loss, grad=gpose,
+                                     ws=ws, stream=stream)
+
+    def step_two_calls():  # forward launch, residual, gradient launch
         dp.project_fwd(g, angles, poses, vol, out=proj, ws=ws, stream=stream)
         torch.sub(proj, y, out=wgrad)
         wgrad.mul_(2.0)
@@ -152,41 +160,47 @@ def run_forward(args, dp, torch):
 
     n_samples = count_ray_samples(g, c["angles"], c["poses"])
     log(f"[bench] in-support samples per step: {n_samples:.4e}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    dp.profile_enable(True)
-    dp.profile_collect()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kern = dp.profile_collect()
-    dp.profile_enable(False)
-    ms_step = dt * 1e3 / args.steps
-    per_kernel = {k: round(v[0] / v[1], 4) for k, v in kern.items()}
-    log(f"[bench] {ms_step:.3f} ms/step; per-kernel avg ms: {per_kernel}")
-    fwd_ms, grad_ms = per_kernel.get("rd_fwd", 0.0), per_kernel.get("rd_grad", 0.0)
-    dominant = "rd_grad" if grad_ms >= fwd_ms else "rd_fwd"
-    dom_ms = max(grad_ms, fwd_ms)
-    # Both ray kernels are bound by VALU issue once their taps come from LDS:
+
+    def measure(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        dp.profile_enable(True)
+        dp.profile_collect()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kern = dp.profile_collect()
+        dp.profile_enable(False)
+        return dt * 1e3 / steps, {k: round(v[0] / v[1], 4) for k, v in kern.items()}
+
+    ms2, per2 = measure(step_two_calls, max(2, args.steps // 2), 1)
+    log(f"[bench] two-call step {ms2:.3f} ms; per-kernel avg ms: {per2}")
+    ms_step, per_kernel = measure(step, args.steps, args.warmup)
+    log(f"[bench] fused step {ms_step:.3f} ms/step; per-kernel avg ms: {per_kernel}")
+    dominant = "rd_fused"
+    dom_ms = per_kernel.get(dominant, 0.0)
+    # The ray kernels are bound by VALU issue once their taps come from LDS:
     # roofline = algorithmic FP32 operations per in-support sample (FMA = 2)
     # against the fp32 vector peak.
     flops = FLOPS_PER_SAMPLE[dominant]
     achieved = flops * n_samples / (dom_ms * 1e-3) / 1e12
     src_hash = _kernel_hash("rd.hip", "dp_internal.h")
+    other = {}
+    for k in ("rd_fwd", "rd_grad"):
+        if per2.get(k):
+            other[k] = {"ms": per2[k], "flops_per_sample": FLOPS_PER_SAMPLE[k],
+                        "tflops": round(FLOPS_PER_SAMPLE[k] * n_samples / (per2[k] * 1e-3) / 1e12, 2),
+                        "traffic": _traffic(k + "_config2", src_hash)}
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
                 "traffic": _traffic(dominant + "_config2", src_hash),
                 "kernel": dominant, "kernel_ms": dom_ms, "flops_per_sample": flops,
-                "source_hash": src_hash,
-                "other": {k: {"ms": per_kernel.get(k), "flops_per_sample": FLOPS_PER_SAMPLE[k],
-                              "tflops": round(FLOPS_PER_SAMPLE[k] * n_samples /
-                                              (per_kernel[k] * 1e-3) / 1e12, 2)}
-                          for k in FLOPS_PER_SAMPLE if k != dominant and per_kernel.get(k)}}
+                "source_hash": src_hash, "other": other}
     return dict(geom=g, V=V, n_samples=n_samples, ms_step=ms_step, per_kernel=per_kernel,
-                roofline=roofline, inputs=c)
+                two_call_ms=ms2, two_call_kernels=per2, roofline=roofline, inputs=c)
 
 
 def run_backproject(args, dp, torch):
@@ -488,11 +502,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "registration scale: 256^3 ellipsoid+shell phantom at 0.8 mm, 64 candidate poses "
                                "(+-10 mm/+-10 deg) x one 512x512 view at 0.6 mm, SAD/SDD 1000/1500 mm, "
-                               "0.5 mm trilinear march; forward + SSD loss gradient + 64x6 pose gradient",
+                               "0.5 mm trilinear march; forward + SSD loss + 64x6 pose gradient in one fused launch",
                    "samples_per_step": fw["n_samples"], "views": fw["V"]},
         "roofline": fw["roofline"],
         "cpu_baseline": cpu,
         "kernels_ms": fw["per_kernel"],
+        "two_call_step": {"ms_per_step": round(fw["two_call_ms"], 4),
+                          "value": fw["n_samples"] / (fw["two_call_ms"] * 1e-3),
+                          "kernels_ms": fw["two_call_kernels"]},
         "backprojector": bp,
         "registration": regr,
         "learned_proposal": learned,

@@ -80,7 +80,7 @@ enum {
 
 enum { DP_W_NONE = 0, DP_W_FDK = 1 };
 
-enum { DP_OP_FWD = 0, DP_OP_FWD_GRAD = 1, DP_OP_BP = 2, DP_OP_BP_GRAD = 3 };
+enum { DP_OP_FWD = 0, DP_OP_FWD_GRAD = 1, DP_OP_BP = 2, DP_OP_BP_GRAD = 3, DP_OP_FWD_SSD = 4 };
 
 /* Workspace size (bytes) needed by operation `op` (DP_OP_*) for this
  * geometry and view count; 0 for invalid arguments. */
@@ -101,6 +101,21 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t n_views, const double* an
                              const double* poses, const float* vol,
                              const float* grad_proj, double* grad_pose,
                              void* ws, size_t ws_bytes, void* stream);
+
+/* Forward projection, SSD loss and its pose gradient in one pass over the
+ * samples (Eq. forward with Eqs. final_forward, dis_forward for the loss
+ * L_v = sum over the view's pixels of (l - y)^2, whose dL/dl = 2 (l - y) is
+ * known at the end of each ray, so the per-ray gradient sums are weighted
+ * after the march and no separate forward launch is needed).
+ *   target [V][nv][nu] f32 = y; proj [V][nv][nu] f32 = l (overwritten);
+ *   loss [V] f64 = L_v (overwritten; may be NULL); grad_pose [V][6] f64 =
+ *   dL_v/dtheta_v (overwritten).  Workspace: dp_workspace_bytes(g, V,
+ *   DP_OP_FWD_SSD).  Same samples, tolerances and errors as the two calls it
+ *   replaces. */
+int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
+                                 const double* poses, const float* vol, const float* target,
+                                 float* proj, double* loss, double* grad_pose,
+                                 void* ws, size_t ws_bytes, void* stream);
 
 /* Voxel-driven back-projection (Eq. back), weight_mode DP_W_NONE | DP_W_FDK.
  *   proj [V][nv][nu] f32 (already filtered by the caller if FDK is meant),
@@ -147,9 +162,11 @@ int dp_project_fwd_grad_pose_batch(const dp_problem* problems, int32_t n, void* 
 
 /* ---------------------------------------------------------------------------
  * Kernel variants of the ray-driven kernels (chunk length and LDS budget:
- * 0, 1 = default, 2).  dp_autotune times every variant of `op` (DP_OP_FWD
- * or DP_OP_FWD_GRAD) on the given inputs (reps timed calls each, after one
- * warm-up; `out` is proj or grad_pose), records the fastest for this shape
+ * 0, 1 = default, 2).  dp_autotune times every variant of `op` (DP_OP_FWD,
+ * DP_OP_FWD_GRAD or DP_OP_FWD_SSD) on the given inputs (reps timed calls
+ * each, after one warm-up; `out` is proj for FWD and FWD_SSD, grad_pose for
+ * FWD_GRAD; grad_proj is dL/dl for FWD_GRAD and the target image for
+ * FWD_SSD, whose pose gradient lands in the workspace), records the fastest for this shape
  * class (grid and detector sizes, view-count octave, pixel-to-voxel ratio)
  * in a process-wide cache used by later calls, and synchronises `stream`.
  * dp_set_variant forces a variant for `op` (-1 = cached / default).
@@ -248,8 +265,8 @@ int32_t dp_version(void);
 enum {
     DP_K_SETUP = 0, DP_K_VOL_PREP = 1, DP_K_RD_FWD = 2, DP_K_RD_GRAD = 3,
     DP_K_DET_PREP = 4, DP_K_VD_BP = 5, DP_K_VD_GRAD = 6, DP_K_FINALIZE = 7,
-    DP_K_FDK_FILTER = 8, DP_K_SHARPNESS = 9,
-    DP_K_COUNT = 10
+    DP_K_FDK_FILTER = 8, DP_K_SHARPNESS = 9, DP_K_RD_FUSED = 10,
+    DP_K_COUNT = 11
 };
 int dp_profile_enable(int32_t on);
 int dp_profile_collect(void);

@@ -20,15 +20,15 @@ LIB_PATH = os.path.join(_HERE, "libdiffproj.so")
 
 W_NONE = 0
 W_FDK = 1
-OP_FWD, OP_FWD_GRAD, OP_BP, OP_BP_GRAD = 0, 1, 2, 3
+OP_FWD, OP_FWD_GRAD, OP_BP, OP_BP_GRAD, OP_FWD_SSD = 0, 1, 2, 3, 4
 KERNELS = ("setup", "vol_prep", "rd_fwd", "rd_grad", "det_prep", "vd_bp", "vd_grad", "finalize",
-           "fdk_filter", "sharpness")
+           "fdk_filter", "sharpness", "rd_fused")
 
 EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "dp_backproject",
            "dp_backproject_grad_pose", "dp_last_error", "dp_version", "dp_profile_enable",
            "dp_profile_collect", "dp_profile_read", "dp_batch_workspace_bytes",
            "dp_project_fwd_batch", "dp_project_fwd_grad_pose_batch", "dp_autotune",
-           "dp_set_variant", "dp_get_variant", "dp_fdk_filter", "dp_sharpness",
+           "dp_set_variant", "dp_get_variant", "dp_project_fwd_ssd_grad_pose", "dp_fdk_filter", "dp_sharpness",
            "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
            "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16")
@@ -71,6 +71,8 @@ def load(path: str | None = None):
     lib.dp_workspace_bytes.restype = sz
     lib.dp_project_fwd.argtypes = [g, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.dp_project_fwd_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.dp_project_fwd_ssd_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.dp_project_fwd_ssd_grad_pose.restype = C.c_int
     lib.dp_backproject.argtypes = [g, i32, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.dp_backproject_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, i32, vp, sz, vp]
     for f in ("dp_project_fwd", "dp_project_fwd_grad_pose", "dp_backproject",
@@ -197,6 +199,32 @@ def project_fwd_grad_pose(geom, angles, poses, vol, grad_proj, out=None, ws=None
     return out
 
 
+def project_fwd_ssd_grad_pose(geom, angles, poses, vol, target, proj=None, loss=None, grad=None,
+                              ws=None, stream=None):
+    """One pass: DRRs l [V][nv][nu] f32, per-view SSD L_v = sum (l - y)^2 [V]
+    f64 and its pose gradient [V][6] f64, for targets y [V][nv][nu] f32."""
+    import torch
+    V = _views(angles, poses)
+    dev = vol.device
+    if proj is None:
+        proj = torch.empty((V, geom.nv, geom.nu), dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(V, dtype=torch.float64, device=dev)
+    if grad is None:
+        grad = torch.empty((V, 6), dtype=torch.float64, device=dev)
+    ws = _workspace(geom, V, OP_FWD_SSD, ws, dev)
+    rc = load().dp_project_fwd_ssd_grad_pose(
+        C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
+        _dev(poses, torch.float64, "poses"),
+        _dev(vol, torch.float32, "vol", (geom.nz, geom.ny, geom.nx)),
+        _dev(target, torch.float32, "target", (V, geom.nv, geom.nu)),
+        _dev(proj, torch.float32, "proj", (V, geom.nv, geom.nu)),
+        _dev(loss, torch.float64, "loss", (V,)), _dev(grad, torch.float64, "grad", (V, 6)),
+        C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "dp_project_fwd_ssd_grad_pose")
+    return proj, loss, grad
+
+
 def backproject(geom, angles, poses, proj, weight_mode=W_NONE, out=None, ws=None, stream=None):
     """Volume [nz][ny][nx] f32 back-projected from proj [V][nv][nu] f32."""
     import torch
@@ -292,7 +320,9 @@ def project_fwd_grad_pose_batch(problems, ws=None, variant=-1, stream=None):
 
 def autotune(op, geom, angles, poses, vol, out, grad_proj=None, ws=None, reps=3, stream=None):
     """Time every kernel variant of `op` on these inputs, cache the fastest for
-    this shape class and return (best, [ms per variant])."""
+    this shape class and return (best, [ms per variant]).  `out` is proj (FWD,
+    FWD_SSD) or grad_pose (FWD_GRAD); `grad_proj` is dL/dl (FWD_GRAD) or the
+    target images (FWD_SSD)."""
     import torch
     V = _views(angles, poses)
     ws = _workspace(geom, V, op, ws, vol.device)

@@ -35,6 +35,7 @@ struct Layout {
     size_t buf = 0;       // offset of the padded volume / image copy
     size_t partials = 0;  // offset of the per-block partial sums
     size_t n_part = 0;    // partial blocks per view
+    size_t spare = 0;     // FWD_SSD: [V][6] f64 pose-gradient slot used by the autotuner
     size_t total = 0;
 };
 
@@ -65,6 +66,14 @@ Layout layout(const dp_geom& g, int V, int op)
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
+        break;
+    case DP_OP_FWD_SSD:
+        off = align_up(off + 4 * padded_volume_elems(g) * sizeof(float));
+        L.n_part = (size_t)rd_tiles(s);
+        L.partials = off;
+        off = align_up(off + (size_t)V * L.n_part * (kRdChannels + 1) * sizeof(float));
+        L.spare = off;
+        off = align_up(off + (size_t)V * 6 * sizeof(double));
         break;
     case DP_OP_BP:
         off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float));
@@ -144,7 +153,7 @@ struct VariantKey {
 };
 std::mutex g_var_mu;
 std::map<VariantKey, int> g_var_cache;
-int g_var_force[4] = {-1, -1, -1, -1};
+int g_var_force[5] = {-1, -1, -1, -1, -1};
 constexpr int kDefaultVariant = 1;
 
 // Shape class: grid and detector sizes, view-count octave and the ratio of
@@ -212,7 +221,7 @@ int32_t dp_version(void) { return 10000; }
 
 size_t dp_workspace_bytes(const dp_geom* g, int32_t n_views, int32_t op)
 {
-    if (op < DP_OP_FWD || op > DP_OP_BP_GRAD) return 0;
+    if (op < DP_OP_FWD || op > DP_OP_FWD_SSD) return 0;
     if (check_geom(g, n_views) != DP_OK) return 0;
     return layout(*g, n_views, op).total;
 }
@@ -259,6 +268,32 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     launch_rd_grad(s, V, views, vol3, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V), st);
     launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_project_fwd_grad_pose");
+}
+
+int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
+                                 const double* poses, const float* vol, const float* target,
+                                 float* proj, double* loss, double* grad_pose, void* ws,
+                                 size_t ws_bytes, void* stream)
+{
+    int rc = check_geom(g, V);
+    if (rc) return rc;
+    if (!angles || !poses || !vol || !target || !proj || !grad_pose)
+        return fail(DP_ERR_ARG, "NULL array argument");
+    if ((rc = check_ws(g, V, DP_OP_FWD_SSD, ws, ws_bytes))) return rc;
+    const Layout L = layout(*g, V, DP_OP_FWD_SSD);
+    const GeoScalars s = make_scalars(*g);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    ViewGeo* views = (ViewGeo*)(base + L.views);
+    float* vol4 = (float*)(base + L.buf);  // planes: padded mu, Gx, Gy, Gz
+    float* part = (float*)(base + L.partials);
+    (void)hipGetLastError();
+    launch_view_setup(s, V, angles, poses, views, st);
+    launch_vol_pad(s, vol, vol4, st);
+    launch_vol_grad(s, vol, vol4 + padded_volume_elems(*g), st);
+    launch_rd_fused(s, V, views, vol4, target, proj, part, variant_for(DP_OP_FWD_SSD, *g, V), st);
+    launch_finalize_fwd_ssd(s, V, views, part, (int)L.n_part, grad_pose, loss, st);
+    return check_launch("dp_project_fwd_ssd_grad_pose");
 }
 
 int dp_backproject(const dp_geom* g, int32_t V, const double* angles, const double* poses,
@@ -317,7 +352,8 @@ int dp_backproject_grad_pose(const dp_geom* g, int32_t V, const double* angles,
 
 int dp_set_variant(int32_t op, int32_t variant)
 {
-    if (op != DP_OP_FWD && op != DP_OP_FWD_GRAD) return fail(DP_ERR_ARG, "op must be FWD or FWD_GRAD");
+    if (op != DP_OP_FWD && op != DP_OP_FWD_GRAD && op != DP_OP_FWD_SSD)
+        return fail(DP_ERR_ARG, "op must be FWD, FWD_GRAD or FWD_SSD");
     if (variant < -1 || variant >= kRdVariants) return fail(DP_ERR_ARG, "variant out of range");
     std::lock_guard<std::mutex> lk(g_var_mu);
     g_var_force[op] = variant;
@@ -334,11 +370,12 @@ int dp_autotune(int32_t op, const dp_geom* g, int32_t V, const double* angles, c
                 const float* vol, const float* grad_proj, void* out, void* ws, size_t ws_bytes,
                 void* stream, int32_t reps, int32_t* best, float* ms_per_variant)
 {
-    if (op != DP_OP_FWD && op != DP_OP_FWD_GRAD) return fail(DP_ERR_ARG, "op must be FWD or FWD_GRAD");
+    if (op != DP_OP_FWD && op != DP_OP_FWD_GRAD && op != DP_OP_FWD_SSD)
+        return fail(DP_ERR_ARG, "op must be FWD, FWD_GRAD or FWD_SSD");
     if (reps <= 0 || reps > 100) return fail(DP_ERR_ARG, "reps must be in [1, 100]");
     int rc = check_geom(g, V);
     if (rc) return rc;
-    if (!angles || !poses || !vol || !out || (op == DP_OP_FWD_GRAD && !grad_proj))
+    if (!angles || !poses || !vol || !out || (op != DP_OP_FWD && !grad_proj))
         return fail(DP_ERR_ARG, "NULL array argument");
     if ((rc = check_ws(g, V, op, ws, ws_bytes))) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -356,10 +393,15 @@ int dp_autotune(int32_t op, const dp_geom* g, int32_t V, const double* angles, c
         dp_set_variant(op, var);
         for (int r = 0; r <= reps && rc == DP_OK; ++r) {  // first call warms up
             if (r == 1) hipEventRecord(e0, st);
-            rc = op == DP_OP_FWD
-                     ? dp_project_fwd(g, V, angles, poses, vol, (float*)out, ws, ws_bytes, stream)
-                     : dp_project_fwd_grad_pose(g, V, angles, poses, vol, grad_proj, (double*)out,
-                                                ws, ws_bytes, stream);
+            if (op == DP_OP_FWD)
+                rc = dp_project_fwd(g, V, angles, poses, vol, (float*)out, ws, ws_bytes, stream);
+            else if (op == DP_OP_FWD_GRAD)
+                rc = dp_project_fwd_grad_pose(g, V, angles, poses, vol, grad_proj, (double*)out,
+                                              ws, ws_bytes, stream);
+            else  // out = proj; the pose gradient goes to the workspace's spare slot
+                rc = dp_project_fwd_ssd_grad_pose(
+                    g, V, angles, poses, vol, grad_proj, (float*)out, nullptr,
+                    (double*)((char*)ws + layout(*g, V, DP_OP_FWD_SSD).spare), ws, ws_bytes, stream);
         }
         hipEventRecord(e1, st);
         if (rc == DP_OK && hipEventSynchronize(e1) == hipSuccess) {

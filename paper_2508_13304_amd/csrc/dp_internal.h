@@ -91,6 +91,12 @@ struct RdBatch {
     RdBatchItem it[kRdMaxBatch];
 };
 void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
+void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
+                     const float* target, float* proj, float* partials, int variant,
+                     hipStream_t st);
+void launch_finalize_fwd_ssd(const GeoScalars& s, int V, const ViewGeo* views,
+                             const float* partials, int n_part, double* grad_pose, double* loss,
+                             hipStream_t st);
 void launch_rd_grad_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
 void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
                   float* vol, int weight_mode, hipStream_t st);

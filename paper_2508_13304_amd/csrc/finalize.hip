@@ -44,16 +44,21 @@ __device__ inline void matvec3(const double* R, const double* x, double* y)
     for (int r = 0; r < 3; ++r) y[r] = R[r * 3 + 0] * x[0] + R[r * 3 + 1] * x[1] + R[r * 3 + 2] * x[2];
 }
 
+// C = 9 gradient channels, or 10 with the per-view SSD of the fused kernel
+// in the last channel (written to loss[v]).
+template <int C>
 __global__ __launch_bounds__(kFinThreads) void finalize_fwd_kernel(GeoScalars s,
                                                                    const ViewGeo* __restrict__ views,
                                                                    const float* __restrict__ partials,
                                                                    int n_part,
-                                                                   double* __restrict__ grad_pose)
+                                                                   double* __restrict__ grad_pose,
+                                                                   double* __restrict__ loss)
 {
     const int v = blockIdx.x;
-    double S[kRdChannels];
-    fixed_order_sum<kRdChannels>(partials + (size_t)v * n_part * kRdChannels, n_part, S);
+    double S[C];
+    fixed_order_sum<C>(partials + (size_t)v * n_part * C, n_part, S);
     if (threadIdx.x != 0) return;
+    if (C > kRdChannels && loss) loss[v] = S[C - 1];
     const ViewGeo& g = views[v];
     const double hx = s.vx, hy = s.vy, hz = s.vz;
     const double b[3] = {S[0] / hx, S[1] / hy, S[2] / hz};
@@ -107,7 +112,18 @@ void launch_finalize_fwd(const GeoScalars& s, int V, const ViewGeo* views, const
                          int n_part, double* grad_pose, hipStream_t st)
 {
     prof_begin(DP_K_FINALIZE, st);
-    finalize_fwd_kernel<<<V, kFinThreads, 0, st>>>(s, views, partials, n_part, grad_pose);
+    finalize_fwd_kernel<kRdChannels><<<V, kFinThreads, 0, st>>>(s, views, partials, n_part, grad_pose,
+                                                               nullptr);
+    prof_end(DP_K_FINALIZE, st);
+}
+
+void launch_finalize_fwd_ssd(const GeoScalars& s, int V, const ViewGeo* views,
+                             const float* partials, int n_part, double* grad_pose, double* loss,
+                             hipStream_t st)
+{
+    prof_begin(DP_K_FINALIZE, st);
+    finalize_fwd_kernel<kRdChannels + 1><<<V, kFinThreads, 0, st>>>(s, views, partials, n_part,
+                                                                   grad_pose, loss);
     prof_end(DP_K_FINALIZE, st);
 }
 

@@ -465,25 +465,35 @@ struct GradAcc {
     }
 };
 
-template <int MCH, int CAP>
+template <int MCH, int CAP, bool FUSED>
 __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
                                     const float* __restrict__ vol3,
-                                    const float* __restrict__ grad_proj,
+                                    const float* __restrict__ gin,
+                                    float* __restrict__ proj_out,
                                     float* __restrict__ partials, int v, int tile, int tiles,
                                     float* lds, TileShared& sh)
 {
+    // FUSED: vol3 holds four planes (mu, Gx, Gy, Gz), gin is the target image
+    // y, and the ray also integrates mu: l is written to proj_out and the
+    // SSD weight w = 2 (l - y) is applied to the gradient sums at the end.
+    // Otherwise vol3 holds (Gx, Gy, Gz) and gin is dL/dl.
+    constexpr int C = FUSED ? 4 : 3;
     const size_t plane = (size_t)(s.nx + 2 * kPadV) * (s.ny + 2 * kPadV) * (s.nz + 2 * kPadV);
-    const float* __restrict__ gx = vol3;
-    const float* __restrict__ gy = vol3 + plane;
-    const float* __restrict__ gz = vol3 + 2 * plane;
+    const float* __restrict__ mu = vol3;
+    const float* __restrict__ gx = vol3 + (FUSED ? plane : 0);
+    const float* __restrict__ gy = gx + plane;
+    const float* __restrict__ gz = gy + plane;
     int a, b, a0, b0;
     rd_pixel(s, tile, a, b, a0, b0);
     const bool inside = a < s.nu && b < s.nv;
-    const float w = inside ? grad_proj[((size_t)v * s.nv + b) * s.nu + a] : 0.0f;
+    const size_t pix = ((size_t)v * s.nv + min(b, s.nv - 1)) * s.nu + min(a, s.nu - 1);
+    const float gpix = inside ? gin[pix] : 0.0f;
     const ViewGeo& g = views[v];
     const RayState r = ray_setup(s, g, min(a, s.nu - 1), min(b, s.nv - 1));
-    // rays with dL/dl = 0 contribute nothing: they only help load the boxes
-    const bool active = inside && w != 0.0f;
+    // unfused: rays with dL/dl = 0 contribute nothing, they only help load
+    // the boxes; fused: w is known only after the march
+    const bool active = FUSED ? inside : (inside && gpix != 0.0f);
+    float lsum = 0.0f;
     int Kmin, Kmax;
     float margin;
     tile_setup(s, r, inside, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
@@ -502,33 +512,50 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             const int Ke = min(K + M - 1, Kmax);
             const Box bx = planned_box(sh, ci);
             __syncthreads();
-            {
+            if (FUSED) {
+                const float* src[4] = {mu, gx, gy, gz};
+                load_box<4, 3>(bx, src, lds, NX, NXY);
+            } else {
                 const float* src[3] = {gx, gy, gz};
                 load_box<3, 4>(bx, src, lds, NX, NXY);
             }
             __syncthreads();
             const int kb = max(K, klo), ke = min(Ke, khi);
             const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
-            const int BX3 = 3 * bx.bx, BXY3 = 3 * bx.bx * bx.by;
+            const int BXC = C * bx.bx, BXYC = C * bx.bx * bx.by;
             const float fbx = (float)bx.bx, fby = (float)bx.by;
-            const int imax = 3 * CAP - 1 - (BXY3 + BX3 + 5);
+            // largest base voxel whose 2x2x2 corners stay inside the box
+            const int vmax = CAP - 2 - (bx.bx * bx.by + bx.bx);
             GradAcc Gc;  // base-corner frame: local box indices
             for (float j = 0.0f; j <= c.n; j += 1.0f) {
                 const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
                 const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-                const int idx = min(max(3 * (int)fmaf(fmaf(fz, fby, fy), fbx, fx), 0), imax);
+                const int idx = C * min(max((int)fmaf(fmaf(fz, fby, fy), fbx, fx), 0), vmax);
                 const float* p = lds + idx;
                 float3 q[2][2][2];
+                float m[2][2][2];
 #pragma unroll
                 for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
                     for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                         for (int dx = 0; dx < 2; ++dx) {
-                            const float* o = p + dz * BXY3 + dy * BX3 + 3 * dx;
-                            q[dz][dy][dx] = make_float3(o[0], o[1], o[2]);
+                            const float* o = p + dz * BXYC + dy * BXC + C * dx;
+                            if (FUSED) {
+                                const float4 t = *reinterpret_cast<const float4*>(o);
+                                m[dz][dy][dx] = t.x;
+                                q[dz][dy][dx] = make_float3(t.y, t.z, t.w);
+                            } else {
+                                q[dz][dy][dx] = make_float3(o[0], o[1], o[2]);
+                            }
                         }
-                Gc.add(q, X - fx, Y - fy, Z - fz, fx, fy, fz);
+                const float wx = X - fx, wy = Y - fy, wz = Z - fz;
+                if (FUSED) {
+                    const float c00 = lerpf(m[0][0][0], m[0][0][1], wx), c10 = lerpf(m[0][1][0], m[0][1][1], wx);
+                    const float c01 = lerpf(m[1][0][0], m[1][0][1], wx), c11 = lerpf(m[1][1][0], m[1][1][1], wx);
+                    lsum += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
+                }
+                Gc.add(q, wx, wy, wz, fx, fy, fz);
             }
             G.merge(Gc, ccx - bx.ox, ccy - bx.oy, ccz - bx.oz);
         }
@@ -551,17 +578,36 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                         const size_t o = (size_t)idx + dz * NXY + dy * NX + dx;
                         q[dz][dy][dx] = make_float3(gx[o], gy[o], gz[o]);
                     }
-            G.add(q, X - fx, Y - fy, Z - fz, fx - ccx, fy - ccy, fz - ccz);
+            const float wx = X - fx, wy = Y - fy, wz = Z - fz;
+            if (FUSED) {
+                const float* pm = mu + idx;
+                const float c00 = lerpf(pm[0], pm[1], wx), c10 = lerpf(pm[NX], pm[NX + 1], wx);
+                const float c01 = lerpf(pm[NXY], pm[NXY + 1], wx);
+                const float c11 = lerpf(pm[NXY + NX], pm[NXY + NX + 1], wx);
+                lsum += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
+            }
+            G.add(q, wx, wy, wz, fx - ccx, fy - ccy, fz - ccz);
         }
     }
-    float acc[kRdChannels] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    constexpr int NC = FUSED ? kRdChannels + 1 : kRdChannels;
+    float acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0f;
+    float w = gpix;
+    if (FUSED && inside) {
+        const float l = lsum * step;
+        proj_out[pix] = l;
+        const float res = l - gpix;
+        w = 2.0f * res;
+        acc[kRdChannels] = res * res;  // SSD of this ray (last channel)
+    }
     if (active) {
         const float ws = w * step;
         acc[0] = G.Bx * ws; acc[1] = G.By * ws; acc[2] = G.Bz * ws;
         acc[3] = G.Txy * ws; acc[4] = G.Txz * ws; acc[5] = G.Tyx * ws;
         acc[6] = G.Tyz * ws; acc[7] = G.Tzx * ws; acc[8] = G.Tzy * ws;
     }
-    block_reduce_store<kRdChannels>(acc, partials + ((size_t)v * tiles + tile) * kRdChannels);
+    block_reduce_store<NC>(acc, partials + ((size_t)v * tiles + tile) * NC);
 }
 
 template <int MCH, int CAP>
@@ -584,8 +630,23 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
 {
     __shared__ float lds[3 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP>(s, views, vol3, grad_proj, partials, blockIdx.y, blockIdx.x, gridDim.x,
-                           lds, sh);
+    rd_grad_tile<MCH, CAP, false>(s, views, vol3, grad_proj, nullptr, partials, blockIdx.y,
+                                  blockIdx.x, gridDim.x, lds, sh);
+}
+
+// Forward projection, SSD loss and its pose gradient in one march.
+template <int MCH, int CAP>
+__global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
+                                                              const ViewGeo* __restrict__ views,
+                                                              const float* __restrict__ vol4,
+                                                              const float* __restrict__ target,
+                                                              float* __restrict__ proj,
+                                                              float* __restrict__ partials)
+{
+    __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
+    __shared__ TileShared sh;
+    rd_grad_tile<MCH, CAP, true>(s, views, vol4, target, proj, partials, blockIdx.y, blockIdx.x,
+                                 gridDim.x, lds, sh);
 }
 
 // Uneven batch: one launch covers every (problem, view, tile) of up to
@@ -620,8 +681,8 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP>(it.s, it.views, it.vol, it.gin, it.out, local / it.tiles,
-                           local % it.tiles, it.tiles, lds, sh);
+    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.gin, nullptr, it.out,
+                                  local / it.tiles, local % it.tiles, it.tiles, lds, sh);
 }
 
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
@@ -648,6 +709,20 @@ void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const floa
     default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, vol3, grad_proj, partials); break;
     }
     prof_end(DP_K_RD_GRAD, st);
+}
+
+void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
+                     const float* target, float* proj, float* partials, int variant,
+                     hipStream_t st)
+{
+    dim3 grid(rd_tiles(s), V);
+    prof_begin(DP_K_RD_FUSED, st);
+    switch (variant) {
+    case 0: rd_fused_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
+    case 2: rd_fused_kernel<32, 4096><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
+    default: rd_fused_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
+    }
+    prof_end(DP_K_RD_FUSED, st);
 }
 
 void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)

@@ -66,9 +66,11 @@ def prefilter(geom, proj):
     return fdk_filter(geom, proj, math.pi / proj.shape[0])
 
 
-def estimate_motion(geom, angles, q, iters=40, nodes=12, lr_t=0.3, lr_r_deg=0.2,
-                    loss=sharpness_loss, init=None, betas=(0.9, 0.999), callback=None) -> MocoResult:
-    """Minimise loss(reconstruct(theta)) over theta = B c with Adam.
+def estimate_motion(geom, angles, q, iters=80, nodes=0, lr_t=0.1, lr_r_deg=0.07,
+                    loss=gradient_entropy_loss, init=None, betas=(0.9, 0.999), decay=1.0,
+                    callback=None) -> MocoResult:
+    """Minimise loss(reconstruct(theta)) over theta = B c with Adam (step
+    sizes lr_t mm and lr_r_deg deg, multiplied by decay**iteration).
 
     geom: reconstruction grid + detector; angles [V] f64; q [V][nv][nu] f32
     pre-filtered projections; loss(vol) -> (0-d loss tensor, dL/dvol f32).
@@ -95,7 +97,7 @@ def estimate_motion(geom, angles, q, iters=40, nodes=12, lr_t=0.3, lr_r_deg=0.2,
         k = it + 1
         m.mul_(betas[0]).add_(gc, alpha=1 - betas[0])
         v2.mul_(betas[1]).addcmul_(gc, gc, value=1 - betas[1])
-        c -= lr * (m / (1 - betas[0] ** k)) / ((v2 / (1 - betas[1] ** k)).sqrt() + 1e-300)
+        c -= (decay ** it) * lr * (m / (1 - betas[0] ** k)) / ((v2 / (1 - betas[1] ** k)).sqrt() + 1e-300)
         losses.append(float(L))
         if callback:
             callback(it, float(L), base + B @ c)
@@ -110,3 +112,18 @@ def demeaned_rms_error(est, truth):
     d = d - d.mean(dim=0, keepdim=True)
     return (float(d[:, :3].pow(2).mean().sqrt()),
             math.degrees(float(d[:, 3:].pow(2).mean().sqrt())))
+
+
+def view_frame_errors(est, truth, angles):
+    """RMS over views of the demeaned translation error resolved in each
+    view's detector frame: along e_u (detector row), e_v (axial) and e_w
+    (depth, towards the detector), in mm.  Depth translations barely change
+    a view's contribution to the reconstruction."""
+    d = est - truth
+    d = d - d.mean(dim=0, keepdim=True)
+    cb, sb = torch.cos(angles), torch.sin(angles)
+    eu = torch.stack([-sb, cb, torch.zeros_like(cb)], dim=1)
+    ew = torch.stack([-cb, -sb, torch.zeros_like(cb)], dim=1)
+    t = d[:, :3]
+    return (float((t * eu).sum(1).pow(2).mean().sqrt()), float(t[:, 2].pow(2).mean().sqrt()),
+            float((t * ew).sum(1).pow(2).mean().sqrt()))

@@ -124,27 +124,41 @@ def register(geom, vol, angles, targets, init_poses, loss="ssd", iters=300, lr_t
 
 
 def autotune_registration(geom, vol, angles, poses, targets, reps=3):
-    """Autotune the forward and pose-gradient kernels for every view-count
-    octave a batched registration of len(poses) problems passes through
-    while it drops converged registrations (the variant cache is keyed by
-    octave).  Returns {views: (fwd variant, grad variant)}."""
-    from . import OP_FWD, OP_FWD_GRAD, autotune
+    """Autotune the registration kernels (the single-pass SSD kernel, and the
+    forward and pose-gradient kernels used by other losses) for every
+    view-count octave a batched registration of len(poses) problems passes
+    through while it drops converged registrations (the variant cache is
+    keyed by octave).  Returns {views: (ssd, fwd, grad variants)}."""
+    from . import OP_FWD, OP_FWD_GRAD, OP_FWD_SSD, autotune
     B = poses.shape[0]
     chosen = {}
     v = B
     while v >= 1:
         proj = torch.empty((v, geom.nv, geom.nu), dtype=torch.float32, device=vol.device)
         gp = torch.empty((v, 6), dtype=torch.float64, device=vol.device)
-        a, p = angles[:v].contiguous(), poses[:v].contiguous()
+        a, p, y = angles[:v].contiguous(), poses[:v].contiguous(), targets[:v].contiguous()
+        bs, _ = autotune(OP_FWD_SSD, geom, a, p, vol, proj, grad_proj=y, reps=reps)
         bf, _ = autotune(OP_FWD, geom, a, p, vol, proj, reps=reps)
-        bg, _ = autotune(OP_FWD_GRAD, geom, a, p, vol, gp, grad_proj=targets[:v].contiguous(),
-                         reps=reps)
-        chosen[v] = (bf, bg)
+        bg, _ = autotune(OP_FWD_GRAD, geom, a, p, vol, gp, grad_proj=y, reps=reps)
+        chosen[v] = (bs, bf, bg)
         v //= 2
     return chosen
 
 
+def _fused_ssd(geom, vol):
+    """Loss and pose gradient of the SSD from the single-pass kernel."""
+    from . import project_fwd_ssd_grad_pose
+
+    def fn(poses, angles, targets):
+        _, L, g = project_fwd_ssd_grad_pose(geom, angles.contiguous(), poses.contiguous(), vol,
+                                            targets.contiguous())
+        return L, g
+    return fn
+
+
 def _loss_and_grad(proj_fn, poses, angles, targets, loss):
+    if callable(loss):
+        return loss(poses.detach().to(torch.float64).contiguous(), angles, targets)
     p = poses.detach().clone().requires_grad_(True)
     l = proj_fn(p, angles)
     L = loss_per_view(l, targets, loss)
@@ -167,9 +181,12 @@ def register_bfgs(geom, vol, angles, targets, init_poses, loss="ssd", iters=150,
     scale *= shrink.  A registration stops once an accepted step is below
     tol in every scaled parameter, or when scale falls below min_scale
     (no further decrease resolvable in FP32).  The first step has length
-    first_step along the negative gradient.
+    first_step along the negative gradient.  With the default projector and
+    the SSD loss, loss and gradient come from the single-pass kernel.
     """
     proj_fn = project or (lambda p, a: ProjectFwd.apply(p, vol, geom, a))
+    if project is None and loss == "ssd":
+        loss = _fused_ssd(geom, vol)
     B = init_poses.shape[0]
     dev = init_poses.device
     f64 = torch.float64

@@ -1,0 +1,103 @@
+"""GPU parity of the fused forward + SSD + pose-gradient entry
+(dp_project_fwd_ssd_grad_pose) against the FP64 oracle: projections
+max|gpu - ref| <= 1e-5 max|ref|; per-view SSD within 1e-5 relative; pose
+gradients per view and triplet within 1e-4, the oracle's gradient taken
+with dL/dl = 2 (l_ref - y).  Targets are rendered at other poses, so the
+residuals are of the order of l itself."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from synth import Geom
+from test_gpu_parity import check_grads, check_values, f32, f64, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _fused_case(dp, oracle, g, vol, angles, poses, y, name, variant=None):
+    say(f"fused case {name}: vol {vol.shape} det {g.nv}x{g.nu} V={len(angles)}")
+    if variant is not None:
+        dp.set_variant(dp.OP_FWD_SSD, variant)
+    try:
+        l, loss, gp = dp.project_fwd_ssd_grad_pose(g, f64(angles), f64(poses), f32(vol), f32(y))
+    finally:
+        if variant is not None:
+            dp.set_variant(dp.OP_FWD_SSD, -1)
+    l_ref = oracle.project_fwd(g, angles, poses, vol)
+    check_values(f"{name} fused proj", l.cpu().numpy(), l_ref)
+    r = l_ref - y
+    loss_ref = (r * r).reshape(len(angles), -1).sum(1)
+    rel = np.abs(loss.cpu().numpy() - loss_ref) / np.maximum(loss_ref, 1e-30)
+    say(f"{name} fused loss: max rel err {rel.max():.3e}")
+    assert rel.max() <= 1e-5
+    g_ref = oracle.project_fwd_grad_pose(g, angles, poses, vol, (2.0 * r).astype(np.float32))
+    check_grads(f"{name} fused grad", gp.cpu().numpy(), g_ref)
+
+
+def test_fused_config1(dp, oracle):
+    c = synth.config1_inputs()
+    g = c["geom"]
+    y = oracle.project_fwd(g, c["angles"], c["target_pose"], c["vol"]).astype(np.float32)
+    _fused_case(dp, oracle, g, c["vol"], c["angles"], c["poses"], y, "config1")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_fused_ragged_multiview_every_variant(dp, oracle, variant):
+    rng = synth.rng_for(210)
+    g = Geom(37, 29, 23, 1.3, 1.1, 1.7, 45, 27, 1.9, 2.3, off_u=1.25, off_v=-0.75)
+    vol = rng.uniform(0, 0.05, g.vol_shape).astype(np.float32)
+    V = 5
+    angles = rng.uniform(0, 2 * math.pi, V)
+    poses = synth.random_poses(V, 8.0, 15.0, rng)
+    y = oracle.project_fwd(g, angles, synth.random_poses(V, 8.0, 15.0, rng), vol).astype(np.float32)
+    _fused_case(dp, oracle, g, vol, angles, poses, y, f"ragged-v{variant}", variant)
+
+
+def test_fused_edges_and_misses(dp, oracle):
+    """Content on the faces, large rotations, and a view that misses the
+    volume entirely (l = 0, loss = sum y^2, zero gradient)."""
+    rng = synth.rng_for(211)
+    g = Geom(20, 20, 20, 2.0, 2.0, 2.0, 40, 36, 2.5, 2.5)
+    vol = rng.uniform(0.0, 1.0, g.vol_shape).astype(np.float32)
+    angles = np.array([0.0, 0.5 * math.pi, 1.0])
+    poses = np.array([[0, 0, 0, 0.5 * math.pi, 0, 0],
+                      [25.0, -20.0, 10.0, 0.7, -1.2, 2.5],
+                      [0.0, 400.0, 0.0, 0, 0, 0]])
+    y = rng.uniform(0.0, 5.0, (3, 36, 40)).astype(np.float32)
+    _fused_case(dp, oracle, g, vol, angles, poses, y, "edges")
+    l, loss, gp = dp.project_fwd_ssd_grad_pose(g, f64(angles), f64(poses), f32(vol), f32(y))
+    assert torch.all(l[2] == 0) and torch.all(gp[2] == 0)
+
+
+def test_fused_tiny(dp, oracle):
+    g = Geom(1, 1, 1, 3.0, 3.0, 3.0, 1, 1, 2.0, 2.0)
+    vol = np.array([[[0.7]]], np.float32)
+    _fused_case(dp, oracle, g, vol, np.array([0.2]), np.array([[0.3, -0.2, 0.1, 0.01, 0.02, -0.03]]),
+                np.array([[[0.5]]], np.float32), "1x1x1")
+
+
+def test_fused_full_size_two_views(dp, oracle):
+    """The registration-scale volume and detector (256^3 at 0.8 mm, 512x512 at
+    0.6 mm), two of the candidate poses, in full."""
+    c = synth.config2_inputs()
+    g = c["geom"]
+    angles, poses = c["angles"][:2], c["poses"][:2]
+    y = np.repeat(oracle.project_fwd(g, [0.0], c["target_pose"], c["vol"]), 2, axis=0).astype(np.float32)
+    _fused_case(dp, oracle, g, c["vol"], angles, poses, y, "full-size")
+
+
+def test_fused_matches_two_call_path(dp, oracle):
+    """Same outputs as project_fwd followed by project_fwd_grad_pose with
+    w = 2 (l - y), up to FP32 summation grouping."""
+    c = synth.config1_inputs()
+    g = c["geom"]
+    y = f32(oracle.project_fwd(g, c["angles"], c["target_pose"], c["vol"]))
+    a, p, v = f64(c["angles"]), f64(c["poses"]), f32(c["vol"])
+    l1, loss, g1 = dp.project_fwd_ssd_grad_pose(g, a, p, v, y)
+    l2 = dp.project_fwd(g, a, p, v)
+    g2 = dp.project_fwd_grad_pose(g, a, p, v, 2.0 * (l2 - y))
+    assert torch.allclose(l1, l2, rtol=0, atol=1e-6 * float(l2.abs().max()))
+    check_grads("fused vs two-call", g1.cpu().numpy(), g2.cpu().numpy())
