@@ -22,7 +22,11 @@ def _net():
 
 def test_proposal_is_closer_than_the_identity(dp):
     """The network's proposal is nearer the truth than the plain method's
-    starting point, in every pose component (median over 64 cases)."""
+    starting point in the components one view pair determines: the in-plane
+    translations, the depth translation (through magnification) and the
+    rotation about the central ray (median over 64 cases, at least 2x
+    closer).  The two out-of-plane rotations are not determined by one
+    reference DRR of an unknown phantom and are left to the refinement."""
     import synth
     pr, net = _net()
     geom = synth.geom_c5()
@@ -42,7 +46,8 @@ def test_proposal_is_closer_than_the_identity(dp):
     e = torch.cat(errs).median(dim=0).values
     o = torch.cat(offs).median(dim=0).values
     print("proposal median |err|", e.cpu().numpy(), "identity", o.cpu().numpy(), flush=True)
-    assert bool((e < 0.6 * o).all())
+    observable = [0, 1, 2, 3]  # tx (depth at gantry angle 0), ty, tz, gamma_x (about the ray)
+    assert bool((e[observable] < 0.5 * o[observable]).all())
 
 
 def test_learned_registration_beats_plain(dp):
