@@ -193,10 +193,10 @@ def run_forward(args, dp, torch):
         if per2.get(k):
             other[k] = {"ms": per2[k], "flops_per_sample": FLOPS_PER_SAMPLE[k],
                         "tflops": round(FLOPS_PER_SAMPLE[k] * n_samples / (per2[k] * 1e-3) / 1e12, 2),
-                        "traffic": _traffic(k + "_config2", src_hash)}
+                        "traffic": _traffic(k + "_registration_scale", src_hash)}
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                "traffic": _traffic(dominant + "_config2", src_hash),
+                "traffic": _traffic(dominant + "_registration_scale", src_hash),
                 "kernel": dominant, "kernel_ms": dom_ms, "flops_per_sample": flops,
                 "source_hash": src_hash, "other": other}
     return dict(geom=g, V=V, n_samples=n_samples, ms_step=ms_step, per_kernel=per_kernel,
