@@ -169,6 +169,23 @@ def project_fwd_grad_pose(geom, angles, poses, vol, grad_proj) -> np.ndarray:
     return out
 
 
+def project_fwd_jacobian(geom, angles, poses, vol) -> np.ndarray:
+    """Per-ray pose Jacobian [V][nv][nu][6] of the forward projection (the
+    gradient's per-ray sums before weighting by dL/dl)."""
+    angles, poses, V = _views(angles, poses)
+    out = np.zeros((V, geom.nv, geom.nu, 6))
+    lib().dpref_project_fwd_jacobian(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(vol)),
+                                     _p(out))
+    return out
+
+
+def gauss_newton_ssd(geom, angles, poses, vol) -> np.ndarray:
+    """Gauss-Newton matrix of the per-view SSD, 2 sum_rays J J^T, [V][6][6]."""
+    J = project_fwd_jacobian(geom, angles, poses, vol)
+    J = J.reshape(J.shape[0], -1, 6)
+    return 2.0 * np.einsum("vpi,vpj->vij", J, J)
+
+
 def backproject(geom, angles, poses, proj, weight_mode=W_NONE) -> np.ndarray:
     angles, poses, V = _views(angles, poses)
     out = np.zeros((geom.nz, geom.ny, geom.nx))

@@ -496,6 +496,49 @@ void dpref_project_fwd_grad_pose(const dpref_geom* g, int V, const double* angle
     free(dLdM);
 }
 
+/* Per-ray Jacobian J[v][b][a][6] = dl_ab/dtheta_v: the same sums as the
+ * gradient with dL/dl = 1 on one ray, contracted per ray (so that
+ * sum_ab w_ab J_ab = dL/dtheta for any w, and 2 sum_ab J_ab J_ab^T is the
+ * Gauss-Newton matrix of the SSD). */
+void dpref_project_fwd_jacobian(const dpref_geom* g, int V, const double* angles,
+                                const double* poses, const double* vol, double* J)
+{
+    double* gr = volume_gradient(g, vol);
+    if (!gr) return;
+    for (int v = 0; v < V; ++v) {
+        view_pose vp = make_view(g, angles, poses, v);
+#pragma omp parallel for schedule(dynamic, 2)
+        for (int b = 0; b < g->nv; ++b)
+            for (int a = 0; a < g->nu; ++a) {
+                double u[3], X[3], G[12], acc[12] = {0};
+                long k_lo, k_hi;
+                ray_direction(g, &vp.f, a, b, u);
+                sample_range(g, &vp, u, &k_lo, &k_hi);
+                for (long k = k_lo; k <= k_hi; ++k) {
+                    sample_index(g, &vp, u, k, X);
+                    if (!in_support(g, X)) continue;
+                    double fx = floor(X[0]), fy = floor(X[1]), fz = floor(X[2]);
+                    double wx[2] = {1.0 - (X[0] - fx), X[0] - fx};
+                    double wy[2] = {1.0 - (X[1] - fy), X[1] - fy};
+                    double wz[2] = {1.0 - (X[2] - fz), X[2] - fz};
+                    for (int dz = 0; dz < 2; ++dz)
+                        for (int dy = 0; dy < 2; ++dy)
+                            for (int dx = 0; dx < 2; ++dx) {
+                                long i = (long)fx + dx, j = (long)fy + dy, kk = (long)fz + dz;
+                                if (i < 0 || j < 0 || kk < 0 || i >= g->nx || j >= g->ny ||
+                                    kk >= g->nz)
+                                    continue;
+                                double a_ij = g->step * wx[dx] * wy[dy] * wz[dz];
+                                forward_G(g, &vp, gr, i, j, kk, G);
+                                for (int e = 0; e < 12; ++e) acc[e] += a_ij * G[e];
+                            }
+                }
+                dpref_contract_pose(poses + 6 * v, acc, J + (((long)v * g->nv + b) * g->nu + a) * 6);
+            }
+    }
+    free(gr);
+}
+
 /* Materialised route: build the 12 channel volumes G_f[m][n] for the view,
  * forward-project each with the same projector, and take the dL/dl-weighted
  * sum over the detector (the paper's "12x memory" alternative). */

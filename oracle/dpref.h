@@ -57,6 +57,8 @@ void dpref_project_fwd_T(const dpref_geom* g, int V, const double* angles,
 void dpref_project_fwd_grad_M(const dpref_geom* g, int V, const double* angles,
                               const double* poses, const double* vol,
                               const double* grad_proj, double* dLdM);
+void dpref_project_fwd_jacobian(const dpref_geom* g, int V, const double* angles,
+                                const double* poses, const double* vol, double* J);
 void dpref_project_fwd_grad_pose(const dpref_geom* g, int V, const double* angles,
                                  const double* poses, const double* vol,
                                  const double* grad_proj, double* grad_pose);
