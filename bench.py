@@ -254,9 +254,9 @@ def run_backproject(args, dp, torch):
 def run_registration(args, dp, torch, fw):
     """Registrations/s at 0.1 mm / 0.1 deg on the registration-scale workload:
     64 single-view targets rendered at the 64 candidate poses, each registered
-    from the identity in one batched launch pair per iteration; BFGS with the
-    default kernel variants, BFGS with the autotuned variants, and the Adam
-    driver at the same batch."""
+    from the identity in one batched launch per iteration; Levenberg-Marquardt
+    (analytic gradient + Gauss-Newton matrix) and BFGS with the default and
+    with the autotuned kernel variants, and the Adam driver at the same batch."""
     from paper_2508_13304_amd import registration as reg
     dev = torch.device("cuda:0")
     c = fw["inputs"]
@@ -283,9 +283,12 @@ def run_registration(args, dp, torch, fw):
         log(f"[bench] registration {name}: {out[name]}")
 
     reg.register_bfgs(g, vol, angles[:4], targets[:4], init[:4], iters=3)  # warm-up
+    reg.register_lm(g, vol, angles[:4], targets[:4], init[:4], iters=3)
+    record("lm_default_variants", reg.register_lm(g, vol, angles, targets, init))
     record("bfgs_default_variants", reg.register_bfgs(g, vol, angles, targets, init))
     out["autotuned_variants"] = {str(k): v for k, v in
                                  reg.autotune_registration(g, vol, angles, truth, targets).items()}
+    record("lm_autotuned", reg.register_lm(g, vol, angles, targets, init))
     record("bfgs_autotuned", reg.register_bfgs(g, vol, angles, targets, init))
     record("adam", reg.register(g, vol, angles, targets, init, iters=300, lr_t=3.0, lr_r_deg=2.0,
                                 decay=0.99))

@@ -117,6 +117,19 @@ int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t n_views, const double
                                  float* proj, double* loss, double* grad_pose,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/* As dp_project_fwd_ssd_grad_pose, plus the Gauss-Newton matrix of each
+ * view's SSD: with J_p = dl_p/dtheta the per-ray pose Jacobian (the sums of
+ * Eqs. final_forward / dis_forward for a unit weight on one ray),
+ *   H_v = 2 sum over the view's rays of J_p J_p^T,
+ * returned as hess [V][21] f64, the upper triangle row by row
+ * ((0,0), (0,1), ..., (0,5), (1,1), ..., (5,5)), parameter order and units
+ * as grad_pose.  Same workspace (DP_OP_FWD_SSD) and samples; the extra cost
+ * is per ray, not per sample. */
+int dp_project_fwd_ssd_gauss_newton(const dp_geom* g, int32_t n_views, const double* angles,
+                                    const double* poses, const float* vol, const float* target,
+                                    float* proj, double* loss, double* grad_pose, double* hess,
+                                    void* ws, size_t ws_bytes, void* stream);
+
 /* Voxel-driven back-projection (Eq. back), weight_mode DP_W_NONE | DP_W_FDK.
  *   proj [V][nv][nu] f32 (already filtered by the caller if FDK is meant),
  *   vol [nz][ny][nx] f32 (overwritten).  No angular scale is applied. */

@@ -28,7 +28,8 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_backproject_grad_pose", "dp_last_error", "dp_version", "dp_profile_enable",
            "dp_profile_collect", "dp_profile_read", "dp_batch_workspace_bytes",
            "dp_project_fwd_batch", "dp_project_fwd_grad_pose_batch", "dp_autotune",
-           "dp_set_variant", "dp_get_variant", "dp_project_fwd_ssd_grad_pose", "dp_fdk_filter", "dp_sharpness",
+           "dp_set_variant", "dp_get_variant", "dp_project_fwd_ssd_grad_pose",
+           "dp_project_fwd_ssd_gauss_newton", "dp_fdk_filter", "dp_sharpness",
            "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
            "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16")
@@ -73,6 +74,8 @@ def load(path: str | None = None):
     lib.dp_project_fwd_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dp_project_fwd_ssd_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dp_project_fwd_ssd_grad_pose.restype = C.c_int
+    lib.dp_project_fwd_ssd_gauss_newton.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.dp_project_fwd_ssd_gauss_newton.restype = C.c_int
     lib.dp_backproject.argtypes = [g, i32, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.dp_backproject_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, i32, vp, sz, vp]
     for f in ("dp_project_fwd", "dp_project_fwd_grad_pose", "dp_backproject",
@@ -223,6 +226,45 @@ def project_fwd_ssd_grad_pose(geom, angles, poses, vol, target, proj=None, loss=
         C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
     _check(rc, "dp_project_fwd_ssd_grad_pose")
     return proj, loss, grad
+
+
+def project_fwd_ssd_gauss_newton(geom, angles, poses, vol, target, proj=None, loss=None,
+                                 grad=None, hess=None, ws=None, stream=None):
+    """One pass: DRRs, per-view SSD, its pose gradient and the Gauss-Newton
+    matrix 2 sum J J^T as a symmetric [V][6][6] f64 tensor."""
+    import torch
+    V = _views(angles, poses)
+    dev = vol.device
+    if proj is None:
+        proj = torch.empty((V, geom.nv, geom.nu), dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(V, dtype=torch.float64, device=dev)
+    if grad is None:
+        grad = torch.empty((V, 6), dtype=torch.float64, device=dev)
+    if hess is None:
+        hess = torch.empty((V, 21), dtype=torch.float64, device=dev)
+    ws = _workspace(geom, V, OP_FWD_SSD, ws, dev)
+    rc = load().dp_project_fwd_ssd_gauss_newton(
+        C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
+        _dev(poses, torch.float64, "poses"),
+        _dev(vol, torch.float32, "vol", (geom.nz, geom.ny, geom.nx)),
+        _dev(target, torch.float32, "target", (V, geom.nv, geom.nu)),
+        _dev(proj, torch.float32, "proj", (V, geom.nv, geom.nu)),
+        _dev(loss, torch.float64, "loss", (V,)), _dev(grad, torch.float64, "grad", (V, 6)),
+        _dev(hess, torch.float64, "hess", (V, 21)),
+        C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "dp_project_fwd_ssd_gauss_newton")
+    return proj, loss, grad, unpack_sym6(hess)
+
+
+def unpack_sym6(h21):
+    """[..., 21] upper triangle (row by row) -> symmetric [..., 6, 6]."""
+    import torch
+    iu = torch.triu_indices(6, 6, device=h21.device)
+    H = torch.zeros(h21.shape[:-1] + (6, 6), dtype=h21.dtype, device=h21.device)
+    H[..., iu[0], iu[1]] = h21
+    H[..., iu[1], iu[0]] = h21
+    return H
 
 
 def backproject(geom, angles, poses, proj, weight_mode=W_NONE, out=None, ws=None, stream=None):

@@ -71,7 +71,7 @@ Layout layout(const dp_geom& g, int V, int op)
         off = align_up(off + 4 * padded_volume_elems(g) * sizeof(float));
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
-        off = align_up(off + (size_t)V * L.n_part * (kRdChannels + 1) * sizeof(float));
+        off = align_up(off + (size_t)V * L.n_part * kRdChannelsGN * sizeof(float));
         L.spare = off;
         off = align_up(off + (size_t)V * 6 * sizeof(double));
         break;
@@ -270,10 +270,10 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     return check_launch("dp_project_fwd_grad_pose");
 }
 
-int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
-                                 const double* poses, const float* vol, const float* target,
-                                 float* proj, double* loss, double* grad_pose, void* ws,
-                                 size_t ws_bytes, void* stream)
+static int fwd_ssd(const dp_geom* g, int32_t V, const double* angles, const double* poses,
+                   const float* vol, const float* target, float* proj, double* loss,
+                   double* grad_pose, double* hess, void* ws, size_t ws_bytes, void* stream,
+                   const char* name)
 {
     int rc = check_geom(g, V);
     if (rc) return rc;
@@ -291,9 +291,29 @@ int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t V, const double* angl
     launch_view_setup(s, V, angles, poses, views, st);
     launch_vol_pad(s, vol, vol4, st);
     launch_vol_grad(s, vol, vol4 + padded_volume_elems(*g), st);
-    launch_rd_fused(s, V, views, vol4, target, proj, part, variant_for(DP_OP_FWD_SSD, *g, V), st);
-    launch_finalize_fwd_ssd(s, V, views, part, (int)L.n_part, grad_pose, loss, st);
-    return check_launch("dp_project_fwd_ssd_grad_pose");
+    launch_rd_fused(s, V, views, vol4, target, proj, part, hess != nullptr,
+                    variant_for(DP_OP_FWD_SSD, *g, V), st);
+    launch_finalize_fwd_ssd(s, V, views, part, (int)L.n_part, grad_pose, loss, hess, st);
+    return check_launch(name);
+}
+
+int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
+                                 const double* poses, const float* vol, const float* target,
+                                 float* proj, double* loss, double* grad_pose, void* ws,
+                                 size_t ws_bytes, void* stream)
+{
+    return fwd_ssd(g, V, angles, poses, vol, target, proj, loss, grad_pose, nullptr, ws, ws_bytes,
+                   stream, "dp_project_fwd_ssd_grad_pose");
+}
+
+int dp_project_fwd_ssd_gauss_newton(const dp_geom* g, int32_t V, const double* angles,
+                                    const double* poses, const float* vol, const float* target,
+                                    float* proj, double* loss, double* grad_pose, double* hess,
+                                    void* ws, size_t ws_bytes, void* stream)
+{
+    if (!hess) return fail(DP_ERR_ARG, "NULL array argument");
+    return fwd_ssd(g, V, angles, poses, vol, target, proj, loss, grad_pose, hess, ws, ws_bytes,
+                   stream, "dp_project_fwd_ssd_gauss_newton");
 }
 
 int dp_backproject(const dp_geom* g, int32_t V, const double* angles, const double* poses,

@@ -77,6 +77,9 @@ void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const floa
 // Uneven batches of ray-driven problems in one launch (descriptors by value).
 constexpr int kRdMaxBatch = 16;
 constexpr int kRdVariants = 3;
+// fused SSD kernel with the Gauss-Newton matrix: 9 gradient sums, the SSD,
+// and the 21 upper-triangle entries of 2 J J^T
+constexpr int kRdChannelsGN = kRdChannels + 1 + 21;
 struct RdBatchItem {
     GeoScalars s;
     const ViewGeo* views;
@@ -92,11 +95,11 @@ struct RdBatch {
 };
 void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
 void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                     const float* target, float* proj, float* partials, int variant,
+                     const float* target, float* proj, float* partials, bool hess, int variant,
                      hipStream_t st);
 void launch_finalize_fwd_ssd(const GeoScalars& s, int V, const ViewGeo* views,
                              const float* partials, int n_part, double* grad_pose, double* loss,
-                             hipStream_t st);
+                             double* hess, hipStream_t st);
 void launch_rd_grad_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
 void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
                   float* vol, int weight_mode, hipStream_t st);

@@ -44,21 +44,25 @@ __device__ inline void matvec3(const double* R, const double* x, double* y)
     for (int r = 0; r < 3; ++r) y[r] = R[r * 3 + 0] * x[0] + R[r * 3 + 1] * x[1] + R[r * 3 + 2] * x[2];
 }
 
-// C = 9 gradient channels, or 10 with the per-view SSD of the fused kernel
-// in the last channel (written to loss[v]).
+// C = 9 gradient channels; 10 with the per-view SSD of the fused kernel in
+// channel 9 (written to loss[v]); 31 with the 21 Gauss-Newton entries after
+// it (written to hess[v][21]).
 template <int C>
 __global__ __launch_bounds__(kFinThreads) void finalize_fwd_kernel(GeoScalars s,
                                                                    const ViewGeo* __restrict__ views,
                                                                    const float* __restrict__ partials,
                                                                    int n_part,
                                                                    double* __restrict__ grad_pose,
-                                                                   double* __restrict__ loss)
+                                                                   double* __restrict__ loss,
+                                                                   double* __restrict__ hess)
 {
     const int v = blockIdx.x;
     double S[C];
     fixed_order_sum<C>(partials + (size_t)v * n_part * C, n_part, S);
     if (threadIdx.x != 0) return;
-    if (C > kRdChannels && loss) loss[v] = S[C - 1];
+    if (C > kRdChannels && loss) loss[v] = S[kRdChannels];
+    if (C == kRdChannelsGN && hess)
+        for (int e = 0; e < 21; ++e) hess[21 * v + e] = S[kRdChannels + 1 + e];
     const ViewGeo& g = views[v];
     const double hx = s.vx, hy = s.vy, hz = s.vz;
     const double b[3] = {S[0] / hx, S[1] / hy, S[2] / hz};
@@ -113,17 +117,21 @@ void launch_finalize_fwd(const GeoScalars& s, int V, const ViewGeo* views, const
 {
     prof_begin(DP_K_FINALIZE, st);
     finalize_fwd_kernel<kRdChannels><<<V, kFinThreads, 0, st>>>(s, views, partials, n_part, grad_pose,
-                                                               nullptr);
+                                                               nullptr, nullptr);
     prof_end(DP_K_FINALIZE, st);
 }
 
 void launch_finalize_fwd_ssd(const GeoScalars& s, int V, const ViewGeo* views,
                              const float* partials, int n_part, double* grad_pose, double* loss,
-                             hipStream_t st)
+                             double* hess, hipStream_t st)
 {
     prof_begin(DP_K_FINALIZE, st);
-    finalize_fwd_kernel<kRdChannels + 1><<<V, kFinThreads, 0, st>>>(s, views, partials, n_part,
-                                                                   grad_pose, loss);
+    if (hess)
+        finalize_fwd_kernel<kRdChannelsGN><<<V, kFinThreads, 0, st>>>(s, views, partials, n_part,
+                                                                      grad_pose, loss, hess);
+    else
+        finalize_fwd_kernel<kRdChannels + 1><<<V, kFinThreads, 0, st>>>(s, views, partials, n_part,
+                                                                       grad_pose, loss, nullptr);
     prof_end(DP_K_FINALIZE, st);
 }
 

@@ -465,7 +465,7 @@ struct GradAcc {
     }
 };
 
-template <int MCH, int CAP, bool FUSED>
+template <int MCH, int CAP, bool FUSED, bool HESS = false>
 __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
                                     const float* __restrict__ vol3,
                                     const float* __restrict__ gin,
@@ -589,7 +589,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             G.add(q, wx, wy, wz, fx - ccx, fy - ccy, fz - ccz);
         }
     }
-    constexpr int NC = FUSED ? kRdChannels + 1 : kRdChannels;
+    constexpr int NC = FUSED ? (HESS ? kRdChannelsGN : kRdChannels + 1) : kRdChannels;
     float acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0f;
@@ -599,13 +599,43 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
         proj_out[pix] = l;
         const float res = l - gpix;
         w = 2.0f * res;
-        acc[kRdChannels] = res * res;  // SSD of this ray (last channel)
+        acc[kRdChannels] = res * res;  // SSD of this ray
     }
     if (active) {
         const float ws = w * step;
         acc[0] = G.Bx * ws; acc[1] = G.By * ws; acc[2] = G.Bz * ws;
         acc[3] = G.Txy * ws; acc[4] = G.Txz * ws; acc[5] = G.Tyx * ws;
         acc[6] = G.Tyz * ws; acc[7] = G.Tzx * ws; acc[8] = G.Tzy * ws;
+        if (HESS) {
+            // This ray's Jacobian dl/dtheta: the finalize map (dL/dt = -R b,
+            // dL/dgamma_a = -omega_a . R tau) applied to its own step-scaled
+            // sums; then the 21 products of 2 J J^T (Gauss-Newton matrix of
+            // the SSD), accumulated in channels kRdChannels + 1 ...
+            const float hx = (float)s.vx, hy = (float)s.vy, hz = (float)s.vz;
+            const float b3[3] = {G.Bx * step / hx, G.By * step / hy, G.Bz * step / hz};
+            const float t3[3] = {(hy / hz * G.Tyz - hz / hy * G.Tzy) * step,
+                                 (hz / hx * G.Tzx - hx / hz * G.Txz) * step,
+                                 (hx / hy * G.Txy - hy / hx * G.Tyx) * step};
+            float J[6];
+#pragma unroll
+            for (int r3 = 0; r3 < 3; ++r3)
+                J[r3] = -((float)g.R[3 * r3] * b3[0] + (float)g.R[3 * r3 + 1] * b3[1] +
+                          (float)g.R[3 * r3 + 2] * b3[2]);
+            float Rt[3];
+#pragma unroll
+            for (int r3 = 0; r3 < 3; ++r3)
+                Rt[r3] = (float)g.R[3 * r3] * t3[0] + (float)g.R[3 * r3 + 1] * t3[1] +
+                         (float)g.R[3 * r3 + 2] * t3[2];
+#pragma unroll
+            for (int a3 = 0; a3 < 3; ++a3)
+                J[3 + a3] = -((float)g.omega[3 * a3] * Rt[0] + (float)g.omega[3 * a3 + 1] * Rt[1] +
+                              (float)g.omega[3 * a3 + 2] * Rt[2]);
+            int o = kRdChannels + 1;
+#pragma unroll
+            for (int i6 = 0; i6 < 6; ++i6)
+#pragma unroll
+                for (int j6 = i6; j6 < 6; ++j6) acc[o++] = 2.0f * J[i6] * J[j6];
+        }
     }
     block_reduce_store<NC>(acc, partials + ((size_t)v * tiles + tile) * NC);
 }
@@ -634,8 +664,9 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                                   blockIdx.x, gridDim.x, lds, sh);
 }
 
-// Forward projection, SSD loss and its pose gradient in one march.
-template <int MCH, int CAP>
+// Forward projection, SSD loss and its pose gradient in one march (HESS:
+// also the per-view Gauss-Newton matrix of the SSD).
+template <int MCH, int CAP, bool HESS>
 __global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
                                                               const ViewGeo* __restrict__ views,
                                                               const float* __restrict__ vol4,
@@ -645,8 +676,8 @@ __global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, true>(s, views, vol4, target, proj, partials, blockIdx.y, blockIdx.x,
-                                 gridDim.x, lds, sh);
+    rd_grad_tile<MCH, CAP, true, HESS>(s, views, vol4, target, proj, partials, blockIdx.y,
+                                       blockIdx.x, gridDim.x, lds, sh);
 }
 
 // Uneven batch: one launch covers every (problem, view, tile) of up to
@@ -711,17 +742,28 @@ void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const floa
     prof_end(DP_K_RD_GRAD, st);
 }
 
-void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                     const float* target, float* proj, float* partials, int variant,
-                     hipStream_t st)
+template <bool HESS>
+static void launch_rd_fused_t(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
+                              const float* target, float* proj, float* partials, int variant,
+                              hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
-    prof_begin(DP_K_RD_FUSED, st);
     switch (variant) {
-    case 0: rd_fused_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
-    case 2: rd_fused_kernel<32, 4096><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
-    default: rd_fused_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
+    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
+    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
+    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
     }
+}
+
+void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
+                     const float* target, float* proj, float* partials, bool hess, int variant,
+                     hipStream_t st)
+{
+    prof_begin(DP_K_RD_FUSED, st);
+    if (hess)
+        launch_rd_fused_t<true>(s, V, views, vol4, target, proj, partials, variant, st);
+    else
+        launch_rd_fused_t<false>(s, V, views, vol4, target, proj, partials, variant, st);
     prof_end(DP_K_RD_FUSED, st);
 }
 

@@ -16,6 +16,10 @@ pose-gradient launch for the whole batch.  Two optimisers:
   each rejection).  It uses the same analytic gradient and converges to the
   exact optimum in a few tens of iterations, where Adam's fixed step sizes
   leave the weakly observed depth translation of a single view short.
+* ``register_lm`` -- Levenberg-Marquardt for the SSD: the single-pass kernel
+  also returns the Gauss-Newton matrix 2 sum J J^T built from the per-ray
+  pose Jacobians (the gradient's sums before weighting), so each iteration
+  is one launch and converges quadratically near the optimum.
 
 Losses: SSD, or NCC (the paper's registration loss), per view.
 """
@@ -232,6 +236,70 @@ def register_bfgs(geom, vol, angles, targets, init_poses, loss="ssd", iters=150,
             scale[active] = torch.where(acc, torch.ones_like(sc), sc * shrink)
             its[active] += 1
             stop = (acc & (d.abs().max(dim=1).values < tol)) | (scale[active] < min_scale)
+            done[active] = stop
+            active = active[~stop]
+    if dev.type == "cuda":
+        torch.cuda.synchronize(dev)
+    return RegistrationResult(poses=z * D, iterations=its, converged=done, final_loss=f,
+                              seconds=time.perf_counter() - t0, launches=launches)
+
+
+def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=4.0, down=3.0,
+                tol=1e-4, lam_max=1e10) -> RegistrationResult:
+    """Batched Levenberg-Marquardt registration on the SSD.
+
+    Each launch evaluates, at one point per registration, the DRR, the SSD
+    f, its analytic pose gradient g and the Gauss-Newton matrix
+    H = 2 sum J J^T (one pass of the fused kernel).  In the scaled
+    parameters z = (t / 1 mm, gamma / 1 deg) the step solves
+    (H + lam diag(H)) d = -g; the next launch evaluates z + d, which is
+    accepted if the SSD decreased (lam /= down) and otherwise discarded
+    (lam *= up, the previous f, g, H kept).  A registration stops once an
+    accepted step is below tol in every scaled parameter, or when lam
+    exceeds lam_max (no decrease resolvable in FP32).
+    """
+    from . import project_fwd_ssd_gauss_newton
+    B = init_poses.shape[0]
+    dev = init_poses.device
+    f64 = torch.float64
+    D = torch.tensor([1.0] * 3 + [math.radians(1.0)] * 3, dtype=f64, device=dev)
+    DD = D[:, None] * D[None, :]
+
+    def evaluate(z, idx):
+        _, L, g, H = project_fwd_ssd_gauss_newton(geom, angles[idx].contiguous(),
+                                                  (z * D).contiguous(), vol,
+                                                  targets[idx].contiguous())
+        return L, g * D, H * DD
+
+    t0 = time.perf_counter()
+    z = (init_poses.detach().to(f64) / D).clone()
+    allidx = torch.arange(B, device=dev)
+    f, g, H = evaluate(z, allidx)
+    launches = 1
+    lam = torch.full((B,), lam0, dtype=f64, device=dev)
+    its = torch.zeros(B, dtype=torch.int64, device=dev)
+    done = torch.zeros(B, dtype=torch.bool, device=dev)
+    eye = torch.eye(6, dtype=f64, device=dev)
+    active = allidx.clone()
+    for _ in range(iters):
+        if active.numel() == 0:
+            break
+        Ha, ga = H[active], g[active]
+        A = Ha + lam[active, None, None] * (torch.diagonal(Ha, dim1=1, dim2=2)[:, :, None] * eye
+                                            + 1e-12 * eye)
+        d = torch.linalg.solve(A, -ga)
+        zt = z[active] + d
+        ft, gt, Ht = evaluate(zt, active)
+        launches += 1
+        with torch.no_grad():
+            acc = ft < f[active]
+            z[active] = torch.where(acc[:, None], zt, z[active])
+            f[active] = torch.where(acc, ft, f[active])
+            g[active] = torch.where(acc[:, None], gt, ga)
+            H[active] = torch.where(acc[:, None, None], Ht, Ha)
+            lam[active] = torch.where(acc, lam[active] / down, lam[active] * up)
+            its[active] += 1
+            stop = (acc & (d.abs().max(dim=1).values < tol)) | (lam[active] > lam_max)
             done[active] = stop
             active = active[~stop]
     if dev.type == "cuda":

@@ -123,6 +123,20 @@ def test_batched_bfgs_registration_reaches_target_accuracy(dp):
     assert bool(res.converged.all())
 
 
+def test_batched_levenberg_marquardt_registration(dp):
+    """The same registrations with the Gauss-Newton matrix of the single-pass
+    kernel: all reach 0.1 mm / 0.1 deg in fewer launches than BFGS."""
+    from paper_2508_13304_amd import registration as reg
+    g, vol, truth, angles, targets = _registration_case(dp)
+    res = reg.register_lm(g, vol, angles, targets, torch.zeros_like(truth))
+    _report(reg, res, truth)
+    assert bool(reg.success(res.poses, truth).all())
+    assert bool(res.converged.all())
+    bf = reg.register_bfgs(g, vol, angles, targets, torch.zeros_like(truth))
+    print("launches: LM", res.launches, "BFGS", bf.launches, flush=True)
+    assert res.launches < bf.launches
+
+
 def test_batched_adam_registration_reduces_error(dp):
     """The Adam driver (fixed step sizes) recovers the rotations and shrinks
     the translation error by an order of magnitude on the same case."""
