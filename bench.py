@@ -425,7 +425,7 @@ def run_learned(args, dp, torch):
     net = pr.ProposalNet.load(pr.WEIGHTS)
     res = pr.evaluate(net, synth.geom_c5(), n_phantoms=4, per_phantom=16, log=log)
     res["workload"] = ("4 unseen 192^3 phantoms at 1 mm x 16 offsets (+-30 mm/+-20 deg), one 256x256 "
-                       "view at 1.2 mm, SSD loss; plain = BFGS from identity")
+                       "view at 1.2 mm, SSD loss; both refined by Levenberg-Marquardt; plain = from identity")
     return res
 
 
