@@ -225,3 +225,37 @@ def backproject_grad_pose(geom, angles, poses, proj, grad_vol, weight_mode=W_NON
     lib().dpref_backproject_grad_pose(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(proj)),
                                       _p(_d(grad_vol)), _p(out), int(weight_mode))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Separable-footprint projector pair (voxel footprint = trapezoid x rectangle)
+# ---------------------------------------------------------------------------
+
+def sf_project(geom, angles, poses, vol) -> np.ndarray:
+    angles, poses, V = _views(angles, poses)
+    out = np.zeros((V, geom.nv, geom.nu))
+    lib().dpref_sf_project(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(vol)), _p(out))
+    return out
+
+
+def sf_backproject(geom, angles, poses, proj) -> np.ndarray:
+    angles, poses, V = _views(angles, poses)
+    out = np.zeros((geom.nz, geom.ny, geom.nx))
+    lib().dpref_sf_backproject(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(proj)), _p(out))
+    return out
+
+
+def sf_project_grad_pose(geom, angles, poses, vol, grad_proj) -> np.ndarray:
+    angles, poses, V = _views(angles, poses)
+    out = np.zeros((V, 6))
+    lib().dpref_sf_project_grad_pose(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(vol)),
+                                     _p(_d(grad_proj)), _p(out))
+    return out
+
+
+def sf_backproject_grad_pose(geom, angles, poses, proj, grad_vol) -> np.ndarray:
+    angles, poses, V = _views(angles, poses)
+    out = np.zeros((V, 6))
+    lib().dpref_sf_backproject_grad_pose(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(proj)),
+                                         _p(_d(grad_vol)), _p(out))
+    return out

@@ -773,3 +773,281 @@ void dpref_backproject_grad_pose(const dpref_geom* g, int V, const double* angle
     for (int v = 0; v < V; ++v) dpref_contract_pose(poses + 6 * v, dLdM + 12 * v, grad_pose + 6 * v);
     free(dLdM);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Separable-footprint (SF) projector pair and its pose gradients           */
+/* ------------------------------------------------------------------------ */
+/* Weights a_ij of voxel j on pixel i (one view), with the voxel moved by the
+ * pose (corners r = R p + t, projected by the view's P):
+ *   transaxial: the four corners (x +- hx, y +- hy) of the voxel's mid-height
+ *     cross-section project to column coordinates tau0 <= .. <= tau3, the
+ *     breakpoints of a unit-height trapezoid T(a);
+ *   axial: the top and bottom centres (z +- hz) project to rows b_lo, b_hi,
+ *     a unit-height rectangle;
+ *   amplitude: the chord L_j of the voxel cut by the line from the source
+ *     through its centre;
+ *   a_ij = L_j * int_{cell a} T * |[b_lo, b_hi] cap cell b|   (pixel cells of
+ *     unit width centred on integer indices).
+ * Forward: l_i = sum_j a_ij mu_j; back-projection: mu_j = sum_i a_ij l_i (the
+ * exact transpose).  Gradients (Eqs. dis_forward / dis_back): the same
+ * weights applied to G_f^j (per voxel) and to G_b^i (per pixel: the
+ * central-difference detector gradient at the pixel, with the projection
+ * Jacobian and grad_M r of the voxel). */
+
+static double trap_cdf(double x, const double t[4])
+{
+    double s = 0.0;
+    if (x > t[0] && t[1] > t[0]) {
+        double xr = x < t[1] ? x : t[1];
+        s += (xr - t[0]) * (xr - t[0]) / (2.0 * (t[1] - t[0]));
+    }
+    if (x > t[1]) s += (x < t[2] ? x : t[2]) - t[1];
+    if (x > t[2] && t[3] > t[2]) {
+        double xf = x < t[3] ? x : t[3];
+        s += ((t[3] - t[2]) * (t[3] - t[2]) - (t[3] - xf) * (t[3] - xf)) / (2.0 * (t[3] - t[2]));
+    }
+    return s;
+}
+
+typedef struct {
+    double tau[4], blo, bhi, L;
+} sf_fp;
+
+static int sf_footprint(const dpref_geom* g, const bp_view* bv, const double sobj[3], long i,
+                        long j, long k, sf_fp* fp)
+{
+    double p[3], q[3], r[3], uvw[3];
+    const double hx = 0.5 * g->vx, hy = 0.5 * g->vy, hz = 0.5 * g->vz;
+    voxel_centre(g, i, j, k, p);
+    for (int c = 0; c < 4; ++c) {
+        q[0] = p[0] + ((c & 1) ? hx : -hx);
+        q[1] = p[1] + ((c & 2) ? hy : -hy);
+        q[2] = p[2];
+        project_point(bv, q, r, uvw);
+        if (!(uvw[2] > 0.0)) return 0;
+        fp->tau[c] = uvw[0] / uvw[2];
+    }
+    for (int a = 1; a < 4; ++a)  /* insertion sort of 4 values */
+        for (int b = a; b > 0 && fp->tau[b - 1] > fp->tau[b]; --b) {
+            double t = fp->tau[b]; fp->tau[b] = fp->tau[b - 1]; fp->tau[b - 1] = t;
+        }
+    double bb[2];
+    for (int c = 0; c < 2; ++c) {
+        q[0] = p[0]; q[1] = p[1]; q[2] = p[2] + (c ? hz : -hz);
+        project_point(bv, q, r, uvw);
+        if (!(uvw[2] > 0.0)) return 0;
+        bb[c] = uvw[1] / uvw[2];
+    }
+    fp->blo = bb[0] < bb[1] ? bb[0] : bb[1];
+    fp->bhi = bb[0] < bb[1] ? bb[1] : bb[0];
+    double d[3] = {p[0] - sobj[0], p[1] - sobj[1], p[2] - sobj[2]};
+    double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double h[3] = {hx, hy, hz}, L = INFINITY;
+    for (int c = 0; c < 3; ++c)
+        if (d[c] != 0.0) {
+            double s = h[c] / (fabs(d[c]) / n);
+            if (s < L) L = s;
+        }
+    fp->L = 2.0 * L;
+    return 1;
+}
+
+/* Pixel window of a footprint: cells overlapping (tau0, tau3) x (blo, bhi). */
+static void sf_window(const dpref_geom* g, const sf_fp* fp, long* a0, long* a1, long* b0, long* b1)
+{
+    *a0 = (long)floor(fp->tau[0] - 0.5) + 1;
+    *a1 = (long)ceil(fp->tau[3] + 0.5) - 1;
+    *b0 = (long)floor(fp->blo - 0.5) + 1;
+    *b1 = (long)ceil(fp->bhi + 0.5) - 1;
+    if (*a0 < 0) *a0 = 0;
+    if (*b0 < 0) *b0 = 0;
+    if (*a1 > g->nu - 1) *a1 = g->nu - 1;
+    if (*b1 > g->nv - 1) *b1 = g->nv - 1;
+}
+
+static double sf_weight(const sf_fp* fp, long a, long b)
+{
+    double ta = trap_cdf(a + 0.5, fp->tau) - trap_cdf(a - 0.5, fp->tau);
+    double lo = b - 0.5 > fp->blo ? b - 0.5 : fp->blo;
+    double hi = b + 0.5 < fp->bhi ? b + 0.5 : fp->bhi;
+    double tb = hi > lo ? hi - lo : 0.0;
+    return fp->L * ta * tb;
+}
+
+static void source_object_frame(const dpref_geom* g, double beta, const bp_view* bv, double s[3])
+{
+    view_frame f = make_frame(g, beta);
+    double d[3] = {f.src[0] - bv->t[0], f.src[1] - bv->t[1], f.src[2] - bv->t[2]};
+    for (int c = 0; c < 3; ++c) s[c] = bv->R[0 * 3 + c] * d[0] + bv->R[1 * 3 + c] * d[1] + bv->R[2 * 3 + c] * d[2];
+}
+
+void dpref_sf_project(const dpref_geom* g, int V, const double* angles, const double* poses,
+                      const double* vol, double* proj)
+{
+    long npix = (long)g->nu * g->nv;
+    for (int v = 0; v < V; ++v) {
+        bp_view bv = make_bp_view(g, angles, poses, v);
+        double sobj[3];
+        source_object_frame(g, angles[v], &bv, sobj);
+        double* img = proj + v * npix;
+        for (long p = 0; p < npix; ++p) img[p] = 0.0;
+#pragma omp parallel
+        {
+            double* loc = (double*)calloc(npix, sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+            for (long k = 0; k < g->nz; ++k)
+                for (long j = 0; j < g->ny; ++j)
+                    for (long i = 0; i < g->nx; ++i) {
+                        double mu = vol[(k * g->ny + j) * g->nx + i];
+                        sf_fp fp;
+                        long a0, a1, b0, b1;
+                        if (mu == 0.0 || !sf_footprint(g, &bv, sobj, i, j, k, &fp)) continue;
+                        sf_window(g, &fp, &a0, &a1, &b0, &b1);
+                        for (long b = b0; b <= b1; ++b)
+                            for (long a = a0; a <= a1; ++a) loc[b * g->nu + a] += sf_weight(&fp, a, b) * mu;
+                    }
+#pragma omp critical
+            for (long p = 0; p < npix; ++p) img[p] += loc[p];
+            free(loc);
+        }
+    }
+}
+
+void dpref_sf_backproject(const dpref_geom* g, int V, const double* angles, const double* poses,
+                          const double* proj, double* vol)
+{
+    long npix = (long)g->nu * g->nv;
+    bp_view* bvs = make_bp_views(g, V, angles, poses);
+    double* src = (double*)malloc(sizeof(double) * 3 * (V > 0 ? V : 1));
+    if (!bvs || !src) { free(bvs); free(src); return; }
+    for (int v = 0; v < V; ++v) source_object_frame(g, angles[v], &bvs[v], src + 3 * v);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long k = 0; k < g->nz; ++k)
+        for (long j = 0; j < g->ny; ++j)
+            for (long i = 0; i < g->nx; ++i) {
+                double s = 0.0;
+                for (int v = 0; v < V; ++v) {
+                    sf_fp fp;
+                    long a0, a1, b0, b1;
+                    if (!sf_footprint(g, &bvs[v], src + 3 * v, i, j, k, &fp)) continue;
+                    sf_window(g, &fp, &a0, &a1, &b0, &b1);
+                    for (long b = b0; b <= b1; ++b)
+                        for (long a = a0; a <= a1; ++a)
+                            s += sf_weight(&fp, a, b) * proj[v * npix + b * g->nu + a];
+                }
+                vol[(k * g->ny + j) * g->nx + i] = s;
+            }
+    free(bvs);
+    free(src);
+}
+
+void dpref_sf_project_grad_M(const dpref_geom* g, int V, const double* angles, const double* poses,
+                             const double* vol, const double* grad_proj, double* dLdM)
+{
+    long npix = (long)g->nu * g->nv;
+    double* gr = volume_gradient(g, vol);
+    if (!gr) return;
+    for (int v = 0; v < V; ++v) {
+        bp_view bv = make_bp_view(g, angles, poses, v);
+        view_pose vp = make_view(g, angles, poses, v);
+        double sobj[3], acc[12] = {0};
+        source_object_frame(g, angles[v], &bv, sobj);
+        const double* w = grad_proj + v * npix;
+#pragma omp parallel
+        {
+            double loc[12] = {0};
+#pragma omp for schedule(dynamic, 1)
+            for (long k = 0; k < g->nz; ++k)
+                for (long j = 0; j < g->ny; ++j)
+                    for (long i = 0; i < g->nx; ++i) {
+                        sf_fp fp;
+                        long a0, a1, b0, b1;
+                        double G[12], s = 0.0;
+                        if (!sf_footprint(g, &bv, sobj, i, j, k, &fp)) continue;
+                        sf_window(g, &fp, &a0, &a1, &b0, &b1);
+                        for (long b = b0; b <= b1; ++b)
+                            for (long a = a0; a <= a1; ++a) s += sf_weight(&fp, a, b) * w[b * g->nu + a];
+                        if (s == 0.0) continue;
+                        forward_G(g, &vp, gr, i, j, k, G);
+                        for (int e = 0; e < 12; ++e) loc[e] += s * G[e];
+                    }
+#pragma omp critical
+            for (int e = 0; e < 12; ++e) acc[e] += loc[e];
+        }
+        memcpy(dLdM + 12 * v, acc, sizeof acc);
+    }
+    free(gr);
+}
+
+void dpref_sf_backproject_grad_M(const dpref_geom* g, int V, const double* angles,
+                                 const double* poses, const double* proj, const double* grad_vol,
+                                 double* dLdM)
+{
+    long npix = (long)g->nu * g->nv;
+    double* la = (double*)malloc(sizeof(double) * npix);
+    double* lb = (double*)malloc(sizeof(double) * npix);
+    if (!la || !lb) { free(la); free(lb); return; }
+    for (int v = 0; v < V; ++v) {
+        bp_view bv = make_bp_view(g, angles, poses, v);
+        double sobj[3], acc[12] = {0};
+        source_object_frame(g, angles[v], &bv, sobj);
+        image_gradient(proj + v * npix, g->nu, g->nv, la, lb);
+#pragma omp parallel
+        {
+            double loc[12] = {0};
+#pragma omp for schedule(dynamic, 1)
+            for (long k = 0; k < g->nz; ++k)
+                for (long j = 0; j < g->ny; ++j)
+                    for (long i = 0; i < g->nx; ++i) {
+                        double e = grad_vol[(k * g->ny + j) * g->nx + i];
+                        sf_fp fp;
+                        long a0, a1, b0, b1;
+                        double p[3], r[3], uvw[3], dl[2] = {0.0, 0.0};
+                        if (e == 0.0 || !sf_footprint(g, &bv, sobj, i, j, k, &fp)) continue;
+                        sf_window(g, &fp, &a0, &a1, &b0, &b1);
+                        for (long b = b0; b <= b1; ++b)
+                            for (long a = a0; a <= a1; ++a) {
+                                double wgt = sf_weight(&fp, a, b);
+                                dl[0] += wgt * la[b * g->nu + a];
+                                dl[1] += wgt * lb[b * g->nu + a];
+                            }
+                        voxel_centre(g, i, j, k, p);
+                        project_point(&bv, p, r, uvw);
+                        double w = uvw[2], pe[4] = {p[0], p[1], p[2], 1.0};
+                        for (int rr = 0; rr < 3; ++rr) {
+                            double J0 = (bv.P[0 * 4 + rr] * w - bv.P[2 * 4 + rr] * uvw[0]) / (w * w);
+                            double J1 = (bv.P[1 * 4 + rr] * w - bv.P[2 * 4 + rr] * uvw[1]) / (w * w);
+                            double gr = J0 * dl[0] + J1 * dl[1];
+                            for (int c = 0; c < 4; ++c) loc[rr * 4 + c] += e * gr * pe[c];
+                        }
+                    }
+#pragma omp critical
+            for (int q = 0; q < 12; ++q) acc[q] += loc[q];
+        }
+        memcpy(dLdM + 12 * v, acc, sizeof acc);
+    }
+    free(la);
+    free(lb);
+}
+
+void dpref_sf_project_grad_pose(const dpref_geom* g, int V, const double* angles,
+                                const double* poses, const double* vol, const double* grad_proj,
+                                double* grad_pose)
+{
+    double* dLdM = (double*)malloc(sizeof(double) * 12 * (V > 0 ? V : 1));
+    if (!dLdM) return;
+    dpref_sf_project_grad_M(g, V, angles, poses, vol, grad_proj, dLdM);
+    for (int v = 0; v < V; ++v) dpref_contract_pose(poses + 6 * v, dLdM + 12 * v, grad_pose + 6 * v);
+    free(dLdM);
+}
+
+void dpref_sf_backproject_grad_pose(const dpref_geom* g, int V, const double* angles,
+                                    const double* poses, const double* proj, const double* grad_vol,
+                                    double* grad_pose)
+{
+    double* dLdM = (double*)malloc(sizeof(double) * 12 * (V > 0 ? V : 1));
+    if (!dLdM) return;
+    dpref_sf_backproject_grad_M(g, V, angles, poses, proj, grad_vol, dLdM);
+    for (int v = 0; v < V; ++v) dpref_contract_pose(poses + 6 * v, dLdM + 12 * v, grad_pose + 6 * v);
+    free(dLdM);
+}
