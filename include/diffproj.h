@@ -80,7 +80,10 @@ enum {
 
 enum { DP_W_NONE = 0, DP_W_FDK = 1 };
 
-enum { DP_OP_FWD = 0, DP_OP_FWD_GRAD = 1, DP_OP_BP = 2, DP_OP_BP_GRAD = 3, DP_OP_FWD_SSD = 4 };
+enum {
+    DP_OP_FWD = 0, DP_OP_FWD_GRAD = 1, DP_OP_BP = 2, DP_OP_BP_GRAD = 3, DP_OP_FWD_SSD = 4,
+    DP_OP_SF_FWD = 5, DP_OP_SF_FWD_GRAD = 6, DP_OP_SF_BP = 7, DP_OP_SF_BP_GRAD = 8
+};
 
 /* Workspace size (bytes) needed by operation `op` (DP_OP_*) for this
  * geometry and view count; 0 for invalid arguments. */
@@ -220,6 +223,35 @@ int dp_act_bwd_bf16(int64_t total, const float* dy, const void* y, int32_t relu,
 int dp_colsum_bf16(int32_t M, int32_t C, const void* dz, float* db, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Separable-footprint (SF) projector pair and its pose gradients (the
+ * discrete projectors of Sec. II-C, l = A mu and mu = A^T l with footprint
+ * weights a_ij; gradients by Eqs. dis_forward / dis_back).  Footprint of a
+ * voxel moved by the view's pose: a unit-height trapezoid in the detector
+ * column (breakpoints: the projected corners of the voxel's mid-height
+ * cross-section) times a unit-height rectangle in the row (the projected
+ * top and bottom centres), scaled by the voxel's chord along the line from
+ * the source through its centre; a_ij = chord x (trapezoid integral over
+ * pixel i's column cell) x (rectangle overlap with its row cell).
+ * Arguments, layouts and errors as for the ray-driven / voxel-driven
+ * entries; workspace: dp_workspace_bytes(g, V, DP_OP_SF_*).
+ *   dp_sf_project: proj [V][nv][nu] (overwritten) = A vol (FP32 atomic
+ *     accumulation: not bitwise reproducible).
+ *   dp_sf_backproject: vol (overwritten) = A^T proj (no angular weight).
+ *   dp_sf_project_grad_pose: dL/dtheta [V][6] from dL/dl = grad_proj.
+ *   dp_sf_backproject_grad_pose: dL/dtheta [V][6] from dL/dmu = grad_vol.
+ * ------------------------------------------------------------------------- */
+int dp_sf_project(const dp_geom* g, int32_t n_views, const double* angles, const double* poses,
+                  const float* vol, float* proj, void* ws, size_t ws_bytes, void* stream);
+int dp_sf_backproject(const dp_geom* g, int32_t n_views, const double* angles, const double* poses,
+                      const float* proj, float* vol, void* ws, size_t ws_bytes, void* stream);
+int dp_sf_project_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
+                            const double* poses, const float* vol, const float* grad_proj,
+                            double* grad_pose, void* ws, size_t ws_bytes, void* stream);
+int dp_sf_backproject_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
+                                const double* poses, const float* proj, const float* grad_vol,
+                                double* grad_pose, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Motion-compensated FDK reconstruction (Sec. III-B, motion-compensated
  * analytical reconstruction: FDK-style back-projection of ramp-filtered
  * projections, motion estimated by maximising image sharpness).
@@ -278,8 +310,8 @@ int32_t dp_version(void);
 enum {
     DP_K_SETUP = 0, DP_K_VOL_PREP = 1, DP_K_RD_FWD = 2, DP_K_RD_GRAD = 3,
     DP_K_DET_PREP = 4, DP_K_VD_BP = 5, DP_K_VD_GRAD = 6, DP_K_FINALIZE = 7,
-    DP_K_FDK_FILTER = 8, DP_K_SHARPNESS = 9, DP_K_RD_FUSED = 10,
-    DP_K_COUNT = 11
+    DP_K_FDK_FILTER = 8, DP_K_SHARPNESS = 9, DP_K_RD_FUSED = 10, DP_K_SF = 11,
+    DP_K_COUNT = 12
 };
 int dp_profile_enable(int32_t on);
 int dp_profile_collect(void);

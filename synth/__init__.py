@@ -154,6 +154,8 @@ def ellipsoid_phantom(n: int, h: float, n_ell: int, rng: np.random.Generator,
     L = n * h
     vol = np.zeros((n, n, n), dtype=np.float64)
     limit = 0.5 * L - 4.0 * h
+    if limit <= 0.05 * L:  # no ellipsoid could pass the bounding-sphere rule
+        raise ValueError(f"grid of {n} voxels is too small for the ellipsoid recipe")
     placed = 0
     while placed < n_ell:
         d = rng.standard_normal(3)
@@ -267,6 +269,8 @@ def draw_ellipsoids(n: int, h: float, n_ell: int, rng: np.random.Generator,
     attenuations [E]."""
     L = n * h
     limit = 0.5 * L - 4.0 * h
+    if limit <= 0.05 * L:  # no ellipsoid could pass the bounding-sphere rule
+        raise ValueError(f"grid of {n} voxels is too small for the ellipsoid recipe")
     cs, ss, rs, vs = [], [], [], []
     while len(cs) < n_ell:
         d = rng.standard_normal(3)

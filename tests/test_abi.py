@@ -52,11 +52,12 @@ def test_struct_layout_matches_header(lib):
 def test_workspace_query(lib):
     import paper_2508_13304_amd as m
     g = synth.geom_c1()
-    for op in range(4):
+    for op in range(9):  # DP_OP_FWD .. DP_OP_SF_BP_GRAD
         assert m.workspace_bytes(g, 1, op) > 0
         assert m.workspace_bytes(g, 1, op) % 256 == 0
     assert m.workspace_bytes(g, 0, 0) == 0
-    assert m.workspace_bytes(g, 1, 7) == 0
+    assert m.workspace_bytes(g, 1, 9) == 0
+    assert m.workspace_bytes(g, 1, -1) == 0
     assert m.workspace_bytes(g.replace(sdd=900.0), 1, 0) == 0
     # grows with the number of views for the image-sized buffers
     assert m.workspace_bytes(g, 8, m.OP_BP) > m.workspace_bytes(g, 1, m.OP_BP)
