@@ -228,34 +228,56 @@ def backproject_grad_pose(geom, angles, poses, proj, grad_vol, weight_mode=W_NON
 
 
 # ---------------------------------------------------------------------------
-# Separable-footprint projector pair (voxel footprint = trapezoid x rectangle)
+# Footprint projector pairs: separable footprint (kind "sf") and
+# distance-driven (kind "dd")
 # ---------------------------------------------------------------------------
 
-def sf_project(geom, angles, poses, vol) -> np.ndarray:
+FP_KINDS = {"sf": 0, "dd": 1}
+
+
+def fp_project(geom, angles, poses, vol, kind="sf") -> np.ndarray:
     angles, poses, V = _views(angles, poses)
     out = np.zeros((V, geom.nv, geom.nu))
-    lib().dpref_sf_project(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(vol)), _p(out))
+    lib().dpref_fp_project(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(vol)), _p(out),
+                           FP_KINDS[kind])
     return out
 
 
-def sf_backproject(geom, angles, poses, proj) -> np.ndarray:
+def fp_backproject(geom, angles, poses, proj, kind="sf") -> np.ndarray:
     angles, poses, V = _views(angles, poses)
     out = np.zeros((geom.nz, geom.ny, geom.nx))
-    lib().dpref_sf_backproject(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(proj)), _p(out))
+    lib().dpref_fp_backproject(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(proj)), _p(out),
+                               FP_KINDS[kind])
     return out
 
 
-def sf_project_grad_pose(geom, angles, poses, vol, grad_proj) -> np.ndarray:
+def fp_project_grad_pose(geom, angles, poses, vol, grad_proj, kind="sf") -> np.ndarray:
     angles, poses, V = _views(angles, poses)
     out = np.zeros((V, 6))
-    lib().dpref_sf_project_grad_pose(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(vol)),
-                                     _p(_d(grad_proj)), _p(out))
+    lib().dpref_fp_project_grad_pose(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(vol)),
+                                     _p(_d(grad_proj)), _p(out), FP_KINDS[kind])
     return out
 
 
-def sf_backproject_grad_pose(geom, angles, poses, proj, grad_vol) -> np.ndarray:
+def fp_backproject_grad_pose(geom, angles, poses, proj, grad_vol, kind="sf") -> np.ndarray:
     angles, poses, V = _views(angles, poses)
     out = np.zeros((V, 6))
-    lib().dpref_sf_backproject_grad_pose(C.byref(_g(geom)), V, _p(angles), _p(poses), _p(_d(proj)),
-                                         _p(_d(grad_vol)), _p(out))
+    lib().dpref_fp_backproject_grad_pose(C.byref(_g(geom)), V, _p(angles), _p(poses),
+                                         _p(_d(proj)), _p(_d(grad_vol)), _p(out), FP_KINDS[kind])
     return out
+
+
+def sf_project(geom, angles, poses, vol):
+    return fp_project(geom, angles, poses, vol, "sf")
+
+
+def sf_backproject(geom, angles, poses, proj):
+    return fp_backproject(geom, angles, poses, proj, "sf")
+
+
+def sf_project_grad_pose(geom, angles, poses, vol, grad_proj):
+    return fp_project_grad_pose(geom, angles, poses, vol, grad_proj, "sf")
+
+
+def sf_backproject_grad_pose(geom, angles, poses, proj, grad_vol):
+    return fp_backproject_grad_pose(geom, angles, poses, proj, grad_vol, "sf")

@@ -813,24 +813,46 @@ typedef struct {
     double tau[4], blo, bhi, L;
 } sf_fp;
 
-static int sf_footprint(const dpref_geom* g, const bp_view* bv, const double sobj[3], long i,
-                        long j, long k, sf_fp* fp)
+/* kind 0 (SF): trapezoid from the mid-height cross-section's corners,
+ * amplitude = the central chord.  kind 1 (DD, distance-driven): a
+ * unit-height rectangle between the projections of the voxel's two
+ * boundaries across the view's dominant transaxial axis (x if the central
+ * ray's object-frame direction has |d_x| >= |d_y|, else y), taken at the
+ * voxel centre, and amplitude = the path length through the slab along the
+ * dominant axis, h_dom |d| / |d_dom| for the line from the source through
+ * the voxel centre.  Both use the same axial rectangle. */
+static int sf_footprint_kind(const dpref_geom* g, const bp_view* bv, const double sobj[3], int kind,
+                             int dom, long i, long j, long k, sf_fp* fp)
 {
     double p[3], q[3], r[3], uvw[3];
     const double hx = 0.5 * g->vx, hy = 0.5 * g->vy, hz = 0.5 * g->vz;
     voxel_centre(g, i, j, k, p);
-    for (int c = 0; c < 4; ++c) {
-        q[0] = p[0] + ((c & 1) ? hx : -hx);
-        q[1] = p[1] + ((c & 2) ? hy : -hy);
-        q[2] = p[2];
-        project_point(bv, q, r, uvw);
-        if (!(uvw[2] > 0.0)) return 0;
-        fp->tau[c] = uvw[0] / uvw[2];
-    }
-    for (int a = 1; a < 4; ++a)  /* insertion sort of 4 values */
-        for (int b = a; b > 0 && fp->tau[b - 1] > fp->tau[b]; --b) {
-            double t = fp->tau[b]; fp->tau[b] = fp->tau[b - 1]; fp->tau[b - 1] = t;
+    if (kind == 0) {
+        for (int c = 0; c < 4; ++c) {
+            q[0] = p[0] + ((c & 1) ? hx : -hx);
+            q[1] = p[1] + ((c & 2) ? hy : -hy);
+            q[2] = p[2];
+            project_point(bv, q, r, uvw);
+            if (!(uvw[2] > 0.0)) return 0;
+            fp->tau[c] = uvw[0] / uvw[2];
         }
+        for (int a = 1; a < 4; ++a)  /* insertion sort of 4 values */
+            for (int b = a; b > 0 && fp->tau[b - 1] > fp->tau[b]; --b) {
+                double t = fp->tau[b]; fp->tau[b] = fp->tau[b - 1]; fp->tau[b - 1] = t;
+            }
+    } else {
+        double e[2];
+        for (int c = 0; c < 2; ++c) {
+            q[0] = p[0]; q[1] = p[1]; q[2] = p[2];
+            if (dom == 0) q[1] += c ? hy : -hy;  /* x-dominant: boundaries across y */
+            else q[0] += c ? hx : -hx;           /* y-dominant: boundaries across x */
+            project_point(bv, q, r, uvw);
+            if (!(uvw[2] > 0.0)) return 0;
+            e[c] = uvw[0] / uvw[2];
+        }
+        fp->tau[0] = fp->tau[1] = e[0] < e[1] ? e[0] : e[1];
+        fp->tau[2] = fp->tau[3] = e[0] < e[1] ? e[1] : e[0];
+    }
     double bb[2];
     for (int c = 0; c < 2; ++c) {
         q[0] = p[0]; q[1] = p[1]; q[2] = p[2] + (c ? hz : -hz);
@@ -842,14 +864,26 @@ static int sf_footprint(const dpref_geom* g, const bp_view* bv, const double sob
     fp->bhi = bb[0] < bb[1] ? bb[1] : bb[0];
     double d[3] = {p[0] - sobj[0], p[1] - sobj[1], p[2] - sobj[2]};
     double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    double h[3] = {hx, hy, hz}, L = INFINITY;
-    for (int c = 0; c < 3; ++c)
-        if (d[c] != 0.0) {
-            double s = h[c] / (fabs(d[c]) / n);
-            if (s < L) L = s;
-        }
-    fp->L = 2.0 * L;
+    double h[3] = {hx, hy, hz};
+    if (kind == 0) {
+        double L = INFINITY;
+        for (int c = 0; c < 3; ++c)
+            if (d[c] != 0.0) {
+                double s = h[c] / (fabs(d[c]) / n);
+                if (s < L) L = s;
+            }
+        fp->L = 2.0 * L;
+    } else {
+        fp->L = d[dom] != 0.0 ? 2.0 * h[dom] * n / fabs(d[dom]) : 0.0;
+    }
     return 1;
+}
+
+/* Dominant transaxial axis of a view: 0 (x) if the central ray (source to
+ * the volume centre, object frame) has |d_x| >= |d_y|, else 1 (y). */
+static int dd_dominant(const double sobj[3])
+{
+    return fabs(sobj[0]) >= fabs(sobj[1]) ? 0 : 1;
 }
 
 /* Pixel window of a footprint: cells overlapping (tau0, tau3) x (blo, bhi). */
@@ -881,14 +915,15 @@ static void source_object_frame(const dpref_geom* g, double beta, const bp_view*
     for (int c = 0; c < 3; ++c) s[c] = bv->R[0 * 3 + c] * d[0] + bv->R[1 * 3 + c] * d[1] + bv->R[2 * 3 + c] * d[2];
 }
 
-void dpref_sf_project(const dpref_geom* g, int V, const double* angles, const double* poses,
-                      const double* vol, double* proj)
+void dpref_fp_project(const dpref_geom* g, int V, const double* angles, const double* poses,
+                      const double* vol, double* proj, int kind)
 {
     long npix = (long)g->nu * g->nv;
     for (int v = 0; v < V; ++v) {
         bp_view bv = make_bp_view(g, angles, poses, v);
         double sobj[3];
         source_object_frame(g, angles[v], &bv, sobj);
+        const int dom = dd_dominant(sobj);
         double* img = proj + v * npix;
         for (long p = 0; p < npix; ++p) img[p] = 0.0;
 #pragma omp parallel
@@ -901,7 +936,7 @@ void dpref_sf_project(const dpref_geom* g, int V, const double* angles, const do
                         double mu = vol[(k * g->ny + j) * g->nx + i];
                         sf_fp fp;
                         long a0, a1, b0, b1;
-                        if (mu == 0.0 || !sf_footprint(g, &bv, sobj, i, j, k, &fp)) continue;
+                        if (mu == 0.0 || !sf_footprint_kind(g, &bv, sobj, kind, dom, i, j, k, &fp)) continue;
                         sf_window(g, &fp, &a0, &a1, &b0, &b1);
                         for (long b = b0; b <= b1; ++b)
                             for (long a = a0; a <= a1; ++a) loc[b * g->nu + a] += sf_weight(&fp, a, b) * mu;
@@ -913,8 +948,8 @@ void dpref_sf_project(const dpref_geom* g, int V, const double* angles, const do
     }
 }
 
-void dpref_sf_backproject(const dpref_geom* g, int V, const double* angles, const double* poses,
-                          const double* proj, double* vol)
+void dpref_fp_backproject(const dpref_geom* g, int V, const double* angles, const double* poses,
+                          const double* proj, double* vol, int kind)
 {
     long npix = (long)g->nu * g->nv;
     bp_view* bvs = make_bp_views(g, V, angles, poses);
@@ -929,7 +964,7 @@ void dpref_sf_backproject(const dpref_geom* g, int V, const double* angles, cons
                 for (int v = 0; v < V; ++v) {
                     sf_fp fp;
                     long a0, a1, b0, b1;
-                    if (!sf_footprint(g, &bvs[v], src + 3 * v, i, j, k, &fp)) continue;
+                    if (!sf_footprint_kind(g, &bvs[v], src + 3 * v, kind, dd_dominant(src + 3 * v), i, j, k, &fp)) continue;
                     sf_window(g, &fp, &a0, &a1, &b0, &b1);
                     for (long b = b0; b <= b1; ++b)
                         for (long a = a0; a <= a1; ++a)
@@ -941,8 +976,8 @@ void dpref_sf_backproject(const dpref_geom* g, int V, const double* angles, cons
     free(src);
 }
 
-void dpref_sf_project_grad_M(const dpref_geom* g, int V, const double* angles, const double* poses,
-                             const double* vol, const double* grad_proj, double* dLdM)
+void dpref_fp_project_grad_M(const dpref_geom* g, int V, const double* angles, const double* poses,
+                             const double* vol, const double* grad_proj, double* dLdM, int kind)
 {
     long npix = (long)g->nu * g->nv;
     double* gr = volume_gradient(g, vol);
@@ -952,6 +987,7 @@ void dpref_sf_project_grad_M(const dpref_geom* g, int V, const double* angles, c
         view_pose vp = make_view(g, angles, poses, v);
         double sobj[3], acc[12] = {0};
         source_object_frame(g, angles[v], &bv, sobj);
+        const int dom = dd_dominant(sobj);
         const double* w = grad_proj + v * npix;
 #pragma omp parallel
         {
@@ -963,7 +999,7 @@ void dpref_sf_project_grad_M(const dpref_geom* g, int V, const double* angles, c
                         sf_fp fp;
                         long a0, a1, b0, b1;
                         double G[12], s = 0.0;
-                        if (!sf_footprint(g, &bv, sobj, i, j, k, &fp)) continue;
+                        if (!sf_footprint_kind(g, &bv, sobj, kind, dom, i, j, k, &fp)) continue;
                         sf_window(g, &fp, &a0, &a1, &b0, &b1);
                         for (long b = b0; b <= b1; ++b)
                             for (long a = a0; a <= a1; ++a) s += sf_weight(&fp, a, b) * w[b * g->nu + a];
@@ -979,9 +1015,9 @@ void dpref_sf_project_grad_M(const dpref_geom* g, int V, const double* angles, c
     free(gr);
 }
 
-void dpref_sf_backproject_grad_M(const dpref_geom* g, int V, const double* angles,
+void dpref_fp_backproject_grad_M(const dpref_geom* g, int V, const double* angles,
                                  const double* poses, const double* proj, const double* grad_vol,
-                                 double* dLdM)
+                                 double* dLdM, int kind)
 {
     long npix = (long)g->nu * g->nv;
     double* la = (double*)malloc(sizeof(double) * npix);
@@ -991,6 +1027,7 @@ void dpref_sf_backproject_grad_M(const dpref_geom* g, int V, const double* angle
         bp_view bv = make_bp_view(g, angles, poses, v);
         double sobj[3], acc[12] = {0};
         source_object_frame(g, angles[v], &bv, sobj);
+        const int dom = dd_dominant(sobj);
         image_gradient(proj + v * npix, g->nu, g->nv, la, lb);
 #pragma omp parallel
         {
@@ -1003,7 +1040,7 @@ void dpref_sf_backproject_grad_M(const dpref_geom* g, int V, const double* angle
                         sf_fp fp;
                         long a0, a1, b0, b1;
                         double p[3], r[3], uvw[3], dl[2] = {0.0, 0.0};
-                        if (e == 0.0 || !sf_footprint(g, &bv, sobj, i, j, k, &fp)) continue;
+                        if (e == 0.0 || !sf_footprint_kind(g, &bv, sobj, kind, dom, i, j, k, &fp)) continue;
                         sf_window(g, &fp, &a0, &a1, &b0, &b1);
                         for (long b = b0; b <= b1; ++b)
                             for (long a = a0; a <= a1; ++a) {
@@ -1030,24 +1067,24 @@ void dpref_sf_backproject_grad_M(const dpref_geom* g, int V, const double* angle
     free(lb);
 }
 
-void dpref_sf_project_grad_pose(const dpref_geom* g, int V, const double* angles,
+void dpref_fp_project_grad_pose(const dpref_geom* g, int V, const double* angles,
                                 const double* poses, const double* vol, const double* grad_proj,
-                                double* grad_pose)
+                                double* grad_pose, int kind)
 {
     double* dLdM = (double*)malloc(sizeof(double) * 12 * (V > 0 ? V : 1));
     if (!dLdM) return;
-    dpref_sf_project_grad_M(g, V, angles, poses, vol, grad_proj, dLdM);
+    dpref_fp_project_grad_M(g, V, angles, poses, vol, grad_proj, dLdM, kind);
     for (int v = 0; v < V; ++v) dpref_contract_pose(poses + 6 * v, dLdM + 12 * v, grad_pose + 6 * v);
     free(dLdM);
 }
 
-void dpref_sf_backproject_grad_pose(const dpref_geom* g, int V, const double* angles,
+void dpref_fp_backproject_grad_pose(const dpref_geom* g, int V, const double* angles,
                                     const double* poses, const double* proj, const double* grad_vol,
-                                    double* grad_pose)
+                                    double* grad_pose, int kind)
 {
     double* dLdM = (double*)malloc(sizeof(double) * 12 * (V > 0 ? V : 1));
     if (!dLdM) return;
-    dpref_sf_backproject_grad_M(g, V, angles, poses, proj, grad_vol, dLdM);
+    dpref_fp_backproject_grad_M(g, V, angles, poses, proj, grad_vol, dLdM, kind);
     for (int v = 0; v < V; ++v) dpref_contract_pose(poses + 6 * v, dLdM + 12 * v, grad_pose + 6 * v);
     free(dLdM);
 }

@@ -94,20 +94,21 @@ void dpref_backproject_grad_pose(const dpref_geom* g, int V, const double* angle
 void dpref_contract_pose(const double pose[6], const double dLdM[12], double grad[6]);
 
 
-/* Separable-footprint projector pair and pose gradients (oracle). */
-void dpref_sf_project(const dpref_geom* g, int V, const double* angles, const double* poses,
-                      const double* vol, double* proj);
-void dpref_sf_backproject(const dpref_geom* g, int V, const double* angles, const double* poses,
-                          const double* proj, double* vol);
-void dpref_sf_project_grad_M(const dpref_geom* g, int V, const double* angles, const double* poses,
-                             const double* vol, const double* grad_proj, double* dLdM);
-void dpref_sf_backproject_grad_M(const dpref_geom* g, int V, const double* angles,
+/* Footprint projector pairs and pose gradients (oracle); kind 0 = separable
+ * footprint (SF), 1 = distance-driven (DD). */
+void dpref_fp_project(const dpref_geom* g, int V, const double* angles, const double* poses,
+                      const double* vol, double* proj, int kind);
+void dpref_fp_backproject(const dpref_geom* g, int V, const double* angles, const double* poses,
+                          const double* proj, double* vol, int kind);
+void dpref_fp_project_grad_M(const dpref_geom* g, int V, const double* angles, const double* poses,
+                             const double* vol, const double* grad_proj, double* dLdM, int kind);
+void dpref_fp_backproject_grad_M(const dpref_geom* g, int V, const double* angles,
                                  const double* poses, const double* proj, const double* grad_vol,
-                                 double* dLdM);
-void dpref_sf_project_grad_pose(const dpref_geom* g, int V, const double* angles,
+                                 double* dLdM, int kind);
+void dpref_fp_project_grad_pose(const dpref_geom* g, int V, const double* angles,
                                 const double* poses, const double* vol, const double* grad_proj,
-                                double* grad_pose);
-void dpref_sf_backproject_grad_pose(const dpref_geom* g, int V, const double* angles,
+                                double* grad_pose, int kind);
+void dpref_fp_backproject_grad_pose(const dpref_geom* g, int V, const double* angles,
                                     const double* poses, const double* proj, const double* grad_vol,
-                                    double* grad_pose);
+                                    double* grad_pose, int kind);
 #endif
