@@ -82,7 +82,7 @@ enum { DP_W_NONE = 0, DP_W_FDK = 1 };
 
 enum {
     DP_OP_FWD = 0, DP_OP_FWD_GRAD = 1, DP_OP_BP = 2, DP_OP_BP_GRAD = 3, DP_OP_FWD_SSD = 4,
-    DP_OP_SF_FWD = 5, DP_OP_SF_FWD_GRAD = 6, DP_OP_SF_BP = 7, DP_OP_SF_BP_GRAD = 8
+    DP_OP_FP_FWD = 5, DP_OP_FP_FWD_GRAD = 6, DP_OP_FP_BP = 7, DP_OP_FP_BP_GRAD = 8
 };
 
 /* Workspace size (bytes) needed by operation `op` (DP_OP_*) for this
@@ -223,33 +223,44 @@ int dp_act_bwd_bf16(int64_t total, const float* dy, const void* y, int32_t relu,
 int dp_colsum_bf16(int32_t M, int32_t C, const void* dz, float* db, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Separable-footprint (SF) projector pair and its pose gradients (the
- * discrete projectors of Sec. II-C, l = A mu and mu = A^T l with footprint
- * weights a_ij; gradients by Eqs. dis_forward / dis_back).  Footprint of a
- * voxel moved by the view's pose: a unit-height trapezoid in the detector
- * column (breakpoints: the projected corners of the voxel's mid-height
- * cross-section) times a unit-height rectangle in the row (the projected
- * top and bottom centres), scaled by the voxel's chord along the line from
- * the source through its centre; a_ij = chord x (trapezoid integral over
- * pixel i's column cell) x (rectangle overlap with its row cell).
- * Arguments, layouts and errors as for the ray-driven / voxel-driven
- * entries; workspace: dp_workspace_bytes(g, V, DP_OP_SF_*).
- *   dp_sf_project: proj [V][nv][nu] (overwritten) = A vol (FP32 atomic
+ * Footprint projector pairs and their pose gradients (the discrete
+ * projectors of Sec. II-C, l = A mu and mu = A^T l with footprint weights
+ * a_ij; gradients by Eqs. dis_forward / dis_back).  The footprint of a
+ * voxel moved by the view's pose is a unit-height shape in the detector
+ * column times a unit-height rectangle in the row (the projected top and
+ * bottom centres), scaled by an amplitude:
+ *   DP_FP_SF (separable footprint): trapezoid with breakpoints at the
+ *     projected corners of the voxel's mid-height cross-section; amplitude
+ *     the voxel's chord along the line from the source through its centre;
+ *   DP_FP_DD (distance-driven): rectangle between the projected boundaries
+ *     across the view's dominant transaxial axis (x if the source's
+ *     object-frame offset from the volume centre has |x| >= |y|, else y);
+ *     amplitude the path through the slab along that axis.
+ * a_ij = amplitude x (column shape integrated over pixel i's column cell)
+ * x (row rectangle's overlap with its row cell).  Arguments, layouts and
+ * errors as for the ray-driven / voxel-driven entries; kind must be
+ * DP_FP_SF or DP_FP_DD; workspace: dp_workspace_bytes(g, V, DP_OP_FP_*).
+ *   dp_fp_project: proj [V][nv][nu] (overwritten) = A vol (FP32 atomic
  *     accumulation: not bitwise reproducible).
- *   dp_sf_backproject: vol (overwritten) = A^T proj (no angular weight).
- *   dp_sf_project_grad_pose: dL/dtheta [V][6] from dL/dl = grad_proj.
- *   dp_sf_backproject_grad_pose: dL/dtheta [V][6] from dL/dmu = grad_vol.
+ *   dp_fp_backproject: vol (overwritten) = A^T proj (no angular weight).
+ *   dp_fp_project_grad_pose: dL/dtheta [V][6] from dL/dl = grad_proj.
+ *   dp_fp_backproject_grad_pose: dL/dtheta [V][6] from dL/dmu = grad_vol.
  * ------------------------------------------------------------------------- */
-int dp_sf_project(const dp_geom* g, int32_t n_views, const double* angles, const double* poses,
-                  const float* vol, float* proj, void* ws, size_t ws_bytes, void* stream);
-int dp_sf_backproject(const dp_geom* g, int32_t n_views, const double* angles, const double* poses,
-                      const float* proj, float* vol, void* ws, size_t ws_bytes, void* stream);
-int dp_sf_project_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
+enum { DP_FP_SF = 0, DP_FP_DD = 1 };
+int dp_fp_project(const dp_geom* g, int32_t n_views, const double* angles, const double* poses,
+                  const float* vol, float* proj, int32_t kind, void* ws, size_t ws_bytes,
+                  void* stream);
+int dp_fp_backproject(const dp_geom* g, int32_t n_views, const double* angles, const double* poses,
+                      const float* proj, float* vol, int32_t kind, void* ws, size_t ws_bytes,
+                      void* stream);
+int dp_fp_project_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
                             const double* poses, const float* vol, const float* grad_proj,
-                            double* grad_pose, void* ws, size_t ws_bytes, void* stream);
-int dp_sf_backproject_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
+                            double* grad_pose, int32_t kind, void* ws, size_t ws_bytes,
+                            void* stream);
+int dp_fp_backproject_grad_pose(const dp_geom* g, int32_t n_views, const double* angles,
                                 const double* poses, const float* proj, const float* grad_vol,
-                                double* grad_pose, void* ws, size_t ws_bytes, void* stream);
+                                double* grad_pose, int32_t kind, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /* ---------------------------------------------------------------------------
  * Motion-compensated FDK reconstruction (Sec. III-B, motion-compensated

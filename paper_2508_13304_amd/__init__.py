@@ -21,17 +21,18 @@ LIB_PATH = os.path.join(_HERE, "libdiffproj.so")
 W_NONE = 0
 W_FDK = 1
 OP_FWD, OP_FWD_GRAD, OP_BP, OP_BP_GRAD, OP_FWD_SSD = 0, 1, 2, 3, 4
-OP_SF_FWD, OP_SF_FWD_GRAD, OP_SF_BP, OP_SF_BP_GRAD = 5, 6, 7, 8
+OP_FP_FWD, OP_FP_FWD_GRAD, OP_FP_BP, OP_FP_BP_GRAD = 5, 6, 7, 8
+FP_KINDS = {"sf": 0, "dd": 1}  # separable footprint, distance-driven
 KERNELS = ("setup", "vol_prep", "rd_fwd", "rd_grad", "det_prep", "vd_bp", "vd_grad", "finalize",
-           "fdk_filter", "sharpness", "rd_fused", "sf")
+           "fdk_filter", "sharpness", "rd_fused", "footprint")
 
 EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "dp_backproject",
            "dp_backproject_grad_pose", "dp_last_error", "dp_version", "dp_profile_enable",
            "dp_profile_collect", "dp_profile_read", "dp_batch_workspace_bytes",
            "dp_project_fwd_batch", "dp_project_fwd_grad_pose_batch", "dp_autotune",
            "dp_set_variant", "dp_get_variant", "dp_project_fwd_ssd_grad_pose",
-           "dp_project_fwd_ssd_gauss_newton", "dp_sf_project", "dp_sf_backproject",
-           "dp_sf_project_grad_pose", "dp_sf_backproject_grad_pose", "dp_fdk_filter", "dp_sharpness",
+           "dp_project_fwd_ssd_gauss_newton", "dp_fp_project", "dp_fp_backproject",
+           "dp_fp_project_grad_pose", "dp_fp_backproject_grad_pose", "dp_fdk_filter", "dp_sharpness",
            "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
            "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16")
@@ -102,11 +103,11 @@ def load(path: str | None = None):
     lib.dp_set_variant.restype = C.c_int
     lib.dp_get_variant.argtypes = [g, i32, i32]
     lib.dp_get_variant.restype = i32
-    for f in ("dp_sf_project", "dp_sf_backproject"):
-        getattr(lib, f).argtypes = [g, i32, vp, vp, vp, vp, vp, sz, vp]
+    for f in ("dp_fp_project", "dp_fp_backproject"):
+        getattr(lib, f).argtypes = [g, i32, vp, vp, vp, vp, i32, vp, sz, vp]
         getattr(lib, f).restype = C.c_int
-    for f in ("dp_sf_project_grad_pose", "dp_sf_backproject_grad_pose"):
-        getattr(lib, f).argtypes = [g, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    for f in ("dp_fp_project_grad_pose", "dp_fp_backproject_grad_pose"):
+        getattr(lib, f).argtypes = [g, i32, vp, vp, vp, vp, vp, i32, vp, sz, vp]
         getattr(lib, f).restype = C.c_int
     lib.dp_fdk_filter.argtypes = [g, i32, vp, vp, C.c_double, vp]
     lib.dp_fdk_filter.restype = C.c_int
@@ -388,65 +389,70 @@ def autotune(op, geom, angles, poses, vol, out, grad_proj=None, ws=None, reps=3,
     return best.value, list(ms)
 
 
-def sf_project(geom, angles, poses, vol, out=None, ws=None, stream=None):
-    """Separable-footprint DRRs [V][nv][nu] f32 (FP32 atomic accumulation)."""
+def fp_project(geom, angles, poses, vol, kind="sf", out=None, ws=None, stream=None):
+    """Footprint-projector DRRs [V][nv][nu] f32; kind "sf" (separable
+    footprint) or "dd" (distance-driven).  FP32 atomic accumulation."""
     import torch
     V = _views(angles, poses)
     if out is None:
         out = torch.empty((V, geom.nv, geom.nu), dtype=torch.float32, device=vol.device)
-    ws = _workspace(geom, V, OP_SF_FWD, ws, vol.device)
-    rc = load().dp_sf_project(C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
+    ws = _workspace(geom, V, OP_FP_FWD, ws, vol.device)
+    rc = load().dp_fp_project(C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
                               _dev(poses, torch.float64, "poses"),
                               _dev(vol, torch.float32, "vol", (geom.nz, geom.ny, geom.nx)),
-                              _dev(out, torch.float32, "out", (V, geom.nv, geom.nu)),
+                              _dev(out, torch.float32, "out", (V, geom.nv, geom.nu)), FP_KINDS[kind],
                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
-    _check(rc, "dp_sf_project")
+    _check(rc, "dp_fp_project")
     return out
 
 
-def sf_backproject(geom, angles, poses, proj, out=None, ws=None, stream=None):
-    """Separable-footprint back-projection [nz][ny][nx] f32 (the transpose of sf_project)."""
+def fp_backproject(geom, angles, poses, proj, kind="sf", out=None, ws=None, stream=None):
+    """Footprint back-projection [nz][ny][nx] f32 (the transpose of fp_project)."""
     import torch
     V = _views(angles, poses)
     if out is None:
         out = torch.empty((geom.nz, geom.ny, geom.nx), dtype=torch.float32, device=proj.device)
-    ws = _workspace(geom, V, OP_SF_BP, ws, proj.device)
-    rc = load().dp_sf_backproject(C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
+    ws = _workspace(geom, V, OP_FP_BP, ws, proj.device)
+    rc = load().dp_fp_backproject(C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
                                   _dev(poses, torch.float64, "poses"),
                                   _dev(proj, torch.float32, "proj", (V, geom.nv, geom.nu)),
                                   _dev(out, torch.float32, "out", (geom.nz, geom.ny, geom.nx)),
-                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
-    _check(rc, "dp_sf_backproject")
+                                  FP_KINDS[kind], C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "dp_fp_backproject")
     return out
 
 
-def sf_project_grad_pose(geom, angles, poses, vol, grad_proj, out=None, ws=None, stream=None):
+def fp_project_grad_pose(geom, angles, poses, vol, grad_proj, kind="sf", out=None, ws=None,
+                         stream=None):
     import torch
     V = _views(angles, poses)
     if out is None:
         out = torch.empty((V, 6), dtype=torch.float64, device=vol.device)
-    ws = _workspace(geom, V, OP_SF_FWD_GRAD, ws, vol.device)
-    rc = load().dp_sf_project_grad_pose(
+    ws = _workspace(geom, V, OP_FP_FWD_GRAD, ws, vol.device)
+    rc = load().dp_fp_project_grad_pose(
         C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
         _dev(poses, torch.float64, "poses"), _dev(vol, torch.float32, "vol", (geom.nz, geom.ny, geom.nx)),
         _dev(grad_proj, torch.float32, "grad_proj", (V, geom.nv, geom.nu)),
-        _dev(out, torch.float64, "out", (V, 6)), C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
-    _check(rc, "dp_sf_project_grad_pose")
+        _dev(out, torch.float64, "out", (V, 6)), FP_KINDS[kind], C.c_void_p(ws.data_ptr()), ws.numel(),
+        _stream(stream))
+    _check(rc, "dp_fp_project_grad_pose")
     return out
 
 
-def sf_backproject_grad_pose(geom, angles, poses, proj, grad_vol, out=None, ws=None, stream=None):
+def fp_backproject_grad_pose(geom, angles, poses, proj, grad_vol, kind="sf", out=None, ws=None,
+                             stream=None):
     import torch
     V = _views(angles, poses)
     if out is None:
         out = torch.empty((V, 6), dtype=torch.float64, device=proj.device)
-    ws = _workspace(geom, V, OP_SF_BP_GRAD, ws, proj.device)
-    rc = load().dp_sf_backproject_grad_pose(
+    ws = _workspace(geom, V, OP_FP_BP_GRAD, ws, proj.device)
+    rc = load().dp_fp_backproject_grad_pose(
         C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
         _dev(poses, torch.float64, "poses"), _dev(proj, torch.float32, "proj", (V, geom.nv, geom.nu)),
         _dev(grad_vol, torch.float32, "grad_vol", (geom.nz, geom.ny, geom.nx)),
-        _dev(out, torch.float64, "out", (V, 6)), C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
-    _check(rc, "dp_sf_backproject_grad_pose")
+        _dev(out, torch.float64, "out", (V, 6)), FP_KINDS[kind], C.c_void_p(ws.data_ptr()), ws.numel(),
+        _stream(stream))
+    _check(rc, "dp_fp_backproject_grad_pose")
     return out
 
 

@@ -78,15 +78,15 @@ Layout layout(const dp_geom& g, int V, int op)
     case DP_OP_BP:
         off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float));
         break;
-    case DP_OP_SF_FWD:
-    case DP_OP_SF_BP:
+    case DP_OP_FP_FWD:
+    case DP_OP_FP_BP:
         break;
-    case DP_OP_SF_FWD_GRAD:
+    case DP_OP_FP_FWD_GRAD:
         L.n_part = (size_t)sf_blocks(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
         break;
-    case DP_OP_SF_BP_GRAD:
+    case DP_OP_FP_BP_GRAD:
         off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float4));
         L.n_part = (size_t)sf_blocks(s);
         L.partials = off;
@@ -235,7 +235,7 @@ int32_t dp_version(void) { return 10000; }
 
 size_t dp_workspace_bytes(const dp_geom* g, int32_t n_views, int32_t op)
 {
-    if (op < DP_OP_FWD || op > DP_OP_SF_BP_GRAD) return 0;
+    if (op < DP_OP_FWD || op > DP_OP_FP_BP_GRAD) return 0;
     if (check_geom(g, n_views) != DP_OK) return 0;
     return layout(*g, n_views, op).total;
 }
@@ -330,74 +330,78 @@ int dp_project_fwd_ssd_gauss_newton(const dp_geom* g, int32_t V, const double* a
                    stream, "dp_project_fwd_ssd_gauss_newton");
 }
 
-// --- separable-footprint pair --------------------------------------------
+// --- footprint projector pairs (SF, DD) --------------------------------------------
 
 static int sf_common(const dp_geom* g, int32_t V, const double* angles, const double* poses,
-                     const void* a, const void* b, int op, void* ws, size_t ws_bytes)
+                     const void* a, const void* b, int op, int kind, void* ws, size_t ws_bytes)
 {
     int rc = check_geom(g, V);
     if (rc) return rc;
+    if (kind != DP_FP_SF && kind != DP_FP_DD) return fail(DP_ERR_ARG, "unknown footprint kind %d", kind);
     if (!angles || !poses || !a || !b) return fail(DP_ERR_ARG, "NULL array argument");
     return check_ws(g, V, op, ws, ws_bytes);
 }
 
-int dp_sf_project(const dp_geom* g, int32_t V, const double* angles, const double* poses,
-                  const float* vol, float* proj, void* ws, size_t ws_bytes, void* stream)
+int dp_fp_project(const dp_geom* g, int32_t V, const double* angles, const double* poses,
+                  const float* vol, float* proj, int32_t kind, void* ws, size_t ws_bytes,
+                  void* stream)
 {
-    int rc = sf_common(g, V, angles, poses, vol, proj, DP_OP_SF_FWD, ws, ws_bytes);
+    int rc = sf_common(g, V, angles, poses, vol, proj, DP_OP_FP_FWD, kind, ws, ws_bytes);
     if (rc) return rc;
-    const Layout L = layout(*g, V, DP_OP_SF_FWD);
+    const Layout L = layout(*g, V, DP_OP_FP_FWD);
     const GeoScalars s = make_scalars(*g);
     hipStream_t st = (hipStream_t)stream;
     ViewGeo* views = (ViewGeo*)((char*)ws + L.views);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_sf_fwd(s, V, views, vol, proj, st);
-    return check_launch("dp_sf_project");
+    launch_sf_fwd(s, V, views, vol, proj, kind, st);
+    return check_launch("dp_fp_project");
 }
 
-int dp_sf_backproject(const dp_geom* g, int32_t V, const double* angles, const double* poses,
-                      const float* proj, float* vol, void* ws, size_t ws_bytes, void* stream)
+int dp_fp_backproject(const dp_geom* g, int32_t V, const double* angles, const double* poses,
+                      const float* proj, float* vol, int32_t kind, void* ws, size_t ws_bytes,
+                      void* stream)
 {
-    int rc = sf_common(g, V, angles, poses, proj, vol, DP_OP_SF_BP, ws, ws_bytes);
+    int rc = sf_common(g, V, angles, poses, proj, vol, DP_OP_FP_BP, kind, ws, ws_bytes);
     if (rc) return rc;
-    const Layout L = layout(*g, V, DP_OP_SF_BP);
+    const Layout L = layout(*g, V, DP_OP_FP_BP);
     const GeoScalars s = make_scalars(*g);
     hipStream_t st = (hipStream_t)stream;
     ViewGeo* views = (ViewGeo*)((char*)ws + L.views);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_sf_bp(s, V, views, proj, vol, st);
-    return check_launch("dp_sf_backproject");
+    launch_sf_bp(s, V, views, proj, vol, kind, st);
+    return check_launch("dp_fp_backproject");
 }
 
-int dp_sf_project_grad_pose(const dp_geom* g, int32_t V, const double* angles, const double* poses,
-                            const float* vol, const float* grad_proj, double* grad_pose, void* ws,
-                            size_t ws_bytes, void* stream)
+int dp_fp_project_grad_pose(const dp_geom* g, int32_t V, const double* angles, const double* poses,
+                            const float* vol, const float* grad_proj, double* grad_pose,
+                            int32_t kind, void* ws, size_t ws_bytes, void* stream)
 {
-    int rc = sf_common(g, V, angles, poses, vol, grad_proj, DP_OP_SF_FWD_GRAD, ws, ws_bytes);
+    int rc = sf_common(g, V, angles, poses, vol, grad_proj, DP_OP_FP_FWD_GRAD, kind, ws, ws_bytes);
     if (rc) return rc;
     if (!grad_pose) return fail(DP_ERR_ARG, "NULL array argument");
-    const Layout L = layout(*g, V, DP_OP_SF_FWD_GRAD);
+    const Layout L = layout(*g, V, DP_OP_FP_FWD_GRAD);
     const GeoScalars s = make_scalars(*g);
     hipStream_t st = (hipStream_t)stream;
     ViewGeo* views = (ViewGeo*)((char*)ws + L.views);
     float* part = (float*)((char*)ws + L.partials);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_sf_fwd_grad(s, V, views, vol, grad_proj, part, st);
+    launch_sf_fwd_grad(s, V, views, vol, grad_proj, part, kind, st);
     launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
-    return check_launch("dp_sf_project_grad_pose");
+    return check_launch("dp_fp_project_grad_pose");
 }
 
-int dp_sf_backproject_grad_pose(const dp_geom* g, int32_t V, const double* angles,
+int dp_fp_backproject_grad_pose(const dp_geom* g, int32_t V, const double* angles,
                                 const double* poses, const float* proj, const float* grad_vol,
-                                double* grad_pose, void* ws, size_t ws_bytes, void* stream)
+                                double* grad_pose, int32_t kind, void* ws, size_t ws_bytes,
+                                void* stream)
 {
-    int rc = sf_common(g, V, angles, poses, proj, grad_vol, DP_OP_SF_BP_GRAD, ws, ws_bytes);
+    int rc = sf_common(g, V, angles, poses, proj, grad_vol, DP_OP_FP_BP_GRAD, kind, ws, ws_bytes);
     if (rc) return rc;
     if (!grad_pose) return fail(DP_ERR_ARG, "NULL array argument");
-    const Layout L = layout(*g, V, DP_OP_SF_BP_GRAD);
+    const Layout L = layout(*g, V, DP_OP_FP_BP_GRAD);
     const GeoScalars s = make_scalars(*g);
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
@@ -407,9 +411,9 @@ int dp_sf_backproject_grad_pose(const dp_geom* g, int32_t V, const double* angle
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
     launch_det_grad(s, V, proj, proj4, st);
-    launch_sf_bp_grad(s, V, views, proj4, grad_vol, part, st);
+    launch_sf_bp_grad(s, V, views, proj4, grad_vol, part, kind, st);
     launch_finalize_bp(s, V, views, part, (int)L.n_part, grad_pose, st);
-    return check_launch("dp_sf_backproject_grad_pose");
+    return check_launch("dp_fp_backproject_grad_pose");
 }
 
 int dp_backproject(const dp_geom* g, int32_t V, const double* angles, const double* poses,

@@ -125,14 +125,15 @@ void launch_colsum(int M, int C, const void* dz, float* db, hipStream_t st);
 
 // Separable-footprint projector pair and gradients (sf.hip).
 int sf_blocks(const GeoScalars& s);
+// kind: DP_FP_SF or DP_FP_DD
 void launch_sf_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* vol, float* proj,
-                   hipStream_t st);
+                   int kind, hipStream_t st);
 void launch_sf_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* proj, float* vol,
-                  hipStream_t st);
+                  int kind, hipStream_t st);
 void launch_sf_fwd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol,
-                        const float* grad_proj, float* partials, hipStream_t st);
+                        const float* grad_proj, float* partials, int kind, hipStream_t st);
 void launch_sf_bp_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
-                       const float* grad_vol, float* partials, hipStream_t st);
+                       const float* grad_vol, float* partials, int kind, hipStream_t st);
 
 // FDK pre-filter and sharpness loss (fdk.hip).
 void launch_fdk_filter(const GeoScalars& s, int V, const float* proj, float* out, double scale,

@@ -1,7 +1,15 @@
-// Separable-footprint (SF) projector pair and its rigid-motion gradients
-// (the discrete projectors l = A mu, mu = A^T l of Sec. II-C with footprint
-// weights a_ij; gradients by Eqs. dis_forward / dis_back: the same weights
-// applied to G_f per voxel and to G_b per pixel).
+// Footprint projector pairs -- separable footprint (SF) and distance-driven
+// (DD) -- and their rigid-motion gradients (the discrete projectors
+// l = A mu, mu = A^T l of Sec. II-C with footprint weights a_ij; gradients by
+// Eqs. dis_forward / dis_back: the same weights applied to G_f per voxel and
+// to G_b per pixel).
+//
+// DD replaces the transaxial trapezoid by a unit-height rectangle between
+// the projections of the voxel's two boundaries across the view's dominant
+// transaxial axis (x if the source's object-frame offset from the volume
+// centre has |x| >= |y|, else y), taken at the voxel centre, and the chord
+// by the path length h_dom |d| / |d_dom| through the slab along that axis.
+// Everything else below is shared.
 //
 // Footprint of voxel j in one view, with the voxel moved by the pose (the
 // view's projective map on voxel indices, FP64):
@@ -33,6 +41,7 @@
 namespace dp {
 
 constexpr int kSfBx = 64, kSfBy = 4, kSfCol = 8;
+constexpr int kFpSF = DP_FP_SF, kFpDD = DP_FP_DD;
 
 struct SfFootprint {
     double tau[4];
@@ -63,32 +72,48 @@ __device__ inline double row_overlap(int b, double lo, double hi)
 }
 
 // Footprint of voxel (i, j, k) in view g; false if any projected point lies
-// at or behind the source plane.  src: the source in object-frame index units.
+// at or behind the source plane.  src: the source in object-frame index
+// units; dom: DD's dominant axis of the view (0 = x, 1 = y).
+template <int KIND>
 __device__ inline bool sf_footprint(const ViewGeo& g, const GeoScalars& s, const double* src,
-                                    int i, int j, int k, SfFootprint& f)
+                                    int dom, int i, int j, int k, SfFootprint& f)
 {
     const double fi = i, fj = j, fk = k;
     const double U0 = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
     const double V0 = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
     const double W0 = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], fk, g.PWd[3])));
     double t[4];
+    if (KIND == kFpSF) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const double dx = (c & 1) ? 0.5 : -0.5, dy = (c & 2) ? 0.5 : -0.5;
-        const double U = fma(g.PUd[0], dx, fma(g.PUd[1], dy, U0));
-        const double W = fma(g.PWd[0], dx, fma(g.PWd[1], dy, W0));
-        if (!(W > 0.0)) return false;
-        t[c] = U / W + s.cu;
-    }
-    // sort the four breakpoints (5 compare-exchanges)
-#define DP_CX(p, q)                                      \
-    {                                                    \
+        for (int c = 0; c < 4; ++c) {
+            const double dx = (c & 1) ? 0.5 : -0.5, dy = (c & 2) ? 0.5 : -0.5;
+            const double U = fma(g.PUd[0], dx, fma(g.PUd[1], dy, U0));
+            const double W = fma(g.PWd[0], dx, fma(g.PWd[1], dy, W0));
+            if (!(W > 0.0)) return false;
+            t[c] = U / W + s.cu;
+        }
+        // sort the four breakpoints (5 compare-exchanges)
+#define DP_CX(p, q)                                                  \
+    {                                                                \
         const double lo_ = fmin(t[p], t[q]), hi_ = fmax(t[p], t[q]); \
-        t[p] = lo_;                                      \
-        t[q] = hi_;                                      \
+        t[p] = lo_;                                                  \
+        t[q] = hi_;                                                  \
     }
-    DP_CX(0, 1) DP_CX(2, 3) DP_CX(0, 2) DP_CX(1, 3) DP_CX(1, 2)
+        DP_CX(0, 1) DP_CX(2, 3) DP_CX(0, 2) DP_CX(1, 3) DP_CX(1, 2)
 #undef DP_CX
+    } else {
+        double e[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double off = c ? 0.5 : -0.5;
+            const int ax = dom == 0 ? 1 : 0;  // boundaries across the other transaxial axis
+            const double U = fma(g.PUd[ax], off, U0), W = fma(g.PWd[ax], off, W0);
+            if (!(W > 0.0)) return false;
+            e[c] = U / W + s.cu;
+        }
+        t[0] = t[1] = fmin(e[0], e[1]);
+        t[2] = t[3] = fmax(e[0], e[1]);
+    }
     double bb[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -100,14 +125,20 @@ __device__ inline bool sf_footprint(const ViewGeo& g, const GeoScalars& s, const
     for (int c = 0; c < 4; ++c) f.tau[c] = t[c];
     f.blo = fmin(bb[0], bb[1]);
     f.bhi = fmax(bb[0], bb[1]);
-    // central chord: min over axes of h_a |d| / |d_a|, d from the source to the centre (mm)
+    // amplitude from d, the line from the source to the centre (mm):
+    // SF the chord min_a h_a |d| / |d_a|, DD the slab path h_dom |d| / |d_dom|
     const double h[3] = {s.vx, s.vy, s.vz};
     const double d[3] = {(fi - src[0]) * h[0], (fj - src[1]) * h[1], (fk - src[2]) * h[2]};
     const double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    double L = INFINITY;
+    double L;
+    if (KIND == kFpSF) {
+        L = INFINITY;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        if (d[c] != 0.0) L = fmin(L, h[c] * n / fabs(d[c]));
+        for (int c = 0; c < 3; ++c)
+            if (d[c] != 0.0) L = fmin(L, h[c] * n / fabs(d[c]));
+    } else {
+        L = d[dom] != 0.0 ? h[dom] * n / fabs(d[dom]) : 0.0;
+    }
     f.L = L;
     // window, clamped in FP64 before the integer conversion
     f.a0 = (int)fmax(floor(t[0] - 0.5) + 1.0, 0.0);
@@ -122,11 +153,14 @@ __device__ inline double sf_col_weight(const SfFootprint& f, int a)
     return trap_cdf(a + 0.5, f.tau) - trap_cdf(a - 0.5, f.tau);
 }
 
-// Source position in object-frame (unpadded) voxel-index units.
-__device__ inline void sf_source(const ViewGeo& g, const GeoScalars& s, double* src)
+// Source position in object-frame (unpadded) voxel-index units, and the
+// view's dominant transaxial axis for DD (0 = x, 1 = y).
+__device__ inline int sf_source(const ViewGeo& g, const GeoScalars& s, double* src)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) src[c] = g.OT[c] - kPadV - s.sad * g.EW[c];
+    const double ox = (src[0] - 0.5 * (s.nx - 1)) * s.vx, oy = (src[1] - 0.5 * (s.ny - 1)) * s.vy;
+    return fabs(ox) >= fabs(oy) ? 0 : 1;
 }
 
 // Gather sum_i a_ij img_i over the footprint (img: [nv][nu]).
@@ -143,6 +177,7 @@ __device__ inline double sf_gather(const SfFootprint& f, const float* __restrict
     return f.L * acc;
 }
 
+template <int KIND>
 __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_kernel(GeoScalars s, int V,
                                                                const ViewGeo* __restrict__ views,
                                                                const float* __restrict__ vol,
@@ -159,9 +194,9 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_kernel(GeoScalars s, int
         for (int v = 0; v < V; ++v) {
             const ViewGeo& g = views[v];
             double src[3];
-            sf_source(g, s, src);
+            const int dom = sf_source(g, s, src);
             SfFootprint f;
-            if (!sf_footprint(g, s, src, i, j, k, f)) continue;
+            if (!sf_footprint<KIND>(g, s, src, dom, i, j, k, f)) continue;
             float* img = proj + (size_t)v * s.nu * s.nv;
             for (int b = f.b0; b <= f.b1; ++b) {
                 const double wb = row_overlap(b, f.blo, f.bhi) * f.L * (double)mu;
@@ -175,6 +210,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_kernel(GeoScalars s, int
     }
 }
 
+template <int KIND>
 __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_kernel(GeoScalars s, int V,
                                                               const ViewGeo* __restrict__ views,
                                                               const float* __restrict__ proj,
@@ -190,13 +226,13 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_kernel(GeoScalars s, int 
     for (int v = 0; v < V; ++v) {
         const ViewGeo& g = views[v];
         double src[3];
-        sf_source(g, s, src);
+        const int dom = sf_source(g, s, src);
         const float* img = proj + (size_t)v * s.nu * s.nv;
 #pragma unroll
         for (int kk = 0; kk < kSfCol; ++kk) {
             if (kb + kk >= s.nz) break;
             SfFootprint f;
-            if (sf_footprint(g, s, src, i, j, kb + kk, f)) acc[kk] += sf_gather(f, img, s.nu);
+            if (sf_footprint<KIND>(g, s, src, dom, i, j, kb + kk, f)) acc[kk] += sf_gather(f, img, s.nu);
         }
     }
 #pragma unroll
@@ -228,6 +264,7 @@ __device__ inline float vol_at(const float* __restrict__ v, const GeoScalars& s,
     return v[((size_t)k * s.ny + j) * s.nx + i];
 }
 
+template <int KIND>
 __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s, int V,
                                                                     const ViewGeo* __restrict__ views,
                                                                     const float* __restrict__ vol,
@@ -255,7 +292,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s
     for (int v = 0; v < V; ++v) {
         const ViewGeo& g = views[v];
         double src[3];
-        sf_source(g, s, src);
+        const int dom = sf_source(g, s, src);
         const float* w = grad_proj + (size_t)v * s.nu * s.nv;
         float r[kRdChannels];
 #pragma unroll
@@ -267,7 +304,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s
                 if (k >= s.nz) break;
                 if (G[kk][0] == 0.0f && G[kk][1] == 0.0f && G[kk][2] == 0.0f) continue;
                 SfFootprint f;
-                if (!sf_footprint(g, s, src, i, j, k, f)) continue;
+                if (!sf_footprint<KIND>(g, s, src, dom, i, j, k, f)) continue;
                 const float sj = (float)sf_gather(f, w, s.nu);
                 const float pk = (float)k - 0.5f * (s.nz - 1);
                 const float gx = sj * G[kk][0], gy = sj * G[kk][1], gz = sj * G[kk][2];
@@ -282,6 +319,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s
     }
 }
 
+template <int KIND>
 __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s, int V,
                                                                    const ViewGeo* __restrict__ views,
                                                                    const float4* __restrict__ proj4,
@@ -304,7 +342,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s,
     for (int v = 0; v < V; ++v) {
         const ViewGeo& g = views[v];
         double src[3];
-        sf_source(g, s, src);
+        const int dom = sf_source(g, s, src);
         const float4* img = proj4 + (size_t)v * NU * NV;
         float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
 #pragma unroll
@@ -312,7 +350,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s,
             const int k = kb + kk;
             if (k >= s.nz || e[kk] == 0.0f) continue;
             SfFootprint f;
-            if (!sf_footprint(g, s, src, i, j, k, f)) continue;
+            if (!sf_footprint<KIND>(g, s, src, dom, i, j, k, f)) continue;
             double da = 0.0, db = 0.0;
             for (int b = f.b0; b <= f.b1; ++b) {
                 const double wb = row_overlap(b, f.blo, f.bhi);
@@ -361,39 +399,48 @@ int sf_blocks(const GeoScalars& s)
     return (int)(g.x * g.y * g.z);
 }
 
+#define DP_FP_LAUNCH(KERNEL, ...)                                                           \
+    do {                                                                                    \
+        if (kind == kFpDD)                                                                  \
+            KERNEL<kFpDD><<<sf_grid(s), dim3(kSfBx, kSfBy), 0, st>>>(__VA_ARGS__);          \
+        else                                                                                \
+            KERNEL<kFpSF><<<sf_grid(s), dim3(kSfBx, kSfBy), 0, st>>>(__VA_ARGS__);          \
+    } while (0)
+
 void launch_sf_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* vol, float* proj,
-                   hipStream_t st)
+                   int kind, hipStream_t st)
 {
     const size_t n = (size_t)V * s.nu * s.nv;
     const int zb = (int)std::min<size_t>((n + 255) / 256, 65536);
     prof_begin(DP_K_SF, st);
     sf_zero_kernel<<<zb, 256, 0, st>>>(n, proj);
-    sf_fwd_kernel<<<sf_grid(s), dim3(kSfBx, kSfBy), 0, st>>>(s, V, views, vol, proj);
+    DP_FP_LAUNCH(sf_fwd_kernel, s, V, views, vol, proj);
     prof_end(DP_K_SF, st);
 }
 
 void launch_sf_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* proj, float* vol,
-                  hipStream_t st)
+                  int kind, hipStream_t st)
 {
     prof_begin(DP_K_SF, st);
-    sf_bp_kernel<<<sf_grid(s), dim3(kSfBx, kSfBy), 0, st>>>(s, V, views, proj, vol);
+    DP_FP_LAUNCH(sf_bp_kernel, s, V, views, proj, vol);
     prof_end(DP_K_SF, st);
 }
 
 void launch_sf_fwd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol,
-                        const float* grad_proj, float* partials, hipStream_t st)
+                        const float* grad_proj, float* partials, int kind, hipStream_t st)
 {
     prof_begin(DP_K_SF, st);
-    sf_fwd_grad_kernel<<<sf_grid(s), dim3(kSfBx, kSfBy), 0, st>>>(s, V, views, vol, grad_proj, partials);
+    DP_FP_LAUNCH(sf_fwd_grad_kernel, s, V, views, vol, grad_proj, partials);
     prof_end(DP_K_SF, st);
 }
 
 void launch_sf_bp_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
-                       const float* grad_vol, float* partials, hipStream_t st)
+                       const float* grad_vol, float* partials, int kind, hipStream_t st)
 {
     prof_begin(DP_K_SF, st);
-    sf_bp_grad_kernel<<<sf_grid(s), dim3(kSfBx, kSfBy), 0, st>>>(s, V, views, proj4, grad_vol, partials);
+    DP_FP_LAUNCH(sf_bp_grad_kernel, s, V, views, proj4, grad_vol, partials);
     prof_end(DP_K_SF, st);
 }
+#undef DP_FP_LAUNCH
 
 }  // namespace dp
