@@ -429,6 +429,83 @@ def run_learned(args, dp, torch):
     return res
 
 
+PAPER_LADDER = [(128, 192), (256, 384), (384, 572), (512, 768)]
+# The paper's own cost tables (RTX 4090; context, not targets): seconds for
+# 100 iterations of a differentiable forward projection of 1 view, and for
+# one differentiable back-projection of 256 views.
+PAPER_FWD_S = {"rd": [1.25, 2.44, 6.24, 12.70], "dd": [1.27, 3.84, 11.02, 23.58],
+               "sf": [1.41, 5.03, 14.49, 32.53]}
+PAPER_BP_S = {"vd": [0.17, 1.21, 3.99, 9.50], "dd": [0.65, 4.99, 16.72, 39.52],
+              "sf": [1.12, 8.45, 28.55, 69.72]}
+
+
+def run_paper_ladder(args, dp, torch):
+    """Every projector type at the paper's cost-table shapes: (128n)^3
+    volumes at 256/(128n) mm, (192n)^2 detectors (572 at n = 3) at
+    384/(192n) mm.  Forward: one view, time of 100 iterations of projection +
+    pose gradient (RD: the single-pass SSD kernel; SF, DD: projection then
+    gradient).  Back-projection: 256 views over 360 deg, one back-projection
+    + pose gradient.  Peak device memory per case."""
+    dev = torch.device("cuda:0")
+    out = {"fwd": {}, "bp": {}, "paper_fwd_s": PAPER_FWD_S, "paper_bp_s": PAPER_BP_S,
+           "note": "paper figures are RTX 4090 timings from its cost tables; context only"}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    for n, (nv_, nd) in enumerate(PAPER_LADDER, start=1):
+        h = 256.0 / nv_
+        du = 384.0 / nd
+        g = synth.Geom(nv_, nv_, nv_, h, h, h, nd, nd, du, du)
+        rng = synth.rng_for(5, n)
+        vol = synth.ellipsoid_phantom_torch(nv_, h, 20, rng, dev, shell=True)
+        key = f"{nv_}^3/{nd}^2"
+        # forward, 1 view
+        a1 = torch.zeros(1, dtype=torch.float64, device=dev)
+        p1 = torch.tensor(synth.random_poses(1, 5.0, 5.0, rng), dtype=torch.float64, device=dev)
+        y1 = dp.project_fwd(g, a1, torch.zeros_like(p1), vol)
+        res = {}
+        torch.cuda.reset_peak_memory_stats(dev)
+        res["rd"] = timed(lambda: dp.project_fwd_ssd_grad_pose(g, a1, p1, vol, y1), 10) * 100
+        for kind in ("sf", "dd"):
+            def step(kind=kind):
+                l = dp.fp_project(g, a1, p1, vol, kind)
+                dp.fp_project_grad_pose(g, a1, p1, vol, 2.0 * (l - y1), kind)
+            res[kind] = timed(step, 3) * 100
+        res["peak_gb"] = round(torch.cuda.max_memory_allocated(dev) / 1e9, 3)
+        out["fwd"][key] = {k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()}
+        # back-projection, 256 views
+        V = 256
+        ang = torch.tensor(np.arange(V) * 2 * math.pi / V, dtype=torch.float64, device=dev)
+        pos = torch.tensor(synth.random_poses(V, 2.0, 1.0, rng), dtype=torch.float64, device=dev)
+        gen = torch.Generator(device=dev).manual_seed(n)
+        proj = torch.rand((V, nd, nd), device=dev, generator=gen)
+        e = torch.randn(vol.shape, device=dev, generator=gen)
+        res = {}
+        torch.cuda.reset_peak_memory_stats(dev)
+        def vd_step():
+            dp.backproject(g, ang, pos, proj, dp.W_NONE)
+            dp.backproject_grad_pose(g, ang, pos, proj, e, dp.W_NONE)
+        res["vd"] = timed(vd_step, 2)
+        for kind in ("sf", "dd"):
+            def bstep(kind=kind):
+                dp.fp_backproject(g, ang, pos, proj, kind)
+                dp.fp_backproject_grad_pose(g, ang, pos, proj, e, kind)
+            res[kind] = timed(bstep, 1)
+        res["peak_gb"] = round(torch.cuda.max_memory_allocated(dev) / 1e9, 3)
+        out["bp"][key] = {k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()}
+        log(f"[bench] ladder {key}: fwd(100 it) {out['fwd'][key]} s; bp(256 views) {out['bp'][key]} s")
+        del vol, proj, e
+        torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
@@ -461,6 +538,8 @@ def main():
     ap.add_argument("--no-fwd", action="store_true", help="skip the forward leg (profiling runs)")
     ap.add_argument("--no-reg", action="store_true", help="skip the registration legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch calibration leg")
+    ap.add_argument("--no-ladder", action="store_true",
+                    help="skip the projector-type comparison at the paper's cost-table shapes")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -488,6 +567,7 @@ def main():
     regr = None if args.no_reg else run_registration(args, dp, torch, fw)
     learned = None if args.no_reg else run_learned(args, dp, torch)
     calib = None if args.no_batch else run_calibration_batch(args, dp, torch)
+    ladder = None if args.no_ladder else run_paper_ladder(args, dp, torch)
     cpu = None if args.no_cpu else run_cpu_baseline(fw)
     value = fw["n_samples"] / (fw["ms_step"] * 1e-3)
     rec = {
@@ -517,6 +597,7 @@ def main():
         "registration": regr,
         "learned_proposal": learned,
         "calibration_batch": calib,
+        "projector_ladder": ladder,
     }
     print(json.dumps(rec), flush=True)
 
