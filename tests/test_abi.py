@@ -103,6 +103,47 @@ def test_invalid_arguments_rejected_before_launch(lib):
                                         wsf - 1, None) == -2
 
 
+def test_newer_entries_validate_before_launch(lib):
+    """Single-pass SSD, footprint, FDK, sharpness, entropy and CNN entries:
+    bad arguments return an error code (and a message) before any launch, so
+    these run without a GPU."""
+    import paper_2508_13304_amd as m
+    g = synth.geom_c1()
+    gs = m.geom_struct(g)
+    p = C.c_void_p(1 << 20)
+    ws = C.c_void_p(1 << 24)
+    wss = m.workspace_bytes(g, 1, m.OP_FWD_SSD)
+    # single-pass SSD: NULL target, short workspace, NULL Hessian
+    assert lib.dp_project_fwd_ssd_grad_pose(C.byref(gs), 1, p, p, p, None, p, None, p, ws, wss,
+                                            None) == -1
+    assert lib.dp_project_fwd_ssd_grad_pose(C.byref(gs), 1, p, p, p, p, p, None, p, ws, wss - 256,
+                                            None) == -2
+    assert lib.dp_project_fwd_ssd_gauss_newton(C.byref(gs), 1, p, p, p, p, p, None, p, None, ws,
+                                               wss, None) == -1
+    # footprint pairs: kind, NULLs, workspace
+    wf = m.workspace_bytes(g, 1, m.OP_FP_FWD_GRAD)
+    assert lib.dp_fp_project_grad_pose(C.byref(gs), 1, p, p, p, p, p, 2, ws, wf, None) == -1
+    assert b"kind" in lib.dp_last_error()
+    assert lib.dp_fp_project_grad_pose(C.byref(gs), 1, p, p, p, p, None, 0, ws, wf, None) == -1
+    assert lib.dp_fp_backproject(C.byref(gs), 1, p, p, None, p, 1, ws,
+                                 m.workspace_bytes(g, 1, m.OP_FP_BP), None) == -1
+    assert lib.dp_fp_backproject_grad_pose(C.byref(gs), 1, p, p, p, p, p, 1, ws,
+                                           m.workspace_bytes(g, 1, m.OP_FP_BP_GRAD) - 256, None) == -2
+    # FDK filter: rows too long, non-finite scale
+    long_rows = m.geom_struct(g.replace(nu=4001))
+    assert lib.dp_fdk_filter(C.byref(long_rows), 1, p, p, 1.0, None) == -4
+    assert lib.dp_fdk_filter(C.byref(gs), 1, p, p, float("inf"), None) == -1
+    # sharpness / gradient entropy: sizes, workspace, eps
+    wsh = lib.dp_sharpness_workspace_bytes(8, 8, 8)
+    assert wsh > 0 and wsh % 256 == 0
+    assert lib.dp_sharpness(0, 8, 8, p, p, None, ws, wsh, None) == -1
+    assert lib.dp_sharpness(8, 8, 8, p, p, None, ws, wsh - 256, None) == -2
+    wge = lib.dp_gradient_entropy_workspace_bytes(8, 8, 8)
+    assert lib.dp_gradient_entropy(8, 8, 8, p, 0.0, p, None, ws, wge, None) == -1
+    assert lib.dp_gradient_entropy(8, 8, 8, p, 1e-12, p, None, C.c_void_p((1 << 24) + 4), wge,
+                                   None) == -1  # misaligned workspace
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     import paper_2508_13304_amd as m
     saved = m._lib
