@@ -570,8 +570,14 @@ def main():
     ladder = None if args.no_ladder else run_paper_ladder(args, dp, torch)
     cpu = None if args.no_cpu else run_cpu_baseline(fw)
     value = fw["n_samples"] / (fw["ms_step"] * 1e-3)
+    reg_rate = None
+    if regr:
+        best = max((v for k, v in regr.items() if isinstance(v, dict) and "registrations_per_s" in v
+                    and v.get("success_rate", 0) >= 1.0), key=lambda v: v["registrations_per_s"],
+                   default=None)
+        reg_rate = best["registrations_per_s"] if best else None
     rec = {
-        "metric": "fwd+pose-grad ray-samples/s",
+        "metric": "fwd+pose-grad ray-samples/s; 6-DoF registrations/s at <0.1mm/0.1° error",
         "value": value,
         "unit": "ray-samples/s",
         "n_gpus": 1,
@@ -587,6 +593,9 @@ def main():
                                "(+-10 mm/+-10 deg) x one 512x512 view at 0.6 mm, SAD/SDD 1000/1500 mm, "
                                "0.5 mm trilinear march; forward + SSD loss + 64x6 pose gradient in one fused launch",
                    "samples_per_step": fw["n_samples"], "views": fw["V"]},
+        "registrations_per_s": reg_rate,
+        "registrations_unit": "registrations/s at <0.1 mm / 0.1 deg (64 single-view targets, "
+                              "+-10 mm / +-10 deg, best method with every registration successful)",
         "roofline": fw["roofline"],
         "cpu_baseline": cpu,
         "kernels_ms": fw["per_kernel"],
