@@ -131,3 +131,45 @@ def test_gauss_newton_matrix_matches_oracle(dp, oracle, case):
     err = np.linalg.norm(Hg - H_ref, axis=(1, 2)) / np.linalg.norm(H_ref, axis=(1, 2))
     say(f"{case} Gauss-Newton matrix: worst per-view rel err {err.max():.3e}")
     assert err.max() <= 1e-4
+
+
+def test_fused_full_launch_the_bench_times(dp, oracle):
+    """The registration-scale launch exactly as the bench times it (256^3,
+    64 poses, 512x512, one single-pass launch).  Targets equal the GPU
+    projections except on 64 random rays per view, where they are offset by
+    N(0, 100^2); so dL/dl = 2 (l - y) is concentrated on those rays and the
+    oracle can evaluate it ray by ray: sampled projections (<= 1e-5), the
+    per-view SSD (<= 1e-5 relative) and the pose gradients (<= 1e-4) against
+    the oracle with dL/dl = 2 (l_ref - y) on the selected rays and 0 elsewhere
+    (the rest of the residual is the FP32 difference between two GPU launches,
+    ~1e-7 of l, which moves the gradient by ~1e-5 of its norm at this offset
+    scale)."""
+    c = synth.config2_inputs()
+    g, vol, angles, poses = c["geom"], c["vol"], c["angles"], c["poses"]
+    V = len(angles)
+    a, p, v = f64(angles), f64(poses), f32(vol)
+    l_fwd = dp.project_fwd(g, a, p, v)
+    rng = np.random.default_rng(13)
+    npix = g.nu * g.nv
+    sel = np.stack([rng.choice(npix, 64, replace=False) for _ in range(V)])
+    ids = (sel + np.arange(V)[:, None] * npix).ravel()
+    delta = rng.normal(0.0, 100.0, ids.size).astype(np.float32)
+    y = l_fwd.clone().reshape(-1)
+    y[torch.from_numpy(ids).cuda()] += torch.from_numpy(delta).cuda()
+    y = y.reshape(V, g.nv, g.nu)
+    l, loss, gp = dp.project_fwd_ssd_grad_pose(g, a, p, v, y)
+    l_ref = oracle.project_fwd_rays(g, angles, poses, vol, ids)
+    got = l.cpu().numpy().reshape(-1)[ids]
+    err = np.abs(got - l_ref).max() / np.abs(l_ref).max()
+    say(f"full launch sampled projections: max rel err {err:.3e}")
+    assert err <= 1e-5
+    y_sel = y.cpu().numpy().reshape(-1)[ids]
+    r_ref = (l_ref - y_sel).reshape(V, 64)
+    loss_ref = (r_ref.astype(np.float64) ** 2).sum(1)
+    rel = np.abs(loss.cpu().numpy() - loss_ref) / loss_ref
+    say(f"full launch per-view SSD: max rel err {rel.max():.3e}")
+    assert rel.max() <= 1e-5
+    w = np.zeros(V * npix, np.float32)
+    w[ids] = (2.0 * (l_ref - y_sel)).astype(np.float32)
+    g_ref = oracle.project_fwd_grad_pose(g, angles, poses, vol, w.reshape(V, g.nv, g.nu))
+    check_grads("full launch fused gradient", gp.cpu().numpy(), g_ref)
