@@ -298,14 +298,18 @@ def run_registration(args, dp, torch, fw):
 def run_calibration_batch(args, dp, torch):
     """Uneven batched geometry calibration: 16 independent problems (cubic
     phantoms of 128^3-384^3 voxels spanning ~200 mm, 1-8 views each on
-    256^2-768^2 detectors, pose perturbations +-5 mm/+-3 deg), each running
-    forward + SSD pose-gradient iterations.  Three ways to run one iteration
-    of all 16: per-problem sequential launches, the batched launches
-    (variant chosen by timing each compiled variant on this batch), and the
-    batched iteration captured once in a HIP graph and replayed."""
+    256^2-768^2 detectors, every view's pose perturbed by +-5 mm/+-3 deg)
+    registered by Levenberg-Marquardt on the SSD, entirely on the device.
+    One iteration = the single-pass SSD / pose-gradient / Gauss-Newton launch
+    for every view of all 16 problems + the FP64 update kernel.  Three ways
+    to run it: one SSD launch per problem, the batched launch (variant
+    chosen by timing each compiled variant on this batch), and the batched
+    iteration captured once in a HIP graph and replayed; then the full
+    calibration from the perturbed poses by graph replays."""
+    from paper_2508_13304_amd.registration import BatchLM, pose_errors
     dev = torch.device("cuda:0")
     rng = synth.rng_for(3, 9)
-    probs = []
+    probs, truth = [], []
     n_samples = 0
     for i in range(16):
         n = int(rng.choice([128, 192, 256, 320, 384]))
@@ -316,50 +320,16 @@ def run_calibration_batch(args, dp, torch):
         g = synth.Geom(n, n, n, h, h, h, nu, nu, du, du)
         vol = synth.ellipsoid_phantom_torch(n, h, 20, rng, dev)
         angles = torch.tensor(rng.uniform(0, 2 * math.pi, V), dtype=torch.float64, device=dev)
-        truth = torch.tensor(synth.random_poses(V, 5.0, 3.0, rng), dtype=torch.float64, device=dev)
-        y = dp.project_fwd(g, angles, truth, vol)
-        poses = torch.zeros_like(truth)
-        n_samples += count_ray_samples(g, angles.cpu().numpy(), poses.cpu().numpy())
-        probs.append(dict(geom=g, angles=angles, poses=poses, vol=vol, target=y,
-                          proj=torch.empty_like(y), grad_proj=torch.empty_like(y),
-                          grad_pose=torch.empty((V, 6), dtype=torch.float64, device=dev)))
-    total_views = sum(p["angles"].numel() for p in probs)
+        tp = torch.tensor(synth.random_poses(V, 5.0, 3.0, rng), dtype=torch.float64, device=dev)
+        probs.append(dict(geom=g, angles=angles, vol=vol, target=dp.project_fwd(g, angles, tp, vol)))
+        truth.append(tp)
+        n_samples += count_ray_samples(g, angles.cpu().numpy(), np.zeros((V, 6)))
+    truth = torch.cat(truth)
+    init = torch.zeros_like(truth)
+    total_views = truth.shape[0]
     log(f"[bench] calibration batch: 16 problems, {total_views} views, {n_samples:.3e} samples/iteration")
-    lr = torch.tensor([0.05] * 3 + [math.radians(0.05)] * 3, dtype=torch.float64, device=dev)
-    ws_f = torch.empty(dp.batch_workspace_bytes(probs, dp.OP_FWD), dtype=torch.uint8, device=dev)
-    ws_g = torch.empty(dp.batch_workspace_bytes(probs, dp.OP_FWD_GRAD), dtype=torch.uint8, device=dev)
-    ws1 = torch.empty(max(max(dp.workspace_bytes(p["geom"], p["angles"].numel(), op) for p in probs)
-                          for op in (dp.OP_FWD, dp.OP_FWD_GRAD)), dtype=torch.uint8, device=dev)
-    init = [p["poses"].clone() for p in probs]
-
-    def residuals():
-        for p in probs:
-            torch.sub(p["proj"], p["target"], out=p["grad_proj"])
-            p["grad_proj"].mul_(2.0)
-
-    def update():
-        for p in probs:
-            p["poses"].sub_(lr * torch.sign(p["grad_pose"]))
-
-    def seq_iter(stream):
-        for p in probs:
-            dp.project_fwd(p["geom"], p["angles"], p["poses"], p["vol"], out=p["proj"], ws=ws1,
-                           stream=stream)
-        residuals()
-        for p in probs:
-            dp.project_fwd_grad_pose(p["geom"], p["angles"], p["poses"], p["vol"], p["grad_proj"],
-                                     out=p["grad_pose"], ws=ws1, stream=stream)
-        update()
-
-    def batch_iter(stream, vf=-1, vg=-1):
-        dp.project_fwd_batch(probs, ws=ws_f, variant=vf, stream=stream)
-        residuals()
-        dp.project_fwd_grad_pose_batch(probs, ws=ws_g, variant=vg, stream=stream)
-        update()
-
-    def reset():
-        for p, p0 in zip(probs, init):
-            p["poses"].copy_(p0)
+    ws1 = torch.empty(max(dp.workspace_bytes(q["geom"], q["angles"].numel(), dp.OP_FWD_SSD)
+                          for q in probs), dtype=torch.uint8, device=dev)
 
     def timed(fn, reps):
         torch.cuda.synchronize()
@@ -370,47 +340,51 @@ def run_calibration_batch(args, dp, torch):
         return (time.perf_counter() - t0) / reps
 
     reps = max(3, min(args.steps, 10))
-    stream = torch.cuda.current_stream()
-    seq_iter(stream)
-    reset()
-    t_seq = timed(lambda: seq_iter(stream), reps)
-    reset()
-    # batch autotuning: time each compiled variant of both batched kernels
+    lm = BatchLM(probs, init)
+    lm.step_sequential(ws1)
+    lm.reset(init)
+    t_seq = timed(lambda: lm.step_sequential(ws1), reps)
+    # batch autotuning: time each compiled variant of the batched launch
     ms = {}
-    for op, fn in ((dp.OP_FWD, dp.project_fwd_batch), (dp.OP_FWD_GRAD, dp.project_fwd_grad_pose_batch)):
-        wsx = ws_f if op == dp.OP_FWD else ws_g
-        for var in range(dp.N_VARIANTS):
-            fn(probs, ws=wsx, variant=var, stream=stream)
-            ms[(op, var)] = timed(lambda: fn(probs, ws=wsx, variant=var, stream=stream), 3)
-    vf = min(range(dp.N_VARIANTS), key=lambda v: ms[(dp.OP_FWD, v)])
-    vg = min(range(dp.N_VARIANTS), key=lambda v: ms[(dp.OP_FWD_GRAD, v)])
-    reset()
-    t_batch = timed(lambda: batch_iter(stream, vf, vg), reps)
-    # graph: capture one batched iteration on a side stream, replay
-    reset()
-    s2 = torch.cuda.Stream()
-    s2.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s2):
-        batch_iter(s2, vf, vg)
-    torch.cuda.current_stream().wait_stream(s2)
+    for var in range(dp.N_VARIANTS):
+        lm.variant = var
+        lm.reset(init)
+        lm.step()
+        lm.reset(init)
+        ms[var] = timed(lm.step, reps)
+    lm.variant = min(ms, key=ms.get)
+    lm.reset(init)
+    t_batch = timed(lm.step, reps)
+    lm.reset(init)
+    lm.capture()
+    t_graph = timed(lambda: lm.run(1), reps)
+    # the calibration itself: graph replays from the perturbed poses
+    iters = 40
+    lm.reset(init)
     torch.cuda.synchronize()
-    reset()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        batch_iter(torch.cuda.current_stream(), vf, vg)
-    reset()
-    t_graph = timed(graph.replay, reps)
+    t0 = time.perf_counter()
+    lm.run(iters)
+    torch.cuda.synchronize()
+    t_cal = time.perf_counter() - t0
+    pose, conv, _ = lm.result()
+    te, re = pose_errors(pose, truth)
+    ok = (te <= 0.1) & (re <= 0.1)
     res = {"workload": "16 problems, 128^3-384^3 phantoms (~200 mm), 1-8 views each on 256^2-768^2 "
-                       "detectors, +-5 mm/+-3 deg perturbations; one iteration = forward + SSD "
-                       "residual + pose gradient + pose step for all 16",
+                       "detectors, every view's pose perturbed +-5 mm/+-3 deg; Levenberg-Marquardt on "
+                       "the SSD; one iteration = single-pass SSD + pose gradient + Gauss-Newton "
+                       "launch for all views + FP64 update kernel",
            "views": total_views, "samples_per_iteration": n_samples,
            "sequential_ms": round(t_seq * 1e3, 3), "batched_ms": round(t_batch * 1e3, 3),
            "graph_ms": round(t_graph * 1e3, 3),
            "graph_samples_per_s": n_samples / t_graph,
            "sequential_samples_per_s": n_samples / t_seq,
-           "batch_variants": {"fwd": vf, "grad": vg,
-                              "ms": {f"{'fwd' if k[0] == dp.OP_FWD else 'grad'}{k[1]}": round(v * 1e3, 3)
-                                     for k, v in ms.items()}}}
+           "batch_variant": lm.variant,
+           "variant_ms": {str(k): round(v * 1e3, 3) for k, v in ms.items()},
+           "calibration": {"iterations": iters, "seconds": round(t_cal, 4),
+                           "views_within_0.1mm_0.1deg": int(ok.sum()),
+                           "success_rate": float(ok.float().mean()),
+                           "converged": int(conv.sum()),
+                           "max_err_mm": float(te.max()), "max_err_deg": float(re.max())}}
     log(f"[bench] calibration batch: {res}")
     return res
 

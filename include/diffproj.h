@@ -166,8 +166,11 @@ typedef struct dp_problem {
     const double* poses;      /* device [V][6]                                  */
     const float*  vol;        /* device [nz][ny][nx]                            */
     float*        proj;       /* device [V][nv][nu]  forward output             */
-    const float*  grad_proj;  /* device [V][nv][nu]  gradient input dL/dl       */
+    const float*  grad_proj;  /* device [V][nv][nu]  gradient input dL/dl; the  */
+                              /* target image y for the single-pass SSD batch    */
     double*       grad_pose;  /* device [V][6]       gradient output            */
+    double*       loss;       /* device [V]  SSD batch: per-view SSD (or NULL)   */
+    double*       hess;       /* device [V][21] SSD batch: Gauss-Newton matrix   */
 } dp_problem;
 
 size_t dp_batch_workspace_bytes(const dp_problem* problems, int32_t n, int32_t op);
@@ -175,6 +178,32 @@ int dp_project_fwd_batch(const dp_problem* problems, int32_t n, void* ws, size_t
                          int32_t variant, void* stream);
 int dp_project_fwd_grad_pose_batch(const dp_problem* problems, int32_t n, void* ws,
                                    size_t ws_bytes, int32_t variant, void* stream);
+/* Single-pass SSD batch (dp_project_fwd_ssd_gauss_newton for every problem
+ * in one ray launch): per problem proj (out), grad_proj = target y, loss
+ * (optional), grad_pose and hess (both required).  Workspace:
+ * dp_batch_workspace_bytes(problems, n, DP_OP_FWD_SSD). */
+int dp_project_fwd_ssd_gauss_newton_batch(const dp_problem* problems, int32_t n, void* ws,
+                                          size_t ws_bytes, int32_t variant, void* stream);
+
+/* One Levenberg-Marquardt update per view, on the device, for n views laid
+ * out back to back (e.g. every view of a batch).  In the scaled parameters
+ * z = (t / 1 mm, gamma / 1 deg), with (f, g, H) the SSD, gradient and
+ * Gauss-Newton matrix just evaluated at the trial poses `trial` [n][6]
+ * (loss [n], grad [n][6], hess [n][21] as written by the SSD entries) and
+ * the state of the last accepted point (state_pose [n][6], state_f [n],
+ * state_g [n][6], state_h [n][21], lam [n]):
+ *   accept if f < state_f (state <- trial values, lam /= 3), else lam *= 4;
+ *   then solve (H + lam diag H) d = -g (FP64 Cholesky) and write the next
+ *   trial pose state_pose + d into `trial`.
+ * A view whose accepted step is below tol in every scaled parameter, or
+ * whose lam exceeds 1e10, is marked done[n] = 1 and its trial pose stays at
+ * the accepted pose.  Initialise state_f to +inf so the first evaluation is
+ * accepted.  All arrays are device FP64 (done: int32); no allocation, no
+ * host synchronisation, so an iteration (SSD batch + this update) can be
+ * captured in a graph and replayed. */
+int dp_lm_update(int32_t n, double* trial, const double* loss, const double* grad,
+                 const double* hess, double* state_pose, double* state_f, double* state_g,
+                 double* state_h, double* lam, int32_t* done, double tol, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel variants of the ray-driven kernels (chunk length and LDS budget:

@@ -35,7 +35,8 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_fp_project_grad_pose", "dp_fp_backproject_grad_pose", "dp_fdk_filter", "dp_sharpness",
            "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
-           "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16")
+           "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16",
+           "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update")
 MAX_BATCH = 16
 N_VARIANTS = 3
 
@@ -54,7 +55,8 @@ class DPProblem(C.Structure):
     """Mirror of `dp_problem`."""
     _fields_ = [("geom", DPGeom), ("n_views", C.c_int32), ("angles", C.c_void_p),
                 ("poses", C.c_void_p), ("vol", C.c_void_p), ("proj", C.c_void_p),
-                ("grad_proj", C.c_void_p), ("grad_pose", C.c_void_p)]
+                ("grad_proj", C.c_void_p), ("grad_pose", C.c_void_p), ("loss", C.c_void_p),
+                ("hess", C.c_void_p)]
 
 
 _lib = None
@@ -96,6 +98,10 @@ def load(path: str | None = None):
     lib.dp_project_fwd_grad_pose_batch.argtypes = [P, i32, vp, sz, i32, vp]
     lib.dp_project_fwd_batch.restype = C.c_int
     lib.dp_project_fwd_grad_pose_batch.restype = C.c_int
+    lib.dp_project_fwd_ssd_gauss_newton_batch.argtypes = [P, i32, vp, sz, i32, vp]
+    lib.dp_project_fwd_ssd_gauss_newton_batch.restype = C.c_int
+    lib.dp_lm_update.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
+    lib.dp_lm_update.restype = C.c_int
     lib.dp_autotune.argtypes = [i32, g, i32, vp, vp, vp, vp, vp, vp, sz, vp, i32,
                                 C.POINTER(i32), C.POINTER(C.c_float)]
     lib.dp_autotune.restype = C.c_int
@@ -238,9 +244,10 @@ def project_fwd_ssd_grad_pose(geom, angles, poses, vol, target, proj=None, loss=
 
 
 def project_fwd_ssd_gauss_newton(geom, angles, poses, vol, target, proj=None, loss=None,
-                                 grad=None, hess=None, ws=None, stream=None):
+                                 grad=None, hess=None, ws=None, stream=None, packed=False):
     """One pass: DRRs, per-view SSD, its pose gradient and the Gauss-Newton
-    matrix 2 sum J J^T as a symmetric [V][6][6] f64 tensor."""
+    matrix 2 sum J J^T as a symmetric [V][6][6] f64 tensor (packed=True:
+    the [V][21] upper triangle as the kernel writes it)."""
     import torch
     V = _views(angles, poses)
     dev = vol.device
@@ -263,7 +270,7 @@ def project_fwd_ssd_gauss_newton(geom, angles, poses, vol, target, proj=None, lo
         _dev(hess, torch.float64, "hess", (V, 21)),
         C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
     _check(rc, "dp_project_fwd_ssd_gauss_newton")
-    return proj, loss, grad, unpack_sym6(hess)
+    return proj, loss, grad, (hess if packed else unpack_sym6(hess))
 
 
 def unpack_sym6(h21):
@@ -317,8 +324,9 @@ def backproject_grad_pose(geom, angles, poses, proj, grad_vol, weight_mode=W_NON
 # --------------------------------------------------------------------------
 
 def _problems(problems, op):
-    """problems: list of dicts with geom, angles, poses, vol and proj (forward)
-    or grad_proj + grad_pose (gradient), all CUDA tensors."""
+    """problems: list of dicts with geom, angles, poses, vol and proj (forward),
+    grad_proj + grad_pose (gradient), or target + proj + grad_pose + hess and
+    optionally loss (single-pass SSD), all CUDA tensors."""
     import torch
     arr = (DPProblem * len(problems))()
     for i, q in enumerate(problems):
@@ -331,6 +339,13 @@ def _problems(problems, op):
         arr[i].vol = _dev(q["vol"], torch.float32, "vol", (g.nz, g.ny, g.nx)).value
         if op == OP_FWD:
             arr[i].proj = _dev(q["proj"], torch.float32, "proj", (V, g.nv, g.nu)).value
+        elif op == OP_FWD_SSD:
+            arr[i].proj = _dev(q["proj"], torch.float32, "proj", (V, g.nv, g.nu)).value
+            arr[i].grad_proj = _dev(q["target"], torch.float32, "target", (V, g.nv, g.nu)).value
+            arr[i].grad_pose = _dev(q["grad_pose"], torch.float64, "grad_pose", (V, 6)).value
+            arr[i].hess = _dev(q["hess"], torch.float64, "hess", (V, 21)).value
+            if q.get("loss") is not None:
+                arr[i].loss = _dev(q["loss"], torch.float64, "loss", (V,)).value
         else:
             arr[i].grad_proj = _dev(q["grad_proj"], torch.float32, "grad_proj", (V, g.nv, g.nu)).value
             arr[i].grad_pose = _dev(q["grad_pose"], torch.float64, "grad_pose", (V, 6)).value
@@ -353,7 +368,8 @@ def _run_batch(problems, op, ws, variant, stream):
             raise ValueError("invalid batch")
         w = ws if ws is not None and ws.numel() >= need else torch.empty(
             need, dtype=torch.uint8, device=chunk[0]["vol"].device)
-        f = lib.dp_project_fwd_batch if op == OP_FWD else lib.dp_project_fwd_grad_pose_batch
+        f = {OP_FWD: lib.dp_project_fwd_batch, OP_FWD_GRAD: lib.dp_project_fwd_grad_pose_batch,
+             OP_FWD_SSD: lib.dp_project_fwd_ssd_gauss_newton_batch}[op]
         _check(f(arr, len(chunk), C.c_void_p(w.data_ptr()), w.numel(), int(variant),
                  _stream(stream)), f.__name__)
 
@@ -367,6 +383,32 @@ def project_fwd_batch(problems, ws=None, variant=-1, stream=None):
 def project_fwd_grad_pose_batch(problems, ws=None, variant=-1, stream=None):
     """Pose gradients of an uneven batch; each problem supplies grad_proj and grad_pose."""
     _run_batch(problems, OP_FWD_GRAD, ws, variant, stream)
+
+
+def project_fwd_ssd_gauss_newton_batch(problems, ws=None, variant=-1, stream=None):
+    """Single-pass SSD, pose gradient and Gauss-Newton matrix of an uneven
+    batch (one ray launch per 16 problems); each problem supplies geom,
+    angles, poses, vol, target and the outputs proj, grad_pose, hess [V][21]
+    and optionally loss [V]."""
+    _run_batch(problems, OP_FWD_SSD, ws, variant, stream)
+
+
+def lm_update(trial, loss, grad, hess, state, tol=1e-4, stream=None):
+    """One device-side Levenberg-Marquardt update for every view (library
+    kernel): trial [n][6] (in: evaluated poses, out: next trial poses), loss
+    [n], grad [n][6], hess [n][21] evaluated there; state: dict of device
+    tensors pose [n][6], f [n] (+inf before the first update), g [n][6],
+    h [n][21], lam [n] (f64) and done [n] (int32)."""
+    import torch
+    n = trial.shape[0]
+    f64 = torch.float64
+    args = [_dev(trial, f64, "trial", (n, 6)), _dev(loss, f64, "loss", (n,)),
+            _dev(grad, f64, "grad", (n, 6)), _dev(hess, f64, "hess", (n, 21)),
+            _dev(state["pose"], f64, "pose", (n, 6)), _dev(state["f"], f64, "f", (n,)),
+            _dev(state["g"], f64, "g", (n, 6)), _dev(state["h"], f64, "h", (n, 21)),
+            _dev(state["lam"], f64, "lam", (n,)),
+            _dev(state["done"], torch.int32, "done", (n,))]
+    _check(load().dp_lm_update(n, *args, float(tol), _stream(stream)), "dp_lm_update")
 
 
 def autotune(op, geom, angles, poses, vol, out, grad_proj=None, ws=None, reps=3, stream=None):

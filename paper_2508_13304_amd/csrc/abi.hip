@@ -36,6 +36,7 @@ struct Layout {
     size_t partials = 0;  // offset of the per-block partial sums
     size_t n_part = 0;    // partial blocks per view
     size_t spare = 0;     // FWD_SSD: [V][6] f64 pose-gradient slot used by the autotuner
+    size_t inter = 0;     // FWD_GRAD, FWD_SSD: per-voxel float4 (mu, Gx, Gy, Gz)
     size_t total = 0;
 };
 
@@ -63,12 +64,16 @@ Layout layout(const dp_geom& g, int V, int op)
         break;
     case DP_OP_FWD_GRAD:
         off = align_up(off + 3 * padded_volume_elems(g) * sizeof(float));
+        L.inter = off;
+        off = align_up(off + padded_volume_elems(g) * sizeof(float4));
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
         break;
     case DP_OP_FWD_SSD:
         off = align_up(off + 4 * padded_volume_elems(g) * sizeof(float));
+        L.inter = off;
+        off = align_up(off + padded_volume_elems(g) * sizeof(float4));
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannelsGN * sizeof(float));
@@ -278,8 +283,10 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     float* part = (float*)(base + L.partials);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_vol_grad(s, vol, vol3, st);
-    launch_rd_grad(s, V, views, vol3, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V), st);
+    float4* inter = (float4*)(base + L.inter);
+    launch_vol_prep(s, vol, nullptr, vol3, inter, st);
+    launch_rd_grad(s, V, views, vol3, inter, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V),
+                   st);
     launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_project_fwd_grad_pose");
 }
@@ -303,9 +310,9 @@ static int fwd_ssd(const dp_geom* g, int32_t V, const double* angles, const doub
     float* part = (float*)(base + L.partials);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_vol_pad(s, vol, vol4, st);
-    launch_vol_grad(s, vol, vol4 + padded_volume_elems(*g), st);
-    launch_rd_fused(s, V, views, vol4, target, proj, part, hess != nullptr,
+    float4* inter = (float4*)(base + L.inter);
+    launch_vol_prep(s, vol, vol4, vol4 + padded_volume_elems(*g), inter, st);
+    launch_rd_fused(s, V, views, vol4, inter, target, proj, part, hess != nullptr,
                     variant_for(DP_OP_FWD_SSD, *g, V), st);
     launch_finalize_fwd_ssd(s, V, views, part, (int)L.n_part, grad_pose, loss, hess, st);
     return check_launch(name);
@@ -565,13 +572,17 @@ static int check_batch(const dp_problem* pr, int32_t n, int op)
         if (op == DP_OP_FWD && !q.proj) return fail(DP_ERR_ARG, "problem %d: NULL proj", i);
         if (op == DP_OP_FWD_GRAD && (!q.grad_proj || !q.grad_pose))
             return fail(DP_ERR_ARG, "problem %d: NULL grad_proj / grad_pose", i);
+        if (op == DP_OP_FWD_SSD && (!q.proj || !q.grad_proj || !q.grad_pose || !q.hess))
+            return fail(DP_ERR_ARG, "problem %d: NULL proj / grad_proj (target) / grad_pose / hess", i);
     }
     return DP_OK;
 }
 
 size_t dp_batch_workspace_bytes(const dp_problem* pr, int32_t n, int32_t op)
 {
-    if ((op != DP_OP_FWD && op != DP_OP_FWD_GRAD) || !pr || n <= 0 || n > kRdMaxBatch) return 0;
+    if ((op != DP_OP_FWD && op != DP_OP_FWD_GRAD && op != DP_OP_FWD_SSD) || !pr || n <= 0 ||
+        n > kRdMaxBatch)
+        return 0;
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
         if (check_geom(&pr[i].geom, pr[i].n_views) != DP_OK) return 0;
@@ -619,16 +630,22 @@ static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t w
         ViewGeo* views = (ViewGeo*)(base + L.views);
         float* buf = (float*)(base + L.buf);
         launch_view_setup(s, q.n_views, q.angles, q.poses, views, st);
-        if (op == DP_OP_FWD)
+        if (op == DP_OP_FWD) {
             launch_vol_pad(s, q.vol, buf, st);
-        else
-            launch_vol_grad(s, q.vol, buf, st);
+        } else if (op == DP_OP_FWD_GRAD) {
+            launch_vol_prep(s, q.vol, nullptr, buf, (float4*)(base + L.inter), st);
+        } else {  // planes: padded mu, Gx, Gy, Gz
+            launch_vol_prep(s, q.vol, buf, buf + padded_volume_elems(q.geom),
+                            (float4*)(base + L.inter), st);
+        }
         RdBatchItem& it = bt.it[j];
         it.s = s;
         it.views = views;
         it.vol = buf;
+        it.inter = op == DP_OP_FWD ? nullptr : (const float4*)(base + L.inter);
         it.gin = op == DP_OP_FWD ? nullptr : q.grad_proj;
         it.out = op == DP_OP_FWD ? q.proj : (float*)(base + L.partials);
+        it.proj = op == DP_OP_FWD_SSD ? q.proj : nullptr;
         it.tiles = rd_tiles(s);
         it.first = (int)blocks;
         blocks += (long long)it.tiles * q.n_views;
@@ -638,16 +655,28 @@ static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t w
     if (op == DP_OP_FWD) {
         launch_rd_fwd_batch(bt, (int)blocks, var, st);
     } else {
-        launch_rd_grad_batch(bt, (int)blocks, var, st);
+        if (op == DP_OP_FWD_GRAD)
+            launch_rd_grad_batch(bt, (int)blocks, var, st);
+        else
+            launch_rd_fused_batch(bt, (int)blocks, var, st);
         for (int j = 0; j < n; ++j) {
             const int i = order[j];
-            const Layout L = layout(pr[i].geom, pr[i].n_views, op);
+            const dp_problem& q = pr[i];
+            const Layout L = layout(q.geom, q.n_views, op);
             char* base = (char*)ws + offs[i];
-            launch_finalize_fwd(make_scalars(pr[i].geom), pr[i].n_views, (ViewGeo*)(base + L.views),
-                                (float*)(base + L.partials), (int)L.n_part, pr[i].grad_pose, st);
+            const ViewGeo* views = (ViewGeo*)(base + L.views);
+            const float* part = (float*)(base + L.partials);
+            if (op == DP_OP_FWD_GRAD)
+                launch_finalize_fwd(make_scalars(q.geom), q.n_views, views, part, (int)L.n_part,
+                                    q.grad_pose, st);
+            else
+                launch_finalize_fwd_ssd(make_scalars(q.geom), q.n_views, views, part,
+                                        (int)L.n_part, q.grad_pose, q.loss, q.hess, st);
         }
     }
-    return check_launch(op == DP_OP_FWD ? "dp_project_fwd_batch" : "dp_project_fwd_grad_pose_batch");
+    return check_launch(op == DP_OP_FWD        ? "dp_project_fwd_batch"
+                        : op == DP_OP_FWD_GRAD ? "dp_project_fwd_grad_pose_batch"
+                                               : "dp_project_fwd_ssd_gauss_newton_batch");
 }
 
 int dp_project_fwd_batch(const dp_problem* problems, int32_t n, void* ws, size_t ws_bytes,
@@ -660,6 +689,27 @@ int dp_project_fwd_grad_pose_batch(const dp_problem* problems, int32_t n, void* 
                                    size_t ws_bytes, int32_t variant, void* stream)
 {
     return run_batch(problems, n, DP_OP_FWD_GRAD, ws, ws_bytes, variant, stream);
+}
+
+int dp_project_fwd_ssd_gauss_newton_batch(const dp_problem* problems, int32_t n, void* ws,
+                                          size_t ws_bytes, int32_t variant, void* stream)
+{
+    return run_batch(problems, n, DP_OP_FWD_SSD, ws, ws_bytes, variant, stream);
+}
+
+int dp_lm_update(int32_t n, double* trial, const double* loss, const double* grad,
+                 const double* hess, double* state_pose, double* state_f, double* state_g,
+                 double* state_h, double* lam, int32_t* done, double tol, void* stream)
+{
+    if (n <= 0) return fail(DP_ERR_ARG, "number of views must be positive (got %d)", n);
+    if (!trial || !loss || !grad || !hess || !state_pose || !state_f || !state_g || !state_h ||
+        !lam || !done)
+        return fail(DP_ERR_ARG, "NULL array argument");
+    if (!(tol >= 0.0)) return fail(DP_ERR_ARG, "tol must be non-negative");
+    (void)hipGetLastError();
+    launch_lm_update(n, trial, loss, grad, hess, state_pose, state_f, state_g, state_h, lam,
+                     (int*)done, tol, (hipStream_t)stream);
+    return check_launch("dp_lm_update");
 }
 
 // ---------------------------------------------------------------------------

@@ -66,13 +66,17 @@ inline GeoScalars make_scalars(const dp_geom& g)
 void launch_view_setup(const GeoScalars& s, int V, const double* angles, const double* poses,
                        ViewGeo* views, hipStream_t st);
 void launch_vol_pad(const GeoScalars& s, const float* vol, float* volp, hipStream_t st);
-void launch_vol_grad(const GeoScalars& s, const float* vol, float* vol3, hipStream_t st);
+// gradient planes (+ the padded mu plane if mu_plane != NULL) and the
+// per-voxel float4 (mu, Gx, Gy, Gz) interleave, in one pass
+void launch_vol_prep(const GeoScalars& s, const float* vol, float* mu_plane, float* g3,
+                     float4* inter, hipStream_t st);
 void launch_det_pad(const GeoScalars& s, int V, const float* proj, float* projp, hipStream_t st);
 void launch_det_grad(const GeoScalars& s, int V, const float* proj, float4* proj4, hipStream_t st);
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
                    float* proj, int variant, hipStream_t st);
 void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
-                    const float* grad_proj, float* partials, int variant, hipStream_t st);
+                    const float4* inter, const float* grad_proj, float* partials, int variant,
+                    hipStream_t st);
 
 // Uneven batches of ray-driven problems in one launch (descriptors by value).
 constexpr int kRdMaxBatch = 16;
@@ -84,8 +88,10 @@ struct RdBatchItem {
     GeoScalars s;
     const ViewGeo* views;
     const float* vol;   // padded volume (forward) or gradient planes (gradient)
-    const float* gin;   // dL/dl (gradient only)
-    float* out;         // DRRs (forward) or per-block partials (gradient)
+    const float4* inter;  // per-voxel (mu, Gx, Gy, Gz) for unstaged tiles (gradient)
+    const float* gin;   // dL/dl (gradient) or the target y (single-pass SSD)
+    float* out;         // DRRs (forward) or per-block partials (gradient, SSD)
+    float* proj;        // DRRs of the single-pass SSD batch
     int tiles;          // detector tiles per view
     int first;          // first block of this problem
 };
@@ -95,12 +101,16 @@ struct RdBatch {
 };
 void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
 void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                     const float* target, float* proj, float* partials, bool hess, int variant,
-                     hipStream_t st);
+                     const float4* inter, const float* target, float* proj, float* partials,
+                     bool hess, int variant, hipStream_t st);
 void launch_finalize_fwd_ssd(const GeoScalars& s, int V, const ViewGeo* views,
                              const float* partials, int n_part, double* grad_pose, double* loss,
                              double* hess, hipStream_t st);
 void launch_rd_grad_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
+void launch_rd_fused_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
+void launch_lm_update(int n, double* trial, const double* loss, const double* grad,
+                      const double* hess, double* state_pose, double* state_f, double* state_g,
+                      double* state_h, double* lam, int* done, double tol, hipStream_t st);
 void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
                   float* vol, int weight_mode, hipStream_t st);
 void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,

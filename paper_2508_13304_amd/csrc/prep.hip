@@ -3,7 +3,8 @@
 //   - volume gradient field (central differences, Sec. II-C: the volume
 //     gradient in G_f is approximated by a central finite difference),
 //     stored as three zero-padded planes Gx, Gy, Gz in voxel-index units
-//     (half the neighbour difference), zero outside the grid;
+//     (half the neighbour difference), zero outside the grid, optionally
+//     with the padded mu plane, and the same values interleaved per voxel;
 //   - zero-padded copy of the detector images for the back-projection;
 //   - detector gradient field (central differences of l, Sec. II-C) stored
 //     as float4 (l, dl/da, dl/db, 0) in pixel-index units, zero outside.
@@ -30,26 +31,37 @@ __global__ __launch_bounds__(256) void vol_pad_kernel(int nx, int ny, int nz,
     volp[((size_t)K * NY + J) * NX + I] = vol_at(vol, nx, ny, nz, I - kPadV, J - kPadV, K - kPadV);
 }
 
-__global__ __launch_bounds__(256) void vol_grad_kernel(int nx, int ny, int nz,
+// One pass for the gradient marches: the central-difference planes Gx, Gy,
+// Gz (and, for the single-pass SSD, the padded mu plane) that the LDS boxes
+// are loaded from, plus the same values interleaved per voxel as float4
+// (mu, Gx, Gy, Gz) for tiles whose rays are too sparse to stage: there each
+// trilinear corner is one 16-byte gather instead of four scattered ones.
+template <bool MU>
+__global__ __launch_bounds__(256) void vol_prep_kernel(int nx, int ny, int nz,
                                                        const float* __restrict__ vol,
-                                                       float* __restrict__ vol3)
+                                                       float* __restrict__ mu_plane,
+                                                       float* __restrict__ g3,
+                                                       float4* __restrict__ inter)
 {
     const int NX = nx + 2 * kPadV, NY = ny + 2 * kPadV, NZ = nz + 2 * kPadV;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y, K = blockIdx.z;
     if (I >= NX) return;
     const int i = I - kPadV, j = J - kPadV, k = K - kPadV;
-    float gx = 0.f, gy = 0.f, gz = 0.f;
+    float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz) {
-        gx = 0.5f * (vol_at(vol, nx, ny, nz, i + 1, j, k) - vol_at(vol, nx, ny, nz, i - 1, j, k));
-        gy = 0.5f * (vol_at(vol, nx, ny, nz, i, j + 1, k) - vol_at(vol, nx, ny, nz, i, j - 1, k));
-        gz = 0.5f * (vol_at(vol, nx, ny, nz, i, j, k + 1) - vol_at(vol, nx, ny, nz, i, j, k - 1));
+        o.x = vol[((size_t)k * ny + j) * nx + i];
+        o.y = 0.5f * (vol_at(vol, nx, ny, nz, i + 1, j, k) - vol_at(vol, nx, ny, nz, i - 1, j, k));
+        o.z = 0.5f * (vol_at(vol, nx, ny, nz, i, j + 1, k) - vol_at(vol, nx, ny, nz, i, j - 1, k));
+        o.w = 0.5f * (vol_at(vol, nx, ny, nz, i, j, k + 1) - vol_at(vol, nx, ny, nz, i, j, k - 1));
     }
     const size_t plane = (size_t)NX * NY * NZ;
-    const size_t o = ((size_t)K * NY + J) * NX + I;
-    vol3[o] = gx;
-    vol3[plane + o] = gy;
-    vol3[2 * plane + o] = gz;
+    const size_t e = ((size_t)K * NY + J) * NX + I;
+    if (MU) mu_plane[e] = o.x;
+    g3[e] = o.y;
+    g3[plane + e] = o.z;
+    g3[2 * plane + e] = o.w;
+    inter[e] = o;
 }
 
 __device__ inline float pix_at(const float* __restrict__ img, int nu, int nv, int a, int b)
@@ -96,12 +108,16 @@ void launch_vol_pad(const GeoScalars& s, const float* vol, float* volp, hipStrea
     prof_end(DP_K_VOL_PREP, st);
 }
 
-void launch_vol_grad(const GeoScalars& s, const float* vol, float* vol3, hipStream_t st)
+void launch_vol_prep(const GeoScalars& s, const float* vol, float* mu_plane, float* g3,
+                     float4* inter, hipStream_t st)
 {
     const int NX = s.nx + 2 * kPadV;
     dim3 grid((NX + 255) / 256, s.ny + 2 * kPadV, s.nz + 2 * kPadV);
     prof_begin(DP_K_VOL_PREP, st);
-    vol_grad_kernel<<<grid, 256, 0, st>>>(s.nx, s.ny, s.nz, vol, vol3);
+    if (mu_plane)
+        vol_prep_kernel<true><<<grid, 256, 0, st>>>(s.nx, s.ny, s.nz, vol, mu_plane, g3, inter);
+    else
+        vol_prep_kernel<false><<<grid, 256, 0, st>>>(s.nx, s.ny, s.nz, vol, nullptr, g3, inter);
     prof_end(DP_K_VOL_PREP, st);
 }
 

@@ -468,6 +468,7 @@ struct GradAcc {
 template <int MCH, int CAP, bool FUSED, bool HESS = false>
 __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
                                     const float* __restrict__ vol3,
+                                    const float4* __restrict__ inter,
                                     const float* __restrict__ gin,
                                     float* __restrict__ proj_out,
                                     float* __restrict__ partials, int v, int tile, int tiles,
@@ -476,7 +477,9 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     // FUSED: vol3 holds four planes (mu, Gx, Gy, Gz), gin is the target image
     // y, and the ray also integrates mu: l is written to proj_out and the
     // SSD weight w = 2 (l - y) is applied to the gradient sums at the end.
-    // Otherwise vol3 holds (Gx, Gy, Gz) and gin is dL/dl.
+    // Otherwise vol3 holds (Gx, Gy, Gz) and gin is dL/dl.  inter holds the
+    // same padded values interleaved per voxel as (mu, Gx, Gy, Gz); tiles
+    // whose chunk boxes do not fit the LDS gather from it directly.
     constexpr int C = FUSED ? 4 : 3;
     const size_t plane = (size_t)(s.nx + 2 * kPadV) * (s.ny + 2 * kPadV) * (s.nz + 2 * kPadV);
     const float* __restrict__ mu = vol3;
@@ -569,21 +572,21 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
             const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
             float3 q[2][2][2];
+            float m[2][2][2];
 #pragma unroll
             for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
                 for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                     for (int dx = 0; dx < 2; ++dx) {
-                        const size_t o = (size_t)idx + dz * NXY + dy * NX + dx;
-                        q[dz][dy][dx] = make_float3(gx[o], gy[o], gz[o]);
+                        const float4 t = inter[(size_t)idx + dz * NXY + dy * NX + dx];
+                        m[dz][dy][dx] = t.x;
+                        q[dz][dy][dx] = make_float3(t.y, t.z, t.w);
                     }
             const float wx = X - fx, wy = Y - fy, wz = Z - fz;
             if (FUSED) {
-                const float* pm = mu + idx;
-                const float c00 = lerpf(pm[0], pm[1], wx), c10 = lerpf(pm[NX], pm[NX + 1], wx);
-                const float c01 = lerpf(pm[NXY], pm[NXY + 1], wx);
-                const float c11 = lerpf(pm[NXY + NX], pm[NXY + NX + 1], wx);
+                const float c00 = lerpf(m[0][0][0], m[0][0][1], wx), c10 = lerpf(m[0][1][0], m[0][1][1], wx);
+                const float c01 = lerpf(m[1][0][0], m[1][0][1], wx), c11 = lerpf(m[1][1][0], m[1][1][1], wx);
                 lsum += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
             }
             G.add(q, wx, wy, wz, fx - ccx, fy - ccy, fz - ccz);
@@ -655,12 +658,13 @@ template <int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                                                              const ViewGeo* __restrict__ views,
                                                              const float* __restrict__ vol3,
+                                                             const float4* __restrict__ inter,
                                                              const float* __restrict__ grad_proj,
                                                              float* __restrict__ partials)
 {
     __shared__ float lds[3 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, false>(s, views, vol3, grad_proj, nullptr, partials, blockIdx.y,
+    rd_grad_tile<MCH, CAP, false>(s, views, vol3, inter, grad_proj, nullptr, partials, blockIdx.y,
                                   blockIdx.x, gridDim.x, lds, sh);
 }
 
@@ -670,13 +674,14 @@ template <int MCH, int CAP, bool HESS>
 __global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
                                                               const ViewGeo* __restrict__ views,
                                                               const float* __restrict__ vol4,
+                                                              const float4* __restrict__ inter,
                                                               const float* __restrict__ target,
                                                               float* __restrict__ proj,
                                                               float* __restrict__ partials)
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, true, HESS>(s, views, vol4, target, proj, partials, blockIdx.y,
+    rd_grad_tile<MCH, CAP, true, HESS>(s, views, vol4, inter, target, proj, partials, blockIdx.y,
                                        blockIdx.x, gridDim.x, lds, sh);
 }
 
@@ -712,8 +717,21 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.gin, nullptr, it.out,
+    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.inter, it.gin, nullptr, it.out,
                                   local / it.tiles, local % it.tiles, it.tiles, lds, sh);
+}
+
+// Single-pass SSD with the Gauss-Newton matrix over an uneven batch.
+template <int MCH, int CAP>
+__global__ __launch_bounds__(kRdThreads) void rd_fused_batch_kernel(RdBatch bt)
+{
+    __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
+    __shared__ TileShared sh;
+    const int p = batch_problem(bt);
+    const RdBatchItem& it = bt.it[p];
+    const int local = (int)blockIdx.x - it.first;
+    rd_grad_tile<MCH, CAP, true, true>(it.s, it.views, it.vol, it.inter, it.gin, it.proj, it.out,
+                                       local / it.tiles, local % it.tiles, it.tiles, lds, sh);
 }
 
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
@@ -730,40 +748,41 @@ void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float
 }
 
 void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
-                    const float* grad_proj, float* partials, int variant, hipStream_t st)
+                    const float4* inter, const float* grad_proj, float* partials, int variant,
+                    hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     prof_begin(DP_K_RD_GRAD, st);
     switch (variant) {
-    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, vol3, grad_proj, partials); break;
-    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, vol3, grad_proj, partials); break;
-    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, vol3, grad_proj, partials); break;
+    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, vol3, inter, grad_proj, partials); break;
+    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, vol3, inter, grad_proj, partials); break;
+    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, vol3, inter, grad_proj, partials); break;
     }
     prof_end(DP_K_RD_GRAD, st);
 }
 
 template <bool HESS>
 static void launch_rd_fused_t(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                              const float* target, float* proj, float* partials, int variant,
-                              hipStream_t st)
+                              const float4* inter, const float* target, float* proj,
+                              float* partials, int variant, hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     switch (variant) {
-    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
-    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
-    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, target, proj, partials); break;
+    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, inter, target, proj, partials); break;
+    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, inter, target, proj, partials); break;
+    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, inter, target, proj, partials); break;
     }
 }
 
 void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                     const float* target, float* proj, float* partials, bool hess, int variant,
-                     hipStream_t st)
+                     const float4* inter, const float* target, float* proj, float* partials,
+                     bool hess, int variant, hipStream_t st)
 {
     prof_begin(DP_K_RD_FUSED, st);
     if (hess)
-        launch_rd_fused_t<true>(s, V, views, vol4, target, proj, partials, variant, st);
+        launch_rd_fused_t<true>(s, V, views, vol4, inter, target, proj, partials, variant, st);
     else
-        launch_rd_fused_t<false>(s, V, views, vol4, target, proj, partials, variant, st);
+        launch_rd_fused_t<false>(s, V, views, vol4, inter, target, proj, partials, variant, st);
     prof_end(DP_K_RD_FUSED, st);
 }
 
@@ -776,6 +795,17 @@ void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t
     default: rd_fwd_batch_kernel<32, 8192><<<blocks, kRdThreads, 0, st>>>(bt); break;
     }
     prof_end(DP_K_RD_FWD, st);
+}
+
+void launch_rd_fused_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)
+{
+    prof_begin(DP_K_RD_FUSED, st);
+    switch (variant) {
+    case 0: rd_fused_batch_kernel<8, 2048><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    case 2: rd_fused_batch_kernel<32, 4096><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    default: rd_fused_batch_kernel<16, 3072><<<blocks, kRdThreads, 0, st>>>(bt); break;
+    }
+    prof_end(DP_K_RD_FUSED, st);
 }
 
 void launch_rd_grad_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)

@@ -306,3 +306,111 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
         torch.cuda.synchronize(dev)
     return RegistrationResult(poses=z * D, iterations=its, converged=done, final_loss=f,
                               seconds=time.perf_counter() - t0, launches=launches)
+
+
+class BatchLM:
+    """Levenberg-Marquardt registration of an uneven batch of problems (up to
+    16 volumes, each with its own geometry and views; every view its own
+    6-DoF pose) that runs entirely on the device.
+
+    One iteration is two library launches: the single-pass SSD batch
+    (DRR, per-view SSD, analytic pose gradient and Gauss-Newton matrix for
+    every view of every problem in one ray launch) and the FP64 update
+    kernel (accept/reject against the last accepted point, damped 6 x 6
+    Cholesky solve, next trial pose).  No host round trip, no allocation,
+    so `capture()` records one iteration into a HIP graph that `run()`
+    replays.  Same rule as `register_lm`: scaled parameters
+    z = (t / 1 mm, gamma / 1 deg), step (H + lam diag H) d = -g, lam /= 3 on
+    accept, *= 4 on reject; a view stops when an accepted step is below tol
+    in every scaled parameter or lam exceeds 1e10.
+
+    problems: list of dicts with geom, angles [V] f64, vol [nz][ny][nx] f32
+    and target [V][nv][nu] f32 (CUDA tensors).
+    """
+
+    def __init__(self, problems, init_poses, lam0=1e-3, tol=1e-4, variant=-1, stream=None):
+        from . import OP_FWD_SSD, batch_workspace_bytes
+        f64 = torch.float64
+        dev = problems[0]["vol"].device
+        counts = [int(q["angles"].numel()) for q in problems]
+        self.n = sum(counts)
+        self.lam0, self.tol, self.variant, self.stream = lam0, tol, variant, stream
+        self.trial = torch.empty((self.n, 6), dtype=f64, device=dev)
+        self.loss = torch.empty(self.n, dtype=f64, device=dev)
+        self.grad = torch.empty((self.n, 6), dtype=f64, device=dev)
+        self.hess = torch.empty((self.n, 21), dtype=f64, device=dev)
+        self.state = dict(pose=torch.empty((self.n, 6), dtype=f64, device=dev),
+                          f=torch.empty(self.n, dtype=f64, device=dev),
+                          g=torch.zeros((self.n, 6), dtype=f64, device=dev),
+                          h=torch.zeros((self.n, 21), dtype=f64, device=dev),
+                          lam=torch.empty(self.n, dtype=f64, device=dev),
+                          done=torch.empty(self.n, dtype=torch.int32, device=dev))
+        self.problems = []
+        a = 0
+        for q, V in zip(problems, counts):
+            g = q["geom"]
+            self.problems.append(dict(
+                geom=g, angles=q["angles"], vol=q["vol"], target=q["target"],
+                poses=self.trial[a:a + V], grad_pose=self.grad[a:a + V],
+                hess=self.hess[a:a + V], loss=self.loss[a:a + V],
+                proj=torch.empty((V, g.nv, g.nu), dtype=torch.float32, device=dev)))
+            a += V
+        self.ws = torch.empty(batch_workspace_bytes(self.problems, OP_FWD_SSD), dtype=torch.uint8,
+                              device=dev)
+        self.graph = None
+        self.reset(init_poses)
+
+    def reset(self, init_poses):
+        """Start again from init_poses [n][6] (all views, problem by problem)."""
+        self.trial.copy_(init_poses)
+        self.state["pose"].copy_(init_poses)
+        self.state["f"].fill_(math.inf)
+        self.state["lam"].fill_(self.lam0)
+        self.state["done"].zero_()
+
+    def step(self, stream=None):
+        """One iteration: evaluate the trial poses, update the state."""
+        from . import lm_update, project_fwd_ssd_gauss_newton_batch
+        st = stream if stream is not None else self.stream
+        project_fwd_ssd_gauss_newton_batch(self.problems, ws=self.ws, variant=self.variant, stream=st)
+        lm_update(self.trial, self.loss, self.grad, self.hess, self.state, tol=self.tol, stream=st)
+
+    def step_sequential(self, ws, stream=None):
+        """The same iteration with one single-problem SSD launch per problem
+        (ws: a workspace large enough for the largest problem)."""
+        from . import lm_update, project_fwd_ssd_gauss_newton
+        st = stream if stream is not None else self.stream
+        for q in self.problems:
+            project_fwd_ssd_gauss_newton(q["geom"], q["angles"], q["poses"], q["vol"], q["target"],
+                                         proj=q["proj"], loss=q["loss"], grad=q["grad_pose"],
+                                         hess=q["hess"], ws=ws, stream=st, packed=True)
+        lm_update(self.trial, self.loss, self.grad, self.hess, self.state, tol=self.tol, stream=st)
+
+    def capture(self):
+        """Record one iteration into a HIP graph (after one eager warm-up
+        iteration on a side stream; the state is restored afterwards)."""
+        saved = {k: v.clone() for k, v in self.state.items()}
+        trial = self.trial.clone()
+        s2 = torch.cuda.Stream()
+        s2.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s2):
+            self.step(torch.cuda.current_stream())
+        torch.cuda.current_stream().wait_stream(s2)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.step(torch.cuda.current_stream())
+        for k, v in saved.items():
+            self.state[k].copy_(v)
+        self.trial.copy_(trial)
+
+    def run(self, iters, graph=True):
+        """iters iterations (graph replays if captured and graph=True)."""
+        for _ in range(iters):
+            if graph and self.graph is not None:
+                self.graph.replay()
+            else:
+                self.step()
+
+    def result(self):
+        """(accepted poses [n][6], converged [n] bool, SSD at the accepted poses [n])."""
+        return (self.state["pose"].clone(), self.state["done"].bool(), self.state["f"].clone())

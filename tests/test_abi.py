@@ -144,6 +144,36 @@ def test_newer_entries_validate_before_launch(lib):
                                    None) == -1  # misaligned workspace
 
 
+def test_batch_ssd_and_lm_update_validate_before_launch(lib):
+    """Batched single-pass SSD and the device LM update: the batch workspace
+    is the sum of the per-problem ones (so the problem array's layout matches
+    the header), and bad arguments are refused before any launch."""
+    import paper_2508_13304_amd as m
+    g1, g2 = synth.geom_c1(), synth.geom_c1().replace(nx=40, nu=70)
+    arr = (m.DPProblem * 2)()
+    p = 1 << 20
+    for i, (g, V) in enumerate(((g1, 3), (g2, 5))):
+        arr[i].geom = m.geom_struct(g)
+        arr[i].n_views = V
+        arr[i].angles = arr[i].poses = arr[i].vol = arr[i].proj = p
+        arr[i].grad_proj = arr[i].grad_pose = arr[i].hess = p
+    need = lib.dp_batch_workspace_bytes(arr, 2, m.OP_FWD_SSD)
+    assert need == m.workspace_bytes(g1, 3, m.OP_FWD_SSD) + m.workspace_bytes(g2, 5, m.OP_FWD_SSD)
+    ws = C.c_void_p(1 << 24)
+    assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 2, ws, need - 256, -1, None) == -2
+    assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 2, ws, need, 3, None) == -1
+    assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 17, ws, need, -1, None) == -4
+    arr[1].hess = None
+    assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 2, ws, need, -1, None) == -1
+    assert b"problem 1" in lib.dp_last_error()
+    q = C.c_void_p(p)
+    args = [q] * 10
+    assert lib.dp_lm_update(0, *args, 1e-4, None) == -1
+    assert lib.dp_lm_update(4, *args, -1.0, None) == -1
+    assert lib.dp_lm_update(4, *(args[:9] + [None]), 1e-4, None) == -1
+    assert b"NULL" in lib.dp_last_error()
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     import paper_2508_13304_amd as m
     saved = m._lib
