@@ -10,7 +10,10 @@ pose-gradient launch for the whole batch.  Two optimisers:
   with separate step sizes for translations (mm) and rotations (deg), a
   step-size decay, and per-registration stopping: a registration whose
   largest update falls below a tolerance for a few consecutive iterations is
-  frozen and dropped from later launches.
+  frozen and dropped from later launches (stop="step"), or the registration
+  experiment's rule (stop="paper", Sec. III-A): stop once the loss changes by
+  less than 1e-5 between iterations or the NCC with the target exceeds
+  0.999; a registration ending below NCC 0.99 counts as failed.
 * ``register_bfgs`` -- quasi-Newton (BFGS inverse-Hessian updates on the six
   parameters in units of 1 mm / 1 deg, Armijo acceptance, a shorter step after
   each rejection).  It uses the same analytic gradient and converges to the
@@ -59,6 +62,8 @@ class RegistrationResult:
     final_loss: torch.Tensor     # [B]
     seconds: float
     launches: int                # forward + gradient launch pairs
+    ncc: torch.Tensor | None = None     # [B] NCC at the last evaluation (stop="paper")
+    failed: torch.Tensor | None = None  # [B] NCC < 0.99 at the end (stop="paper")
 
 
 def pose_errors(est: torch.Tensor, truth: torch.Tensor):
@@ -75,13 +80,19 @@ def success(est, truth, t_tol_mm=0.1, r_tol_deg=0.1):
 def register(geom, vol, angles, targets, init_poses, loss="ssd", iters=300, lr_t=2.0,
              lr_r_deg=2.0, decay=0.985, min_lr_frac=0.01, tol_t=1e-3, tol_r_deg=1e-3,
              patience=5, compact_every=10, betas=(0.9, 0.999), eps=1e-12,
-             project=None) -> RegistrationResult:
+             project=None, stop="step", dloss_tol=1e-5, ncc_stop=0.999,
+             ncc_fail=0.99) -> RegistrationResult:
     """Register every target image to the volume, starting from init_poses.
 
     geom: projector geometry; vol [nz][ny][nx] f32; angles [B] f64;
     targets [B][nv][nu] f32; init_poses [B][6] f64 (all on the GPU).
     `project` overrides the differentiable projector (defaults to ProjectFwd).
+    stop: "step" (updates below tol_t / tol_r_deg for `patience` iterations)
+    or "paper" (|loss change| < dloss_tol or NCC > ncc_stop; NCC < ncc_fail
+    at the end marks a failure).
     """
+    if stop not in ("step", "paper"):
+        raise ValueError(f"unknown stopping rule {stop}")
     proj_fn = project or (lambda p, a: ProjectFwd.apply(p, vol, geom, a))
     B = init_poses.shape[0]
     dev = init_poses.device
@@ -94,6 +105,7 @@ def register(geom, vol, angles, targets, init_poses, loss="ssd", iters=300, lr_t
     calm = torch.zeros(B, dtype=torch.int64, device=dev)
     done = torch.zeros(B, dtype=torch.bool, device=dev)
     last_loss = torch.zeros(B, dtype=torch.float64, device=dev)
+    ncc = torch.zeros(B, dtype=torch.float64, device=dev)
     active = torch.arange(B, device=dev)
     launches = 0
     t0 = time.perf_counter()
@@ -116,15 +128,29 @@ def register(geom, vol, angles, targets, init_poses, loss="ssd", iters=300, lr_t
             upd = lr * scale * mh / (vh.sqrt() + eps)
             poses[active] = p.detach() - upd
             m[active], v[active], its[active] = ma, va, k
+            if stop == "paper":
+                # the rule judges the pose just evaluated: freeze it there
+                c = ncc_per_view(l.detach(), targets[active])
+                stalled = (k > 1) & ((L.detach() - last_loss[active]).abs() < dloss_tol)
+                hit = stalled | (c > ncc_stop)
+                poses[active] = torch.where(hit[:, None], p.detach(), poses[active])
+                ncc[active] = c
+                done[active] = hit
+            else:
+                small = (upd.abs() < tol).all(dim=1)
+                calm[active] = torch.where(small, calm[active] + 1, torch.zeros_like(calm[active]))
+                done[active] = calm[active] >= patience
             last_loss[active] = L.detach()
-            small = (upd.abs() < tol).all(dim=1)
-            calm[active] = torch.where(small, calm[active] + 1, torch.zeros_like(calm[active]))
-            done[active] = calm[active] >= patience
-            if (it + 1) % compact_every == 0:
+            # the paper's rule freezes a registration at the pose it judged
+            if stop == "paper" or (it + 1) % compact_every == 0:
                 active = active[~done[active]]
     torch.cuda.synchronize(dev) if dev.type == "cuda" else None
-    return RegistrationResult(poses=poses, iterations=its, converged=done, final_loss=last_loss,
-                              seconds=time.perf_counter() - t0, launches=launches)
+    res = RegistrationResult(poses=poses, iterations=its, converged=done, final_loss=last_loss,
+                             seconds=time.perf_counter() - t0, launches=launches)
+    if stop == "paper":
+        res.ncc = ncc
+        res.failed = ncc < ncc_fail
+    return res
 
 
 def autotune_registration(geom, vol, angles, poses, targets, reps=3):

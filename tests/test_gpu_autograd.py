@@ -148,3 +148,25 @@ def test_batched_adam_registration_reduces_error(dp):
     et0, er0 = reg.pose_errors(torch.zeros_like(truth), truth)
     assert bool((er < 0.1).all()), er
     assert float(et.median()) < 0.1 * float(et0.median())
+
+
+def test_adam_with_the_papers_stopping_rule(dp):
+    """NCC loss with the registration experiment's rule: every registration
+    stops (loss change below 1e-5 or NCC above 0.999) and none ends below
+    NCC 0.99; stopped registrations are frozen at the pose the rule judged
+    (their NCC there is what the result reports)."""
+    from paper_2508_13304_amd import registration as reg
+    g, vol, truth, angles, targets = _registration_case(dp)
+    res = reg.register(g, vol, angles, targets, torch.zeros_like(truth), loss="ncc", iters=300,
+                       lr_t=2.0, lr_r_deg=2.0, decay=0.985, stop="paper")
+    et, er = _report(reg, res, truth)
+    print("NCC", res.ncc.cpu().numpy().round(5), flush=True)
+    assert bool(res.converged.all())
+    assert not bool(res.failed.any())
+    l = dp.project_fwd(g, angles, res.poses, vol)
+    assert torch.allclose(reg.ncc_per_view(l, targets), res.ncc, rtol=0, atol=1e-9)
+    assert bool((res.ncc > 0.99).all())
+    et0, er0 = reg.pose_errors(torch.zeros_like(truth), truth)
+    assert float(et.median()) < float(et0.median()) and float(er.median()) < float(er0.median())
+    with pytest.raises(ValueError):
+        reg.register(g, vol, angles, targets, torch.zeros_like(truth), stop="never")
