@@ -129,7 +129,13 @@ struct Corner {
 
 struct Box {
     int ox, oy, oz, bx, by, bz;
+    int px, py;  // LDS row and slice pitch in voxels (bx, by rounded up to odd)
 };
+
+// Odd LDS pitches: rays of one wavefront that sample neighbouring rows
+// (or slices) of a box then read different LDS banks; an even pitch maps
+// every other row onto the same banks.
+__device__ inline int lds_pitch(int n) { return n | 1; }
 
 // Block-wide state shared by both kernels.
 struct TileShared {
@@ -214,6 +220,8 @@ __device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step,
     Box bx;
     bx.ox = o[0]; bx.oy = o[1]; bx.oz = o[2];
     bx.bx = e[0] - o[0] + 1; bx.by = e[1] - o[1] + 1; bx.bz = e[2] - o[2] + 1;
+    bx.px = lds_pitch(bx.bx);
+    bx.py = lds_pitch(bx.by);
     return bx;
 }
 
@@ -234,7 +242,7 @@ __device__ inline int plan_chunks(TileShared& sh, int Kmin, int Kmax, int Mmax, 
             unsigned short* q = sh.box[threadIdx.x];
             q[0] = (unsigned short)b.ox; q[1] = (unsigned short)b.oy; q[2] = (unsigned short)b.oz;
             q[3] = (unsigned short)b.bx; q[4] = (unsigned short)b.by; q[5] = (unsigned short)b.bz;
-            vol = b.bx * b.by * b.bz;
+            vol = lds_pitch(b.bx) * lds_pitch(b.by) * b.bz;
         }
         for (int off = 32; off > 0; off >>= 1) vol = max(vol, __shfl_xor(vol, off));
         if (lane == 0) sh.vmax[wave] = vol;
@@ -252,13 +260,16 @@ __device__ inline Box planned_box(const TileShared& sh, int i)
     const unsigned short* q = sh.box[i];
     Box b;
     b.ox = q[0]; b.oy = q[1]; b.oz = q[2]; b.bx = q[3]; b.by = q[4]; b.bz = q[5];
+    b.px = lds_pitch(b.bx);
+    b.py = lds_pitch(b.by);
     return b;
 }
 
 // Cooperative copy of the box from padded global planes into LDS, in the
 // box's own x-fastest order with C channels interleaved per voxel (LDS
-// index = C * flat box index).  e -> (x, y, z) uses multiply-high
-// reciprocals; each thread issues BATCH loads before writing any to LDS.
+// index = C * ((z * py + y) * px + x); the pitch padding is never read).
+// e -> (x, y, z) uses multiply-high reciprocals; each thread issues BATCH
+// loads before writing any to LDS.
 template <int C, int BATCH>
 __device__ inline void load_box(const Box& b, const float* const (&src)[C], float* dst, int NX,
                                 int NXY)
@@ -274,6 +285,7 @@ __device__ inline void load_box(const Box& b, const float* const (&src)[C], floa
     for (int c = 0; c < C; ++c) sb[c] = src[c] + base;
     for (int e0 = threadIdx.x; e0 < vol; e0 += kRdThreads * BATCH) {
         float val[BATCH][C];
+        unsigned slot[BATCH];
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
             const int e = e0 + i * kRdThreads;
@@ -285,14 +297,20 @@ __device__ inline void load_box(const Box& b, const float* const (&src)[C], floa
                 const unsigned off = lz * (unsigned)NXY + ly * (unsigned)NX + lx;
 #pragma unroll
                 for (int c = 0; c < C; ++c) val[i][c] = sb[c][off];
+                slot[i] = C * ((lz * (unsigned)b.py + ly) * (unsigned)b.px + lx);
             }
         }
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
             const int e = e0 + i * kRdThreads;
             if (e < vol) {
+                if constexpr (C == 4) {  // one 16-byte store: lanes 16 B apart, no bank conflict
+                    *reinterpret_cast<float4*>(dst + slot[i]) =
+                        make_float4(val[i][0], val[i][1], val[i][2], val[i][3]);
+                } else {
 #pragma unroll
-                for (int c = 0; c < C; ++c) dst[C * e + c] = val[i][c];
+                    for (int c = 0; c < C; ++c) dst[slot[i] + c] = val[i][c];
+                }
             }
         }
     }
@@ -349,8 +367,8 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
             __syncthreads();
             const int kb = max(K, klo), ke = min(Ke, khi);
             const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
-            const int BX = bx.bx, BXY = bx.bx * bx.by;
-            const float fbx = (float)bx.bx, fby = (float)bx.by;
+            const int BX = bx.px, BXY = bx.px * bx.py;
+            const float fbx = (float)bx.px, fby = (float)bx.py;
             const int imax = CAP - 1 - (BXY + BX + 1);
             for (float j = 0.0f; j <= c.n; j += 1.0f) {
                 const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
@@ -525,10 +543,10 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             __syncthreads();
             const int kb = max(K, klo), ke = min(Ke, khi);
             const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
-            const int BXC = C * bx.bx, BXYC = C * bx.bx * bx.by;
-            const float fbx = (float)bx.bx, fby = (float)bx.by;
+            const int BXC = C * bx.px, BXYC = C * bx.px * bx.py;
+            const float fbx = (float)bx.px, fby = (float)bx.py;
             // largest base voxel whose 2x2x2 corners stay inside the box
-            const int vmax = CAP - 2 - (bx.bx * bx.by + bx.bx);
+            const int vmax = CAP - 2 - (bx.px * bx.py + bx.px);
             GradAcc Gc;  // base-corner frame: local box indices
             for (float j = 0.0f; j <= c.n; j += 1.0f) {
                 const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
