@@ -99,7 +99,7 @@ Layout layout(const dp_geom& g, int V, int op)
         break;
     case DP_OP_BP_GRAD:
         off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float4));
-        L.n_part = (size_t)vd_blocks(s, kVdGradCol);
+        L.n_part = (size_t)vd_blocks(s, kVdGradCol) * kVdBy;  // one partial set per wavefront
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kVdChannels * sizeof(float));
         break;
@@ -205,6 +205,7 @@ struct Prof {
     std::vector<hipEvent_t> ev;          // pairs (start, stop)
     std::vector<int> kern;               // kernel id of each pair
     size_t used = 0;
+    bool open = false;                   // a start event of pair `used` was recorded
     double total_ms[DP_K_COUNT] = {0};
     int64_t count[DP_K_COUNT] = {0};
 };
@@ -213,19 +214,22 @@ constexpr size_t kProfPairs = 4096;
 
 }  // namespace
 
+// Best effort: a pair whose events could not be recorded is dropped.
 void prof_begin(int kernel, hipStream_t st)
 {
+    g_prof.open = false;
     if (!g_prof.on || g_prof.used >= kProfPairs) return;
-    hipEventRecord(g_prof.ev[2 * g_prof.used], st);
+    if (hipEventRecord(g_prof.ev[2 * g_prof.used], st) != hipSuccess) return;
     g_prof.kern[g_prof.used] = kernel;
+    g_prof.open = true;
 }
 
 void prof_end(int kernel, hipStream_t st)
 {
     (void)kernel;
-    if (!g_prof.on || g_prof.used >= kProfPairs) return;
-    hipEventRecord(g_prof.ev[2 * g_prof.used + 1], st);
-    ++g_prof.used;
+    if (!g_prof.on || !g_prof.open) return;
+    g_prof.open = false;
+    if (hipEventRecord(g_prof.ev[2 * g_prof.used + 1], st) == hipSuccess) ++g_prof.used;
 }
 
 }  // namespace dp
@@ -519,7 +523,10 @@ int dp_autotune(int32_t op, const dp_geom* g, int32_t V, const double* angles, c
     for (int var = 0; var < kRdVariants && rc == DP_OK; ++var) {
         dp_set_variant(op, var);
         for (int r = 0; r <= reps && rc == DP_OK; ++r) {  // first call warms up
-            if (r == 1) hipEventRecord(e0, st);
+            if (r == 1 && hipEventRecord(e0, st) != hipSuccess) {
+                rc = fail(DP_ERR_HIP, "hipEventRecord failed");
+                break;
+            }
             if (op == DP_OP_FWD)
                 rc = dp_project_fwd(g, V, angles, poses, vol, (float*)out, ws, ws_bytes, stream);
             else if (op == DP_OP_FWD_GRAD)
@@ -530,20 +537,22 @@ int dp_autotune(int32_t op, const dp_geom* g, int32_t V, const double* angles, c
                     g, V, angles, poses, vol, grad_proj, (float*)out, nullptr,
                     (double*)((char*)ws + layout(*g, V, DP_OP_FWD_SSD).spare), ws, ws_bytes, stream);
         }
-        hipEventRecord(e1, st);
-        if (rc == DP_OK && hipEventSynchronize(e1) == hipSuccess) {
-            hipEventElapsedTime(&times[var], e0, e1);
-            times[var] /= reps;
-            if (times[var] < times[arg]) arg = var;
+        if (rc != DP_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&times[var], e0, e1) != hipSuccess) {
+            rc = fail(DP_ERR_HIP, "event timing failed");
+            break;
         }
+        times[var] /= reps;
+        if (times[var] < times[arg]) arg = var;
     }
     {
         std::lock_guard<std::mutex> lk(g_var_mu);
         g_var_force[op] = saved;
         if (rc == DP_OK) g_var_cache[variant_key(op, *g, V)] = arg;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (best) *best = arg;
     if (ms_per_variant)

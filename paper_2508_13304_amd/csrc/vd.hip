@@ -142,12 +142,13 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, in
                                                                 const float* __restrict__ grad_vol,
                                                                 float* __restrict__ partials)
 {
-    __shared__ float red[kVdBy][kVdChannels];
     const int i = blockIdx.x * kVdBx + threadIdx.x;
     const int j = blockIdx.y * kVdBy + threadIdx.y;
     const int kb = blockIdx.z * K;
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    // one partial set per wavefront (threadIdx.y), [V][blocks * kVdBy][kVdChannels]
+    const int wv = blk * kVdBy + (int)threadIdx.y;
+    const int nwv = gridDim.x * gridDim.y * gridDim.z * kVdBy;
     const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
     const float D2 = (float)(s.sad * s.sad);
     const float kappa = MODE == DP_W_FDK ? 2.0f : 0.0f;
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, in
         e[kk] = in ? grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
         if (MODE == DP_W_FDK) e[kk] *= D2;
     }
-    const int lane = threadIdx.x, wave = threadIdx.y;
+    const int lane = threadIdx.x;  // kVdBx = 64: one wavefront per threadIdx.y
     for (int v = 0; v < V; ++v) {
         const ViewGeo& g = views[v];
         const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
@@ -196,21 +197,36 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, in
             A1 += c1; A2 += c2; A3 += c3;
             Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
         }
-        float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
-                                pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
+        // Channel-halving butterfly over the wavefront: at the xor-32 and
+        // xor-16 steps each lane keeps half of the channels and receives the
+        // partner's sums of them, so the 12 channels take 6 + 3 + 4 x 3 = 21
+        // cross-lane exchanges instead of 72.  Lane 16 q (q = 0..3) ends with
+        // channels 3 q .. 3 q + 2 of the whole wavefront; each wavefront
+        // writes its own partials (no block barrier, fixed summation order).
+        const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
+                                      pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
+        const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
+        float s6[6], s3[3];
 #pragma unroll
-        for (int ch = 0; ch < kVdChannels; ++ch)
-            for (int off = 32; off > 0; off >>= 1) r[ch] += __shfl_xor(r[ch], off);
-        if (lane == 0) {
+        for (int t = 0; t < 6; ++t) {
+            const float keep = h32 ? r[6 + t] : r[t], give = h32 ? r[t] : r[6 + t];
+            s6[t] = keep + __shfl_xor(give, 32);
+        }
 #pragma unroll
-            for (int ch = 0; ch < kVdChannels; ++ch) red[wave][ch] = r[ch];
+        for (int t = 0; t < 3; ++t) {
+            const float keep = h16 ? s6[3 + t] : s6[t], give = h16 ? s6[t] : s6[3 + t];
+            s3[t] = keep + __shfl_xor(give, 16);
         }
-        __syncthreads();
-        if (wave == 0 && lane < kVdChannels) {
-            const float sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-            partials[((size_t)v * nblk + blk) * kVdChannels + lane] = sum;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) s3[t] += __shfl_xor(s3[t], off);
+        if ((lane & 15) == 0) {
+            float* out = partials + ((size_t)v * nwv + wv) * kVdChannels + (lane >> 4) * 3;
+            out[0] = s3[0];
+            out[1] = s3[1];
+            out[2] = s3[2];
         }
-        __syncthreads();
     }
 }
 
