@@ -21,7 +21,8 @@
 //   amplitude: the chord L_j of the voxel along the line from the source
 //     through its centre;
 //   a_ij = L_j * int_{a_i - 1/2}^{a_i + 1/2} T * |[b_lo, b_hi] cap [b_i - 1/2, b_i + 1/2]|.
-// Every thread owns a column of K voxels along z and walks the views; per
+// Every thread owns a column of K voxels along z and walks the views (the
+// forward scatter picks the column per view, see sf_fwd_kernel); per
 // voxel-view it visits the footprint's pixel window (clipped to the
 // detector).  The forward projection scatters a_ij mu_j with FP32 atomics;
 // the back-projection and both gradients gather, so they are deterministic.
@@ -177,27 +178,44 @@ __device__ inline double sf_gather(const SfFootprint& f, const float* __restrict
     return f.L * acc;
 }
 
+// Forward scatter.  A wavefront's 64 lanes take 64 neighbouring voxels
+// across the view's rays, not along them: lanes along y when the rays run
+// closest to the x axis (DD's dominant axis 0), along x otherwise, so their
+// footprints cover neighbouring pixels instead of all landing on the same
+// ones (their FP32 atomics would serialise).  The flat block index covers
+// both tilings of the (x, y) plane; each block decodes it per view.
 template <int KIND>
 __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_kernel(GeoScalars s, int V,
                                                                const ViewGeo* __restrict__ views,
                                                                const float* __restrict__ vol,
                                                                float* __restrict__ proj)
 {
-    const int i = blockIdx.x * kSfBx + threadIdx.x;
-    const int j = blockIdx.y * kSfBy + threadIdx.y;
     const int kb = blockIdx.z * kSfCol;
-    if (i >= s.nx || j >= s.ny) return;
-    for (int kk = 0; kk < kSfCol && kb + kk < s.nz; ++kk) {
-        const int k = kb + kk;
-        const float mu = vol[((size_t)k * s.ny + j) * s.nx + i];
-        if (mu == 0.0f) continue;
-        for (int v = 0; v < V; ++v) {
-            const ViewGeo& g = views[v];
-            double src[3];
-            const int dom = sf_source(g, s, src);
+    const int bxx = (s.nx + kSfBx - 1) / kSfBx, byx = (s.ny + kSfBy - 1) / kSfBy;  // lanes along x
+    const int bxy = (s.ny + kSfBx - 1) / kSfBx, byy = (s.nx + kSfBy - 1) / kSfBy;  // lanes along y
+    const int blk = blockIdx.x;
+    for (int v = 0; v < V; ++v) {
+        const ViewGeo& g = views[v];
+        double src[3];
+        const int dom = sf_source(g, s, src);
+        int i, j;
+        if (dom == 0) {
+            if (blk >= bxy * byy) continue;
+            j = (blk % bxy) * kSfBx + (int)threadIdx.x;
+            i = (blk / bxy) * kSfBy + (int)threadIdx.y;
+        } else {
+            if (blk >= bxx * byx) continue;
+            i = (blk % bxx) * kSfBx + (int)threadIdx.x;
+            j = (blk / bxx) * kSfBy + (int)threadIdx.y;
+        }
+        if (i >= s.nx || j >= s.ny) continue;
+        float* img = proj + (size_t)v * s.nu * s.nv;
+        for (int kk = 0; kk < kSfCol && kb + kk < s.nz; ++kk) {
+            const int k = kb + kk;
+            const float mu = vol[((size_t)k * s.ny + j) * s.nx + i];
+            if (mu == 0.0f) continue;
             SfFootprint f;
             if (!sf_footprint<KIND>(g, s, src, dom, i, j, k, f)) continue;
-            float* img = proj + (size_t)v * s.nu * s.nv;
             for (int b = f.b0; b <= f.b1; ++b) {
                 const double wb = row_overlap(b, f.blo, f.bhi) * f.L * (double)mu;
                 if (wb == 0.0) continue;
@@ -412,9 +430,16 @@ void launch_sf_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float
 {
     const size_t n = (size_t)V * s.nu * s.nv;
     const int zb = (int)std::min<size_t>((n + 255) / 256, 65536);
+    // flat (x, y) block index large enough for either lane order
+    const int bx = std::max(((s.nx + kSfBx - 1) / kSfBx) * ((s.ny + kSfBy - 1) / kSfBy),
+                            ((s.ny + kSfBx - 1) / kSfBx) * ((s.nx + kSfBy - 1) / kSfBy));
+    const dim3 grid(bx, 1, (s.nz + kSfCol - 1) / kSfCol);
     prof_begin(DP_K_SF, st);
     sf_zero_kernel<<<zb, 256, 0, st>>>(n, proj);
-    DP_FP_LAUNCH(sf_fwd_kernel, s, V, views, vol, proj);
+    if (kind == kFpDD)
+        sf_fwd_kernel<kFpDD><<<grid, dim3(kSfBx, kSfBy), 0, st>>>(s, V, views, vol, proj);
+    else
+        sf_fwd_kernel<kFpSF><<<grid, dim3(kSfBx, kSfBy), 0, st>>>(s, V, views, vol, proj);
     prof_end(DP_K_SF, st);
 }
 
