@@ -353,8 +353,18 @@ def _problems(problems, op):
 
 
 def batch_workspace_bytes(problems, op) -> int:
-    arr = _problems(problems, op)
-    return int(load().dp_batch_workspace_bytes(arr, len(problems), op))
+    """Workspace for the batched entries over `problems`: batches of more than
+    16 problems run as consecutive launches of 16 on one stream, which reuse
+    one workspace, so this is the largest chunk's requirement (0 if invalid)."""
+    lib = load()
+    need = 0
+    for s0 in range(0, len(problems), MAX_BATCH):
+        chunk = problems[s0:s0 + MAX_BATCH]
+        n = int(lib.dp_batch_workspace_bytes(_problems(chunk, op), len(chunk), op))
+        if n == 0:
+            return 0
+        need = max(need, n)
+    return need
 
 
 def _run_batch(problems, op, ws, variant, stream):

@@ -335,9 +335,10 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
 
 
 class BatchLM:
-    """Levenberg-Marquardt registration of an uneven batch of problems (up to
-    16 volumes, each with its own geometry and views; every view its own
-    6-DoF pose) that runs entirely on the device.
+    """Levenberg-Marquardt registration of an uneven batch of problems (each
+    with its own volume, geometry and views; every view its own 6-DoF pose)
+    that runs entirely on the device.  More than 16 problems run as
+    consecutive batch launches of 16 sharing one workspace.
 
     One iteration is two library launches: the single-pass SSD batch
     (DRR, per-view SSD, analytic pose gradient and Gauss-Newton matrix for
@@ -381,8 +382,10 @@ class BatchLM:
                 hess=self.hess[a:a + V], loss=self.loss[a:a + V],
                 proj=torch.empty((V, g.nv, g.nu), dtype=torch.float32, device=dev)))
             a += V
-        self.ws = torch.empty(batch_workspace_bytes(self.problems, OP_FWD_SSD), dtype=torch.uint8,
-                              device=dev)
+        need = batch_workspace_bytes(self.problems, OP_FWD_SSD)
+        if need == 0:
+            raise ValueError("invalid batch (geometry or sizes rejected by the library)")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
         self.graph = None
         self.reset(init_poses)
 

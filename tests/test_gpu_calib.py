@@ -232,3 +232,23 @@ def test_batch_lm_graph_replays_like_eager(dp):
         assert torch.equal(lm.state["lam"], lam), i
         assert torch.equal(lm.trial, tr), i
         _ = (lm.loss.sum() + 1.0).item()  # eager work between replays
+
+
+def test_batch_lm_beyond_sixteen_problems(dp):
+    """18 problems run as launches of 16 + 2 sharing one workspace: the
+    iterations equal those of two separate batches bit for bit, and the
+    workspace query reports the larger chunk."""
+    from paper_2508_13304_amd.registration import BatchLM
+    specs = [(16 + 4 * (i % 3), 3.0, 24 + 4 * (i % 2), 3.1, 1 + i % 2) for i in range(18)]
+    probs, truth, init = _problems(dp, 640, specs=specs)
+    n16 = sum(q["angles"].numel() for q in probs[:16])
+    both = BatchLM(probs, init)
+    first, second = BatchLM(probs[:16], init[:n16]), BatchLM(probs[16:], init[n16:])
+    assert both.ws.numel() == max(first.ws.numel(), second.ws.numel())
+    for _ in range(3):
+        both.step()
+        first.step()
+        second.step()
+    torch.cuda.synchronize()
+    assert torch.equal(both.state["pose"], torch.cat([first.state["pose"], second.state["pose"]]))
+    assert torch.equal(both.trial, torch.cat([first.trial, second.trial]))
