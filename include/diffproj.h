@@ -236,7 +236,9 @@ int32_t dp_get_variant(const dp_geom* g, int32_t n_views, int32_t op);
 int dp_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
                  const void* A, int32_t lda, const void* B, int32_t ldb, float* C,
                  int32_t ldc, int32_t accumulate, void* stream);
-/* col [N Ho Wo][9 C] BF16 from x [N][H][W][C] BF16; K index (ky, kx, c). */
+/* col [N Ho Wo][9 C] BF16 from x [N][H][W][C] BF16; K index (ky, kx, c).
+ * N Ho Wo 9 C and N H W C must stay below 2^31 (DP_ERR_UNSUPPORTED otherwise;
+ * split the batch).  The same limit holds for dp_col2im3x3. */
 int dp_im2col3x3_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
                       const void* x, void* col, void* stream);
 /* dx [N][H][W][C] FP32 = adjoint of im2col applied to dcol [N Ho Wo][9 C] FP32. */
@@ -248,7 +250,9 @@ int dp_bias_act_bf16(int64_t rows, int32_t C, const float* z, const float* bias,
 /* dz BF16 = dy * (y > 0) if relu else dy, elementwise (y BF16, dy FP32). */
 int dp_act_bwd_bf16(int64_t total, const float* dy, const void* y, int32_t relu, void* dz,
                     void* stream);
-/* db[c] = sum over the M rows of dz [M][C] (BF16), FP32 out. */
+/* db[c] = sum over the M rows of dz [M][C] (BF16), FP32 out (db is
+ * overwritten; block sums are combined with FP32 atomics, so the last bits
+ * can differ between runs). */
 int dp_colsum_bf16(int32_t M, int32_t C, const void* dz, float* db, void* stream);
 
 /* ---------------------------------------------------------------------------

@@ -745,6 +745,10 @@ static int conv_dims(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride)
 {
     if (N <= 0 || H <= 0 || W <= 0 || C <= 0 || stride <= 0)
         return fail(DP_ERR_ARG, "conv sizes must be positive");
+    // the im2col / col2im kernels index with 32 bits
+    const int64_t Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
+    if ((int64_t)N * Ho * Wo * 9 * C >= ((int64_t)1 << 31) || (int64_t)N * H * W * C >= ((int64_t)1 << 31))
+        return fail(DP_ERR_UNSUPPORTED, "conv: N x H x W x 9 C exceeds 2^31 elements; split the batch");
     return DP_OK;
 }
 

@@ -182,38 +182,57 @@ void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int 
 #undef DP_GEMM
 }
 
-// im2col of a 3x3 convolution (stride s, padding 1) on NHWC BF16 input.
+// im2col of a 3x3 convolution (stride s, padding 1) on NHWC BF16 input:
+// col[m][t C + c] = x[n][yo s + ky - 1][xo s + kx - 1][c] (zero outside),
+// t = 3 ky + kx.  One thread per (output pixel m, tap t, group of G
+// channels); G = 8 copies 16 bytes at a time.  Index math is 32-bit (the
+// host checks that every index space fits).
+template <int G>
 __global__ __launch_bounds__(256) void im2col_kernel(int N, int H, int W, int C, int s, int Ho,
                                                      int Wo, const __bf16* __restrict__ x,
                                                      __bf16* __restrict__ col)
 {
-    const size_t K = (size_t)9 * C;
-    const size_t total = (size_t)N * Ho * Wo * K;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const size_t m = i / K;
-        const int k = (int)(i - m * K);
-        const int ci = k % C, kk = k / C, kx = kk % 3, ky = kk / 3;
-        const int xo = (int)(m % Wo), yo = (int)((m / Wo) % Ho), n = (int)(m / ((size_t)Wo * Ho));
+    const unsigned groups = (unsigned)(C / G);
+    const unsigned total = (unsigned)N * Ho * Wo * 9u * groups;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const unsigned g = i % groups, r = i / groups;
+        const unsigned t = r % 9u, m = r / 9u;
+        const int xo = (int)(m % (unsigned)Wo);
+        const unsigned q = m / (unsigned)Wo;
+        const int yo = (int)(q % (unsigned)Ho), n = (int)(q / (unsigned)Ho);
+        const int ky = (int)t / 3, kx = (int)t - 3 * ky;
         const int yi = yo * s + ky - 1, xi = xo * s + kx - 1;
-        col[i] = (yi >= 0 && yi < H && xi >= 0 && xi < W)
-                     ? x[(((size_t)n * H + yi) * W + xi) * C + ci] : to_bf16(0.f);
+        __bf16* dst = col + (size_t)m * 9 * C + t * C + g * G;
+        const bool in = yi >= 0 && yi < H && xi >= 0 && xi < W;
+        const __bf16* src = x + (((size_t)n * H + yi) * W + xi) * C + g * G;
+        if constexpr (G == 8) {
+            *reinterpret_cast<uint4*>(dst) = in ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int c = 0; c < G; ++c) dst[c] = in ? src[c] : to_bf16(0.f);
+        }
     }
 }
 
-// dx = col2im(dcol): each input element gathers the window entries that read it.
+// dx = col2im(dcol): each input element gathers the window entries that read
+// it (taps in ky, kx order).  One thread per (n, yi, xi, group of G
+// channels); G = 4 moves float4.
+template <int G>
 __global__ __launch_bounds__(256) void col2im_kernel(int N, int H, int W, int C, int s, int Ho,
                                                      int Wo, const float* __restrict__ dcol,
                                                      float* __restrict__ dx)
 {
-    const size_t total = (size_t)N * H * W * C;
+    const unsigned groups = (unsigned)(C / G);
+    const unsigned total = (unsigned)N * H * W * groups;
     const int K = 9 * C;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const int ci = (int)(i % C);
-        const int xi = (int)((i / C) % W), yi = (int)((i / ((size_t)C * W)) % H);
-        const int n = (int)(i / ((size_t)C * W * H));
-        float acc = 0.f;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const unsigned g = i % groups, p = i / groups;
+        const int xi = (int)(p % (unsigned)W);
+        const unsigned q = p / (unsigned)W;
+        const int yi = (int)(q % (unsigned)H), n = (int)(q / (unsigned)H);
+        float acc[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) acc[c] = 0.f;
         for (int ky = 0; ky < 3; ++ky) {
             const int ty = yi + 1 - ky;  // = yo * s
             if (ty < 0 || ty % s) continue;
@@ -224,11 +243,23 @@ __global__ __launch_bounds__(256) void col2im_kernel(int N, int H, int W, int C,
                 if (tx < 0 || tx % s) continue;
                 const int xo = tx / s;
                 if (xo >= Wo) continue;
-                const size_t m = ((size_t)n * Ho + yo) * Wo + xo;
-                acc += dcol[m * K + (ky * 3 + kx) * C + ci];
+                const float* src = dcol + ((size_t)((n * Ho + yo) * Wo + xo)) * K + (ky * 3 + kx) * C + g * G;
+                if constexpr (G == 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(src);
+                    acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < G; ++c) acc[c] += src[c];
+                }
             }
         }
-        dx[i] = acc;
+        float* dst = dx + (size_t)p * C + g * G;
+        if constexpr (G == 4) {
+            *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < G; ++c) dst[c] = acc[c];
+        }
     }
 }
 
@@ -258,20 +289,45 @@ __global__ __launch_bounds__(256) void relu_bwd_kernel(size_t total, const float
 }
 
 // db[c] = sum over rows of dz (BF16 operand as used by the weight GEMM).
+// Grid-stride over rows with consecutive threads on consecutive elements:
+// for C < 256 a block covers R = 256 / C rows per pass (thread t: column
+// t % C, row offset t / C), for C >= 256 strips of 256 columns.  Each block
+// adds its column sums to db with FP32 atomics (db zeroed first), so the
+// summation order, and the last bits, vary from run to run.
 __global__ __launch_bounds__(256) void colsum_kernel(int M, int C, const __bf16* __restrict__ dz,
                                                      float* __restrict__ db)
 {
     __shared__ float red[256];
-    const int c = blockIdx.x;
-    float acc = 0.f;
-    for (int m = threadIdx.x; m < M; m += 256) acc += (float)dz[(size_t)m * C + c];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    const int t = threadIdx.x;
+    const bool narrow = C < 256;
+    const int R = narrow ? 256 / C : 1;
+    for (int c0 = 0; c0 < C; c0 += 256) {
+        const int c = narrow ? t % C : c0 + t;
+        const int ro = narrow ? t / C : 0;
+        const bool act = narrow ? t < R * C : c < C;
+        float acc = 0.f;
+        if (act)
+            for (size_t r = (size_t)blockIdx.x * R + ro; r < (size_t)M; r += (size_t)gridDim.x * R)
+                acc += (float)dz[r * C + c];
+        if (narrow) {
+            red[t] = acc;
+            __syncthreads();
+            if (t < C) {
+                float sum = 0.f;
+                for (int k = 0; k < R; ++k) sum += red[k * C + t];
+                atomicAdd(db + t, sum);
+            }
+            __syncthreads();
+        } else if (act) {
+            atomicAdd(db + c, acc);
+        }
     }
-    if (threadIdx.x == 0) db[c] = red[0];
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(int n, float* __restrict__ p)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
 }
 
 static int grid_for(size_t total)
@@ -283,16 +339,25 @@ static int grid_for(size_t total)
 void launch_im2col(int N, int H, int W, int C, int s, int Ho, int Wo, const void* x, void* col,
                    hipStream_t st)
 {
-    const size_t total = (size_t)N * Ho * Wo * 9 * C;
-    im2col_kernel<<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, (const __bf16*)x,
-                                                   (__bf16*)col);
+    const bool vec = C % 8 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)col % 16 == 0;
+    const size_t total = (size_t)N * Ho * Wo * 9 * (vec ? C / 8 : C);
+    if (vec)
+        im2col_kernel<8><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, (const __bf16*)x,
+                                                          (__bf16*)col);
+    else
+        im2col_kernel<1><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, (const __bf16*)x,
+                                                          (__bf16*)col);
 }
 
 void launch_col2im(int N, int H, int W, int C, int s, int Ho, int Wo, const float* dcol, float* dx,
                    hipStream_t st)
 {
-    const size_t total = (size_t)N * H * W * C;
-    col2im_kernel<<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx);
+    const bool vec = C % 4 == 0 && (uintptr_t)dcol % 16 == 0 && (uintptr_t)dx % 16 == 0;
+    const size_t total = (size_t)N * H * W * (vec ? C / 4 : C);
+    if (vec)
+        col2im_kernel<4><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx);
+    else
+        col2im_kernel<1><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx);
 }
 
 void launch_bias_relu(size_t total, int C, const float* z, const float* b, bool relu, void* y,
@@ -310,7 +375,10 @@ void launch_relu_bwd(size_t total, const float* dy, const void* y, bool relu, vo
 
 void launch_colsum(int M, int C, const void* dz, float* db, hipStream_t st)
 {
-    colsum_kernel<<<C, 256, 0, st>>>(M, C, (const __bf16*)dz, db);
+    const int R = C < 256 ? 256 / C : 1;
+    const int blocks = (int)std::min<long long>(1024, ((long long)M + R - 1) / R);
+    fill_zero_kernel<<<(C + 255) / 256, 256, 0, st>>>(C, db);
+    colsum_kernel<<<blocks, 256, 0, st>>>(M, C, (const __bf16*)dz, db);
 }
 
 }  // namespace dp

@@ -142,6 +142,10 @@ def test_newer_entries_validate_before_launch(lib):
     assert lib.dp_gradient_entropy(8, 8, 8, p, 0.0, p, None, ws, wge, None) == -1
     assert lib.dp_gradient_entropy(8, 8, 8, p, 1e-12, p, None, C.c_void_p((1 << 24) + 4), wge,
                                    None) == -1  # misaligned workspace
+    # CNN helpers: 32-bit index spaces
+    assert lib.dp_im2col3x3_bf16(512, 256, 256, 64, 1, p, p, None) == -4
+    assert lib.dp_col2im3x3(512, 256, 256, 64, 1, p, p, None) == -4
+    assert lib.dp_im2col3x3_bf16(0, 8, 8, 8, 1, p, p, None) == -1
 
 
 def test_batch_ssd_and_lm_update_validate_before_launch(lib):

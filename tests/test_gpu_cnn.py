@@ -49,11 +49,15 @@ def test_gemm_split_k_and_accumulate(dp):
     assert np.all(np.abs(C0.cpu().numpy() - (ref + 2.0)) <= 1e-5 * bound + 1e-6)
 
 
-@pytest.mark.parametrize("stride", [1, 2])
-def test_conv_layer_forward_backward(dp, stride):
+@pytest.mark.parametrize("stride,Ci,Co", [(1, 5, 7), (2, 5, 7), (2, 16, 300), (1, 8, 32)])
+def test_conv_layer_forward_backward(dp, stride, Ci, Co):
+    """One conv layer through the library (im2col, GEMMs, col2im, column
+    sums) against the oracle; channel counts that take the 16-byte im2col /
+    float4 col2im paths (Ci multiple of 8 / 4) and the element paths, and a
+    column sum wider than one 256-column strip."""
     from paper_2508_13304_amd import proposal as pr
-    rng = np.random.default_rng(11 + stride)
-    N, H, W, Ci, Co = 2, 13, 10, 5, 7
+    rng = np.random.default_rng(11 + stride + Ci)
+    N, H, W = 2, 13, 10
     x = ocnn.bf16(rng.standard_normal((N, H, W, Ci)))
     Wt = ocnn.bf16(rng.standard_normal((Co, 3, 3, Ci)))
     b = rng.standard_normal(Co).astype(np.float32).astype(np.float64)
