@@ -313,22 +313,13 @@ def run_calibration_batch(args, dp, torch):
     calibration from the perturbed poses by graph replays."""
     from paper_2508_13304_amd.registration import BatchLM, pose_errors
     dev = torch.device("cuda:0")
-    rng = synth.rng_for(3, 9)
     probs, truth = [], []
     n_samples = 0
-    for i in range(16):
-        n = int(rng.choice([128, 192, 256, 320, 384]))
-        h = 200.0 / n
-        V = int(rng.integers(1, 9))
-        nu = int(rng.choice([256, 384, 512, 640, 768]))
-        du = 1.5 * 240.0 / nu
-        g = synth.Geom(n, n, n, h, h, h, nu, nu, du, du)
-        vol = synth.ellipsoid_phantom_torch(n, h, 20, rng, dev)
-        angles = torch.tensor(rng.uniform(0, 2 * math.pi, V), dtype=torch.float64, device=dev)
-        tp = torch.tensor(synth.random_poses(V, 5.0, 3.0, rng), dtype=torch.float64, device=dev)
+    for q in synth.config4_problems(dev):
+        g, angles, vol, tp = q["geom"], q["angles"], q["vol"], q["truth"]
         probs.append(dict(geom=g, angles=angles, vol=vol, target=dp.project_fwd(g, angles, tp, vol)))
         truth.append(tp)
-        n_samples += count_ray_samples(g, angles.cpu().numpy(), np.zeros((V, 6)))
+        n_samples += count_ray_samples(g, angles.cpu().numpy(), np.zeros((len(angles), 6)))
     truth = torch.cat(truth)
     init = torch.zeros_like(truth)
     total_views = truth.shape[0]

@@ -326,3 +326,27 @@ def ellipsoid_phantom_torch(n: int, h: float, n_ell: int, rng: np.random.Generat
 def geom_c5() -> Geom:
     """192^3 at 1 mm; one 256x256 view at 1.2 mm; SAD/SDD 1000/1500; 0.5 mm steps."""
     return Geom(192, 192, 192, 1.0, 1.0, 1.0, 256, 256, 1.2, 1.2)
+
+
+def config4_problems(device, n_problems: int = 16):
+    """The uneven calibration batch: n_problems independent problems, each a
+    cubic phantom of N^3 voxels spanning ~200 mm (N from {128, ..., 384},
+    20 ellipsoids), 1-8 views at uniform gantry angles on an N_d^2 detector
+    (N_d from {256, ..., 768}, pitch 1.5 x 240 mm / N_d) and true poses
+    uniform in +-5 mm / +-3 deg.  Returns a list of dicts with geom, vol
+    (device FP32), angles and truth (device FP64)."""
+    import torch
+    rng = rng_for(3, 9)
+    out = []
+    for _ in range(n_problems):
+        n = int(rng.choice([128, 192, 256, 320, 384]))
+        h = 200.0 / n
+        V = int(rng.integers(1, 9))
+        nu = int(rng.choice([256, 384, 512, 640, 768]))
+        du = 1.5 * 240.0 / nu
+        g = Geom(n, n, n, h, h, h, nu, nu, du, du)
+        vol = ellipsoid_phantom_torch(n, h, 20, rng, device)
+        angles = torch.tensor(rng.uniform(0, 2 * math.pi, V), dtype=torch.float64, device=device)
+        truth = torch.tensor(random_poses(V, 5.0, 3.0, rng), dtype=torch.float64, device=device)
+        out.append(dict(geom=g, vol=vol, angles=angles, truth=truth))
+    return out
