@@ -112,3 +112,34 @@ def test_training_reduces_loss_on_a_fixed_batch(dp):
         grads, head = net.backward(cache, 2.0 * d / d.numel())
         net.adam_step(grads, head, lr=3e-3)
     assert losses[-1] < 0.2 * losses[0], losses[::10]
+
+
+def test_full_size_trained_network_against_oracle(dp):
+    """The committed proposal network at its real size (256^2 two-channel
+    input, channels 32-64-128-256-256-256, batch 2, the batched layer shapes
+    the training and inference launch) against the FP64 oracle network with
+    the same BF16 rounding points: output and every parameter gradient within
+    2e-2 in norm (BF16 roundings may fall on different sides once FP32 sums
+    differ in order)."""
+    import os
+    from paper_2508_13304_amd import proposal as pr
+    if not os.path.exists(pr.WEIGHTS):
+        pytest.skip("no trained proposal weights committed")
+    net = pr.ProposalNet.load(pr.WEIGHTS)
+    rng = np.random.default_rng(7)
+    x = ocnn.bf16(rng.uniform(0, 1, (2, net.size, net.size, 2)))
+    out, cache = net.forward(bf(x), keep=True)
+    convs = [(W.cpu().numpy().astype(np.float64).reshape(W.shape[0], 3, 3, -1), b.cpu().numpy(), s)
+             for W, b, s in net.convs]
+    params = (convs, (net.Wfc.cpu().numpy().astype(np.float64), net.bfc.cpu().numpy()))
+    ref, acts = ocnn.network_forward(x, params)
+    got = out.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 2e-2 * np.linalg.norm(ref)
+    dout = rng.standard_normal((2, 6))
+    grads, (dWfc, dbfc) = net.backward(cache, torch.tensor(dout, dtype=torch.float32, device=DEV))
+    rgrads, (rWfc, rbfc) = ocnn.network_backward(params, acts, dout)
+    assert np.linalg.norm(dWfc.cpu().numpy() - rWfc) <= 2e-2 * np.linalg.norm(rWfc)
+    for (dW, db), (rW, rb) in zip(grads, rgrads):
+        rW = rW.reshape(rW.shape[0], -1)
+        assert np.linalg.norm(dW.cpu().numpy() - rW) <= 2e-2 * np.linalg.norm(rW)
+        assert np.linalg.norm(db.cpu().numpy() - rb) <= 2e-2 * np.linalg.norm(rb) + 1e-12
