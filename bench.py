@@ -354,22 +354,37 @@ def run_calibration_batch(args, dp, torch):
     lm.reset(init)
     lm.capture()
     t_graph = timed(lambda: lm.run(1), reps)
-    # the calibration itself: graph replays from the perturbed poses, in
-    # blocks of 5 iterations until every view has converged (at most 60)
-    lm.reset(init)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    while iters < 60:
-        lm.run(5)
-        iters += 5
-        if bool(lm.state["done"].bool().all()):
-            break
-    torch.cuda.synchronize()
-    t_cal = time.perf_counter() - t0
+    def converge(max_iters=60):
+        """Graph replays from the perturbed poses until every view has
+        converged (one host check per iteration), at most max_iters."""
+        lm.reset(init)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while n < max_iters:
+            lm.run(1)
+            n += 1
+            if bool(lm.state["done"].bool().all()):
+                break
+        torch.cuda.synchronize()
+        return n, time.perf_counter() - t0
+
+    # the calibration itself
+    iters, t_cal = converge()
     pose, conv, _ = lm.result()
     te, re = pose_errors(pose, truth)
     ok = (te <= 0.1) & (re <= 0.1)
+
+    # the same calibration stopping once an accepted step is below one tenth
+    # of the target accuracy (the update kernel takes tol as an argument, so
+    # the iteration is captured again)
+    lm.tol = 1e-2
+    lm.reset(init)
+    lm.capture()
+    iters2, t_cal2 = converge()
+    pose2, conv2, _ = lm.result()
+    te2, re2 = pose_errors(pose2, truth)
+    ok2 = (te2 <= 0.1) & (re2 <= 0.1)
     res = {"workload": "16 problems, 128^3-384^3 phantoms (~200 mm), 1-8 views each on 256^2-768^2 "
                        "detectors, every view's pose perturbed +-5 mm/+-3 deg; Levenberg-Marquardt on "
                        "the SSD; one iteration = single-pass SSD + pose gradient + Gauss-Newton "
@@ -385,7 +400,12 @@ def run_calibration_batch(args, dp, torch):
                            "views_within_0.1mm_0.1deg": int(ok.sum()),
                            "success_rate": int(ok.sum()) / ok.numel(),
                            "converged": int(conv.sum()),
-                           "max_err_mm": float(te.max()), "max_err_deg": float(re.max())}}
+                           "max_err_mm": float(te.max()), "max_err_deg": float(re.max())},
+           "calibration_tol_0.01": {"iterations": iters2, "seconds": round(t_cal2, 4),
+                                    "views_within_0.1mm_0.1deg": int(ok2.sum()),
+                                    "success_rate": int(ok2.sum()) / ok2.numel(),
+                                    "converged": int(conv2.sum()),
+                                    "max_err_mm": float(te2.max()), "max_err_deg": float(re2.max())}}
     log(f"[bench] calibration batch: {res}")
     return res
 

@@ -12,7 +12,8 @@
 // Everything else below is shared.
 //
 // Footprint of voxel j in one view, with the voxel moved by the pose (the
-// view's projective map on voxel indices, FP64):
+// view's projective map on voxel indices; FP64 anchors per voxel column and
+// view, exact FP32 offsets per voxel, see SfColumn):
 //   transaxial: the corners (i +- 1/2, j +- 1/2) of the mid-height
 //     cross-section project to columns tau0 <= tau1 <= tau2 <= tau3, the
 //     breakpoints of a unit-height trapezoid T(a);
@@ -44,37 +45,115 @@ namespace dp {
 constexpr int kSfBx = 64, kSfBy = 4, kSfCol = 8;
 constexpr int kFpSF = DP_FP_SF, kFpDD = DP_FP_DD;
 
+// Footprint of one voxel in one view, in FP32 pixel coordinates relative
+// to an integer base pixel (abase, bbase), so that breakpoints of magnitude
+// ~1e3 pixels keep ~1e-6 pixel resolution.
 struct SfFootprint {
-    double tau[4];
-    double blo, bhi;
-    double L;
-    int a0, a1, b0, b1;  // pixel window (inclusive), clipped; empty if a0 > a1 or b0 > b1
+    float tau[4];     // trapezoid breakpoints (column), relative to abase
+    float r01, r23;   // 1 / (2 (tau1 - tau0)), 1 / (2 (tau3 - tau2)); 0 for a vertical edge
+    float blo, bhi;   // row rectangle, relative to bbase
+    float L;          // amplitude
+    int abase, bbase;
+    int a0, a1, b0, b1;  // pixel window (inclusive, absolute), clipped; empty if a0 > a1 or b0 > b1
 };
 
-__device__ inline double trap_cdf(double x, const double* t)
+constexpr double kSfPixClamp = 1048576.0;  // projections beyond 2^20 pixels are off any detector
+
+// Integral of the unit-height trapezoid over [x0, x1] (relative to abase),
+// segment by segment: rising edge (x - t0) / (t1 - t0), plateau, falling
+// edge (t3 - x) / (t3 - t2).  Each term is a product of short differences,
+// so no digits are lost when breakpoints lie far from the cell.
+__device__ inline float trap_integral(float x0, float x1, const SfFootprint& f)
 {
-    double s = 0.0;
-    if (x > t[0] && t[1] > t[0]) {
-        const double xr = fmin(x, t[1]);
-        s += (xr - t[0]) * (xr - t[0]) / (2.0 * (t[1] - t[0]));
+    const float* t = f.tau;
+    float s = fmaxf(fminf(x1, t[2]) - fmaxf(x0, t[1]), 0.0f);
+    if (t[1] > t[0]) {
+        const float l = fmaxf(x0, t[0]), r = fminf(x1, t[1]);
+        if (r > l) s += (r - l) * ((r - t[0]) + (l - t[0])) * f.r01;
     }
-    if (x > t[1]) s += fmin(x, t[2]) - t[1];
-    if (x > t[2] && t[3] > t[2]) {
-        const double xf = fmin(x, t[3]);
-        s += ((t[3] - t[2]) * (t[3] - t[2]) - (t[3] - xf) * (t[3] - xf)) / (2.0 * (t[3] - t[2]));
+    if (t[3] > t[2]) {
+        const float l = fmaxf(x0, t[2]), r = fminf(x1, t[3]);
+        if (r > l) s += (r - l) * ((t[3] - l) + (t[3] - r)) * f.r23;
     }
     return s;
 }
 
-__device__ inline double row_overlap(int b, double lo, double hi)
+__device__ inline float row_overlap(float b, float lo, float hi)
 {
-    const double o = fmin(b + 0.5, hi) - fmax(b - 0.5, lo);
-    return o > 0.0 ? o : 0.0;
+    const float o = fminf(b + 0.5f, hi) - fmaxf(b - 0.5f, lo);
+    return o > 0.0f ? o : 0.0f;
 }
 
-// Footprint of voxel (i, j, k) in view g; false if any projected point lies
-// at or behind the source plane.  src: the source in object-frame index
-// units; dom: DD's dominant axis of the view (0 = x, 1 = y).
+// The parts every producer shares: sort (SF), slopes, amplitude, window.
+// t: column breakpoints (SF: four corners; DD: the two boundaries in t[0],
+// t[1]), bb: the two row bounds, both relative to the bases; d: the line
+// from the source to the voxel centre (mm).
+template <int KIND>
+__device__ inline void sf_finish(const GeoScalars& s, int dom, float* t, const float* bb,
+                                 const float* d, int abase, int bbase, SfFootprint& f)
+{
+    if (KIND == kFpSF) {
+#define DP_CX(p, q)                                                  \
+    {                                                                \
+        const float lo_ = fminf(t[p], t[q]), hi_ = fmaxf(t[p], t[q]); \
+        t[p] = lo_;                                                  \
+        t[q] = hi_;                                                  \
+    }
+        DP_CX(0, 1) DP_CX(2, 3) DP_CX(0, 2) DP_CX(1, 3) DP_CX(1, 2)
+#undef DP_CX
+    } else {
+        const float lo = fminf(t[0], t[1]), hi = fmaxf(t[0], t[1]);
+        t[0] = t[1] = lo;
+        t[2] = t[3] = hi;
+    }
+    for (int c = 0; c < 4; ++c) f.tau[c] = t[c];
+    // reciprocals to ~1 ulp (hardware rcp): every quantity here needs only
+    // relative precision
+    f.r01 = t[1] > t[0] ? 0.5f * __builtin_amdgcn_rcpf(t[1] - t[0]) : 0.0f;
+    f.r23 = t[3] > t[2] ? 0.5f * __builtin_amdgcn_rcpf(t[3] - t[2]) : 0.0f;
+    f.blo = fminf(bb[0], bb[1]);
+    f.bhi = fmaxf(bb[0], bb[1]);
+    // amplitude: SF the chord min_a h_a |d| / |d_a|, DD the slab path
+    // h_dom |d| / |d_dom|; it scales the weights, so FP32 is enough
+    const float h[3] = {(float)s.vx, (float)s.vy, (float)s.vz};
+    const float n = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    float L;
+    if (KIND == kFpSF) {
+        L = INFINITY;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (d[c] != 0.0f) L = fminf(L, h[c] * n * __builtin_amdgcn_rcpf(fabsf(d[c])));
+    } else {
+        L = d[dom] != 0.0f ? h[dom] * n * __builtin_amdgcn_rcpf(fabsf(d[dom])) : 0.0f;
+    }
+    f.L = L;
+    f.abase = abase;
+    f.bbase = bbase;
+    // window (the bases and relative offsets are bounded, so no overflow)
+    f.a0 = max(abase + (int)floorf(t[0] - 0.5f) + 1, 0);
+    f.a1 = min(abase + (int)ceilf(t[3] + 0.5f) - 1, s.nu - 1);
+    f.b0 = max(bbase + (int)floorf(f.blo - 0.5f) + 1, 0);
+    f.b1 = min(bbase + (int)ceilf(f.bhi + 0.5f) - 1, s.nv - 1);
+}
+
+// Column breakpoint line q of voxel column (i, j): SF corner (i +- 1/2,
+// j +- 1/2), DD boundary across the non-dominant transaxial axis.
+template <int KIND>
+__device__ inline void sf_line(int q, int dom, double& dx, double& dy)
+{
+    if (KIND == kFpSF) {
+        dx = (q & 1) ? 0.5 : -0.5;
+        dy = (q & 2) ? 0.5 : -0.5;
+    } else {
+        const double off = q ? 0.5 : -0.5;
+        dx = dom == 0 ? 0.0 : off;  // dom x: boundaries across y
+        dy = dom == 0 ? off : 0.0;
+    }
+}
+
+// Per-voxel FP64 footprint of voxel (i, j, k) in view g; false if any
+// projected point lies at or behind the source plane.  src: the source in
+// object-frame index units; dom: DD's dominant axis of the view.
 template <int KIND>
 __device__ inline bool sf_footprint(const ViewGeo& g, const GeoScalars& s, const double* src,
                                     int dom, int i, int j, int k, SfFootprint& f)
@@ -83,75 +162,128 @@ __device__ inline bool sf_footprint(const ViewGeo& g, const GeoScalars& s, const
     const double U0 = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
     const double V0 = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
     const double W0 = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], fk, g.PWd[3])));
-    double t[4];
-    if (KIND == kFpSF) {
+    constexpr int NL = KIND == kFpSF ? 4 : 2;
+    double td[NL];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double dx = (c & 1) ? 0.5 : -0.5, dy = (c & 2) ? 0.5 : -0.5;
-            const double U = fma(g.PUd[0], dx, fma(g.PUd[1], dy, U0));
-            const double W = fma(g.PWd[0], dx, fma(g.PWd[1], dy, W0));
-            if (!(W > 0.0)) return false;
-            t[c] = U / W + s.cu;
-        }
-        // sort the four breakpoints (5 compare-exchanges)
-#define DP_CX(p, q)                                                  \
-    {                                                                \
-        const double lo_ = fmin(t[p], t[q]), hi_ = fmax(t[p], t[q]); \
-        t[p] = lo_;                                                  \
-        t[q] = hi_;                                                  \
+    for (int q = 0; q < NL; ++q) {
+        double dx, dy;
+        sf_line<KIND>(q, dom, dx, dy);
+        const double U = fma(g.PUd[0], dx, fma(g.PUd[1], dy, U0));
+        const double W = fma(g.PWd[0], dx, fma(g.PWd[1], dy, W0));
+        if (!(W > 0.0)) return false;
+        td[q] = fmin(fmax(U / W + s.cu, -kSfPixClamp), kSfPixClamp);
     }
-        DP_CX(0, 1) DP_CX(2, 3) DP_CX(0, 2) DP_CX(1, 3) DP_CX(1, 2)
-#undef DP_CX
-    } else {
-        double e[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const double off = c ? 0.5 : -0.5;
-            const int ax = dom == 0 ? 1 : 0;  // boundaries across the other transaxial axis
-            const double U = fma(g.PUd[ax], off, U0), W = fma(g.PWd[ax], off, W0);
-            if (!(W > 0.0)) return false;
-            e[c] = U / W + s.cu;
-        }
-        t[0] = t[1] = fmin(e[0], e[1]);
-        t[2] = t[3] = fmax(e[0], e[1]);
-    }
-    double bb[2];
+    double bd[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double dz = c ? 0.5 : -0.5;
         const double V = fma(g.PVd[2], dz, V0), W = fma(g.PWd[2], dz, W0);
         if (!(W > 0.0)) return false;
-        bb[c] = V / W + s.cv;
+        bd[c] = fmin(fmax(V / W + s.cv, -kSfPixClamp), kSfPixClamp);
     }
-    for (int c = 0; c < 4; ++c) f.tau[c] = t[c];
-    f.blo = fmin(bb[0], bb[1]);
-    f.bhi = fmax(bb[0], bb[1]);
-    // amplitude from d, the line from the source to the centre (mm):
-    // SF the chord min_a h_a |d| / |d_a|, DD the slab path h_dom |d| / |d_dom|
-    const double h[3] = {s.vx, s.vy, s.vz};
-    const double d[3] = {(fi - src[0]) * h[0], (fj - src[1]) * h[1], (fk - src[2]) * h[2]};
-    const double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    double L;
-    if (KIND == kFpSF) {
-        L = INFINITY;
+    const double ab = floor(td[0]), bbv = floor(bd[0]);
+    float t[4], bb[2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (d[c] != 0.0) L = fmin(L, h[c] * n / fabs(d[c]));
-    } else {
-        L = d[dom] != 0.0 ? h[dom] * n / fabs(d[dom]) : 0.0;
-    }
-    f.L = L;
-    // window, clamped in FP64 before the integer conversion
-    f.a0 = (int)fmax(floor(t[0] - 0.5) + 1.0, 0.0);
-    f.a1 = (int)fmin(ceil(t[3] + 0.5) - 1.0, (double)(s.nu - 1));
-    f.b0 = (int)fmax(floor(f.blo - 0.5) + 1.0, 0.0);
-    f.b1 = (int)fmin(ceil(f.bhi + 0.5) - 1.0, (double)(s.nv - 1));
+    for (int q = 0; q < NL; ++q) t[q] = (float)(td[q] - ab);
+    bb[0] = (float)(bd[0] - bbv);
+    bb[1] = (float)(bd[1] - bbv);
+    const float d[3] = {(float)((fi - src[0]) * s.vx), (float)((fj - src[1]) * s.vy),
+                        (float)((fk - src[2]) * s.vz)};
+    sf_finish<KIND>(s, dom, t, bb, d, (int)ab, (int)bbv, f);
     return true;
 }
 
-__device__ inline double sf_col_weight(const SfFootprint& f, int a)
+// FP64 anchors of voxel column (i, j) at height ka for one view.  Along the
+// column each breakpoint line and the centre line move only in z, so with
+// U(dk) = U0 + dk P_uz and W(dk) = W0 + dk P_wz the projection is exactly
+//   U(dk) / W(dk) = U0 / W0 + dk N / W(dk),   N = (P_uz W0 - P_wz U0) / W0,
+// and only the small offset dk N / W(dk) is evaluated per voxel, in FP32.
+struct SfColumn {
+    bool fast;       // false: an anchor within 1 mm of the source plane (per-voxel FP64)
+    int abase, bbase;
+    float tfr[4], tn[4], tw[4];  // breakpoint lines: anchor offset from abase, N, W0
+    float bfr, bn, bw;           // centre line: row offset from bbase, N_v, W0
+    float ucfr, ucn;             // centre line: column offset from abase, N_u
+    float uco, bco;              // abase - c_u, bbase - c_v (offsets from the detector centre)
+    float pwz, ka;
+    float d0, d1, d2o;           // source-to-voxel line: x, y (mm) and z offset
+};
+
+template <int KIND>
+__device__ inline SfColumn sf_column(const ViewGeo& g, const GeoScalars& s, const double* src,
+                                     int dom, int i, int j, int ka)
 {
-    return trap_cdf(a + 0.5, f.tau) - trap_cdf(a - 0.5, f.tau);
+    SfColumn c;
+    c.fast = false;
+    const double fi = i, fj = j, fk = ka;
+    constexpr int NL = KIND == kFpSF ? 4 : 2;
+    double A[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        double dx, dy;
+        sf_line<KIND>(q, dom, dx, dy);
+        const double U = fma(g.PUd[0], fi + dx, fma(g.PUd[1], fj + dy, fma(g.PUd[2], fk, g.PUd[3])));
+        const double W = fma(g.PWd[0], fi + dx, fma(g.PWd[1], fj + dy, fma(g.PWd[2], fk, g.PWd[3])));
+        if (!(W >= 1.0)) return c;
+        const double iw = 1.0 / W;
+        A[q] = fmin(fmax(U * iw + s.cu, -kSfPixClamp), kSfPixClamp);
+        c.tn[q] = (float)((g.PUd[2] * W - g.PWd[2] * U) * iw);
+        c.tw[q] = (float)W;
+    }
+    const double Uc = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
+    const double V = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
+    const double W = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], fk, g.PWd[3])));
+    if (!(W >= 1.0)) return c;
+    const double iw = 1.0 / W;
+    const double B = fmin(fmax(V * iw + s.cv, -kSfPixClamp), kSfPixClamp);
+    const double Ac = fmin(fmax(Uc * iw + s.cu, -kSfPixClamp), kSfPixClamp);
+    c.bn = (float)((g.PVd[2] * W - g.PWd[2] * V) * iw);
+    c.ucn = (float)((g.PUd[2] * W - g.PWd[2] * Uc) * iw);
+    c.bw = (float)W;
+    const double ab = floor(A[0]), bb = floor(B);
+    c.abase = (int)ab;
+    c.bbase = (int)bb;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) c.tfr[q] = (float)(A[q] - ab);
+    c.bfr = (float)(B - bb);
+    c.ucfr = (float)(Ac - ab);
+    c.uco = (float)(ab - s.cu);
+    c.bco = (float)(bb - s.cv);
+    c.pwz = (float)g.PWd[2];
+    c.ka = (float)ka;
+    c.d0 = (float)((fi - src[0]) * s.vx);
+    c.d1 = (float)((fj - src[1]) * s.vy);
+    c.d2o = (float)(-src[2] * s.vz);
+    c.fast = true;
+    return c;
+}
+
+// Footprint of voxel (i, j, k) from its column's anchors (FP32), falling
+// back to the per-voxel FP64 footprint when the column has no safe anchor.
+template <int KIND>
+__device__ inline bool sf_voxel(const SfColumn& c, const ViewGeo& g, const GeoScalars& s,
+                                const double* src, int dom, int i, int j, int k, SfFootprint& f)
+{
+    if (!c.fast) return sf_footprint<KIND>(g, s, src, dom, i, j, k, f);
+    constexpr int NL = KIND == kFpSF ? 4 : 2;
+    const float dk = (float)k - c.ka;
+    float t[4] = {0.f, 0.f, 0.f, 0.f}, bb[2];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const float W = fmaf(dk, c.pwz, c.tw[q]);
+        if (!(W > 0.0f)) return false;
+        t[q] = fmaf(dk * c.tn[q], __builtin_amdgcn_rcpf(W), c.tfr[q]);  // offset <~ 10 px
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dz = dk + (e ? 0.5f : -0.5f);
+        const float W = fmaf(dz, c.pwz, c.bw);
+        if (!(W > 0.0f)) return false;
+        bb[e] = fmaf(dz * c.bn, __builtin_amdgcn_rcpf(W), c.bfr);
+    }
+    const float d[3] = {c.d0, c.d1, fmaf((float)k, (float)s.vz, c.d2o)};
+    sf_finish<KIND>(s, dom, t, bb, d, c.abase, c.bbase, f);
+    return true;
 }
 
 // Source position in object-frame (unpadded) voxel-index units, and the
@@ -164,17 +296,29 @@ __device__ inline int sf_source(const ViewGeo& g, const GeoScalars& s, double* s
     return fabs(ox) >= fabs(oy) ? 0 : 1;
 }
 
-// Gather sum_i a_ij img_i over the footprint (img: [nv][nu]).
-__device__ inline double sf_gather(const SfFootprint& f, const float* __restrict__ img, int nu)
+// The footprint's pixels column by column: fn(a, b, w) for every pixel of
+// the window with a non-zero weight w = column integral x row overlap
+// (without the amplitude L); the column integral is evaluated once per
+// column.
+template <typename Fn>
+__device__ inline void sf_for_each(const SfFootprint& f, Fn&& fn)
 {
-    double acc = 0.0;
-    for (int b = f.b0; b <= f.b1; ++b) {
-        const double wb = row_overlap(b, f.blo, f.bhi);
-        if (wb == 0.0) continue;
-        double row = 0.0;
-        for (int a = f.a0; a <= f.a1; ++a) row += sf_col_weight(f, a) * (double)img[(size_t)b * nu + a];
-        acc += wb * row;
+    for (int a = f.a0; a <= f.a1; ++a) {
+        const float x = (float)(a - f.abase);
+        const float wa = trap_integral(x - 0.5f, x + 0.5f, f);
+        if (wa == 0.0f) continue;
+        for (int b = f.b0; b <= f.b1; ++b) {
+            const float wb = row_overlap((float)(b - f.bbase), f.blo, f.bhi);
+            if (wb != 0.0f) fn(a, b, wa * wb);
+        }
     }
+}
+
+// Gather sum_i a_ij img_i over the footprint (img: [nv][nu]).
+__device__ inline float sf_gather(const SfFootprint& f, const float* __restrict__ img, int nu)
+{
+    float acc = 0.0f;
+    sf_for_each(f, [&](int a, int b, float w) { acc = fmaf(w, img[(size_t)b * nu + a], acc); });
     return f.L * acc;
 }
 
@@ -210,20 +354,17 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_kernel(GeoScalars s, int
         }
         if (i >= s.nx || j >= s.ny) continue;
         float* img = proj + (size_t)v * s.nu * s.nv;
+        const SfColumn col = sf_column<KIND>(g, s, src, dom, i, j, kb + kSfCol / 2);
         for (int kk = 0; kk < kSfCol && kb + kk < s.nz; ++kk) {
             const int k = kb + kk;
             const float mu = vol[((size_t)k * s.ny + j) * s.nx + i];
             if (mu == 0.0f) continue;
             SfFootprint f;
-            if (!sf_footprint<KIND>(g, s, src, dom, i, j, k, f)) continue;
-            for (int b = f.b0; b <= f.b1; ++b) {
-                const double wb = row_overlap(b, f.blo, f.bhi) * f.L * (double)mu;
-                if (wb == 0.0) continue;
-                for (int a = f.a0; a <= f.a1; ++a) {
-                    const double w = wb * sf_col_weight(f, a);
-                    if (w != 0.0) atomicAdd(img + (size_t)b * s.nu + a, (float)w);
-                }
-            }
+            if (!sf_voxel<KIND>(col, g, s, src, dom, i, j, k, f)) continue;
+            const float scale = f.L * mu;
+            sf_for_each(f, [&](int a, int b, float w) {
+                atomicAdd(img + (size_t)b * s.nu + a, w * scale);
+            });
         }
     }
 }
@@ -246,11 +387,12 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_kernel(GeoScalars s, int 
         double src[3];
         const int dom = sf_source(g, s, src);
         const float* img = proj + (size_t)v * s.nu * s.nv;
+        const SfColumn col = sf_column<KIND>(g, s, src, dom, i, j, kb + kSfCol / 2);
 #pragma unroll
         for (int kk = 0; kk < kSfCol; ++kk) {
             if (kb + kk >= s.nz) break;
             SfFootprint f;
-            if (sf_footprint<KIND>(g, s, src, dom, i, j, kb + kk, f)) acc[kk] += sf_gather(f, img, s.nu);
+            if (sf_voxel<KIND>(col, g, s, src, dom, i, j, kb + kk, f)) acc[kk] += sf_gather(f, img, s.nu);
         }
     }
 #pragma unroll
@@ -316,14 +458,15 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s
 #pragma unroll
         for (int ch = 0; ch < kRdChannels; ++ch) r[ch] = 0.0f;
         if (active) {
+            const SfColumn col = sf_column<KIND>(g, s, src, dom, i, j, kb + kSfCol / 2);
 #pragma unroll
             for (int kk = 0; kk < kSfCol; ++kk) {
                 const int k = kb + kk;
                 if (k >= s.nz) break;
                 if (G[kk][0] == 0.0f && G[kk][1] == 0.0f && G[kk][2] == 0.0f) continue;
                 SfFootprint f;
-                if (!sf_footprint<KIND>(g, s, src, dom, i, j, k, f)) continue;
-                const float sj = (float)sf_gather(f, w, s.nu);
+                if (!sf_voxel<KIND>(col, g, s, src, dom, i, j, k, f)) continue;
+                const float sj = sf_gather(f, w, s.nu);
                 const float pk = (float)k - 0.5f * (s.nz - 1);
                 const float gx = sj * G[kk][0], gy = sj * G[kk][1], gz = sj * G[kk][2];
                 // B_c, then T_xy, T_xz, T_yx, T_yz, T_zx, T_zy (T_ac = sum s P_a G_c)
@@ -363,33 +506,41 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s,
         const int dom = sf_source(g, s, src);
         const float4* img = proj4 + (size_t)v * NU * NV;
         float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
+        const SfColumn col = sf_column<KIND>(g, s, src, dom, i, j, kb + kSfCol / 2);
 #pragma unroll
         for (int kk = 0; kk < kSfCol; ++kk) {
             const int k = kb + kk;
             if (k >= s.nz || e[kk] == 0.0f) continue;
             SfFootprint f;
-            if (!sf_footprint<KIND>(g, s, src, dom, i, j, k, f)) continue;
-            double da = 0.0, db = 0.0;
-            for (int b = f.b0; b <= f.b1; ++b) {
-                const double wb = row_overlap(b, f.blo, f.bhi);
-                if (wb == 0.0) continue;
-                for (int a = f.a0; a <= f.a1; ++a) {
-                    const double wgt = wb * sf_col_weight(f, a);
-                    const float4 p = img[(size_t)(b + kPadD) * NU + (a + kPadD)];
-                    da += wgt * (double)p.y;
-                    db += wgt * (double)p.z;
-                }
-            }
+            if (!sf_voxel<KIND>(col, g, s, src, dom, i, j, k, f)) continue;
+            float da = 0.0f, db = 0.0f;
+            sf_for_each(f, [&](int a, int b, float w) {
+                const float4 p = img[(size_t)(b + kPadD) * NU + (a + kPadD)];
+                da = fmaf(w, p.y, da);
+                db = fmaf(w, p.z, db);
+            });
             da *= f.L;
             db *= f.L;
-            // projection of the voxel centre: offsets from the detector centre, depth
-            const double fi = i, fj = j, fk = k;
-            const double U = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
-            const double Vv = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
-            const double W = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], fk, g.PWd[3])));
-            const double ec = (double)e[kk] / W;
-            const float c1 = (float)(ec * da), c2 = (float)(ec * db);
-            const float c3 = (float)(-ec * (da * (U / W) + db * (Vv / W)));
+            // projection of the voxel centre: offsets from the detector centre (pixels), depth
+            float ap, bp, Wc;
+            if (col.fast) {
+                const float dk = (float)k - col.ka;
+                Wc = fmaf(dk, col.pwz, col.bw);
+                const float iw = __builtin_amdgcn_rcpf(Wc);
+                ap = col.uco + fmaf(dk * col.ucn, iw, col.ucfr);
+                bp = col.bco + fmaf(dk * col.bn, iw, col.bfr);
+            } else {
+                const double fi = i, fj = j, fk = k;
+                const double U = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
+                const double Vv = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
+                const double W = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], fk, g.PWd[3])));
+                Wc = (float)W;
+                ap = (float)(U / W);
+                bp = (float)(Vv / W);
+            }
+            const float ec = e[kk] * __builtin_amdgcn_rcpf(Wc);
+            const float c1 = ec * da, c2 = ec * db;
+            const float c3 = -ec * fmaf(da, ap, db * bp);
             const float pk = (float)k - 0.5f * (s.nz - 1);
             A1 += c1; A2 += c2; A3 += c3;
             Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);

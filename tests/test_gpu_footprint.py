@@ -31,6 +31,11 @@ CASES = {
     "ragged": (Geom(37, 29, 23, 1.3, 1.1, 1.7, 45, 27, 1.9, 2.3, off_u=1.25, off_v=-0.75), 4),
     "fine-detector": (Geom(24, 24, 24, 2.0, 2.0, 2.0, 80, 72, 1.0, 1.0), 3),
     "tiny": (Geom(3, 2, 4, 1.0, 1.5, 0.8, 5, 4, 1.0, 1.0), 2),
+    # source inside the volume: voxels at or behind the source plane are
+    # skipped, columns anchored within 1 mm of it take the per-voxel FP64
+    # footprint, and voxels just in front of it have footprints far wider
+    # than the detector
+    "source-inside": (Geom(24, 24, 24, 2.0, 2.0, 2.0, 40, 36, 2.0, 2.0, sad=20.0, sdd=40.0), 3),
 }
 
 
