@@ -437,40 +437,42 @@ struct GradAcc {
                                float Py, float Pz)
     {
         // q[dz][dy][dx]
-        // Channel Gx: lerp along x first; moments along y and z.
-        float Gx, Mxy, Mxz;
+        // Channel Gx: lerp along x first; moments along y and z.  Each moment
+        // sum_phi delta_a G_c is w_a times the upper lerp input along a; it is
+        // added to T with a second FMA instead of being formed first.
+        float Gx, Yx1, Zx1;
         {
             const float L00 = lerpf(q[0][0][0].x, q[0][0][1].x, wx), L10 = lerpf(q[0][1][0].x, q[0][1][1].x, wx);
             const float L01 = lerpf(q[1][0][0].x, q[1][0][1].x, wx), L11 = lerpf(q[1][1][0].x, q[1][1][1].x, wx);
             const float Y0 = lerpf(L00, L01, wz), Y1 = lerpf(L10, L11, wz);
             Gx = lerpf(Y0, Y1, wy);
-            Mxy = wy * Y1;
-            Mxz = wz * lerpf(L01, L11, wy);
+            Yx1 = Y1;                       // moment along y: wy * Y1
+            Zx1 = lerpf(L01, L11, wy);      // moment along z: wz * Zx1
         }
         // Channel Gy: lerp along y first; moments along x and z.
-        float Gy, Myx, Myz;
+        float Gy, Xy1, Zy1;
         {
             const float L00 = lerpf(q[0][0][0].y, q[0][1][0].y, wy), L10 = lerpf(q[0][0][1].y, q[0][1][1].y, wy);
             const float L01 = lerpf(q[1][0][0].y, q[1][1][0].y, wy), L11 = lerpf(q[1][0][1].y, q[1][1][1].y, wy);
             const float X0 = lerpf(L00, L01, wz), X1 = lerpf(L10, L11, wz);
             Gy = lerpf(X0, X1, wx);
-            Myx = wx * X1;
-            Myz = wz * lerpf(L01, L11, wx);
+            Xy1 = X1;
+            Zy1 = lerpf(L01, L11, wx);
         }
         // Channel Gz: lerp along z first; moments along x and y.
-        float Gz, Mzx, Mzy;
+        float Gz, Xz1, Yz1;
         {
             const float L00 = lerpf(q[0][0][0].z, q[1][0][0].z, wz), L10 = lerpf(q[0][0][1].z, q[1][0][1].z, wz);
             const float L01 = lerpf(q[0][1][0].z, q[1][1][0].z, wz), L11 = lerpf(q[0][1][1].z, q[1][1][1].z, wz);
             const float X0 = lerpf(L00, L01, wy), X1 = lerpf(L10, L11, wy);
             Gz = lerpf(X0, X1, wx);
-            Mzx = wx * X1;
-            Mzy = wy * lerpf(L01, L11, wx);
+            Xz1 = X1;
+            Yz1 = lerpf(L01, L11, wx);
         }
         Bx += Gx; By += Gy; Bz += Gz;
-        Txy += fmaf(Px, Gy, Myx); Txz += fmaf(Px, Gz, Mzx);
-        Tyx += fmaf(Py, Gx, Mxy); Tyz += fmaf(Py, Gz, Mzy);
-        Tzx += fmaf(Pz, Gx, Mxz); Tzy += fmaf(Pz, Gy, Myz);
+        Txy = fmaf(wx, Xy1, fmaf(Px, Gy, Txy)); Txz = fmaf(wx, Xz1, fmaf(Px, Gz, Txz));
+        Tyx = fmaf(wy, Yx1, fmaf(Py, Gx, Tyx)); Tyz = fmaf(wy, Yz1, fmaf(Py, Gz, Tyz));
+        Tzx = fmaf(wz, Zx1, fmaf(Pz, Gx, Tzx)); Tzy = fmaf(wz, Zy1, fmaf(Pz, Gy, Tzy));
     }
 
     // this += o with o's base-corner frame shifted by -c.
