@@ -271,7 +271,7 @@ def register_bfgs(geom, vol, angles, targets, init_poses, loss="ssd", iters=150,
 
 
 def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=4.0, down=3.0,
-                tol=1e-4, lam_max=1e10) -> RegistrationResult:
+                tol=1e-4, lam_max=1e10, rule="step") -> RegistrationResult:
     """Batched Levenberg-Marquardt registration on the SSD.
 
     Each launch evaluates, at one point per registration, the DRR, the SSD
@@ -280,10 +280,16 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
     parameters z = (t / 1 mm, gamma / 1 deg) the step solves
     (H + lam diag(H)) d = -g; the next launch evaluates z + d, which is
     accepted if the SSD decreased (lam /= down) and otherwise discarded
-    (lam *= up, the previous f, g, H kept).  A registration stops once an
-    accepted step is below tol in every scaled parameter, or when lam
-    exceeds lam_max (no decrease resolvable in FP32).
+    (lam *= up, the previous f, g, H kept).  A registration stops when lam
+    exceeds lam_max (no decrease resolvable in FP32) or, with rule="step",
+    once an accepted step is below tol in every scaled parameter; with
+    rule="newton", once the undamped Gauss-Newton step -H^-1 g at the
+    accepted point is below tol in every scaled parameter (near the optimum
+    that step is the remaining distance, so the evaluation that would only
+    confirm convergence is skipped).
     """
+    if rule not in ("step", "newton"):
+        raise ValueError(f"unknown stopping rule {rule}")
     from . import project_fwd_ssd_gauss_newton
     B = init_poses.shape[0]
     dev = init_poses.device
@@ -325,7 +331,14 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
             H[active] = torch.where(acc[:, None, None], Ht, Ha)
             lam[active] = torch.where(acc, lam[active] / down, lam[active] * up)
             its[active] += 1
-            stop = (acc & (d.abs().max(dim=1).values < tol)) | (lam[active] > lam_max)
+            if rule == "step":
+                small = acc & (d.abs().max(dim=1).values < tol)
+            else:
+                Hn = H[active]
+                reg = 1e-12 * (torch.diagonal(Hn, dim1=1, dim2=2)[:, :, None] + 1.0) * eye
+                dn = torch.linalg.solve(Hn + reg, -g[active])
+                small = dn.abs().max(dim=1).values < tol
+            stop = small | (lam[active] > lam_max)
             done[active] = stop
             active = active[~stop]
     if dev.type == "cuda":

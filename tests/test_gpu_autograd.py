@@ -137,6 +137,22 @@ def test_batched_levenberg_marquardt_registration(dp):
     assert res.launches < bf.launches
 
 
+def test_levenberg_marquardt_newton_stopping_rule(dp):
+    """Stopping on the undamped Gauss-Newton step at the accepted pose: the
+    same registrations still reach 0.1 mm / 0.1 deg, in no more launches
+    than stopping on the accepted step with the same tolerance."""
+    from paper_2508_13304_amd import registration as reg
+    g, vol, truth, angles, targets = _registration_case(dp)
+    a = reg.register_lm(g, vol, angles, targets, torch.zeros_like(truth), tol=1e-2)
+    b = reg.register_lm(g, vol, angles, targets, torch.zeros_like(truth), tol=1e-2, rule="newton")
+    _report(reg, b, truth)
+    print("launches: accepted-step rule", a.launches, "Gauss-Newton rule", b.launches, flush=True)
+    assert bool(reg.success(b.poses, truth).all()) and bool(b.converged.all())
+    assert b.launches <= a.launches
+    with pytest.raises(ValueError):
+        reg.register_lm(g, vol, angles, targets, torch.zeros_like(truth), rule="never")
+
+
 def test_batched_adam_registration_reduces_error(dp):
     """The Adam driver (fixed step sizes) recovers the rotations and shrinks
     the translation error by an order of magnitude on the same case."""
