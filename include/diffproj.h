@@ -192,15 +192,20 @@ int dp_project_fwd_ssd_gauss_newton_batch(const dp_problem* problems, int32_t n,
  * (loss [n], grad [n][6], hess [n][21] as written by the SSD entries) and
  * the state of the last accepted point (state_pose [n][6], state_f [n],
  * state_g [n][6], state_h [n][21], lam [n]):
- *   accept if f < state_f (state <- trial values, lam /= 3), else lam *= 4;
- *   then solve (H + lam diag H) d = -g (FP64 Cholesky) and write the next
- *   trial pose state_pose + d into `trial`.
- * A view whose accepted step is below tol in every scaled parameter, or
- * whose lam exceeds 1e10, is marked done[n] = 1 and its trial pose stays at
- * the accepted pose.  Initialise state_f to +inf so the first evaluation is
- * accepted.  All arrays are device FP64 (done: int32); no allocation, no
- * host synchronisation, so an iteration (SSD batch + this update) can be
- * captured in a graph and replayed. */
+ *   accept if f < state_f (state <- trial values, lam /= 3; a NaN f is
+ *   rejected), else lam *= 4; then solve (H + lam (diag H + 1e-12)) d = -g
+ *   by FP64 Cholesky and write the next trial pose state_pose + d into
+ *   `trial`.
+ * A view whose accepted step is below tol in every scaled parameter, whose
+ * lam exceeds 1e10, or whose damped matrix is not positive definite is
+ * marked done[n] = 1 and its trial pose stays at the accepted pose; done
+ * views are left untouched by later calls.  Initialise state_f to +inf (the
+ * first evaluation is then accepted without changing lam), state_g and
+ * state_h to anything finite, lam to the initial damping and done to 0.
+ * All arrays are caller-owned device memory, FP64 (done: int32), disjoint;
+ * no allocation, no host synchronisation, so an iteration (SSD batch + this
+ * update) can be captured in a graph and replayed.  Returns DP_ERR_ARG for
+ * n <= 0, a NULL array or a negative tol. */
 int dp_lm_update(int32_t n, double* trial, const double* loss, const double* grad,
                  const double* hess, double* state_pose, double* state_f, double* state_g,
                  double* state_h, double* lam, int32_t* done, double tol, void* stream);
