@@ -219,7 +219,9 @@ int dp_lm_update(int32_t n, double* trial, const double* loss, const double* gra
  * FWD_SSD, whose pose gradient lands in the workspace), records the fastest for this shape
  * class (grid and detector sizes, view-count octave, pixel-to-voxel ratio)
  * in a process-wide cache used by later calls, and synchronises `stream`.
- * dp_set_variant forces a variant for `op` (-1 = cached / default).
+ * dp_set_variant forces a variant for `op` (-1 = cached / default);
+ * dp_get_variant returns the variant a call of `op` on this shape would use
+ * (-1 for another op or a NULL geometry).
  * ------------------------------------------------------------------------- */
 int dp_autotune(int32_t op, const dp_geom* g, int32_t n_views, const double* angles,
                 const double* poses, const float* vol, const float* grad_proj, void* out,

@@ -493,7 +493,7 @@ int dp_set_variant(int32_t op, int32_t variant)
 
 int32_t dp_get_variant(const dp_geom* g, int32_t n_views, int32_t op)
 {
-    if (!g || (op != DP_OP_FWD && op != DP_OP_FWD_GRAD)) return -1;
+    if (!g || (op != DP_OP_FWD && op != DP_OP_FWD_GRAD && op != DP_OP_FWD_SSD)) return -1;
     return variant_for(op, *g, n_views);
 }
 

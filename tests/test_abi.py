@@ -142,6 +142,11 @@ def test_newer_entries_validate_before_launch(lib):
     assert lib.dp_gradient_entropy(8, 8, 8, p, 0.0, p, None, ws, wge, None) == -1
     assert lib.dp_gradient_entropy(8, 8, 8, p, 1e-12, p, None, C.c_void_p((1 << 24) + 4), wge,
                                    None) == -1  # misaligned workspace
+    # kernel variants: every ray-driven op, including the single-pass SSD
+    for op in (m.OP_FWD, m.OP_FWD_GRAD, m.OP_FWD_SSD):
+        assert lib.dp_get_variant(C.byref(gs), 1, op) in (0, 1, 2)
+    assert lib.dp_get_variant(C.byref(gs), 1, m.OP_BP) == -1
+    assert lib.dp_set_variant(m.OP_BP, 0) == -1
     # CNN helpers: 32-bit index spaces
     assert lib.dp_im2col3x3_bf16(512, 256, 256, 64, 1, p, p, None) == -4
     assert lib.dp_col2im3x3(512, 256, 256, 64, 1, p, p, None) == -4

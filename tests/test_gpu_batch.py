@@ -113,6 +113,25 @@ def test_autotune_records_choice(dp):
     assert dp.get_variant(g, V, dp.OP_FWD_GRAD) == bestg
 
 
+def test_autotune_single_pass_ssd(dp, oracle):
+    """Autotuning the single-pass SSD launch: every variant is timed, the
+    fastest is cached for the shape class and used by later calls, and the
+    caller's outputs hold a valid evaluation (its DRRs match the oracle)."""
+    rng = synth.rng_for(505)
+    g = Geom(48, 48, 48, 1.5, 1.5, 1.5, 64, 64, 1.6, 1.6)
+    vol = synth.ellipsoid_phantom(48, 1.5, 8, rng)
+    V = 3
+    angles, poses = rng.uniform(0, 6, V), synth.random_poses(V, 4, 4, rng)
+    y = T(oracle.project_fwd(g, angles, synth.random_poses(V, 4, 4, rng), vol), torch.float32)
+    proj = torch.empty((V, g.nv, g.nu), dtype=torch.float32, device=DEV)
+    best, ms = dp.autotune(dp.OP_FWD_SSD, g, T(angles), T(poses), T(vol, torch.float32), proj,
+                           grad_proj=y, reps=2)
+    assert 0 <= best < dp.N_VARIANTS and all(m > 0 for m in ms) and ms[best] == min(ms)
+    assert dp.get_variant(g, V, dp.OP_FWD_SSD) == best
+    ref = oracle.project_fwd(g, angles, poses, vol)
+    assert np.abs(proj.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
 def test_graph_captured_registration_step_replays_like_eager(dp):
     """One registration iteration (forward, SSD gradient, pose gradient, step)
     captured once and replayed several times, with eager work and
