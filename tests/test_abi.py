@@ -192,3 +192,23 @@ def test_binding_fails_loudly_without_library(tmp_path):
             m.load(str(tmp_path / "missing.so"))
     finally:
         m._lib = saved
+
+
+def test_python_tables_match_the_header():
+    """The binding's kernel-name table follows the header's DP_K_* order, and
+    its op and footprint-kind constants equal the header's."""
+    import paper_2508_13304_amd as m
+    src = open(os.path.join(ROOT, "include", "diffproj.h")).read()
+    ks = sorted((int(v), n) for n, v in re.findall(r"\bDP_K_(\w+)\s*=\s*(\d+)", src) if n != "COUNT")
+    names = {"SETUP": "setup", "VOL_PREP": "vol_prep", "RD_FWD": "rd_fwd", "RD_GRAD": "rd_grad",
+             "DET_PREP": "det_prep", "VD_BP": "vd_bp", "VD_GRAD": "vd_grad", "FINALIZE": "finalize",
+             "FDK_FILTER": "fdk_filter", "SHARPNESS": "sharpness", "RD_FUSED": "rd_fused",
+             "SF": "footprint"}
+    assert [names[n] for _, n in ks] == list(m.KERNELS)
+    count = int(re.search(r"\bDP_K_COUNT\s*=\s*(\d+)", src).group(1))
+    assert count == len(m.KERNELS)
+    ops = dict(re.findall(r"\bDP_OP_(\w+)\s*=\s*(\d+)", src))
+    for n, v in ops.items():
+        assert getattr(m, "OP_" + n) == int(v), n
+    kinds = dict(re.findall(r"\bDP_FP_(SF|DD)\s*=\s*(\d+)", src))
+    assert m.FP_KINDS == {"sf": int(kinds["SF"]), "dd": int(kinds["DD"])}

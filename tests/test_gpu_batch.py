@@ -182,3 +182,29 @@ def test_graph_captured_registration_step_replays_like_eager(dp):
         torch.cuda.synchronize()
         assert torch.equal(poses, ref[i]), i
         _ = (l.sum() + 1.0).item()  # eager work between replays
+
+
+def test_per_kernel_profiler(dp):
+    """The event-based per-kernel timer: every library kernel a call launches
+    is counted once per launch with a positive time, collecting resets the
+    counts, and nothing is recorded while it is off."""
+    rng = synth.rng_for(506)
+    g = Geom(32, 32, 32, 2.0, 2.0, 2.0, 40, 40, 2.4, 2.4)
+    vol = T(synth.ellipsoid_phantom(32, 2.0, 6, rng), torch.float32)
+    V = 2
+    a, p = T(rng.uniform(0, 6, V)), T(synth.random_poses(V, 3, 3, rng))
+    dp.profile_collect()  # drop anything recorded before
+    dp.profile_enable(True)
+    try:
+        l = dp.project_fwd(g, a, p, vol)
+        dp.project_fwd_ssd_grad_pose(g, a, p, vol, l)
+        dp.backproject(g, a, p, l, dp.W_FDK)
+        got = dp.profile_collect()
+    finally:
+        dp.profile_enable(False)
+    for k, n in (("setup", 3), ("vol_prep", 2), ("rd_fwd", 1), ("rd_fused", 1), ("finalize", 1),
+                 ("det_prep", 1), ("vd_bp", 1)):
+        assert got[k][1] == n and got[k][0] > 0, (k, got.get(k))
+    assert dp.profile_collect() == {}
+    dp.project_fwd(g, a, p, vol)
+    assert dp.profile_collect() == {}
