@@ -40,6 +40,8 @@ VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec (packed FMA)
 #             centre offsets 3, accumulation of B (3) and T (6 x 3)
 #   fused   : the gradient's 113 plus the mu trilinear (21) and its sum (1)
 FLOPS_PER_SAMPLE = {"rd_fwd": 33, "rd_grad": 113, "rd_fused": 135}
+# bytes one forward + gradient sample gathers: 8 trilinear corners x (mu, Gx, Gy, Gz) x 4 B
+GATHER_BYTES_PER_SAMPLE = 128
 
 
 def log(*a):
@@ -112,9 +114,10 @@ def _kernel_hash(*names):
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_key, src_hash):
-    """HBM bytes per launch measured with rocprofv3 counters (committed under
-    profiles/), valid only while the kernel source is unchanged."""
+def _traffic(kernel_key, src_hash, field="hbm_bytes_per_launch"):
+    """Bytes per launch measured with rocprofv3 counters (committed under
+    profiles/; HBM by default, or the L2 read bytes), valid only while the
+    kernel source is unchanged."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -124,7 +127,7 @@ def _traffic(kernel_key, src_hash):
         return None
     if not rec or rec.get("source_hash") != src_hash:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get(field)
 
 
 def run_forward(args, dp, torch):
@@ -201,6 +204,83 @@ def run_forward(args, dp, torch):
                 "source_hash": src_hash, "other": other}
     return dict(geom=g, V=V, n_samples=n_samples, ms_step=ms_step, per_kernel=per_kernel,
                 two_call_ms=ms2, two_call_kernels=per2, roofline=roofline, inputs=c)
+
+
+def run_cache_probe(dp, torch, quick=False):
+    """Measured read bandwidths of this GPU: L2 (every block streams a small
+    footprint that stays resident in each XCD's L2) and HBM (the blocks split a
+    2 GiB buffer, nontemporal loads).  The best of a small sweep of footprints
+    and grid sizes;
+    bytes are what the loads request, timed with HIP events on the launch
+    stream, median of 5 launches after one warm-up."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def timed(buf, reps, shared, blocks):
+        out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+        dp.read_probe(buf, reps, shared, blocks, out=out, stream=stream)
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dp.read_probe(buf, reps, shared, blocks, out=out, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[2]
+
+    l2 = {}
+    for mib in ((2,) if quick else (1, 2)):
+        buf = torch.ones(mib * (1 << 18), dtype=torch.float32, device=dev)
+        n_vec = buf.numel() // 4
+        for blocks in ((2048,) if quick else (1024, 2048, 4096)):
+            reps = max(1, (16 << 30) // (blocks * n_vec * 16))  # ~16 GiB requested per launch
+            ms = timed(buf, reps, True, blocks)
+            l2[f"{mib}MiB_x{blocks}blocks"] = round(blocks * reps * n_vec * 16 / (ms * 1e-3) / 1e9, 1)
+        del buf
+    hbm = {}
+    buf = torch.ones(1 << 29, dtype=torch.float32, device=dev)  # 2 GiB, far above L2 + MALL
+    for blocks in ((2048,) if quick else (1024, 2048, 4096)):
+        ms = timed(buf, 1, False, blocks)
+        hbm[f"2GiB_x{blocks}blocks"] = round(buf.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    del buf
+    res = {"l2_read_GBps": max(l2.values()), "hbm_read_GBps": max(hbm.values()),
+           "l2_sweep": l2, "hbm_sweep": hbm}
+    log(f"[bench] read probe: L2 {res['l2_read_GBps']:.0f} GB/s, HBM {res['hbm_read_GBps']:.0f} GB/s")
+    return res
+
+
+def gather_roofline(fw, probe):
+    """Gather roofline: the measured L2 read bandwidth over the 128
+    bytes a forward + gradient sample gathers (8 trilinear corners x 4
+    channels x 4 B), with the dominant kernel's measured L2 and HBM traffic
+    (rocprofv3 counters, valid while the kernel source is unchanged)."""
+    ceiling = probe["l2_read_GBps"] * 1e9 / GATHER_BYTES_PER_SAMPLE
+    rf = fw["roofline"]
+    k_ms = rf["kernel_ms"]
+    step_rate = fw["n_samples"] / (fw["ms_step"] * 1e-3)
+    kern_rate = fw["n_samples"] / (k_ms * 1e-3)
+    l2_bytes = _traffic(rf["kernel"] + "_registration_scale", rf["source_hash"], "l2_bytes_per_launch")
+    hbm_bytes = rf["traffic"]
+    out = {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE,
+           "l2_read_GBps_measured": probe["l2_read_GBps"],
+           "hbm_read_GBps_measured": probe["hbm_read_GBps"],
+           "ceiling_samples_per_s": ceiling,
+           "step_frac": round(step_rate / ceiling, 4),
+           "kernel_frac": round(kern_rate / ceiling, 4),
+           "kernel": rf["kernel"],
+           "lds_bytes_per_sample": GATHER_BYTES_PER_SAMPLE,
+           "l2_bytes_per_launch": l2_bytes,
+           "l2_GBps": round(l2_bytes / (k_ms * 1e-3) / 1e9, 1) if l2_bytes else None,
+           "l2_frac": round(l2_bytes / (k_ms * 1e-3) / 1e9 / probe["l2_read_GBps"], 4) if l2_bytes else None,
+           "l2_hit_rate": _traffic(rf["kernel"] + "_registration_scale", rf["source_hash"], "l2_hit_rate"),
+           # L2 misses (FETCH_SIZE + WRITE_SIZE) are served by the last-level
+           # cache or HBM; compared with the measured HBM stream
+           "beyond_l2_GBps": round(hbm_bytes / (k_ms * 1e-3) / 1e9, 1) if hbm_bytes else None,
+           "beyond_l2_frac_of_hbm_stream":
+               round(hbm_bytes / (k_ms * 1e-3) / 1e9 / probe["hbm_read_GBps"], 4) if hbm_bytes else None,
+           "probe": probe}
+    return out
 
 
 def run_backproject(args, dp, torch):
@@ -543,6 +623,9 @@ def main():
                     help="skip the projector-type comparison at the paper's cost-table shapes")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--probe-calib", action="store_true",
+                    help="only run one L2 and one HBM read-probe launch (L2 counter calibration) and exit")
+    ap.add_argument("--no-probe", action="store_true", help="skip the L2 / HBM read-bandwidth probe")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -559,11 +642,23 @@ def main():
         return
     import paper_2508_13304_amd as dp
     dp.load()
+    if args.probe_calib:
+        dev = torch.device("cuda:0")
+        l2 = torch.ones(1 << 19, dtype=torch.float32, device=dev)   # 2 MiB footprint
+        hbm = torch.ones(1 << 29, dtype=torch.float32, device=dev)  # 2 GiB
+        torch.cuda.synchronize()
+        dp.read_probe(l2, 32, True, 2048)    # 2048 blocks x 32 passes x 2 MiB = 128 GiB requested
+        dp.read_probe(hbm, 1, False, 4096)   # every element of 2 GiB once
+        torch.cuda.synchronize()
+        print(json.dumps({"l2_probe_bytes": 2048 * 32 * l2.numel() * 4,
+                          "hbm_probe_bytes": hbm.numel() * 4}), flush=True)
+        return
     if args.no_fwd:
         bp = run_backproject(args, dp, torch)
         print(json.dumps({"backprojector": bp}), flush=True)
         return
     fw = run_forward(args, dp, torch)
+    probe = None if args.no_probe else run_cache_probe(dp, torch)
     bp = None if args.no_bp else run_backproject(args, dp, torch)
     regr = None if args.no_reg else run_registration(args, dp, torch, fw)
     learned = None if args.no_reg else run_learned(args, dp, torch)
@@ -598,6 +693,7 @@ def main():
         "registrations_unit": "registrations/s at <0.1 mm / 0.1 deg (64 single-view targets, "
                               "+-10 mm / +-10 deg, best method with every registration successful)",
         "roofline": fw["roofline"],
+        "gather_roofline": gather_roofline(fw, probe) if probe else None,
         "cpu_baseline": cpu,
         "kernels_ms": fw["per_kernel"],
         "two_call_step": {"ms_per_step": round(fw["two_call_ms"], 4),

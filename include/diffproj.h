@@ -343,6 +343,35 @@ size_t dp_gradient_entropy_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
 int dp_gradient_entropy(int32_t nx, int32_t ny, int32_t nz, const float* vol, float eps,
                         double* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Streaming-read probe (measurement only; not part of the paper's method).
+ * The ray kernels gather trilinear taps through the cache hierarchy, so their
+ * ceiling is a read bandwidth: this kernel measures it on the running GPU.
+ *
+ * dp_read_probe: n_blocks blocks of 256 threads read the FP32 device buffer
+ * buf (16-byte aligned, n_vec float4) and write one FP32 sum per thread to
+ * out (n_blocks * 256 floats, device).
+ *   shared != 0: every block reads all n_vec float4 `reps` times (from its
+ *     own starting offset, wrapping around); n_vec must be a power of two in
+ *     [2048, 2^30].  A footprint of a few MiB stays resident in every XCD's
+ *     L2 and far exceeds a CU's L1, so bytes read = n_blocks * reps * n_vec * 16
+ *     measures the L2 read bandwidth.
+ *   shared == 0: with per = 2048 * floor(n_vec / (2048 * n_blocks)), block b
+ *     reads float4 [b * per, (b + 1) * per) with nontemporal loads (thread j
+ *     the ones whose offset in the slab is j mod 256), then the blocks share
+ *     the tail [n_blocks * per, n_vec) grid-stride (thread j of block b from
+ *     n_blocks * per + 256 b + j, stepping 256 n_blocks); every float4 is read
+ *     once per pass.  n_vec + 256 * n_blocks must stay below 2^32.  A buffer
+ *     far above L2 and the last-level cache measures HBM read bandwidth.
+ * Thread j of block b writes the sum of the components of the float4 it read
+ * to out[256 b + j]; with buf all ones and shared != 0 every sum is
+ * reps * n_vec * 4 / 256.  Errors: DP_ERR_ARG for
+ * NULL or misaligned pointers, non-positive sizes or a bad shared footprint,
+ * DP_ERR_UNSUPPORTED beyond the index range or 2^20 blocks.
+ * ------------------------------------------------------------------------- */
+int dp_read_probe(const void* buf, int64_t n_vec, int32_t reps, int32_t shared, int32_t n_blocks,
+                  float* out, void* stream);
+
 /* Thread-local description of the last non-zero return. */
 const char* dp_last_error(void);
 

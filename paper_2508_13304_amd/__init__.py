@@ -36,7 +36,7 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
            "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16",
-           "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update")
+           "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update", "dp_read_probe")
 MAX_BATCH = 16
 N_VARIANTS = 3
 
@@ -102,6 +102,8 @@ def load(path: str | None = None):
     lib.dp_project_fwd_ssd_gauss_newton_batch.restype = C.c_int
     lib.dp_lm_update.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
     lib.dp_lm_update.restype = C.c_int
+    lib.dp_read_probe.argtypes = [vp, C.c_int64, i32, i32, i32, vp, vp]
+    lib.dp_read_probe.restype = C.c_int
     lib.dp_autotune.argtypes = [i32, g, i32, vp, vp, vp, vp, vp, vp, sz, vp, i32,
                                 C.POINTER(i32), C.POINTER(C.c_float)]
     lib.dp_autotune.restype = C.c_int
@@ -419,6 +421,25 @@ def lm_update(trial, loss, grad, hess, state, tol=1e-4, stream=None):
             _dev(state["lam"], f64, "lam", (n,)),
             _dev(state["done"], torch.int32, "done", (n,))]
     _check(load().dp_lm_update(n, *args, float(tol), _stream(stream)), "dp_lm_update")
+
+
+def read_probe(buf, reps, shared, n_blocks, out=None, stream=None):
+    """Streaming-read probe (measurement only): n_blocks blocks of 256 threads
+    read the float32 device tensor `buf` (numel a multiple of 4).  shared=True:
+    every block reads all of it `reps` times (L2-resident footprint);
+    shared=False: the blocks split it (HBM streaming).  Returns the per-thread
+    sums, float32 [n_blocks * 256]."""
+    import torch
+    if not isinstance(buf, torch.Tensor) or not buf.is_cuda or buf.dtype != torch.float32 \
+            or not buf.is_contiguous() or buf.numel() % 4:
+        raise ValueError("buf must be a contiguous float32 CUDA tensor with numel % 4 == 0")
+    if out is None:
+        out = torch.empty(n_blocks * 256, dtype=torch.float32, device=buf.device)
+    out_p = _dev(out, torch.float32, "out", (n_blocks * 256,))
+    _check(load().dp_read_probe(C.c_void_p(buf.data_ptr()), buf.numel() // 4, int(reps),
+                                1 if shared else 0, int(n_blocks), out_p, _stream(stream)),
+           "dp_read_probe")
+    return out
 
 
 def autotune(op, geom, angles, poses, vol, out, grad_proj=None, ws=None, reps=3, stream=None):

@@ -722,6 +722,38 @@ int dp_lm_update(int32_t n, double* trial, const double* loss, const double* gra
 }
 
 // ---------------------------------------------------------------------------
+// Streaming-read probe (measurement only)
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace dp {
+void launch_read_probe(const void* buf, uint32_t n_vec, int reps, bool shared, int n_blocks,
+                       float* out, hipStream_t st);
+}
+
+extern "C" {
+
+int dp_read_probe(const void* buf, int64_t n_vec, int32_t reps, int32_t shared, int32_t n_blocks,
+                  float* out, void* stream)
+{
+    if (!buf || !out) return fail(DP_ERR_ARG, "read probe: NULL pointer");
+    if (((uintptr_t)buf & 15) != 0) return fail(DP_ERR_ARG, "read probe: buf must be 16-byte aligned");
+    if (n_vec <= 0 || reps <= 0 || n_blocks <= 0)
+        return fail(DP_ERR_ARG, "read probe: n_vec, reps and n_blocks must be positive");
+    if (n_blocks > (1 << 20)) return fail(DP_ERR_UNSUPPORTED, "read probe: more than 2^20 blocks");
+    if (shared) {
+        if ((n_vec & (n_vec - 1)) != 0 || n_vec < 2048 || n_vec > ((int64_t)1 << 30))
+            return fail(DP_ERR_ARG, "read probe: shared footprint must be a power of two in [2048, 2^30] float4");
+    } else if (n_vec + (int64_t)n_blocks * 256 >= ((int64_t)1 << 32)) {
+        return fail(DP_ERR_UNSUPPORTED, "read probe: buffer beyond the kernel's 32-bit index range");
+    }
+    (void)hipGetLastError();
+    launch_read_probe(buf, (uint32_t)n_vec, reps, shared != 0, n_blocks, out, (hipStream_t)stream);
+    return check_launch("dp_read_probe");
+}
+
+// ---------------------------------------------------------------------------
 // Learned-proposal CNN primitives (BF16 MFMA GEMM and conv helpers)
 // ---------------------------------------------------------------------------
 

@@ -183,6 +183,23 @@ def test_batch_ssd_and_lm_update_validate_before_launch(lib):
     assert b"NULL" in lib.dp_last_error()
 
 
+def test_read_probe_argument_validation(lib):
+    """The measurement probe rejects bad arguments before any launch."""
+    buf, out = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
+    assert lib.dp_read_probe(None, 2048, 1, 1, 1, out, None) == -1
+    assert lib.dp_read_probe(buf, 2048, 1, 1, 1, None, None) == -1
+    assert lib.dp_read_probe(C.c_void_p((1 << 20) + 4), 2048, 1, 1, 1, out, None) == -1
+    assert b"aligned" in lib.dp_last_error()
+    assert lib.dp_read_probe(buf, 0, 1, 0, 1, out, None) == -1
+    assert lib.dp_read_probe(buf, 2048, 0, 1, 1, out, None) == -1
+    assert lib.dp_read_probe(buf, 2048, 1, 1, 0, out, None) == -1
+    assert lib.dp_read_probe(buf, 3072, 1, 1, 1, out, None) == -1   # not a power of two
+    assert lib.dp_read_probe(buf, 1024, 1, 1, 1, out, None) == -1   # below 2048
+    assert b"power of two" in lib.dp_last_error()
+    assert lib.dp_read_probe(buf, (1 << 32) - 256, 1, 0, 1, out, None) == -4
+    assert lib.dp_read_probe(buf, 2048, 1, 0, (1 << 20) + 1, out, None) == -4
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     import paper_2508_13304_amd as m
     saved = m._lib

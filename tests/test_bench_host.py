@@ -41,3 +41,28 @@ def test_multi_gpu_request_exits(monkeypatch, capsys):
     with pytest.raises(SystemExit) as e:
         bench.main()
     assert e.value.code == 2
+
+
+def test_gather_roofline_fields(monkeypatch):
+    """The gather roofline divides the measured L2 bandwidth by 128 B per
+    sample, and takes counter figures only while the kernel hash matches."""
+    import bench
+    probe = {"l2_read_GBps": 32000.0, "hbm_read_GBps": 7000.0}
+    fw = {"n_samples": 6.4e9, "ms_step": 20.0,
+          "roofline": {"kernel": "rd_fused", "kernel_ms": 16.0, "traffic": 1.6e11,
+                       "source_hash": "nomatch"}}
+    g = bench.gather_roofline(fw, probe)
+    assert g["ceiling_samples_per_s"] == pytest.approx(32000e9 / 128)
+    assert g["step_frac"] == pytest.approx(round(6.4e9 / 0.02 / (32000e9 / 128), 4))
+    assert g["kernel_frac"] == pytest.approx(round(6.4e9 / 0.016 / (32000e9 / 128), 4))
+    assert g["l2_bytes_per_launch"] is None and g["l2_frac"] is None  # stale hash
+    assert g["beyond_l2_GBps"] == pytest.approx(1.6e11 / 0.016 / 1e9)
+    assert g["beyond_l2_frac_of_hbm_stream"] == pytest.approx(round(1.6e11 / 0.016 / 1e9 / 7000.0, 4))
+    monkeypatch.setattr(bench, "_traffic",
+                        lambda key, h, field="hbm_bytes_per_launch": {"l2_bytes_per_launch": 1.28e11,
+                                                                      "l2_hit_rate": 0.3}.get(field))
+    g = bench.gather_roofline(fw, probe)
+    assert g["l2_GBps"] == pytest.approx(1.28e11 / 0.016 / 1e9)
+    assert g["l2_frac"] == pytest.approx(round(1.28e11 / 0.016 / 1e9 / 32000.0, 4))
+    assert g["l2_hit_rate"] == 0.3
+
