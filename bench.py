@@ -591,22 +591,83 @@ def run_paper_ladder(args, dp, torch):
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
 
-def run_cpu_baseline(fw, n_poses=16):
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def run_cpu_baseline(fw, n_poses=16, n_bp_views=8):
+    """The plain FP64 oracle on the host cores (not a tuned CPU projector):
+    forward + SSD pose gradient on a sample of the registration-scale poses
+    with all threads and with one, and the back-projector and its pose
+    gradient on a sample of the reconstruction-scale views."""
     import oracle
     c = fw["inputs"]
     g = c["geom"]
+    host = _host_cpu()
+    threads = oracle.num_threads()
     angles, poses = c["angles"][:n_poses], c["poses"][:n_poses]
     y = oracle.project_fwd(g, [0.0], c["target_pose"], c["vol"])
+
+    def fwd_grad(geom, a, p, target):
+        t0 = time.perf_counter()
+        l = oracle.project_fwd(geom, a, p, c["vol"])
+        oracle.project_fwd_grad_pose(geom, a, p, c["vol"], 2.0 * (l - target))
+        return time.perf_counter() - t0
+
     n = count_ray_samples(g, angles, poses)
+    dt = fwd_grad(g, angles, poses, y)
+    log(f"[bench] oracle: {n_poses} poses in {dt:.2f} s ({threads} threads; {host})")
+    # one thread, first pose, the detector's central 128 rows (the same rays as
+    # those rows of the full detector: the row centre stays on the axis)
+    gband = g.replace(nv=128)
+    yband = y[:, (g.nv - 128) // 2:(g.nv + 128) // 2]
+    n1 = count_ray_samples(gband, angles[:1], poses[:1])
+    oracle.set_num_threads(1)
+    try:
+        dt1 = fwd_grad(gband, angles[:1], poses[:1], yband)
+    finally:
+        oracle.set_num_threads(threads)
+    log(f"[bench] oracle: central 128 rows of 1 pose in {dt1:.2f} s (1 thread)")
+    # back-projection sample: the first views of the 360-view motion at 512^3
+    gb = synth.geom_c3_recon()
+    m = synth.config3_motion()
+    rng = np.random.default_rng(3)
+    proj = synth.smooth_images(n_bp_views, gb.nv, gb.nu, rng, n_blobs=4, signed=True).astype(np.float64)
+    a_b, p_b = m["angles"][:n_bp_views], m["poses"][:n_bp_views]
     t0 = time.perf_counter()
-    l = oracle.project_fwd(g, angles, poses, c["vol"])
-    w = 2.0 * (l - y)
-    oracle.project_fwd_grad_pose(g, angles, poses, c["vol"], w)
-    dt = time.perf_counter() - t0
-    log(f"[bench] oracle: {n_poses} poses in {dt:.2f} s ({oracle.num_threads()} threads)")
-    return {"value": n / dt, "unit": "ray-samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+    oracle.backproject(gb, a_b, p_b, proj, oracle.W_FDK)
+    t_bp = time.perf_counter() - t0
+    e = np.random.default_rng(5).standard_normal((gb.nz, gb.ny, gb.nx))
+    t0 = time.perf_counter()
+    oracle.backproject_grad_pose(gb, a_b, p_b, proj, e, oracle.W_FDK)
+    t_bpg = time.perf_counter() - t0
+    upd = gb.nx * gb.ny * gb.nz * n_bp_views
+    log(f"[bench] oracle: back-projection {n_bp_views} views in {t_bp:.2f} s, gradient {t_bpg:.2f} s")
+    return {"value": n / dt, "unit": "ray-samples/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_poses} of 64 poses, all 512x512 rays, forward + SSD pose gradient "
-                      f"({n:.3e} samples, {dt:.1f} s); plain FP64 oracle, not a tuned CPU projector"}
+                      f"({n:.3e} samples, {dt:.1f} s); plain FP64 oracle, not a tuned CPU projector",
+            "host": host,
+            "one_thread": {"value": n1 / dt1, "unit": "ray-samples/s", "cores": 1,
+                           "sample": f"first pose, central 128 of 512 detector rows, forward + SSD pose "
+                                     f"gradient ({n1:.3e} samples, {dt1:.1f} s)"},
+            "backprojector": {"backproject_updates_per_s": upd / t_bp,
+                              "backproject_grad_updates_per_s": upd / t_bpg, "cores": threads,
+                              "sample": f"first {n_bp_views} of 360 views at 512^3 with the FDK weight "
+                                        f"({upd:.3e} voxel-view updates; {t_bp:.1f} s back-projection, "
+                                        f"{t_bpg:.1f} s gradient); the full 360 views take 45x as long"}}
 
 
 def main():

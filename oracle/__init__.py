@@ -54,6 +54,8 @@ def lib():
         _lib = C.CDLL(_LIB)
         _lib.dpref_count_samples.restype = C.c_int64
         _lib.dpref_num_threads.restype = C.c_int
+        _lib.dpref_set_num_threads.argtypes = [C.c_int]
+        _lib.dpref_set_num_threads.restype = None
     return _lib
 
 
@@ -81,6 +83,12 @@ def _views(angles, poses):
 
 def num_threads() -> int:
     return int(lib().dpref_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for the following calls (for timing; the parallel FP64
+    sums may then add in another order)."""
+    lib().dpref_set_num_threads(int(n))
 
 
 def rotation(gamma) -> np.ndarray:

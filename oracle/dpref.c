@@ -47,6 +47,17 @@ int dpref_num_threads(void)
 #endif
 }
 
+/* Thread count for the following calls (timing only: no result depends on it
+ * beyond the order of FP64 additions in the parallel sums). */
+void dpref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Pose algebra                                                             */
 /* ------------------------------------------------------------------------ */

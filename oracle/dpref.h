@@ -30,6 +30,7 @@ typedef struct {
 enum { DPREF_W_NONE = 0, DPREF_W_FDK = 1 };
 
 int  dpref_num_threads(void);
+void dpref_set_num_threads(int n);
 
 /* Pose algebra (notation table: theta = (t, gamma), M = [R | t]). */
 void dpref_rotation(const double gam[3], double R[9]);

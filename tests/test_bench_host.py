@@ -66,3 +66,29 @@ def test_gather_roofline_fields(monkeypatch):
     assert g["l2_frac"] == pytest.approx(round(1.28e11 / 0.016 / 1e9 / 32000.0, 4))
     assert g["l2_hit_rate"] == 0.3
 
+
+
+def test_host_cpu_description():
+    import bench
+    h = bench._host_cpu()
+    assert set(h) == {"cpu_model", "nproc", "usable_cpus"}
+    assert h["nproc"] >= 1
+
+
+def test_oracle_thread_count_changes_only_the_timing():
+    """The one-thread CPU baseline calls the same oracle: per-ray forward
+    projections do not depend on the OpenMP thread count."""
+    import oracle
+    g = synth.geom_c1()
+    vol = np.random.default_rng(0).random((g.nz, g.ny, g.nx))
+    pose = [[1.0, -2.0, 0.5, 0.02, -0.03, 0.01]]
+    n = oracle.num_threads()
+    ref = oracle.project_fwd(g, [0.3], pose, vol)
+    oracle.set_num_threads(1)
+    try:
+        assert oracle.num_threads() == 1
+        one = oracle.project_fwd(g, [0.3], pose, vol)
+    finally:
+        oracle.set_num_threads(n)
+    assert oracle.num_threads() == n
+    assert np.array_equal(ref, one)
