@@ -42,6 +42,11 @@ VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec (packed FMA)
 FLOPS_PER_SAMPLE = {"rd_fwd": 33, "rd_grad": 113, "rd_fused": 135}
 # bytes one forward + gradient sample gathers: 8 trilinear corners x (mu, Gx, Gy, Gz) x 4 B
 GATHER_BYTES_PER_SAMPLE = 128
+# bytes one voxel-view update gathers: 4 bilinear taps of l (back-projection), of
+# (l, dl/da, dl/db) (its pose gradient)
+VD_GATHER_BYTES_PER_UPDATE = {"vd_bp": 16, "vd_grad": 48}
+# wave64 VALU issue on a 4-cycle model: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 
 
 def log(*a):
@@ -280,6 +285,39 @@ def gather_roofline(fw, probe):
            "beyond_l2_frac_of_hbm_stream":
                round(hbm_bytes / (k_ms * 1e-3) / 1e9 / probe["hbm_read_GBps"], 4) if hbm_bytes else None,
            "probe": probe}
+    return out
+
+
+def vd_rooflines(bp, probe):
+    """Both ceilings of each back-projector kernel: the gather ceiling (the
+    measured L2 read bandwidth over the bytes an update gathers) and the VALU
+    ceiling (4-cycle wave64 issue over the VALU lane instructions per update,
+    counted by SQ_INSTS_VALU; read from profiles/traffic.json while the kernel
+    source is unchanged).  Each kernel is graded against the lower one."""
+    h = _kernel_hash("vd.hip", "dp_internal.h")
+    out = {}
+    for k, nbytes in VD_GATHER_BYTES_PER_UPDATE.items():
+        ms = bp["kernels_ms"].get(k)
+        if not ms:
+            continue
+        rate = bp["voxel_view_updates"] / (ms * 1e-3)
+        gather = probe["l2_read_GBps"] * 1e9 / nbytes
+        ipu = _traffic(k + "_reconstruction_scale", h, "valu_lane_instr_per_update")
+        valu = VALU_LANE_INSTR_PER_S / ipu if ipu else None
+        bound = "valu" if valu is not None and valu < gather else "gather"
+        ceiling = min(gather, valu) if valu is not None else gather
+        out[k] = {"updates_per_s": rate, "gather_bytes_per_update": nbytes,
+                  "gather_ceiling_updates_per_s": gather, "gather_frac": round(rate / gather, 4),
+                  "valu_lane_instr_per_update": ipu,
+                  "valu_ceiling_updates_per_s": valu,
+                  "valu_frac": round(rate / valu, 4) if valu else None,
+                  "graded_against": bound, "frac": round(rate / ceiling, 4),
+                  "valu_busy": _traffic(k + "_reconstruction_scale", h, "valu_busy"),
+                  "ta_busy": _traffic(k + "_reconstruction_scale", h, "ta_busy"),
+                  "l2_hit_rate": _traffic(k + "_reconstruction_scale", h, "l2_hit_rate")}
+        l2b = _traffic(k + "_reconstruction_scale", h, "l2_bytes_per_launch")
+        out[k]["l2_GBps"] = round(l2b / (ms * 1e-3) / 1e9, 1) if l2b else None
+        out[k]["l2_frac"] = round(l2b / (ms * 1e-3) / 1e9 / probe["l2_read_GBps"], 4) if l2b else None
     return out
 
 
@@ -760,7 +798,7 @@ def main():
         "two_call_step": {"ms_per_step": round(fw["two_call_ms"], 4),
                           "value": fw["n_samples"] / (fw["two_call_ms"] * 1e-3),
                           "kernels_ms": fw["two_call_kernels"]},
-        "backprojector": bp,
+        "backprojector": dict(bp, rooflines=vd_rooflines(bp, probe)) if bp and probe else bp,
         "registration": regr,
         "learned_proposal": learned,
         "calibration_batch": calib,
