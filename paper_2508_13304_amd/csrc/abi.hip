@@ -81,7 +81,7 @@ Layout layout(const dp_geom& g, int V, int op)
         off = align_up(off + (size_t)V * 6 * sizeof(double));
         break;
     case DP_OP_BP:
-        off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float));
+        off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float4));
         break;
     case DP_OP_FP_FWD:
     case DP_OP_FP_BP:
@@ -442,11 +442,11 @@ int dp_backproject(const dp_geom* g, int32_t V, const double* angles, const doub
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
-    float* projp = (float*)(base + L.buf);
+    float4* projq = (float4*)(base + L.buf);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_det_pad(s, V, proj, projp, st);
-    launch_vd_bp(s, V, views, projp, vol, weight_mode, st);
+    launch_det_pad(s, V, proj, projq, st);
+    launch_vd_bp(s, V, views, projq, vol, weight_mode, st);
     return check_launch("dp_backproject");
 }
 

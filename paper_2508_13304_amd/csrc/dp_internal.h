@@ -21,10 +21,11 @@ constexpr int kRdThreads = 256;
 constexpr int kRdChannels = 9;   // B (3) and T (6) accumulators of the pose gradient
 
 // Voxel-driven launch shape: 64 (x) x 4 (y) threads, each thread owns a
-// column of kVdCol voxels along z.
+// column of voxels along z (kVdBpCol for the back-projection, kVdGradCol for
+// its gradient); the FP64 column anchor is computed once per view per column.
 constexpr int kVdBx = 64;
 constexpr int kVdBy = 4;
-constexpr int kVdCol = 16;
+constexpr int kVdBpCol = 32;
 constexpr int kVdGradCol = 32;
 constexpr int kVdChannels = 12;  // A (3), QX (3), QY (3), QZ (3)
 
@@ -70,7 +71,8 @@ void launch_vol_pad(const GeoScalars& s, const float* vol, float* volp, hipStrea
 // per-voxel float4 (mu, Gx, Gy, Gz) interleave, in one pass
 void launch_vol_prep(const GeoScalars& s, const float* vol, float* mu_plane, float* g3,
                      float4* inter, hipStream_t st);
-void launch_det_pad(const GeoScalars& s, int V, const float* proj, float* projp, hipStream_t st);
+// per padded pixel, the 2x2 bilinear footprint of l as one float4
+void launch_det_pad(const GeoScalars& s, int V, const float* proj, float4* projq, hipStream_t st);
 void launch_det_grad(const GeoScalars& s, int V, const float* proj, float4* proj4, hipStream_t st);
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
                    float* proj, int variant, hipStream_t st);
@@ -111,7 +113,7 @@ void launch_rd_fused_batch(const RdBatch& bt, int blocks, int variant, hipStream
 void launch_lm_update(int n, double* trial, const double* loss, const double* grad,
                       const double* hess, double* state_pose, double* state_f, double* state_g,
                       double* state_h, double* lam, int* done, double tol, hipStream_t st);
-void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
+void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float4* projq,
                   float* vol, int weight_mode, hipStream_t st);
 void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
                     const float* grad_vol, float* partials, int weight_mode, hipStream_t st);

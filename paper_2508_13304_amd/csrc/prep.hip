@@ -5,7 +5,8 @@
 //     stored as three zero-padded planes Gx, Gy, Gz in voxel-index units
 //     (half the neighbour difference), zero outside the grid, optionally
 //     with the padded mu plane, and the same values interleaved per voxel;
-//   - zero-padded copy of the detector images for the back-projection;
+//   - per padded detector pixel, the 2x2 bilinear footprint of the
+//     zero-extended image as one float4, for the back-projection;
 //   - detector gradient field (central differences of l, Sec. II-C) stored
 //     as float4 (l, dl/da, dl/db, 0) in pixel-index units, zero outside.
 #include "dp_internal.h"
@@ -70,15 +71,21 @@ __device__ inline float pix_at(const float* __restrict__ img, int nu, int nv, in
     return img[(size_t)b * nu + a];
 }
 
+// Per padded pixel (A, B), the 2x2 bilinear footprint {(A, B), (A+1, B),
+// (A, B+1), (A+1, B+1)} of the zero-extended image as one float4, so that a
+// back-projection update gathers one 16-byte vector instead of two rows.
 __global__ __launch_bounds__(256) void det_pad_kernel(int nu, int nv, const float* __restrict__ proj,
-                                                      float* __restrict__ projp)
+                                                      float4* __restrict__ projq)
 {
     const int NU = nu + 2 * kPadD, NV = nv + 2 * kPadD;
     const int A = blockIdx.x * blockDim.x + threadIdx.x;
     const int B = blockIdx.y, v = blockIdx.z;
     if (A >= NU) return;
     const float* img = proj + (size_t)v * nu * nv;
-    projp[((size_t)v * NV + B) * NU + A] = pix_at(img, nu, nv, A - kPadD, B - kPadD);
+    const int a = A - kPadD, b = B - kPadD;
+    projq[((size_t)v * NV + B) * NU + A] =
+        make_float4(pix_at(img, nu, nv, a, b), pix_at(img, nu, nv, a + 1, b),
+                    pix_at(img, nu, nv, a, b + 1), pix_at(img, nu, nv, a + 1, b + 1));
 }
 
 __global__ __launch_bounds__(256) void det_grad_kernel(int nu, int nv, const float* __restrict__ proj,
@@ -121,12 +128,12 @@ void launch_vol_prep(const GeoScalars& s, const float* vol, float* mu_plane, flo
     prof_end(DP_K_VOL_PREP, st);
 }
 
-void launch_det_pad(const GeoScalars& s, int V, const float* proj, float* projp, hipStream_t st)
+void launch_det_pad(const GeoScalars& s, int V, const float* proj, float4* projq, hipStream_t st)
 {
     const int NU = s.nu + 2 * kPadD;
     dim3 grid((NU + 255) / 256, s.nv + 2 * kPadD, V);
     prof_begin(DP_K_DET_PREP, st);
-    det_pad_kernel<<<grid, 256, 0, st>>>(s.nu, s.nv, proj, projp);
+    det_pad_kernel<<<grid, 256, 0, st>>>(s.nu, s.nv, proj, projq);
     prof_end(DP_K_DET_PREP, st);
 }
 

@@ -82,14 +82,53 @@ __device__ inline ColumnAnchor column_anchor(const ViewGeo& g, const GeoScalars&
     return c;
 }
 
+// floor(x) as an integer in one VALU instruction (|x| far below 2^31 here).
+__device__ inline int floor_to_int(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Window clamp: positions more than half a pixel outside the detector (or
 // behind the source) land in the zero border; all others are unchanged.
 __device__ inline float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
 
+// One view's contribution to a column of K voxels.  FRONT: the caller has
+// checked that every voxel of the column lies in front of the source (W > 0 at
+// both ends of the column, W being linear along it), so no per-voxel test.
+template <int MODE, int K, bool FRONT>
+__device__ inline void bp_column(const ColumnAnchor& c, float pw2, const float4* __restrict__ img,
+                                 int NU, float (&acc)[K])
+{
+    float dk = -c.ka;  // kk - ka, exact: small integers
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk, dk += 1.0f) {
+        const float W = fmaf(dk, pw2, c.w0);
+        const bool front = FRONT || W > 0.0f;  // voxels at or behind the source get no ray
+        const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
+        float A = fmaf(dk * c.nu, iw, c.a0f);
+        const float B0 = fmaf(dk * c.nv, iw, c.b0f);
+        if (!FRONT) A = front ? A : -1.0e9f;
+        A = __builtin_amdgcn_fmed3f(A, c.alo, c.ahi);
+        const float B = __builtin_amdgcn_fmed3f(B0, c.blo, c.bhi);
+        const int ia = floor_to_int(A), ib = floor_to_int(B);
+        const float wa = __builtin_amdgcn_fractf(A), wb = __builtin_amdgcn_fractf(B);
+        const float4 q = img[ib * NU + ia];
+        const float t0 = lerp_f(q.x, q.y, wa);
+        const float t1 = lerp_f(q.z, q.w, wa);
+        const float val = lerp_f(t0, t1, wb);
+        if (MODE == DP_W_FDK)
+            acc[kk] = fmaf(iw * iw, val, acc[kk]);
+        else
+            acc[kk] += val;
+    }
+}
+
 template <int MODE, int K>
 __global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int V,
                                                               const ViewGeo* __restrict__ views,
-                                                              const float* __restrict__ projp,
+                                                              const float4* __restrict__ projq,
                                                               float* __restrict__ vol)
 {
     const int i = blockIdx.x * kVdBx + threadIdx.x;
@@ -104,34 +143,53 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int 
         const ViewGeo& g = views[v];
         const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
         const float pw2 = g.PW[2];
-        const long long img = (long long)v * NU * NV + c.off;  // anchor pixel of this view
-#pragma unroll
-        for (int kk = 0; kk < K; ++kk) {
-            const float dk = (float)kk - c.ka;
-            const float W = fmaf(dk, pw2, c.w0);
-            const bool front = W > 0.0f;  // voxels at or behind the source get no ray
-            const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
-            float A = fmaf(dk * c.nu, iw, c.a0f);
-            float B = fmaf(dk * c.nv, iw, c.b0f);
-            A = front ? A : -1.0e9f;
-            A = clampf(A, c.alo, c.ahi);
-            B = clampf(B, c.blo, c.bhi);
-            const float fa = floorf(A), fb = floorf(B);
-            const float wa = A - fa, wb = B - fb;
-            const float* p = projp + (img + ((int)fb * NU + (int)fa));
-            const float t0 = lerp_f(p[0], p[1], wa);
-            const float t1 = lerp_f(p[NU], p[NU + 1], wa);
-            const float val = lerp_f(t0, t1, wb);
-            if (MODE == DP_W_FDK)
-                acc[kk] = fmaf(D2 * (iw * iw), val, acc[kk]);
-            else
-                acc[kk] += val;
-        }
+        const float4* img = projq + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
+        if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
+            bp_column<MODE, K, true>(c, pw2, img, NU, acc);
+        else
+            bp_column<MODE, K, false>(c, pw2, img, NU, acc);
     }
     if (i < s.nx && j < s.ny) {
 #pragma unroll
         for (int kk = 0; kk < K; ++kk)
-            if (kb + kk < s.nz) vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] = acc[kk];
+            if (kb + kk < s.nz)
+                vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] = MODE == DP_W_FDK ? D2 * acc[kk] : acc[kk];
+    }
+}
+
+// One view's gradient sums over a column of K voxels (FRONT as in bp_column):
+// A_k += e c_k and Z_k += e c_k (k - centre_z) for k = u, v, w.
+template <int MODE, int K, bool FRONT>
+__device__ inline void grad_column(const ColumnAnchor& c, float pw2, const float4* __restrict__ img,
+                                   int NU, const float (&e)[K], float pk0, float kappa, float& A1,
+                                   float& A2, float& A3, float& Z1, float& Z2, float& Z3)
+{
+    float dk = -c.ka;  // kk - ka, exact: small integers
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk, dk += 1.0f) {
+        const float W = fmaf(dk, pw2, c.w0);
+        const bool front = FRONT || W > 0.0f;  // voxels at or behind the source get no ray
+        const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
+        const float da = dk * c.nu * iw, db = dk * c.nv * iw;
+        const float ap = c.apc + da, bp = c.bpc + db;  // offsets from the detector centre
+        float A = c.a0f + da;
+        if (!FRONT) A = front ? A : -1.0e9f;
+        A = __builtin_amdgcn_fmed3f(A, c.alo, c.ahi);
+        const float B = __builtin_amdgcn_fmed3f(c.b0f + db, c.blo, c.bhi);
+        const int ia = floor_to_int(A), ib = floor_to_int(B);
+        const float wa = __builtin_amdgcn_fractf(A), wb = __builtin_amdgcn_fractf(B);
+        const float4* p = img + (ib * NU + ia);
+        const float4 p00 = p[0], p10 = p[1], p01 = p[NU], p11 = p[NU + 1];
+        const float l = lerp_f(lerp_f(p00.x, p10.x, wa), lerp_f(p01.x, p11.x, wa), wb);
+        const float la = lerp_f(lerp_f(p00.y, p10.y, wa), lerp_f(p01.y, p11.y, wa), wb);
+        const float lb = lerp_f(lerp_f(p00.z, p10.z, wa), lerp_f(p01.z, p11.z, wa), wb);
+        // e * W / w' (FDK: e D^2 / w'^3, with D^2 folded into e)
+        const float ec = MODE == DP_W_FDK ? e[kk] * (iw * iw) * iw : e[kk] * iw;
+        const float c1 = ec * la, c2 = ec * lb;
+        const float c3 = -ec * fmaf(la, ap, fmaf(lb, bp, kappa * l));
+        const float pk = pk0 + (float)kk;
+        A1 += c1; A2 += c2; A3 += c3;
+        Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
     }
 }
 
@@ -168,35 +226,12 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, in
         const ViewGeo& g = views[v];
         const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
         const float pw2 = g.PW[2];
-        const long long img = (long long)v * NU * NV + c.off;  // anchor pixel of this view
         float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < K; ++kk) {
-            const float dk = (float)kk - c.ka;
-            const float W = fmaf(dk, pw2, c.w0);
-            const bool front = W > 0.0f;  // voxels at or behind the source get no ray
-            const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
-            const float da = dk * c.nu * iw, db = dk * c.nv * iw;
-            const float ap = c.apc + da, bp = c.bpc + db;  // offsets from the detector centre
-            float A = c.a0f + da, B = c.b0f + db;
-            A = front ? A : -1.0e9f;
-            A = clampf(A, c.alo, c.ahi);
-            B = clampf(B, c.blo, c.bhi);
-            const float fa = floorf(A), fb = floorf(B);
-            const float wa = A - fa, wb = B - fb;
-            const float4* p = proj4 + (img + ((int)fb * NU + (int)fa));
-            const float4 p00 = p[0], p10 = p[1], p01 = p[NU], p11 = p[NU + 1];
-            const float l = lerp_f(lerp_f(p00.x, p10.x, wa), lerp_f(p01.x, p11.x, wa), wb);
-            const float la = lerp_f(lerp_f(p00.y, p10.y, wa), lerp_f(p01.y, p11.y, wa), wb);
-            const float lb = lerp_f(lerp_f(p00.z, p10.z, wa), lerp_f(p01.z, p11.z, wa), wb);
-            // e * W / w' (FDK: e D^2 / w'^3, with D^2 folded into e)
-            const float ec = MODE == DP_W_FDK ? e[kk] * (iw * iw) * iw : e[kk] * iw;
-            const float c1 = ec * la, c2 = ec * lb;
-            const float c3 = -ec * fmaf(la, ap, fmaf(lb, bp, kappa * l));
-            const float pk = pk0 + (float)kk;
-            A1 += c1; A2 += c2; A3 += c3;
-            Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
-        }
+        const float4* img = proj4 + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
+        if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
+            grad_column<MODE, K, true>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
+        else
+            grad_column<MODE, K, false>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
         // Channel-halving butterfly over the wavefront: at the xor-32 and
         // xor-16 steps each lane keeps half of the channels and receives the
         // partner's sums of them, so the 12 channels take 6 + 3 + 4 x 3 = 21
@@ -231,22 +266,22 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, in
 }
 
 template <int MODE>
-static void vd_bp_dispatch(const GeoScalars& s, int V, const ViewGeo* views, const float* projp,
+static void vd_bp_dispatch(const GeoScalars& s, int V, const ViewGeo* views, const float4* projq,
                            float* vol, hipStream_t st)
 {
     dim3 block(kVdBx, kVdBy);
-    dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy, (s.nz + kVdCol - 1) / kVdCol);
-    vd_bp_kernel<MODE, kVdCol><<<grid, block, 0, st>>>(s, V, views, projp, vol);
+    dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy, (s.nz + kVdBpCol - 1) / kVdBpCol);
+    vd_bp_kernel<MODE, kVdBpCol><<<grid, block, 0, st>>>(s, V, views, projq, vol);
 }
 
-void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* projp, float* vol,
+void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float4* projq, float* vol,
                   int weight_mode, hipStream_t st)
 {
     prof_begin(DP_K_VD_BP, st);
     if (weight_mode == DP_W_FDK)
-        vd_bp_dispatch<DP_W_FDK>(s, V, views, projp, vol, st);
+        vd_bp_dispatch<DP_W_FDK>(s, V, views, projq, vol, st);
     else
-        vd_bp_dispatch<DP_W_NONE>(s, V, views, projp, vol, st);
+        vd_bp_dispatch<DP_W_NONE>(s, V, views, projq, vol, st);
     prof_end(DP_K_VD_BP, st);
 }
 
