@@ -711,8 +711,8 @@ def run_cpu_baseline(fw, n_poses=16, n_bp_views=8):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bp", action="store_true", help="skip the back-projector leg")
     ap.add_argument("--no-fwd", action="store_true", help="skip the forward leg (profiling runs)")
