@@ -97,8 +97,11 @@ __device__ inline float clampf(float x, float lo, float hi) { return fminf(fmaxf
 // One view's contribution to a column of K voxels.  FRONT: the caller has
 // checked that every voxel of the column lies in front of the source (W > 0 at
 // both ends of the column, W being linear along it), so no per-voxel test.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const f32x4 global_float4;
+
 template <int MODE, int K, bool FRONT>
-__device__ inline void bp_column(const ColumnAnchor& c, float pw2, const float4* __restrict__ img,
+__device__ inline void bp_column(const ColumnAnchor& c, float pw2, global_float4* __restrict__ img,
                                  int NU, float (&acc)[K])
 {
     float dk = -c.ka;  // kk - ka, exact: small integers
@@ -114,7 +117,7 @@ __device__ inline void bp_column(const ColumnAnchor& c, float pw2, const float4*
         const float B = __builtin_amdgcn_fmed3f(B0, c.blo, c.bhi);
         const int ia = floor_to_int(A), ib = floor_to_int(B);
         const float wa = __builtin_amdgcn_fractf(A), wb = __builtin_amdgcn_fractf(B);
-        const float4 q = img[ib * NU + ia];
+        const f32x4 q = img[ib * NU + ia];
         const float t0 = lerp_f(q.x, q.y, wa);
         const float t1 = lerp_f(q.z, q.w, wa);
         const float val = lerp_f(t0, t1, wb);
@@ -143,7 +146,11 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int 
         const ViewGeo& g = views[v];
         const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
         const float pw2 = g.PW[2];
-        const float4* img = projq + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
+        const float4* base = projq + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
+        // one 64-bit base per view and column (kept whole, in global memory's
+        // address space), so each update adds only its 32-bit pixel offset
+        asm volatile("" : "+v"(base));
+        global_float4* img = (global_float4*)base;
         if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
             bp_column<MODE, K, true>(c, pw2, img, NU, acc);
         else
