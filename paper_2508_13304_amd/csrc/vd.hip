@@ -41,6 +41,7 @@ struct ColumnAnchor {
     float ka;           // anchor position in the column
     float alo, ahi, blo, bhi;  // safe window of the padded image, relative to the anchor
     float apc, bpc;     // anchor offsets from the detector centre (pixels)
+    bool exact;         // no usable anchor: project every voxel in FP64 instead
 };
 
 __device__ inline ColumnAnchor column_anchor(const ViewGeo& g, const GeoScalars& s, int i, int j,
@@ -49,21 +50,30 @@ __device__ inline ColumnAnchor column_anchor(const ViewGeo& g, const GeoScalars&
     ColumnAnchor c;
     int ka = K / 2;
     const double fi = i, fj = j;
-    double W0 = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], (double)(kb + ka), g.PWd[3])));
-    if (!(fabs(W0) >= 1.0)) {  // anchor within 1 mm of the source plane: move it
-        ka = 0;
-        W0 = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], (double)kb, g.PWd[3])));
-        if (!(fabs(W0) >= 1.0)) W0 = 1.0;  // whole column at the source plane: no ray reaches it
+    const double Wij = fma(g.PWd[0], fi, fma(g.PWd[1], fj, g.PWd[3]));
+    double W0 = fma(g.PWd[2], (double)(kb + ka), Wij);
+    c.exact = false;
+    if (!(fabs(W0) >= 1.0)) {
+        // anchor within 1 mm of the source plane: move it to the column end
+        // farther from that plane (the depth is linear along the column)
+        const double Wlo = fma(g.PWd[2], (double)kb, Wij), Whi = fma(g.PWd[2], (double)(kb + K - 1), Wij);
+        ka = fabs(Wlo) >= fabs(Whi) ? 0 : K - 1;
+        W0 = ka == 0 ? Wlo : Whi;
+        if (!(fabs(W0) >= 1.0)) {  // the whole column lies within 1 mm of it
+            c.exact = true;
+            W0 = 1.0;
+        }
     }
     const double fk = kb + ka;
     const double U0 = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
     const double V0 = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
     const double iw0 = 1.0 / W0;
     const double ap = U0 * iw0, bp = V0 * iw0;
-    // anchors far outside the detector are pulled in; their voxels still
-    // land in the zero border after the per-voxel window clamp
-    const double a0 = fmin(fmax(ap + s.cu + kPadD, -65536.0), 65536.0);
-    const double b0 = fmin(fmax(bp + s.cv + kPadD, -65536.0), 65536.0);
+    // an anchor projecting far outside the detector (or a non-finite one) is
+    // no reference for the offsets of the other voxels of its column
+    if (!(fabs(ap) <= 65536.0 && fabs(bp) <= 65536.0)) c.exact = true;
+    const double a0 = c.exact ? 0.0 : ap + s.cu + kPadD;
+    const double b0 = c.exact ? 0.0 : bp + s.cv + kPadD;
     const double A0 = floor(a0), B0 = floor(b0);
     const int NU = s.nu + 2 * kPadD;
     c.off = (long long)B0 * NU + (long long)A0;
@@ -128,6 +138,62 @@ __device__ inline void bp_column(const ColumnAnchor& c, float pw2, global_float4
     }
 }
 
+// A column with no usable FP64 anchor (it lies within 1 mm of the source
+// plane, which only happens with the source inside the volume): every voxel
+// is projected on its own in FP64, with the same window clamp and weights.
+struct ExactVoxel {
+    bool front;        // in front of the source
+    float A, B;        // padded-image coordinates, window-clamped
+    float iw;          // 1 / depth
+    float ap, bp;      // pixel offsets from the detector centre
+};
+
+// U, V, W: the projective rows at the voxel (FP64, stepped along the column).
+__device__ inline ExactVoxel exact_voxel(const GeoScalars& s, double U, double V, double W)
+{
+    ExactVoxel x;
+    x.front = W > 0.0;
+    const double iw = x.front ? 1.0 / W : 0.0;
+    const double ap = U * iw, bp = V * iw;
+    const double a = x.front ? ap + s.cu + kPadD : -1.0e9;
+    x.A = (float)fmin(fmax(a, kPadD - 1.5), s.nu + kPadD + 0.5);
+    x.B = (float)fmin(fmax(bp + s.cv + kPadD, kPadD - 1.5), s.nv + kPadD + 0.5);
+    x.iw = (float)iw;
+    x.ap = (float)ap;
+    x.bp = (float)bp;
+    return x;
+}
+
+// Projective rows of voxel (i, j, k) for one view.
+__device__ inline void exact_rows(const ViewGeo& g, int i, int j, int k, double& U, double& V, double& W)
+{
+    const double fi = i, fj = j, fk = k;
+    U = fma(g.PUd[0], fi, fma(g.PUd[1], fj, fma(g.PUd[2], fk, g.PUd[3])));
+    V = fma(g.PVd[0], fi, fma(g.PVd[1], fj, fma(g.PVd[2], fk, g.PVd[3])));
+    W = fma(g.PWd[0], fi, fma(g.PWd[1], fj, fma(g.PWd[2], fk, g.PWd[3])));
+}
+
+template <int MODE, int K>
+__device__ inline void bp_column_exact(const ViewGeo& g, const GeoScalars& s, int i, int j, int kb,
+                                       global_float4* __restrict__ view, int NU, float (&acc)[K])
+{
+    // a rolled loop keeps the FP64 code (and its registers) out of the fast
+    // paths; each voxel's term reaches its register by compile-time selects
+    double U, V, W;
+    exact_rows(g, i, j, kb, U, V, W);
+#pragma unroll 1
+    for (int kk = 0; kk < K; ++kk, U += g.PUd[2], V += g.PVd[2], W += g.PWd[2]) {
+        const ExactVoxel x = exact_voxel(s, U, V, W);
+        const int ia = floor_to_int(x.A), ib = floor_to_int(x.B);
+        const float wa = __builtin_amdgcn_fractf(x.A), wb = __builtin_amdgcn_fractf(x.B);
+        const f32x4 q = view[ib * NU + ia];
+        const float val = lerp_f(lerp_f(q.x, q.y, wa), lerp_f(q.z, q.w, wa), wb);
+        const float term = MODE == DP_W_FDK ? x.iw * x.iw * val : val;
+#pragma unroll
+        for (int t = 0; t < K; ++t) acc[t] += t == kk ? term : 0.0f;
+    }
+}
+
 template <int MODE, int K>
 __global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int V,
                                                               const ViewGeo* __restrict__ views,
@@ -146,6 +212,11 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int 
         const ViewGeo& g = views[v];
         const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
         const float pw2 = g.PW[2];
+        if (c.exact) {
+            bp_column_exact<MODE, K>(g, s, i, j, kb, (global_float4*)(projq + (long long)v * NU * NV),
+                                     NU, acc);
+            continue;
+        }
         const float4* base = projq + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
         // one 64-bit base per view and column (kept whole, in global memory's
         // address space), so each update adds only its 32-bit pixel offset
@@ -200,8 +271,40 @@ __device__ inline void grad_column(const ColumnAnchor& c, float pw2, const float
     }
 }
 
+// Sum 12 channels over the wavefront and store (ADD: add) them to out[12].
+// Channel-halving butterfly: at the xor-32 and xor-16 steps each lane keeps
+// half of the channels and receives the partner's sums of them, so the 12
+// channels take 6 + 3 + 4 x 3 = 21 cross-lane exchanges instead of 72.  Lane
+// 16 q (q = 0..3) ends with channels 3 q .. 3 q + 2 of the whole wavefront;
+// each wavefront owns its partials (no block barrier, fixed summation order).
+template <bool ADD>
+__device__ inline void wave_partials(const float (&r)[kVdChannels], int lane, float* __restrict__ out)
+{
+    const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
+    float s6[6], s3[3];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const float keep = h32 ? r[6 + t] : r[t], give = h32 ? r[t] : r[6 + t];
+        s6[t] = keep + __shfl_xor(give, 32);
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const float keep = h16 ? s6[3 + t] : s6[t], give = h16 ? s6[t] : s6[3 + t];
+        s3[t] = keep + __shfl_xor(give, 16);
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) s3[t] += __shfl_xor(s3[t], off);
+    if ((lane & 15) == 0) {
+        float* o = out + (lane >> 4) * 3;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) o[t] = ADD ? o[t] + s3[t] : s3[t];
+    }
+}
+
 template <int MODE, int K>
-__global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, int V,
+__global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(4))) void vd_grad_kernel(GeoScalars s, int V,
                                                                 const ViewGeo* __restrict__ views,
                                                                 const float4* __restrict__ proj4,
                                                                 const float* __restrict__ grad_vol,
@@ -235,40 +338,88 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_kernel(GeoScalars s, in
         const float pw2 = g.PW[2];
         float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
         const float4* img = proj4 + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
-        if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
+        if (c.exact) {
+            // no usable anchor: vd_grad_exact_kernel adds this column's sums
+        } else if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
             grad_column<MODE, K, true>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
         else
             grad_column<MODE, K, false>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
-        // Channel-halving butterfly over the wavefront: at the xor-32 and
-        // xor-16 steps each lane keeps half of the channels and receives the
-        // partner's sums of them, so the 12 channels take 6 + 3 + 4 x 3 = 21
-        // cross-lane exchanges instead of 72.  Lane 16 q (q = 0..3) ends with
-        // channels 3 q .. 3 q + 2 of the whole wavefront; each wavefront
-        // writes its own partials (no block barrier, fixed summation order).
         const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
                                       pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
-        const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
-        float s6[6], s3[3];
-#pragma unroll
-        for (int t = 0; t < 6; ++t) {
-            const float keep = h32 ? r[6 + t] : r[t], give = h32 ? r[t] : r[6 + t];
-            s6[t] = keep + __shfl_xor(give, 32);
+        wave_partials<false>(r, lane, partials + ((size_t)v * nwv + wv) * kVdChannels);
+    }
+}
+
+// Columns with no usable FP64 anchor (every voxel within 1 mm of the source
+// plane, or an anchor projecting beyond 65536 pixels; only with the source
+// inside or next to the volume), which vd_grad_kernel leaves out: their
+// voxels are projected one by one in FP64 and their sums added to the same
+// per-wavefront partials.  A conservative FP32 test of the column ends skips
+// every other column: if the depth keeps its sign and exceeds 2 mm at both
+// ends, it exceeds 1 mm along the whole column, so the middle voxel is the
+// anchor, and its projection lies between those of the ends (the projective
+// map has no pole in between), so it is within 65536 pixels when both ends
+// are within 60000.
+template <int MODE, int K>
+__global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(GeoScalars s, int V,
+                                                                      const ViewGeo* __restrict__ views,
+                                                                      const float4* __restrict__ proj4,
+                                                                      const float* __restrict__ grad_vol,
+                                                                      float* __restrict__ partials)
+{
+    const int i = blockIdx.x * kVdBx + threadIdx.x;
+    const int j = blockIdx.y * kVdBy + threadIdx.y;
+    const int kb = blockIdx.z * K;
+    const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int wv = blk * kVdBy + (int)threadIdx.y;
+    const int nwv = gridDim.x * gridDim.y * gridDim.z * kVdBy;
+    const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
+    const float escale = MODE == DP_W_FDK ? (float)(s.sad * s.sad) : 1.0f;
+    const float kappa = MODE == DP_W_FDK ? 2.0f : 0.0f;
+    const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
+    const float pk0 = (float)kb - 0.5f * (s.nz - 1);
+    const int lane = threadIdx.x;
+    const float fi = (float)i, fj = (float)j, flo = (float)kb, fhi = (float)(kb + K - 1);
+    for (int v = 0; v < V; ++v) {
+        const ViewGeo& g = views[v];
+        const float wij = fmaf(g.PW[0], fi, fmaf(g.PW[1], fj, g.PW[3]));
+        const float uij = fmaf(g.PU[0], fi, fmaf(g.PU[1], fj, g.PU[3]));
+        const float vij = fmaf(g.PV[0], fi, fmaf(g.PV[1], fj, g.PV[3]));
+        const float wlo = fmaf(g.PW[2], flo, wij), whi = fmaf(g.PW[2], fhi, wij);
+        const float ulo = fmaf(g.PU[2], flo, uij), uhi = fmaf(g.PU[2], fhi, uij);
+        const float vlo = fmaf(g.PV[2], flo, vij), vhi = fmaf(g.PV[2], fhi, vij);
+        const bool safe = (wlo > 2.0f && whi > 2.0f) || (wlo < -2.0f && whi < -2.0f);
+        const float lim_lo = 60000.0f * fabsf(wlo), lim_hi = 60000.0f * fabsf(whi);
+        const bool cand = !(safe && fabsf(ulo) < lim_lo && fabsf(uhi) < lim_hi &&
+                            fabsf(vlo) < lim_lo && fabsf(vhi) < lim_hi);
+        if (__ballot(cand) == 0) continue;  // wave-uniform: no column of this wavefront
+        float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
+        if (cand && column_anchor(g, s, i, j, kb, K).exact) {
+            const float4* view = proj4 + (long long)v * NU * NV;
+            double U, V, W;
+            exact_rows(g, i, j, kb, U, V, W);
+            for (int kk = 0; kk < K; ++kk, U += g.PUd[2], V += g.PVd[2], W += g.PWd[2]) {
+                const bool in = i < s.nx && j < s.ny && kb + kk < s.nz;
+                const float ek = in ? escale * grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
+                const ExactVoxel x = exact_voxel(s, U, V, W);
+                const int ia = floor_to_int(x.A), ib = floor_to_int(x.B);
+                const float wa = __builtin_amdgcn_fractf(x.A), wb = __builtin_amdgcn_fractf(x.B);
+                const float4* p = view + (ib * NU + ia);
+                const float4 p00 = p[0], p10 = p[1], p01 = p[NU], p11 = p[NU + 1];
+                const float l = lerp_f(lerp_f(p00.x, p10.x, wa), lerp_f(p01.x, p11.x, wa), wb);
+                const float la = lerp_f(lerp_f(p00.y, p10.y, wa), lerp_f(p01.y, p11.y, wa), wb);
+                const float lb = lerp_f(lerp_f(p00.z, p10.z, wa), lerp_f(p01.z, p11.z, wa), wb);
+                const float ec = MODE == DP_W_FDK ? ek * (x.iw * x.iw) * x.iw : ek * x.iw;
+                const float c1 = ec * la, c2 = ec * lb;
+                const float c3 = -ec * fmaf(la, x.ap, fmaf(lb, x.bp, kappa * l));
+                const float pk = pk0 + (float)kk;
+                A1 += c1; A2 += c2; A3 += c3;
+                Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
+            }
         }
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const float keep = h16 ? s6[3 + t] : s6[t], give = h16 ? s6[t] : s6[3 + t];
-            s3[t] = keep + __shfl_xor(give, 16);
-        }
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1)
-#pragma unroll
-            for (int t = 0; t < 3; ++t) s3[t] += __shfl_xor(s3[t], off);
-        if ((lane & 15) == 0) {
-            float* out = partials + ((size_t)v * nwv + wv) * kVdChannels + (lane >> 4) * 3;
-            out[0] = s3[0];
-            out[1] = s3[1];
-            out[2] = s3[2];
-        }
+        const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
+                                      pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
+        wave_partials<true>(r, lane, partials + ((size_t)v * nwv + wv) * kVdChannels);
     }
 }
 
@@ -300,6 +451,7 @@ static void vd_grad_dispatch(const GeoScalars& s, int V, const ViewGeo* views, c
     dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy,
               (s.nz + kVdGradCol - 1) / kVdGradCol);
     vd_grad_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol, partials);
+    vd_grad_exact_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol, partials);
 }
 
 void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,

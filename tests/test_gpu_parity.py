@@ -199,6 +199,19 @@ def test_backproject_volume_larger_than_field_of_view(dp, oracle, mode):
     _bp_case(dp, oracle, g, proj, angles, poses, mode, name=f"bp-fov-{mode}")
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backproject_source_inside_volume(dp, oracle, mode):
+    """Source inside the volume: voxels at or behind it get no ray, and voxel
+    columns cross the source plane (both kernel paths of a column)."""
+    rng = synth.rng_for(205)
+    g = Geom(24, 24, 24, 2.0, 2.0, 2.0, 40, 36, 2.0, 2.0, sad=20.0, sdd=40.0)
+    V = 3
+    angles = rng.uniform(0, 2 * math.pi, V)
+    poses = synth.random_poses(V, 2.0, 3.0, rng)
+    proj = synth.smooth_images(V, g.nv, g.nu, rng, signed=True)
+    _bp_case(dp, oracle, g, proj, angles, poses, mode, name=f"bp-source-inside-{mode}")
+
+
 def test_backproject_tiny(dp, oracle):
     g = Geom(1, 1, 1, 1.0, 1.0, 1.0, 2, 1, 1.0, 1.0)
     proj = np.array([[[0.5, 1.5]]], np.float32)
