@@ -200,16 +200,19 @@ def test_backproject_volume_larger_than_field_of_view(dp, oracle, mode):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-def test_backproject_source_inside_volume(dp, oracle, mode):
-    """Source inside the volume: voxels at or behind it get no ray, and voxel
-    columns cross the source plane (both kernel paths of a column)."""
+@pytest.mark.parametrize("tilt_deg", [3.0, 40.0])
+def test_backproject_source_inside_volume(dp, oracle, mode, tilt_deg):
+    """Source inside the volume: voxels at or behind it get no ray.  With small
+    rotations whole voxel columns lie within 1 mm of the source plane (no
+    usable anchor); with large ones columns cross that plane (voxels on both
+    sides of the source in one column)."""
     rng = synth.rng_for(205)
     g = Geom(24, 24, 24, 2.0, 2.0, 2.0, 40, 36, 2.0, 2.0, sad=20.0, sdd=40.0)
     V = 3
     angles = rng.uniform(0, 2 * math.pi, V)
-    poses = synth.random_poses(V, 2.0, 3.0, rng)
+    poses = synth.random_poses(V, 2.0, tilt_deg, rng)
     proj = synth.smooth_images(V, g.nv, g.nu, rng, signed=True)
-    _bp_case(dp, oracle, g, proj, angles, poses, mode, name=f"bp-source-inside-{mode}")
+    _bp_case(dp, oracle, g, proj, angles, poses, mode, name=f"bp-source-inside-{mode}-tilt{tilt_deg:g}")
 
 
 def test_backproject_tiny(dp, oracle):
