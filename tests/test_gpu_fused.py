@@ -72,6 +72,19 @@ def test_fused_edges_and_misses(dp, oracle):
     assert torch.all(l[2] == 0) and torch.all(gp[2] == 0)
 
 
+def test_fused_source_inside_volume(dp, oracle):
+    """Single-pass SSD with the source inside the volume (rays start inside)."""
+    rng = synth.rng_for(207)
+    g = Geom(24, 24, 24, 2.0, 2.0, 2.0, 40, 36, 2.0, 2.0, sad=20.0, sdd=40.0)
+    vol = rng.uniform(0, 0.05, g.vol_shape).astype(np.float32)
+    V = 3
+    angles = rng.uniform(0, 2 * math.pi, V)
+    poses = synth.random_poses(V, 2.0, 20.0, rng)
+    y = oracle.project_fwd(g, np.zeros(1), np.zeros((1, 6)), vol).astype(np.float32)
+    y = np.repeat(y, V, axis=0)
+    _fused_case(dp, oracle, g, vol, angles, poses, y, "source-inside")
+
+
 def test_fused_tiny(dp, oracle):
     g = Geom(1, 1, 1, 3.0, 3.0, 3.0, 1, 1, 2.0, 2.0)
     vol = np.array([[[0.7]]], np.float32)

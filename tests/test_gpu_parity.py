@@ -99,6 +99,18 @@ def test_ragged_anisotropic_multiview(dp, oracle):
     _fwd_case(dp, oracle, g, vol, angles, poses, name="ragged")
 
 
+def test_forward_source_inside_volume(dp, oracle):
+    """Source inside the volume: every ray starts inside it (the march begins
+    at the source) and the chunk boxes start at the source."""
+    rng = synth.rng_for(206)
+    g = Geom(24, 24, 24, 2.0, 2.0, 2.0, 40, 36, 2.0, 2.0, sad=20.0, sdd=40.0)
+    vol = rng.uniform(0, 0.05, g.vol_shape).astype(np.float32)
+    V = 3
+    angles = rng.uniform(0, 2 * math.pi, V)
+    poses = synth.random_poses(V, 2.0, 20.0, rng)
+    _fwd_case(dp, oracle, g, vol, angles, poses, name="source-inside")
+
+
 def test_edges_boundary_content_and_large_rotations(dp, oracle):
     """Content on the volume faces (zero-extension and gradient masking),
     quarter-turn and large rotations, rays grazing the volume."""
