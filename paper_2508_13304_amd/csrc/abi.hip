@@ -101,7 +101,8 @@ Layout layout(const dp_geom& g, int V, int op)
         off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float4));
         L.n_part = (size_t)vd_blocks(s, kVdGradCol) * kVdBy;  // one partial set per wavefront
         L.partials = off;
-        off = align_up(off + (size_t)V * L.n_part * kVdChannels * sizeof(float));
+        // partials, then one int per view: "a column of this view has no usable anchor"
+        off = align_up(off + (size_t)V * L.n_part * kVdChannels * sizeof(float) + (size_t)V * sizeof(int));
         break;
     default:
         break;

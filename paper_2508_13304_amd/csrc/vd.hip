@@ -308,7 +308,8 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(4
                                                                 const ViewGeo* __restrict__ views,
                                                                 const float4* __restrict__ proj4,
                                                                 const float* __restrict__ grad_vol,
-                                                                float* __restrict__ partials)
+                                                                float* __restrict__ partials,
+                                                                int* __restrict__ exact_views)
 {
     const int i = blockIdx.x * kVdBx + threadIdx.x;
     const int j = blockIdx.y * kVdBy + threadIdx.y;
@@ -340,6 +341,7 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(4
         const float4* img = proj4 + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
         if (c.exact) {
             // no usable anchor: vd_grad_exact_kernel adds this column's sums
+            exact_views[v] = 1;
         } else if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
             grad_column<MODE, K, true>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
         else
@@ -352,10 +354,11 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(4
 
 // Columns with no usable FP64 anchor (every voxel within 1 mm of the source
 // plane, or an anchor projecting beyond 65536 pixels; only with the source
-// inside or next to the volume), which vd_grad_kernel leaves out: their
-// voxels are projected one by one in FP64 and their sums added to the same
-// per-wavefront partials.  A conservative FP32 test of the column ends skips
-// every other column: if the depth keeps its sign and exceeds 2 mm at both
+// inside or next to the volume), which vd_grad_kernel leaves out and flags
+// per view: their voxels are projected one by one in FP64 and their sums
+// added to the same per-wavefront partials.  Views without a flag are
+// skipped; in the others a conservative FP32 test of the column ends skips
+// every column that cannot be such a column: if the depth keeps its sign and exceeds 2 mm at both
 // ends, it exceeds 1 mm along the whole column, so the middle voxel is the
 // anchor, and its projection lies between those of the ends (the projective
 // map has no pole in between), so it is within 65536 pixels when both ends
@@ -365,7 +368,8 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(GeoScalars
                                                                       const ViewGeo* __restrict__ views,
                                                                       const float4* __restrict__ proj4,
                                                                       const float* __restrict__ grad_vol,
-                                                                      float* __restrict__ partials)
+                                                                      float* __restrict__ partials,
+                                                                      const int* __restrict__ exact_views)
 {
     const int i = blockIdx.x * kVdBx + threadIdx.x;
     const int j = blockIdx.y * kVdBy + threadIdx.y;
@@ -381,6 +385,7 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(GeoScalars
     const int lane = threadIdx.x;
     const float fi = (float)i, fj = (float)j, flo = (float)kb, fhi = (float)(kb + K - 1);
     for (int v = 0; v < V; ++v) {
+        if (exact_views[v] == 0) continue;  // no column of this view was left out
         const ViewGeo& g = views[v];
         const float wij = fmaf(g.PW[0], fi, fmaf(g.PW[1], fj, g.PW[3]));
         const float uij = fmaf(g.PU[0], fi, fmaf(g.PU[1], fj, g.PU[3]));
@@ -443,6 +448,12 @@ void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float4
     prof_end(DP_K_VD_BP, st);
 }
 
+__global__ __launch_bounds__(256) void fill_zero_i32_kernel(int* __restrict__ p, int n)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
 template <int MODE>
 static void vd_grad_dispatch(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
                              const float* grad_vol, float* partials, hipStream_t st)
@@ -450,8 +461,13 @@ static void vd_grad_dispatch(const GeoScalars& s, int V, const ViewGeo* views, c
     dim3 block(kVdBx, kVdBy);
     dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy,
               (s.nz + kVdGradCol - 1) / kVdGradCol);
-    vd_grad_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol, partials);
-    vd_grad_exact_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol, partials);
+    // the per-view flags follow the partials (one set of kVdChannels per wavefront and view)
+    int* exact_views = reinterpret_cast<int*>(partials + (size_t)V * grid.x * grid.y * grid.z * kVdBy * kVdChannels);
+    fill_zero_i32_kernel<<<(V + 255) / 256, 256, 0, st>>>(exact_views, V);
+    vd_grad_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol, partials,
+                                                             exact_views);
+    vd_grad_exact_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol,
+                                                                   partials, exact_views);
 }
 
 void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
