@@ -36,14 +36,18 @@ CASES = {
     # footprint, and voxels just in front of it have footprints far wider
     # than the detector
     "source-inside": (Geom(24, 24, 24, 2.0, 2.0, 2.0, 40, 36, 2.0, 2.0, sad=20.0, sdd=40.0), 3),
+    # the same with large rotations: voxel columns cross the source plane
+    "source-inside-tilted": (Geom(24, 24, 24, 2.0, 2.0, 2.0, 40, 36, 2.0, 2.0, sad=20.0, sdd=40.0), 3),
 }
+TILT_DEG = {"source-inside-tilted": 40.0}
 
 
 @pytest.mark.parametrize("kind", ["sf", "dd"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_footprint_pair_and_gradients_match_oracle(dp, oracle, name, kind):
     g, V = CASES[name]
-    rng, vol, angles, poses = _case(700 + len(name), g, V, smooth=name != "tiny")
+    rng, vol, angles, poses = _case(700 + len(name), g, V, r_deg=TILT_DEG.get(name, 8.0),
+                                    smooth=name != "tiny")
     say(f"{kind} case {name}: vol {vol.shape} det {g.nv}x{g.nu} V={V}")
     a, p = f64(angles), f64(poses)
     l = dp.fp_project(g, a, p, f32(vol), kind).cpu().numpy()
