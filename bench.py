@@ -45,8 +45,12 @@ GATHER_BYTES_PER_SAMPLE = 128
 # bytes one voxel-view update gathers: 4 bilinear taps of l (back-projection), of
 # (l, dl/da, dl/db) (its pose gradient)
 VD_GATHER_BYTES_PER_UPDATE = {"vd_bp": 16, "vd_grad": 48}
-# wave64 VALU issue on a 4-cycle model: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
+# Algorithmic FP32 operations per voxel-view update (FMA counted as 2):
+#   vd_bp  : depth 2, reciprocal 1, two pixel coordinates 3 + 3, bilinear 3 lerps x 3,
+#            FDK weight 3                                                     = 21
+#   vd_grad: depth 2, reciprocal 1, pixel offsets 4, centre offsets 2, coordinates 2,
+#            3 bilinears x 9, e W / w' 3, c1 c2 c3 8, moment position 1, A and Z sums 9 = 59
+VD_FLOPS_PER_UPDATE = {"vd_bp": 21, "vd_grad": 59}
 
 
 def log(*a):
@@ -186,6 +190,19 @@ def run_forward(args, dp, torch):
 
     ms2, per2 = measure(step_two_calls, max(2, args.steps // 2), 1)
     log(f"[bench] two-call step {ms2:.3f} ms; per-kernel avg ms: {per2}")
+
+    # the same step through the autograd Function: ProjectFwd.apply, the SSD
+    # in torch, loss.backward() (the pose gradient kernel as the backward)
+    from paper_2508_13304_amd.autograd import ProjectFwd
+
+    def step_autograd():
+        p = poses.detach().clone().requires_grad_(True)
+        l = ProjectFwd.apply(p, vol, g, angles, ws)
+        loss_ag = ((l - y) ** 2).sum()
+        loss_ag.backward()
+
+    ms_ag, per_ag = measure(step_autograd, max(2, args.steps // 2), 1)
+    log(f"[bench] autograd step {ms_ag:.3f} ms; per-kernel avg ms: {per_ag}")
     ms_step, per_kernel = measure(step, args.steps, args.warmup)
     log(f"[bench] fused step {ms_step:.3f} ms/step; per-kernel avg ms: {per_kernel}")
     dominant = "rd_fused"
@@ -208,7 +225,8 @@ def run_forward(args, dp, torch):
                 "kernel": dominant, "kernel_ms": dom_ms, "flops_per_sample": flops,
                 "source_hash": src_hash, "other": other}
     return dict(geom=g, V=V, n_samples=n_samples, ms_step=ms_step, per_kernel=per_kernel,
-                two_call_ms=ms2, two_call_kernels=per2, roofline=roofline, inputs=c)
+                two_call_ms=ms2, two_call_kernels=per2, autograd_ms=ms_ag,
+                autograd_kernels=per_ag, roofline=roofline, inputs=c)
 
 
 def run_cache_probe(dp, torch, quick=False):
@@ -249,18 +267,39 @@ def run_cache_probe(dp, torch, quick=False):
         ms = timed(buf, 1, False, blocks)
         hbm[f"2GiB_x{blocks}blocks"] = round(buf.numel() * 4 / (ms * 1e-3) / 1e9, 1)
     del buf
+    # LDS: every block reads 16-byte vectors from 32 KiB of LDS, conflict-free
+    lds = {}
+    for blocks in ((2048,) if quick else (1024, 2048, 4096)):
+        reps = 1024
+        out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+        dp.lds_probe(reps, blocks, out=out, stream=stream)
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dp.lds_probe(reps, blocks, out=out, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[2]
+        lds[f"x{blocks}blocks"] = round(blocks * 256 * reps * 128 / (ms * 1e-3) / 1e9, 1)
     res = {"l2_read_GBps": max(l2.values()), "hbm_read_GBps": max(hbm.values()),
-           "l2_sweep": l2, "hbm_sweep": hbm}
-    log(f"[bench] read probe: L2 {res['l2_read_GBps']:.0f} GB/s, HBM {res['hbm_read_GBps']:.0f} GB/s")
+           "lds_read_GBps": max(lds.values()),
+           "l2_sweep": l2, "hbm_sweep": hbm, "lds_sweep": lds}
+    log(f"[bench] read probe: LDS {res['lds_read_GBps']:.0f} GB/s, L2 {res['l2_read_GBps']:.0f} GB/s, "
+        f"HBM {res['hbm_read_GBps']:.0f} GB/s")
     return res
 
 
 def gather_roofline(fw, probe):
-    """Gather roofline: the measured L2 read bandwidth over the 128
-    bytes a forward + gradient sample gathers (8 trilinear corners x 4
-    channels x 4 B), with the dominant kernel's measured L2 and HBM traffic
-    (rocprofv3 counters, valid while the kernel source is unchanged)."""
-    ceiling = probe["l2_read_GBps"] * 1e9 / GATHER_BYTES_PER_SAMPLE
+    """Gather roofline of the ray kernels: every trilinear tap of a forward +
+    gradient sample comes from LDS (8 corners x (mu, Gx, Gy, Gz) x 4 B = 128
+    B per sample), so the ceiling is the measured LDS read bandwidth over 128
+    B.  The L2 and HBM traffic of the dominant kernel (rocprofv3 counters,
+    valid while its source is unchanged) is what the chunk-box staging moves
+    into LDS; it is reported beside, against the measured L2 and HBM read
+    bandwidths."""
+    ceiling = probe["lds_read_GBps"] * 1e9 / GATHER_BYTES_PER_SAMPLE
     rf = fw["roofline"]
     k_ms = rf["kernel_ms"]
     step_rate = fw["n_samples"] / (fw["ms_step"] * 1e-3)
@@ -268,13 +307,15 @@ def gather_roofline(fw, probe):
     l2_bytes = _traffic(rf["kernel"] + "_registration_scale", rf["source_hash"], "l2_bytes_per_launch")
     hbm_bytes = rf["traffic"]
     out = {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE,
+           "ceiling": "lds",
+           "lds_read_GBps_measured": probe["lds_read_GBps"],
            "l2_read_GBps_measured": probe["l2_read_GBps"],
            "hbm_read_GBps_measured": probe["hbm_read_GBps"],
            "ceiling_samples_per_s": ceiling,
            "step_frac": round(step_rate / ceiling, 4),
            "kernel_frac": round(kern_rate / ceiling, 4),
            "kernel": rf["kernel"],
-           "lds_bytes_per_sample": GATHER_BYTES_PER_SAMPLE,
+           "lds_GBps": round(kern_rate * GATHER_BYTES_PER_SAMPLE / 1e9, 1),
            "l2_bytes_per_launch": l2_bytes,
            "l2_GBps": round(l2_bytes / (k_ms * 1e-3) / 1e9, 1) if l2_bytes else None,
            "l2_frac": round(l2_bytes / (k_ms * 1e-3) / 1e9 / probe["l2_read_GBps"], 4) if l2_bytes else None,
@@ -289,11 +330,13 @@ def gather_roofline(fw, probe):
 
 
 def vd_rooflines(bp, probe):
-    """Both ceilings of each back-projector kernel: the gather ceiling (the
-    measured L2 read bandwidth over the bytes an update gathers) and the VALU
-    ceiling (4-cycle wave64 issue over the VALU lane instructions per update,
-    counted by SQ_INSTS_VALU; read from profiles/traffic.json while the kernel
-    source is unchanged).  Each kernel is graded against the lower one."""
+    """Both ceilings of each back-projector kernel: the FP32 arithmetic
+    ceiling (published FP32 vector peak over the algorithmic operations per
+    update) and the gather ceiling (the measured L2 read bandwidth over the
+    bytes an update gathers: its taps come through the cache hierarchy).
+    Each kernel is graded against the lower ceiling; the texture-addresser
+    busy fraction (rocprofv3, while the kernel source is unchanged) is
+    reported beside."""
     h = _kernel_hash("vd.hip", "dp_internal.h")
     out = {}
     for k, nbytes in VD_GATHER_BYTES_PER_UPDATE.items():
@@ -302,15 +345,14 @@ def vd_rooflines(bp, probe):
             continue
         rate = bp["voxel_view_updates"] / (ms * 1e-3)
         gather = probe["l2_read_GBps"] * 1e9 / nbytes
-        ipu = _traffic(k + "_reconstruction_scale", h, "valu_lane_instr_per_update")
-        valu = VALU_LANE_INSTR_PER_S / ipu if ipu else None
-        bound = "valu" if valu is not None and valu < gather else "gather"
-        ceiling = min(gather, valu) if valu is not None else gather
+        flops = VD_FLOPS_PER_UPDATE[k]
+        alu = VALU_PEAK_TFLOPS * 1e12 / flops
+        bound = "alu" if alu < gather else "gather"
+        ceiling = min(gather, alu)
         out[k] = {"updates_per_s": rate, "gather_bytes_per_update": nbytes,
                   "gather_ceiling_updates_per_s": gather, "gather_frac": round(rate / gather, 4),
-                  "valu_lane_instr_per_update": ipu,
-                  "valu_ceiling_updates_per_s": valu,
-                  "valu_frac": round(rate / valu, 4) if valu else None,
+                  "flops_per_update": flops, "tflops": round(rate * flops / 1e12, 2),
+                  "alu_ceiling_updates_per_s": alu, "alu_frac": round(rate / alu, 4),
                   "graded_against": bound, "frac": round(rate / ceiling, 4),
                   "valu_busy": _traffic(k + "_reconstruction_scale", h, "valu_busy"),
                   "ta_busy": _traffic(k + "_reconstruction_scale", h, "ta_busy"),
@@ -358,15 +400,38 @@ def run_backproject(args, dp, torch):
     kern = dp.profile_collect()
     dp.profile_enable(False)
     upd = float(g.nx) * g.ny * g.nz * V
-    per_kernel = {k: round(v[0] / v[1], 4) for k, v in kern.items()}
+    # per call (the views are processed in chunks: several launches per call)
+    per_kernel = {k: round(v[0] / reps, 4) for k, v in kern.items()}
+    launches = {k: v[1] // reps for k, v in kern.items()}
     log(f"[bench] BP {t_bp * 1e3:.2f} ms, BP-grad {t_bpg * 1e3:.2f} ms; kernels {per_kernel}")
+    # The config's chain as written: the FDK pre-filter of the projections,
+    # then per motion-compensation iteration the FDK back-projection, the
+    # gradient-entropy loss and its gradient on the 512^3 volume, the
+    # back-projection pose gradient and an Adam step on the 360 x 6 poses.
+    from paper_2508_13304_amd import moco
+    del vol, e
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q = moco.prefilter(g, proj)
+    torch.cuda.synchronize()
+    t_filter = time.perf_counter() - t0
+    moco.estimate_motion(g, angles, q, iters=1)  # warm-up
+    n_it = 3
+    r = moco.estimate_motion(g, angles, q, iters=n_it)
+    t_iter = r.seconds / n_it
+    log(f"[bench] motion compensation: pre-filter {t_filter * 1e3:.2f} ms, "
+        f"{t_iter * 1e3:.2f} ms per iteration")
     return {"workload": "512^3 recon at 0.375 mm, 360 views 512x384 at 0.776 mm, FDK weight, "
                         "sinusoidal motion 3 mm / 2 deg",
             "voxel_view_updates": upd,
             "backproject_updates_per_s": upd / t_bp,
             "backproject_grad_updates_per_s": upd / t_bpg,
             "backproject_ms": round(t_bp * 1e3, 3), "backproject_grad_ms": round(t_bpg * 1e3, 3),
-            "kernels_ms": per_kernel}
+            "kernels_ms": per_kernel, "launches_per_call": launches,
+            "moco_chain": {"prefilter_ms": round(t_filter * 1e3, 3),
+                           "iteration_ms": round(t_iter * 1e3, 3),
+                           "iteration": "FDK back-projection + gradient-entropy loss and gradient "
+                                        "+ back-projection pose gradient + Adam step (360 x 6)"}}
 
 
 def run_registration(args, dp, torch, fw):
@@ -421,6 +486,56 @@ def run_registration(args, dp, torch, fw):
     record("bfgs_autotuned", reg.register_bfgs(g, vol, angles, targets, init))
     record("adam", reg.register(g, vol, angles, targets, init, iters=300, lr_t=3.0, lr_r_deg=2.0,
                                 decay=0.99))
+    return out
+
+
+def run_registration_paper(args, dp, torch, fw):
+    """Registration under the paper's imaging conditions (Sec. III-B): the
+    registration-scale workload (64 single-view registrations, truth offsets
+    +-10 mm / +-10 deg, start at the identity) with targets carrying Poisson
+    noise of a transmission measurement at 1e5 photons per pixel.  Drivers:
+    Levenberg-Marquardt on the SSD of the noisy line integrals, Adam on NCC
+    with the paper's stopping rule (loss change < 1e-5 or NCC > 0.999; NCC <
+    0.99 at the end is the paper's failure), and BFGS on NCC.  Reported per
+    driver: success at 0.1 mm / 0.1 deg (and at 0.5 / 1 mm and deg for
+    context), registrations/s and the mean absolute error per pose parameter."""
+    from paper_2508_13304_amd import proposal as pr
+    from paper_2508_13304_amd import registration as reg
+    dev = torch.device("cuda:0")
+    c = fw["inputs"]
+    g = c["geom"]
+    T = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)  # noqa: E731
+    vol = T(c["vol"], torch.float32)
+    truth = T(c["poses"], torch.float64)
+    angles = T(c["angles"], torch.float64)
+    B = truth.shape[0]
+    photons = 1e5
+    gen = torch.Generator(device=dev).manual_seed(13304)
+    targets = synth.poisson_log_noise(dp.project_fwd(g, angles, truth, vol), photons, gen)
+    init = torch.zeros_like(truth)
+    out = {"workload": f"{B} single-view registrations, 256^3 phantom at 0.8 mm, 512x512 at 0.6 mm, "
+                       "truth offsets +-10 mm/+-10 deg, start at identity, targets with Poisson noise "
+                       f"at {photons:.0e} photons per pixel", "photons": photons}
+
+    def record(name, res):
+        row = {"registrations_per_s": round(B / res.seconds, 3), "seconds": round(res.seconds, 3),
+               "mean_iterations": float(res.iterations.double().mean()),
+               "mae_tx_ty_tz_mm_gx_gy_gz_deg": pr.pose_mae(res.poses, truth)}
+        for t in (0.1, 0.5, 1.0):
+            ok = reg.success(res.poses, truth, t, t)
+            row[f"success_{t:g}"] = int(ok.sum()) / B
+        row["successful_per_s"] = round(row["success_0.1"] * B / res.seconds, 3)
+        if res.failed is not None:
+            row["paper_success_ncc_0.99"] = 1.0 - float(res.failed.double().mean())
+        out[name] = row
+        log(f"[bench] noisy registration {name}: {row}")
+
+    reg.register_lm(g, vol, angles[:4], targets[:4], init[:4], iters=3)  # warm-up
+    record("lm_ssd", reg.register_lm(g, vol, angles, targets, init))
+    record("adam_ncc_paper_stop", reg.register(g, vol, angles, targets, init, loss="ncc",
+                                               stop="paper", iters=300, lr_t=3.0, lr_r_deg=2.0,
+                                               decay=0.99))
+    record("bfgs_ncc", reg.register_bfgs(g, vol, angles, targets, init, loss="ncc"))
     return out
 
 
@@ -545,6 +660,9 @@ def run_learned(args, dp, torch):
     res = pr.evaluate(net, synth.geom_c5(), n_phantoms=4, per_phantom=16, log=log)
     res["workload"] = ("4 unseen 192^3 phantoms at 1 mm x 16 offsets (+-30 mm/+-20 deg), one 256x256 "
                        "view at 1.2 mm, SSD loss; both refined by Levenberg-Marquardt; plain = from identity")
+    noisy = pr.evaluate(net, synth.geom_c5(), n_phantoms=4, per_phantom=16, log=log, photons=1e5)
+    noisy["workload"] = res["workload"] + "; targets with Poisson noise at 1e5 photons per pixel"
+    res["noisy"] = noisy
     return res
 
 
@@ -564,7 +682,9 @@ def run_paper_ladder(args, dp, torch):
     384/(192n) mm.  Forward: one view, time of 100 iterations of projection +
     pose gradient (RD: the single-pass SSD kernel; SF, DD: projection then
     gradient).  Back-projection: 256 views over 360 deg, one back-projection
-    + pose gradient.  Peak device memory per case."""
+    + pose gradient.  Peak device memory per case and projector type (GB,
+    torch's allocator peak over the projector's own step: inputs, outputs and
+    the library workspace)."""
     dev = torch.device("cuda:0")
     out = {"fwd": {}, "bp": {}, "paper_fwd_s": PAPER_FWD_S, "paper_bp_s": PAPER_BP_S,
            "note": "paper figures are RTX 4090 timings from its cost tables; context only"}
@@ -590,14 +710,28 @@ def run_paper_ladder(args, dp, torch):
         p1 = torch.tensor(synth.random_poses(1, 5.0, 5.0, rng), dtype=torch.float64, device=dev)
         y1 = dp.project_fwd(g, a1, torch.zeros_like(p1), vol)
         res = {}
-        torch.cuda.reset_peak_memory_stats(dev)
+        peak = {}
+
+        def reset():
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats(dev)
+
+        def peak_gb():
+            torch.cuda.synchronize()
+            return round(torch.cuda.max_memory_allocated(dev) / 1e9, 3)
+
+        reset()
         res["rd"] = timed(lambda: dp.project_fwd_ssd_grad_pose(g, a1, p1, vol, y1), 10) * 100
+        peak["rd"] = peak_gb()
         for kind in ("sf", "dd"):
             def step(kind=kind):
                 l = dp.fp_project(g, a1, p1, vol, kind)
                 dp.fp_project_grad_pose(g, a1, p1, vol, 2.0 * (l - y1), kind)
+            reset()
             res[kind] = timed(step, 3) * 100
-        res["peak_gb"] = round(torch.cuda.max_memory_allocated(dev) / 1e9, 3)
+            peak[kind] = peak_gb()
+        res["peak_gb"] = peak
         out["fwd"][key] = {k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()}
         # back-projection, 256 views
         V = 256
@@ -607,17 +741,21 @@ def run_paper_ladder(args, dp, torch):
         proj = torch.rand((V, nd, nd), device=dev, generator=gen)
         e = torch.randn(vol.shape, device=dev, generator=gen)
         res = {}
-        torch.cuda.reset_peak_memory_stats(dev)
+        peak = {}
         def vd_step():
             dp.backproject(g, ang, pos, proj, dp.W_NONE)
             dp.backproject_grad_pose(g, ang, pos, proj, e, dp.W_NONE)
+        reset()
         res["vd"] = timed(vd_step, 2)
+        peak["vd"] = peak_gb()
         for kind in ("sf", "dd"):
             def bstep(kind=kind):
                 dp.fp_backproject(g, ang, pos, proj, kind)
                 dp.fp_backproject_grad_pose(g, ang, pos, proj, e, kind)
+            reset()
             res[kind] = timed(bstep, 1)
-        res["peak_gb"] = round(torch.cuda.max_memory_allocated(dev) / 1e9, 3)
+            peak[kind] = peak_gb()
+        res["peak_gb"] = peak
         out["bp"][key] = {k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()}
         log(f"[bench] ladder {key}: fwd(100 it) {out['fwd'][key]} s; bp(256 views) {out['bp'][key]} s")
         del vol, proj, e
@@ -760,6 +898,7 @@ def main():
     probe = None if args.no_probe else run_cache_probe(dp, torch)
     bp = None if args.no_bp else run_backproject(args, dp, torch)
     regr = None if args.no_reg else run_registration(args, dp, torch, fw)
+    regr_noisy = None if args.no_reg else run_registration_paper(args, dp, torch, fw)
     learned = None if args.no_reg else run_learned(args, dp, torch)
     calib = None if args.no_batch else run_calibration_batch(args, dp, torch)
     ladder = None if args.no_ladder else run_paper_ladder(args, dp, torch)
@@ -798,8 +937,13 @@ def main():
         "two_call_step": {"ms_per_step": round(fw["two_call_ms"], 4),
                           "value": fw["n_samples"] / (fw["two_call_ms"] * 1e-3),
                           "kernels_ms": fw["two_call_kernels"]},
+        "autograd_step": {"ms_per_step": round(fw["autograd_ms"], 4),
+                          "value": fw["n_samples"] / (fw["autograd_ms"] * 1e-3),
+                          "kernels_ms": fw["autograd_kernels"],
+                          "what": "ProjectFwd.apply + torch SSD + loss.backward() for the 64 poses"},
         "backprojector": dict(bp, rooflines=vd_rooflines(bp, probe)) if bp and probe else bp,
         "registration": regr,
+        "registration_noisy": regr_noisy,
         "learned_proposal": learned,
         "calibration_batch": calib,
         "projector_ladder": ladder,

@@ -135,7 +135,11 @@ int dp_project_fwd_ssd_gauss_newton(const dp_geom* g, int32_t n_views, const dou
 
 /* Voxel-driven back-projection (Eq. back), weight_mode DP_W_NONE | DP_W_FDK.
  *   proj [V][nv][nu] f32 (already filtered by the caller if FDK is meant),
- *   vol [nz][ny][nx] f32 (overwritten).  No angular scale is applied. */
+ *   vol [nz][ny][nx] f32 (overwritten; between chunks of views it holds the
+ *   unscaled partial sums, so it must not alias proj).  No angular scale is
+ *   applied.  Views are processed in chunks whose detector-image copies fit
+ *   a fixed budget of the workspace; the result does not depend on the
+ *   chunking (the per-voxel sums run in view order either way). */
 int dp_backproject(const dp_geom* g, int32_t n_views, const double* angles,
                    const double* poses, const float* proj, float* vol,
                    int32_t weight_mode, void* ws, size_t ws_bytes, void* stream);
@@ -147,6 +151,15 @@ int dp_backproject_grad_pose(const dp_geom* g, int32_t n_views, const double* an
                              const double* poses, const float* proj,
                              const float* grad_vol, double* grad_pose,
                              int32_t weight_mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Diagnostics of dp_backproject_grad_pose: byte offset, within its
+ * workspace (DP_OP_BP_GRAD, same geometry and view count), of int32
+ * flags[V].  After a call, flags[v] != 0 iff some voxel column of view v had
+ * no usable FP32 anchor (it lies within 1 mm of the source plane, or its
+ * middle voxel projects more than 2 max(nu, nv) + 64 pixels from the
+ * detector centre) and was projected voxel by voxel in FP64.  Returns
+ * (size_t)-1 for invalid arguments. */
+size_t dp_bp_grad_flags_offset(const dp_geom* g, int32_t n_views);
 
 /* ---------------------------------------------------------------------------
  * Uneven batches: many independent ray-driven problems (own volume,
@@ -372,6 +385,16 @@ int dp_gradient_entropy(int32_t nx, int32_t ny, int32_t nz, const float* vol, fl
 int dp_read_probe(const void* buf, int64_t n_vec, int32_t reps, int32_t shared, int32_t n_blocks,
                   float* out, void* stream);
 
+/* dp_lds_probe (measurement only): n_blocks blocks of 256 threads each fill
+ * 32 KiB of LDS with 2048 float4 (vector i = (i, 1, 2, 3)), then every
+ * thread reads `reps` * 8 float4 from it with 16-byte LDS loads (in step r,
+ * lane j reads vectors (64 r + 256 u + j) mod 2048, u = 0..7: conflict-free), and
+ * writes the sum of their components to out[256 b + j] (n_blocks * 256
+ * floats, device).  LDS bytes read = n_blocks * 256 * reps * 128, the ceiling
+ * of LDS-staged gathers.  Errors: DP_ERR_ARG for NULL out or non-positive
+ * sizes, DP_ERR_UNSUPPORTED beyond 2^20 blocks. */
+int dp_lds_probe(int32_t reps, int32_t n_blocks, float* out, void* stream);
+
 /* Thread-local description of the last non-zero return. */
 const char* dp_last_error(void);
 
@@ -386,7 +409,9 @@ int32_t dp_version(void);
  *   dp_profile_collect() waits for the recorded events and accumulates
  *   their durations per kernel;
  *   dp_profile_read(k, &ms, &n) returns the accumulated time and launch
- *   count of kernel k (DP_K_*) and resets them. */
+ *   count of kernel k (DP_K_*) and resets them.  DP_K_VOL_PREP keeps its
+ *   number but is no longer launched: the ray-driven kernels read the
+ *   caller's volume and form its gradient while staging it. */
 enum {
     DP_K_SETUP = 0, DP_K_VOL_PREP = 1, DP_K_RD_FWD = 2, DP_K_RD_GRAD = 3,
     DP_K_DET_PREP = 4, DP_K_VD_BP = 5, DP_K_VD_GRAD = 6, DP_K_FINALIZE = 7,

@@ -36,7 +36,8 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
            "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16",
-           "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update", "dp_read_probe")
+           "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update", "dp_read_probe",
+           "dp_bp_grad_flags_offset", "dp_lds_probe")
 MAX_BATCH = 16
 N_VARIANTS = 3
 
@@ -75,6 +76,8 @@ def load(path: str | None = None):
     g = C.POINTER(DPGeom)
     lib.dp_workspace_bytes.argtypes = [g, i32, i32]
     lib.dp_workspace_bytes.restype = sz
+    lib.dp_bp_grad_flags_offset.argtypes = [g, i32]
+    lib.dp_bp_grad_flags_offset.restype = sz
     lib.dp_project_fwd.argtypes = [g, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.dp_project_fwd_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dp_project_fwd_ssd_grad_pose.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -104,6 +107,8 @@ def load(path: str | None = None):
     lib.dp_lm_update.restype = C.c_int
     lib.dp_read_probe.argtypes = [vp, C.c_int64, i32, i32, i32, vp, vp]
     lib.dp_read_probe.restype = C.c_int
+    lib.dp_lds_probe.argtypes = [i32, i32, vp, vp]
+    lib.dp_lds_probe.restype = C.c_int
     lib.dp_autotune.argtypes = [i32, g, i32, vp, vp, vp, vp, vp, vp, sz, vp, i32,
                                 C.POINTER(i32), C.POINTER(C.c_float)]
     lib.dp_autotune.restype = C.c_int
@@ -302,6 +307,16 @@ def backproject(geom, angles, poses, proj, weight_mode=W_NONE, out=None, ws=None
     return out
 
 
+def bp_grad_flags(geom, n_views: int, ws):
+    """The per-view "projected voxel by voxel in FP64" flags [V] int32 that
+    the last backproject_grad_pose call left in its workspace `ws`."""
+    import torch
+    off = int(load().dp_bp_grad_flags_offset(C.byref(geom_struct(geom)), int(n_views)))
+    if off == C.c_size_t(-1).value:
+        raise ValueError("invalid geometry / view count")
+    return ws[off:off + 4 * n_views].view(torch.int32)
+
+
 def backproject_grad_pose(geom, angles, poses, proj, grad_vol, weight_mode=W_NONE, out=None,
                           ws=None, stream=None):
     """dL/dtheta [V][6] f64 given dL/dmu [nz][ny][nx] f32."""
@@ -439,6 +454,18 @@ def read_probe(buf, reps, shared, n_blocks, out=None, stream=None):
     _check(load().dp_read_probe(C.c_void_p(buf.data_ptr()), buf.numel() // 4, int(reps),
                                 1 if shared else 0, int(n_blocks), out_p, _stream(stream)),
            "dp_read_probe")
+    return out
+
+
+def lds_probe(reps, n_blocks, out=None, stream=None):
+    """LDS read probe (measurement only): n_blocks blocks of 256 threads each
+    read reps * 8 16-byte vectors per thread from 32 KiB of LDS.  Returns the
+    per-thread sums, float32 [n_blocks * 256]."""
+    import torch
+    if out is None:
+        out = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda:0")
+    out_p = _dev(out, torch.float32, "out", (n_blocks * 256,))
+    _check(load().dp_lds_probe(int(reps), int(n_blocks), out_p, _stream(stream)), "dp_lds_probe")
     return out
 
 

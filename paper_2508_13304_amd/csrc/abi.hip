@@ -32,11 +32,12 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t views = 0;     // offset of ViewGeo[V]
-    size_t buf = 0;       // offset of the padded volume / image copy
+    size_t buf = 0;       // offset of the detector image copy (back-projection ops)
     size_t partials = 0;  // offset of the per-block partial sums
     size_t n_part = 0;    // partial blocks per view
     size_t spare = 0;     // FWD_SSD: [V][6] f64 pose-gradient slot used by the autotuner
-    size_t inter = 0;     // FWD_GRAD, FWD_SSD: per-voxel float4 (mu, Gx, Gy, Gz)
+    size_t flags = 0;     // BP_GRAD: [V] int, "a column of this view has no usable anchor"
+    int chunk = 0;        // back-projection ops: views per detector-image chunk
     size_t total = 0;
 };
 
@@ -45,9 +46,22 @@ size_t padded_volume_elems(const dp_geom& g)
     return (size_t)(g.nx + 2 * kPadV) * (g.ny + 2 * kPadV) * (g.nz + 2 * kPadV);
 }
 
+size_t volume_elems(const dp_geom& g) { return (size_t)g.nx * g.ny * g.nz; }
+
+
 size_t padded_image_elems(const dp_geom& g)
 {
     return (size_t)(g.nu + 2 * kPadD) * (g.nv + 2 * kPadD);
+}
+
+// Views whose detector-image copies (bytes_per_px per padded pixel) fit the
+// chunk budget, at least one and at most min(V, vmax).
+int det_chunk(const dp_geom& g, int V, size_t bytes_per_px, int vmax)
+{
+    const size_t per_view = padded_image_elems(g) * bytes_per_px;
+    size_t c = kDetChunkBytes / std::max<size_t>(per_view, 1);
+    c = std::min(c, (size_t)std::min(V, vmax));
+    return (int)std::max<size_t>(c, 1);
 }
 
 Layout layout(const dp_geom& g, int V, int op)
@@ -59,21 +73,16 @@ Layout layout(const dp_geom& g, int V, int op)
     off = align_up(off + sizeof(ViewGeo) * (size_t)V);
     L.buf = off;
     switch (op) {
+    // The ray-driven kernels read the caller's volume directly and form the
+    // volume gradient while staging it: no volume-sized workspace.
     case DP_OP_FWD:
-        off = align_up(off + padded_volume_elems(g) * sizeof(float));
         break;
     case DP_OP_FWD_GRAD:
-        off = align_up(off + 3 * padded_volume_elems(g) * sizeof(float));
-        L.inter = off;
-        off = align_up(off + padded_volume_elems(g) * sizeof(float4));
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
         break;
     case DP_OP_FWD_SSD:
-        off = align_up(off + 4 * padded_volume_elems(g) * sizeof(float));
-        L.inter = off;
-        off = align_up(off + padded_volume_elems(g) * sizeof(float4));
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannelsGN * sizeof(float));
@@ -81,7 +90,8 @@ Layout layout(const dp_geom& g, int V, int op)
         off = align_up(off + (size_t)V * 6 * sizeof(double));
         break;
     case DP_OP_BP:
-        off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float4));
+        L.chunk = det_chunk(g, V, sizeof(float4), V);
+        off = align_up(off + (size_t)L.chunk * padded_image_elems(g) * sizeof(float4));
         break;
     case DP_OP_FP_FWD:
     case DP_OP_FP_BP:
@@ -92,17 +102,20 @@ Layout layout(const dp_geom& g, int V, int op)
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
         break;
     case DP_OP_FP_BP_GRAD:
-        off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float4));
+        L.chunk = det_chunk(g, V, sizeof(float4), V);
+        off = align_up(off + (size_t)L.chunk * padded_image_elems(g) * sizeof(float4));
         L.n_part = (size_t)sf_blocks(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kVdChannels * sizeof(float));
         break;
     case DP_OP_BP_GRAD:
-        off = align_up(off + (size_t)V * padded_image_elems(g) * sizeof(float4));
-        L.n_part = (size_t)vd_blocks(s, kVdGradCol) * kVdBy;  // one partial set per wavefront
+        L.chunk = det_chunk(g, V, sizeof(DetTap3), kVdMaxChunk);
+        off = align_up(off + (size_t)L.chunk * padded_image_elems(g) * sizeof(DetTap3));
+        L.n_part = (size_t)vd_grad_grid(s).blocks;  // one partial set per block
         L.partials = off;
         // partials, then one int per view: "a column of this view has no usable anchor"
-        off = align_up(off + (size_t)V * L.n_part * kVdChannels * sizeof(float) + (size_t)V * sizeof(int));
+        L.flags = off + (size_t)V * L.n_part * kVdChannels * sizeof(float);
+        off = align_up(L.flags + (size_t)V * sizeof(int));
         break;
     default:
         break;
@@ -131,8 +144,11 @@ int check_geom(const dp_geom* g, int32_t V)
     if (!finite_pos(g->step)) return fail(DP_ERR_ARG, "ray step must be finite and positive");
     if (V <= 0) return fail(DP_ERR_ARG, "n_views must be positive (got %d)", V);
     if (V > 65535) return fail(DP_ERR_UNSUPPORTED, "n_views above 65535 (got %d)", V);
-    if (padded_volume_elems(*g) >= (size_t)1 << 31 || g->ny + 2 * kPadV > 65535 ||
-        g->nz + 2 * kPadV > 65535)
+    // LDS box origins and extents are stored as 16-bit values per axis
+    // the ray-driven kernels address the volume with 32-bit byte offsets
+    if (padded_volume_elems(*g) >= (size_t)1 << 31 || volume_elems(*g) > (size_t)1 << 30 ||
+        g->nx + 2 * kPadV > 65535 ||
+        g->ny + 2 * kPadV > 65535 || g->nz + 2 * kPadV > 65535)
         return fail(DP_ERR_UNSUPPORTED, "volume too large for 32-bit voxel indexing");
     if (g->nu > 16384 || g->nv > 16384)
         return fail(DP_ERR_UNSUPPORTED, "detector larger than 16384 pixels per side");
@@ -250,6 +266,12 @@ size_t dp_workspace_bytes(const dp_geom* g, int32_t n_views, int32_t op)
     return layout(*g, n_views, op).total;
 }
 
+size_t dp_bp_grad_flags_offset(const dp_geom* g, int32_t n_views)
+{
+    if (check_geom(g, n_views) != DP_OK) return (size_t)-1;
+    return layout(*g, n_views, DP_OP_BP_GRAD).flags;
+}
+
 int dp_project_fwd(const dp_geom* g, int32_t V, const double* angles, const double* poses,
                    const float* vol, float* proj, void* ws, size_t ws_bytes, void* stream)
 {
@@ -262,11 +284,9 @@ int dp_project_fwd(const dp_geom* g, int32_t V, const double* angles, const doub
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
-    float* volp = (float*)(base + L.buf);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_vol_pad(s, vol, volp, st);
-    launch_rd_fwd(s, V, views, volp, proj, variant_for(DP_OP_FWD, *g, V), st);
+    launch_rd_fwd(s, V, views, vol, proj, variant_for(DP_OP_FWD, *g, V), st);
     return check_launch("dp_project_fwd");
 }
 
@@ -284,14 +304,10 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
-    float* vol3 = (float*)(base + L.buf);
     float* part = (float*)(base + L.partials);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    float4* inter = (float4*)(base + L.inter);
-    launch_vol_prep(s, vol, nullptr, vol3, inter, st);
-    launch_rd_grad(s, V, views, vol3, inter, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V),
-                   st);
+    launch_rd_grad(s, V, views, vol, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V), st);
     launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_project_fwd_grad_pose");
 }
@@ -311,13 +327,10 @@ static int fwd_ssd(const dp_geom* g, int32_t V, const double* angles, const doub
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
-    float* vol4 = (float*)(base + L.buf);  // planes: padded mu, Gx, Gy, Gz
     float* part = (float*)(base + L.partials);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    float4* inter = (float4*)(base + L.inter);
-    launch_vol_prep(s, vol, vol4, vol4 + padded_volume_elems(*g), inter, st);
-    launch_rd_fused(s, V, views, vol4, inter, target, proj, part, hess != nullptr,
+    launch_rd_fused(s, V, views, vol, target, proj, part, hess != nullptr,
                     variant_for(DP_OP_FWD_SSD, *g, V), st);
     launch_finalize_fwd_ssd(s, V, views, part, (int)L.n_part, grad_pose, loss, hess, st);
     return check_launch(name);
@@ -422,8 +435,12 @@ int dp_fp_backproject_grad_pose(const dp_geom* g, int32_t V, const double* angle
     float* part = (float*)(base + L.partials);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_det_grad(s, V, proj, proj4, st);
-    launch_sf_bp_grad(s, V, views, proj4, grad_vol, part, kind, st);
+    const size_t img = (size_t)g->nu * g->nv;
+    for (int v0 = 0; v0 < V; v0 += L.chunk) {
+        const int vc = std::min(L.chunk, V - v0);
+        launch_det_grad(s, vc, proj + v0 * img, proj4, st);
+        launch_sf_bp_grad(s, v0, vc, views, proj4, grad_vol, part, kind, st);
+    }
     launch_finalize_bp(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_fp_backproject_grad_pose");
 }
@@ -446,8 +463,13 @@ int dp_backproject(const dp_geom* g, int32_t V, const double* angles, const doub
     float4* projq = (float4*)(base + L.buf);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_det_pad(s, V, proj, projq, st);
-    launch_vd_bp(s, V, views, projq, vol, weight_mode, st);
+    // views in chunks: the column sums are carried in vol between chunks
+    const size_t img = (size_t)g->nu * g->nv;
+    for (int v0 = 0; v0 < V; v0 += L.chunk) {
+        const int vc = std::min(L.chunk, V - v0);
+        launch_det_pad(s, vc, proj + v0 * img, projq, st);
+        launch_vd_bp(s, v0, vc, views, projq, vol, weight_mode, v0 == 0, v0 + vc == V, st);
+    }
     return check_launch("dp_backproject");
 }
 
@@ -468,12 +490,18 @@ int dp_backproject_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
-    float4* proj4 = (float4*)(base + L.buf);
+    DetTap3* det = (DetTap3*)(base + L.buf);
     float* part = (float*)(base + L.partials);
+    int* flags = (int*)(base + L.flags);
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_det_grad(s, V, proj, proj4, st);
-    launch_vd_grad(s, V, views, proj4, grad_vol, part, weight_mode, st);
+    launch_vd_flags_clear(V, flags, st);
+    const size_t img = (size_t)g->nu * g->nv;
+    for (int v0 = 0; v0 < V; v0 += L.chunk) {
+        const int vc = std::min(L.chunk, V - v0);
+        launch_det_tap3(s, vc, proj + v0 * img, det, st);
+        launch_vd_grad(s, v0, vc, views, det, grad_vol, part, flags, weight_mode, st);
+    }
     launch_finalize_bp(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_backproject_grad_pose");
 }
@@ -638,21 +666,11 @@ static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t w
         const GeoScalars s = make_scalars(q.geom);
         char* base = (char*)ws + offs[i];
         ViewGeo* views = (ViewGeo*)(base + L.views);
-        float* buf = (float*)(base + L.buf);
         launch_view_setup(s, q.n_views, q.angles, q.poses, views, st);
-        if (op == DP_OP_FWD) {
-            launch_vol_pad(s, q.vol, buf, st);
-        } else if (op == DP_OP_FWD_GRAD) {
-            launch_vol_prep(s, q.vol, nullptr, buf, (float4*)(base + L.inter), st);
-        } else {  // planes: padded mu, Gx, Gy, Gz
-            launch_vol_prep(s, q.vol, buf, buf + padded_volume_elems(q.geom),
-                            (float4*)(base + L.inter), st);
-        }
         RdBatchItem& it = bt.it[j];
         it.s = s;
         it.views = views;
-        it.vol = buf;
-        it.inter = op == DP_OP_FWD ? nullptr : (const float4*)(base + L.inter);
+        it.vol = q.vol;
         it.gin = op == DP_OP_FWD ? nullptr : q.grad_proj;
         it.out = op == DP_OP_FWD ? q.proj : (float*)(base + L.partials);
         it.proj = op == DP_OP_FWD_SSD ? q.proj : nullptr;
@@ -731,6 +749,7 @@ int dp_lm_update(int32_t n, double* trial, const double* loss, const double* gra
 namespace dp {
 void launch_read_probe(const void* buf, uint32_t n_vec, int reps, bool shared, int n_blocks,
                        float* out, hipStream_t st);
+void launch_lds_probe(int reps, int n_blocks, float* out, hipStream_t st);
 }
 
 extern "C" {
@@ -752,6 +771,16 @@ int dp_read_probe(const void* buf, int64_t n_vec, int32_t reps, int32_t shared, 
     (void)hipGetLastError();
     launch_read_probe(buf, (uint32_t)n_vec, reps, shared != 0, n_blocks, out, (hipStream_t)stream);
     return check_launch("dp_read_probe");
+}
+
+int dp_lds_probe(int32_t reps, int32_t n_blocks, float* out, void* stream)
+{
+    if (!out) return fail(DP_ERR_ARG, "lds probe: NULL pointer");
+    if (reps <= 0 || n_blocks <= 0) return fail(DP_ERR_ARG, "lds probe: reps and n_blocks must be positive");
+    if (n_blocks > (1 << 20)) return fail(DP_ERR_UNSUPPORTED, "lds probe: more than 2^20 blocks");
+    (void)hipGetLastError();
+    launch_lds_probe(reps, n_blocks, out, (hipStream_t)stream);
+    return check_launch("dp_lds_probe");
 }
 
 // ---------------------------------------------------------------------------

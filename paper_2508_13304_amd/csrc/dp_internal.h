@@ -28,6 +28,28 @@ constexpr int kVdBy = 4;
 constexpr int kVdBpCol = 32;
 constexpr int kVdGradCol = 32;
 constexpr int kVdChannels = 12;  // A (3), QX (3), QY (3), QZ (3)
+// Views per back-projection gradient launch (per-view block sums held in LDS)
+// and the block count below which blocks stop taking several column groups.
+constexpr int kVdMaxChunk = 64;
+constexpr int kVdGradMinBlocks = 2048;
+// Detector images are staged per chunk of views, within this many bytes
+// (a build-time choice; results do not depend on it).
+#ifndef DP_DET_CHUNK_MIB
+#define DP_DET_CHUNK_MIB 512
+#endif
+constexpr size_t kDetChunkBytes = (size_t)DP_DET_CHUNK_MIB << 20;
+
+// Per padded detector pixel (A, B): the 2x2 bilinear footprints
+// {(A, B), (A+1, B), (A, B+1), (A+1, B+1)} of l, dl/da and dl/db.
+struct alignas(16) DetTap3 {
+    float4 l, a, b;
+};
+
+struct VdGradGrid {
+    int zpb;     // column groups of kVdGradCol voxels per block
+    int gz;      // blocks along z
+    int blocks;  // blocks per launch = partial sets per view
+};
 
 // Per-view parameters, produced on the device by the setup kernel from the
 // gantry angles and the (device-resident) poses.
@@ -66,19 +88,15 @@ inline GeoScalars make_scalars(const dp_geom& g)
 // Kernel launchers (defined next to their kernels).
 void launch_view_setup(const GeoScalars& s, int V, const double* angles, const double* poses,
                        ViewGeo* views, hipStream_t st);
-void launch_vol_pad(const GeoScalars& s, const float* vol, float* volp, hipStream_t st);
-// gradient planes (+ the padded mu plane if mu_plane != NULL) and the
-// per-voxel float4 (mu, Gx, Gy, Gz) interleave, in one pass
-void launch_vol_prep(const GeoScalars& s, const float* vol, float* mu_plane, float* g3,
-                     float4* inter, hipStream_t st);
 // per padded pixel, the 2x2 bilinear footprint of l as one float4
 void launch_det_pad(const GeoScalars& s, int V, const float* proj, float4* projq, hipStream_t st);
 void launch_det_grad(const GeoScalars& s, int V, const float* proj, float4* proj4, hipStream_t st);
-void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
+void launch_det_tap3(const GeoScalars& s, int V, const float* proj, DetTap3* det, hipStream_t st);
+// The ray-driven kernels read the caller's volume [nz][ny][nx] directly.
+void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
                    float* proj, int variant, hipStream_t st);
-void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
-                    const float4* inter, const float* grad_proj, float* partials, int variant,
-                    hipStream_t st);
+void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
+                    const float* grad_proj, float* partials, int variant, hipStream_t st);
 
 // Uneven batches of ray-driven problems in one launch (descriptors by value).
 constexpr int kRdMaxBatch = 16;
@@ -89,8 +107,7 @@ constexpr int kRdChannelsGN = kRdChannels + 1 + 21;
 struct RdBatchItem {
     GeoScalars s;
     const ViewGeo* views;
-    const float* vol;   // padded volume (forward) or gradient planes (gradient)
-    const float4* inter;  // per-voxel (mu, Gx, Gy, Gz) for unstaged tiles (gradient)
+    const float* vol;   // the problem's volume [nz][ny][nx]
     const float* gin;   // dL/dl (gradient) or the target y (single-pass SSD)
     float* out;         // DRRs (forward) or per-block partials (gradient, SSD)
     float* proj;        // DRRs of the single-pass SSD batch
@@ -102,9 +119,9 @@ struct RdBatch {
     RdBatchItem it[kRdMaxBatch];
 };
 void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
-void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                     const float4* inter, const float* target, float* proj, float* partials,
-                     bool hess, int variant, hipStream_t st);
+void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
+                     const float* target, float* proj, float* partials, bool hess, int variant,
+                     hipStream_t st);
 void launch_finalize_fwd_ssd(const GeoScalars& s, int V, const ViewGeo* views,
                              const float* partials, int n_part, double* grad_pose, double* loss,
                              double* hess, hipStream_t st);
@@ -113,10 +130,17 @@ void launch_rd_fused_batch(const RdBatch& bt, int blocks, int variant, hipStream
 void launch_lm_update(int n, double* trial, const double* loss, const double* grad,
                       const double* hess, double* state_pose, double* state_f, double* state_g,
                       double* state_h, double* lam, int* done, double tol, hipStream_t st);
-void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float4* projq,
-                  float* vol, int weight_mode, hipStream_t st);
-void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
-                    const float* grad_vol, float* partials, int weight_mode, hipStream_t st);
+// Back-projection of the views [v0, v0 + Vc), whose footprint images are
+// projq[0 .. Vc); sums carried in vol between chunks (first / last chunk).
+void launch_vd_bp(const GeoScalars& s, int v0, int Vc, const ViewGeo* views, const float4* projq,
+                  float* vol, int weight_mode, bool first, bool last, hipStream_t st);
+// Pose-gradient partials of the views [v0, v0 + Vc) (images det[0 .. Vc)),
+// partials[v][blocks][kVdChannels]; flags[V] must be cleared before the first chunk.
+VdGradGrid vd_grad_grid(const GeoScalars& s);
+void launch_vd_flags_clear(int V, int* flags, hipStream_t st);
+void launch_vd_grad(const GeoScalars& s, int v0, int Vc, const ViewGeo* views, const DetTap3* det,
+                    const float* grad_vol, float* partials, int* flags, int weight_mode,
+                    hipStream_t st);
 void launch_finalize_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* partials,
                          int n_part, double* grad_pose, hipStream_t st);
 void launch_finalize_bp(const GeoScalars& s, int V, const ViewGeo* views, const float* partials,
@@ -144,8 +168,10 @@ void launch_sf_bp(const GeoScalars& s, int V, const ViewGeo* views, const float*
                   int kind, hipStream_t st);
 void launch_sf_fwd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol,
                         const float* grad_proj, float* partials, int kind, hipStream_t st);
-void launch_sf_bp_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
-                       const float* grad_vol, float* partials, int kind, hipStream_t st);
+// views [v0, v0 + Vc), proj4 = this chunk's detector gradient images
+void launch_sf_bp_grad(const GeoScalars& s, int v0, int Vc, const ViewGeo* views,
+                       const float4* proj4, const float* grad_vol, float* partials, int kind,
+                       hipStream_t st);
 
 // FDK pre-filter and sharpness loss (fdk.hip).
 void launch_fdk_filter(const GeoScalars& s, int V, const float* proj, float* out, double scale,
@@ -163,10 +189,6 @@ inline int rd_tiles(const GeoScalars& s)
     return ((s.nu + kRdTile - 1) / kRdTile) * ((s.nv + kRdTile - 1) / kRdTile);
 }
 
-inline int vd_blocks(const GeoScalars& s, int col)
-{
-    return ((s.nx + kVdBx - 1) / kVdBx) * ((s.ny + kVdBy - 1) / kVdBy) * ((s.nz + col - 1) / col);
-}
 
 // Profiling hooks (abi.hip): bracket a launch with events when enabled.
 void prof_begin(int kernel, hipStream_t st);

@@ -1,4 +1,4 @@
-// Streaming-read probes: the cache-hierarchy and HBM read bandwidths against
+// Read probes: the LDS, cache-hierarchy and HBM read bandwidths against
 // which the gather-bound ray kernels are rated.  Not part of the projection
 // method; the kernels only read a buffer and write one sum per thread.
 #include "dp_internal.h"
@@ -73,7 +73,42 @@ __global__ __launch_bounds__(kProbeThreads) void read_probe_kernel(const float4*
     out[blockIdx.x * kProbeThreads + t] = total;
 }
 
+// LDS read probe: each block fills kLdsProbeVec float4 of LDS, then every
+// thread reads 16-byte vectors (consecutive lanes, consecutive vectors: no
+// bank conflicts), kProbeUnroll per step, `reps` steps, and writes its sum.
+// Bytes read = n_blocks * 256 * reps * kProbeUnroll * 16.
+constexpr uint32_t kLdsProbeVec = 2048;  // 32 KiB per block
+
+__global__ __launch_bounds__(kProbeThreads) void lds_probe_kernel(int reps, float* __restrict__ out)
+{
+    __shared__ float4 lds[kLdsProbeVec];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < kLdsProbeVec; i += kProbeThreads)
+        lds[i] = make_float4((float)i, 1.0f, 2.0f, 3.0f);
+    __syncthreads();
+    float acc[kProbeUnroll] = {};
+    uint32_t base = t;
+    for (int r = 0; r < reps; ++r) {
+        float4 v[kProbeUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kProbeUnroll; ++u)
+            v[u] = lds[(base + u * kProbeThreads) & (kLdsProbeVec - 1)];
+#pragma unroll
+        for (uint32_t u = 0; u < kProbeUnroll; ++u) acc[u] += sum4(v[u]);
+        base += 64;  // a new window each step (the loads cannot be hoisted), lanes still consecutive
+    }
+    float total = 0.f;
+#pragma unroll
+    for (uint32_t u = 0; u < kProbeUnroll; ++u) total += acc[u];
+    out[blockIdx.x * kProbeThreads + t] = total;
+}
+
 }  // namespace
+
+void launch_lds_probe(int reps, int n_blocks, float* out, hipStream_t st)
+{
+    lds_probe_kernel<<<n_blocks, kProbeThreads, 0, st>>>(reps, out);
+}
 
 void launch_read_probe(const void* buf, uint32_t n_vec, int reps, bool shared, int n_blocks,
                        float* out, hipStream_t st)

@@ -47,6 +47,11 @@ namespace dp {
 //   forward : (16, 4096) (32, 8192) (64, 12288)
 //   gradient: ( 8, 2048) (16, 3072) (32, 5120)
 constexpr int kMaxChunks = kRdThreads;  // one chunk box planned per thread
+// 16-byte row loads for interior boxes of volumes with aligned rows (a
+// build-time switch for measurements; 1 in the library)
+#ifndef RD_VEC_ROWS
+#define RD_VEC_ROWS 1
+#endif
 
 struct RayState {
     float x0, y0, z0;   // padded voxel index of the iso-plane anchor
@@ -265,55 +270,367 @@ __device__ inline Box planned_box(const TileShared& sh, int i)
     return b;
 }
 
-// Cooperative copy of the box from padded global planes into LDS, in the
-// box's own x-fastest order with C channels interleaved per voxel (LDS
-// index = C * ((z * py + y) * px + x); the pitch padding is never read).
-// e -> (x, y, z) uses multiply-high reciprocals; each thread issues BATCH
-// loads before writing any to LDS.
-template <int C, int BATCH>
-__device__ inline void load_box(const Box& b, const float* const (&src)[C], float* dst, int NX,
-                                int NXY)
+// Cooperative copy of a chunk box into LDS straight from the caller's volume
+// (no padded copy, no precomputed gradient planes).  The box lives in padded
+// index space: padded voxel (I, J, K) is grid voxel (I, J, K) - kPadV, and
+// everything outside the grid reads as zero.  C floats per voxel, in the
+// box's own x-fastest order (LDS index = C * ((z * py + y) * px + x); the
+// pitch padding is never read):
+//   C == 1: mu;
+//   C == 3: (Gx, Gy, Gz);
+//   C == 4: (mu, Gx, Gy, Gz);
+// G_c = the central difference of mu along c in index units (twice the
+// gradient field; the factor 1/2 is applied to the per-ray sums) on grid
+// voxels, mu zero-extended; G is zero off the grid.
+//
+// Interior boxes are staged in items: item i covers up to SEG consecutive
+// voxels of one z column of the box (plane position p = i / nseg, z segment
+// i mod nseg), so the position decode is paid once per SEG voxels.  Along an
+// item the z neighbours slide (mu at z + 1 is the next voxel's centre): the
+// gradient staging reads 2 + 5 SEG values per item (-z and the centre of its
+// first voxel, then +z, -x, +x, -y, +y of each), the mu staging SEG.  An item
+// shorter than SEG (the end of a column) re-reads its last voxel (in bounds,
+// never stored).
+template <int C>
+struct BoxItem {
+    static constexpr int SEG = C == 1 ? 8 : 4;
+    static constexpr int NV = C == 1 ? SEG : 2 + 5 * SEG;
+    float v[NV];
+    unsigned slot;  // LDS index of the item's first voxel
+    int cnt;        // voxels of the item (0: no item)
+};
+
+// Box-wide item decode constants (uniform over the block).
+struct BoxItems {
+    unsigned nseg, items, mseg, mx;
+};
+
+template <int C>
+__device__ inline BoxItems box_items(const Box& b)
 {
-    const int vol = b.bx * b.by * b.bz;
+    BoxItems bi;
+    bi.nseg = ((unsigned)b.bz + BoxItem<C>::SEG - 1) / BoxItem<C>::SEG;
+    bi.items = (unsigned)(b.bx * b.by) * bi.nseg;
     // q = floor(e / d) = umulhi(e, floor(2^32 / d) + 1), exact for e * d < 2^32
-    const unsigned mx = b.bx > 1 ? 0xFFFFFFFFu / (unsigned)b.bx + 1u : 0u;
-    const unsigned my = b.by > 1 ? 0xFFFFFFFFu / (unsigned)b.by + 1u : 0u;
-    // box origin pointers are uniform; element offsets fit 32 bits
-    const size_t base = ((size_t)b.oz * NXY + (size_t)b.oy * NX) + b.ox;
-    const float* sb[C];
+    bi.mseg = bi.nseg > 1 ? 0xFFFFFFFFu / bi.nseg + 1u : 0u;
+    bi.mx = b.bx > 1 ? 0xFFFFFFFFu / (unsigned)b.bx + 1u : 0u;
+    return bi;
+}
+
+// Load at a byte offset from the volume base (offsets stay below 4 GiB: the
+// volume has at most 2^30 voxels).
+__device__ inline float ldv(const float* __restrict__ mu, unsigned boff)
+{
+    return *(const float*)((const char*)mu + boff);
+}
+
+// Issue the loads of item `it` of an interior box.
+template <int C>
+__device__ inline void item_load(const Box& b, const BoxItems& bi, unsigned it,
+                                 const float* __restrict__ mu, int nx, int ny, BoxItem<C>& r)
+{
+    constexpr int SEG = BoxItem<C>::SEG;
+    const unsigned p = bi.nseg > 1 ? __umulhi(it, bi.mseg) : it;
+    const unsigned sg = it - p * bi.nseg;
+    const unsigned ly = b.bx > 1 ? __umulhi(p, bi.mx) : p;
+    const unsigned lx = p - ly * (unsigned)b.bx;
+    const unsigned z0 = sg * SEG;
+    r.cnt = min(SEG, b.bz - (int)z0);
+    const unsigned nx4 = 4u * (unsigned)nx, nxy4 = nx4 * (unsigned)ny;
+    const unsigned i = (unsigned)b.ox + lx - kPadV, j = (unsigned)b.oy + ly - kPadV;
+    const unsigned k0 = (unsigned)b.oz + z0 - kPadV;
+    const unsigned o0 = ((k0 * (unsigned)ny + j) * (unsigned)nx + i) * 4u;
+    const unsigned olast = o0 + (unsigned)(r.cnt - 1) * nxy4;
+    r.slot = (unsigned)C * ((z0 * (unsigned)b.py + ly) * (unsigned)b.px + lx);
+    if constexpr (C == 1) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) sb[c] = src[c] + base;
-    for (int e0 = threadIdx.x; e0 < vol; e0 += kRdThreads * BATCH) {
-        float val[BATCH][C];
-        unsigned slot[BATCH];
+        for (int q = 0; q < SEG; ++q) r.v[q] = ldv(mu, min(o0 + (unsigned)q * nxy4, olast));
+    } else {
+        r.v[0] = ldv(mu, o0 - nxy4);
+        r.v[1] = ldv(mu, o0);
 #pragma unroll
-        for (int i = 0; i < BATCH; ++i) {
-            const int e = e0 + i * kRdThreads;
-            if (e < vol) {
-                const unsigned q = b.bx > 1 ? __umulhi((unsigned)e, mx) : (unsigned)e;
-                const unsigned lx = (unsigned)e - q * (unsigned)b.bx;
-                const unsigned lz = b.by > 1 ? __umulhi(q, my) : q;
-                const unsigned ly = q - lz * (unsigned)b.by;
-                const unsigned off = lz * (unsigned)NXY + ly * (unsigned)NX + lx;
+        for (int q = 0; q < SEG; ++q) {
+            const unsigned o = min(o0 + (unsigned)q * nxy4, olast);
+            r.v[2 + 5 * q + 0] = ldv(mu, o + nxy4);
+            r.v[2 + 5 * q + 1] = ldv(mu, o - 4u);
+            r.v[2 + 5 * q + 2] = ldv(mu, o + 4u);
+            r.v[2 + 5 * q + 3] = ldv(mu, o - nx4);
+            r.v[2 + 5 * q + 4] = ldv(mu, o + nx4);
+        }
+    }
+}
+
+template <int C>
+__device__ inline void box_store(float* dst, unsigned slot, float m, float gx, float gy, float gz)
+{
+    float* d = dst + slot;
+    if constexpr (C == 4) {  // one 16-byte store: lanes 16 B apart, no bank conflict
+        *reinterpret_cast<float4*>(d) = make_float4(m, gx, gy, gz);
+    } else if constexpr (C == 3) {
+        d[0] = gx; d[1] = gy; d[2] = gz;
+    } else {
+        d[0] = m;
+    }
+}
+
+// Form the staged values of a loaded item and store them to LDS.
+template <int C>
+__device__ inline void item_store(const Box& b, const BoxItem<C>& r, float* dst)
+{
+    constexpr int SEG = BoxItem<C>::SEG;
+    const unsigned dslot = (unsigned)(C * b.py * b.px);
+    unsigned slot = r.slot;
 #pragma unroll
-                for (int c = 0; c < C; ++c) val[i][c] = sb[c][off];
-                slot[i] = C * ((lz * (unsigned)b.py + ly) * (unsigned)b.px + lx);
-            }
+    for (int q = 0; q < SEG; ++q, slot += dslot) {
+        if (q >= r.cnt) break;
+        if constexpr (C == 1) {
+            box_store<C>(dst, slot, r.v[q], 0.f, 0.f, 0.f);
+        } else {
+            const float c = q == 0 ? r.v[1] : r.v[2 + 5 * (q - 1)];
+            const float zm = q == 0 ? r.v[0] : (q == 1 ? r.v[1] : r.v[2 + 5 * (q - 2)]);
+            const float* w = &r.v[2 + 5 * q];
+            box_store<C>(dst, slot, c, w[2] - w[1], w[4] - w[3], w[0] - zm);
+        }
+    }
+}
+
+// True if every voxel of the box lies on the grid, with a one-voxel margin
+// when its neighbours are read too (C >= 3).
+template <int C>
+__device__ inline bool box_interior(const Box& b, int nx, int ny, int nz)
+{
+    constexpr int m = C >= 3 ? 1 : 0;
+    return b.ox - kPadV >= m && b.oy - kPadV >= m && b.oz - kPadV >= m &&
+           b.ox - kPadV + b.bx + m <= nx && b.oy - kPadV + b.by + m <= ny &&
+           b.oz - kPadV + b.bz + m <= nz;
+}
+
+// Interior box, volume rows 16-byte aligned (nx a multiple of 4 and an
+// aligned base): the box is covered by aligned 4-voxel x segments, and item
+// i is one segment of one box row over up to VSEG consecutive z (segment
+// fastest, so a wavefront's loads are contiguous 16-byte pieces of a row).
+// Per z step an item loads the +z, -y and +y rows as 16-byte vectors and the
+// two x neighbours of the segment as scalars: 5 loads for 4 voxels instead
+// of 20.  Segment voxels outside the box (at most 3 at either end of a row)
+// are loaded and not stored.
+constexpr int kVecSeg = 4;
+
+struct VecItems {
+    int gx0;               // first grid x of the box
+    unsigned s0, nxs;      // first aligned segment, segments per row
+    unsigned nseg, items;  // z runs per column, items of the box
+    unsigned mxs, mby;     // division magics for nxs and by
+};
+
+__device__ inline VecItems vec_items(const Box& b)
+{
+    VecItems vi;
+    vi.gx0 = b.ox - kPadV;
+    vi.s0 = (unsigned)vi.gx0 >> 2;
+    vi.nxs = ((unsigned)(vi.gx0 + b.bx - 1) >> 2) - vi.s0 + 1;
+    vi.nseg = ((unsigned)b.bz + kVecSeg - 1) / kVecSeg;
+    vi.items = vi.nxs * (unsigned)b.by * vi.nseg;
+    vi.mxs = vi.nxs > 1 ? 0xFFFFFFFFu / vi.nxs + 1u : 0u;
+    vi.mby = b.by > 1 ? 0xFFFFFFFFu / (unsigned)b.by + 1u : 0u;
+    return vi;
+}
+
+__device__ inline float4 ldv4(const float* __restrict__ mu, unsigned boff)
+{
+    return *(const float4*)((const char*)mu + boff);
+}
+
+__device__ inline float f4at(const float4& v, int e)
+{
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+
+template <int C>
+__device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
+                                const float* __restrict__ mu, int nx, int ny, float* dst)
+{
+    const unsigned t = vi.nxs > 1 ? __umulhi(it, vi.mxs) : it;
+    const unsigned xs = it - t * vi.nxs;
+    const unsigned zs = b.by > 1 ? __umulhi(t, vi.mby) : t;
+    const unsigned ly = t - zs * (unsigned)b.by;
+    const int gxs = (int)(vi.s0 + xs) * 4;        // grid x of the segment's first voxel
+    const int lx0 = gxs - vi.gx0;                 // its box x (may be negative)
+    const unsigned z0 = zs * kVecSeg;
+    const int cnt = min(kVecSeg, b.bz - (int)z0);
+    const unsigned nx4 = 4u * (unsigned)nx, nxy4 = nx4 * (unsigned)ny;
+    const unsigned j = (unsigned)b.oy + ly - kPadV, k0 = (unsigned)b.oz + z0 - kPadV;
+    const unsigned o0 = ((k0 * (unsigned)ny + j) * (unsigned)nx + (unsigned)gxs) * 4u;
+    const unsigned olast = o0 + (unsigned)(cnt - 1) * nxy4;
+    const unsigned dslot = (unsigned)(C * b.py * b.px);
+    // LDS index of segment voxel e at the item's first z (only for 0 <= lx0 + e < bx)
+    const int slot0 = C * (((int)z0 * b.py + (int)ly) * b.px + lx0);
+    if constexpr (C == 1) {
+        float4 v[kVecSeg];
+#pragma unroll
+        for (int q = 0; q < kVecSeg; ++q) v[q] = ldv4(mu, min(o0 + (unsigned)q * nxy4, olast));
+#pragma unroll
+        for (int q = 0; q < kVecSeg; ++q) {
+            if (q >= cnt) break;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (lx0 + e >= 0 && lx0 + e < b.bx)
+                    dst[slot0 + (int)(q * dslot) + C * e] = f4at(v[q], e);
+        }
+    } else {
+        // x neighbours of the segment: clamped onto the segment at the row ends
+        // (those voxels are never stored: an interior box keeps a margin)
+        const unsigned dl = gxs > 0 ? 4u : 0u, dr = gxs + 4 < nx ? 16u : 12u;
+        float4 zc[kVecSeg + 2], ym[kVecSeg], yp[kVecSeg];
+        float xl[kVecSeg], xr[kVecSeg];
+        zc[0] = ldv4(mu, o0 - nxy4);
+        zc[1] = ldv4(mu, o0);
+#pragma unroll
+        for (int q = 0; q < kVecSeg; ++q) {
+            const unsigned o = min(o0 + (unsigned)q * nxy4, olast);
+            zc[q + 2] = ldv4(mu, o + nxy4);
+            ym[q] = ldv4(mu, o - nx4);
+            yp[q] = ldv4(mu, o + nx4);
+            xl[q] = ldv(mu, o - dl);
+            xr[q] = ldv(mu, o + dr);
         }
 #pragma unroll
-        for (int i = 0; i < BATCH; ++i) {
-            const int e = e0 + i * kRdThreads;
-            if (e < vol) {
-                if constexpr (C == 4) {  // one 16-byte store: lanes 16 B apart, no bank conflict
-                    *reinterpret_cast<float4*>(dst + slot[i]) =
-                        make_float4(val[i][0], val[i][1], val[i][2], val[i][3]);
-                } else {
+        for (int q = 0; q < kVecSeg; ++q) {
+            if (q >= cnt) break;
+            const float4 c = zc[q + 1], zm = zc[q], zp = zc[q + 2];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) dst[slot[i] + c] = val[i][c];
-                }
+            for (int e = 0; e < 4; ++e) {
+                if (lx0 + e < 0 || lx0 + e >= b.bx) continue;
+                const float right = e < 3 ? f4at(c, e + 1) : xr[q];
+                const float left = e > 0 ? f4at(c, e - 1) : xl[q];
+                box_store<C>(dst, (unsigned)(slot0 + (int)(q * dslot) + C * e), f4at(c, e),
+                             right - left, f4at(yp[q], e) - f4at(ym[q], e), f4at(zp, e) - f4at(zm, e));
             }
         }
     }
+}
+
+template <int C>
+__device__ inline void load_box_vec(const Box& b, const float* __restrict__ mu, int nx, int ny,
+                                    float* dst)
+{
+    const VecItems vi = vec_items(b);
+    for (unsigned it = threadIdx.x; it < vi.items; it += kRdThreads)
+        vec_item<C>(b, vi, it, mu, nx, ny, dst);
+}
+
+// Interior box staged in one go: every item loaded and stored, two items per
+// thread in flight.
+template <int C>
+__device__ inline void load_box_interior(const Box& b, const float* __restrict__ mu, int nx,
+                                         int ny, float* dst)
+{
+    const BoxItems bi = box_items<C>(b);
+    for (unsigned it = threadIdx.x; it < bi.items; it += 2 * kRdThreads) {
+        BoxItem<C> r0, r1;
+        r1.cnt = 0;
+        item_load<C>(b, bi, it, mu, nx, ny, r0);
+        if (it + kRdThreads < bi.items) item_load<C>(b, bi, it + kRdThreads, mu, nx, ny, r1);
+        item_store<C>(b, r0, dst);
+        if (r1.cnt > 0) item_store<C>(b, r1, dst);
+    }
+}
+
+// Box touching the grid's faces (or beyond): every voxel tested, neighbour
+// offsets clamped onto the voxel itself at the grid faces and their values
+// masked, loads only for voxels on the grid.
+template <int C>
+__device__ inline void load_box_edge(const Box& b, const float* __restrict__ mu, int nx, int ny,
+                                     int nz, float* dst)
+{
+    const int nxy = nx * ny;
+    const unsigned dslot = (unsigned)(C * b.py * b.px);
+    const BoxItems bi = box_items<C>(b);
+    constexpr int SEG = BoxItem<C>::SEG;
+    for (unsigned it = threadIdx.x; it < bi.items; it += kRdThreads) {
+        const unsigned p = bi.nseg > 1 ? __umulhi(it, bi.mseg) : it;
+        const unsigned sg = it - p * bi.nseg;
+        const unsigned uly = b.bx > 1 ? __umulhi(p, bi.mx) : p;
+        struct { int lx, ly, z0, z1; } w;
+        w.lx = (int)(p - uly * (unsigned)b.bx);
+        w.ly = (int)uly;
+        w.z0 = (int)sg * SEG;
+        w.z1 = min(w.z0 + SEG, b.bz);
+        const int i = b.ox + w.lx - kPadV, j = b.oy + w.ly - kPadV;
+        const bool col = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        const bool fxm = i > 0, fxp = i + 1 < nx, fym = j > 0, fyp = j + 1 < ny;
+        const int oxm = fxm ? -1 : 0, oxp = fxp ? 1 : 0;
+        const int oym = fym ? -nx : 0, oyp = fyp ? nx : 0;
+        int k = b.oz + w.z0 - kPadV;
+        int off = (k * ny + j) * nx + i;  // element offset, meaningful only on the grid
+        unsigned slot = (unsigned)C * (((unsigned)w.z0 * (unsigned)b.py + (unsigned)w.ly) *
+                                       (unsigned)b.px + (unsigned)w.lx);
+        for (int z = w.z0; z < w.z1; ++z, ++k, off += nxy, slot += dslot) {
+            float m = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+            if (col && (unsigned)k < (unsigned)nz) {
+                const float* pc = mu + off;
+                m = pc[0];
+                if constexpr (C >= 3) {
+                    const bool fzm = k > 0, fzp = k + 1 < nz;
+                    const float xm = pc[oxm], xp = pc[oxp], ym = pc[oym], yp = pc[oyp];
+                    const float zm = pc[fzm ? -nxy : 0], zp = pc[fzp ? nxy : 0];
+                    gx = (fxp ? xp : 0.0f) - (fxm ? xm : 0.0f);
+                    gy = (fyp ? yp : 0.0f) - (fym ? ym : 0.0f);
+                    gz = (fzp ? zp : 0.0f) - (fzm ? zm : 0.0f);
+                }
+            }
+            box_store<C>(dst, slot, m, gx, gy, gz);
+        }
+    }
+}
+
+// Wait for every outstanding vector-memory load of this wavefront (s_waitcnt
+// vmcnt(0), expcnt and lgkmcnt left at their maxima).  A staging step ends
+// with it: the items it loaded and stored are complete by then, and the
+// compiler's wait tracking otherwise keeps the re-read tails of short items
+// (loaded, never stored) pending into the sample loop, where it stalls on
+// them at the loop's first LDS reads.
+__device__ inline void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <int C>
+__device__ inline void load_box(const Box& b, const float* __restrict__ mu, int nx, int ny, int nz,
+                                float* dst)
+{
+    // uniform over the block; rows of mu are 16-byte aligned when nx % 4 == 0
+    if (box_interior<C>(b, nx, ny, nz)) {
+        if (RD_VEC_ROWS && (nx & 3) == 0 && ((uintptr_t)mu & 15) == 0)
+            load_box_vec<C>(b, mu, nx, ny, dst);
+        else
+            load_box_interior<C>(b, mu, nx, ny, dst);
+    } else {
+        load_box_edge<C>(b, mu, nx, ny, nz, dst);
+    }
+    vm_drain();
+}
+
+
+// mu at padded voxel (I, J, K): zero off the grid.
+__device__ inline float mu_at(const float* __restrict__ mu, int nx, int ny, int nz, int I, int J,
+                              int K)
+{
+    const int i = I - kPadV, j = J - kPadV, k = K - kPadV;
+    if ((unsigned)i >= (unsigned)nx || (unsigned)j >= (unsigned)ny || (unsigned)k >= (unsigned)nz)
+        return 0.0f;
+    return mu[((size_t)k * ny + j) * nx + i];
+}
+
+// (mu, Gx, Gy, Gz) at padded voxel (I, J, K), as the box loaders form them.
+__device__ inline float4 mug_at(const float* __restrict__ mu, int nx, int ny, int nz, int I, int J,
+                                int K)
+{
+    const int i = I - kPadV, j = J - kPadV, k = K - kPadV;
+    if ((unsigned)i >= (unsigned)nx || (unsigned)j >= (unsigned)ny || (unsigned)k >= (unsigned)nz)
+        return make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 o;
+    o.x = mu_at(mu, nx, ny, nz, I, J, K);
+    o.y = mu_at(mu, nx, ny, nz, I + 1, J, K) - mu_at(mu, nx, ny, nz, I - 1, J, K);
+    o.z = mu_at(mu, nx, ny, nz, I, J + 1, K) - mu_at(mu, nx, ny, nz, I, J - 1, K);
+    o.w = mu_at(mu, nx, ny, nz, I, J, K + 1) - mu_at(mu, nx, ny, nz, I, J, K - 1);
+    return o;
 }
 
 // One chunk of one ray: first local position and per-sample increment.
@@ -337,7 +654,7 @@ __device__ inline ChunkRay chunk_ray(const RayState& r, int kb, int ke, const Bo
 
 template <int MCH, int CAP>
 __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
-                                   const float* __restrict__ volp, float* __restrict__ proj,
+                                   const float* __restrict__ mu, float* __restrict__ proj,
                                    int v, int tile, float* lds, TileShared& sh)
 {
     int a, b, a0, b0;
@@ -349,7 +666,6 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
     float margin;
     tile_setup(s, r, active, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
     const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
-    const int NXY = NX * NY;
     const float step = (float)s.step;
     const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
     float acc = 0.0f;
@@ -360,10 +676,7 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
             const int Ke = min(K + M - 1, Kmax);
             const Box bx = planned_box(sh, ci);
             __syncthreads();  // the previous chunk's readers are done
-            {
-                const float* src[1] = {volp};
-                load_box<1, 8>(bx, src, lds, NX, NXY);
-            }
+            load_box<1>(bx, mu, s.nx, s.ny, s.nz, lds);
             __syncthreads();
             const int kb = max(K, klo), ke = min(Ke, khi);
             const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
@@ -384,7 +697,7 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
             }
         }
     } else {
-        // chunk boxes too large for LDS: taps straight from the padded volume
+        // chunk boxes too large for LDS: taps straight from the volume
         const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
         for (int k = klo; k <= khi; ++k) {
             const float t = fmaf((float)(k - r.k0), step, r.f);
@@ -393,11 +706,19 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
             const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
             const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
             const float wx = X - fx, wy = Y - fy, wz = Z - fz;
-            const float* p = volp + (((int)fz * NY + (int)fy) * NX + (int)fx);
-            const float c00 = lerpf(p[0], p[1], wx);
-            const float c10 = lerpf(p[NX], p[NX + 1], wx);
-            const float c01 = lerpf(p[NXY], p[NXY + 1], wx);
-            const float c11 = lerpf(p[NXY + NX], p[NXY + NX + 1], wx);
+            const int I = (int)fx, J = (int)fy, Kz = (int)fz;
+            float m[2][2][2];
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx)
+                        m[dz][dy][dx] = mu_at(mu, s.nx, s.ny, s.nz, I + dx, J + dy, Kz + dz);
+            const float c00 = lerpf(m[0][0][0], m[0][0][1], wx);
+            const float c10 = lerpf(m[0][1][0], m[0][1][1], wx);
+            const float c01 = lerpf(m[1][0][0], m[1][0][1], wx);
+            const float c11 = lerpf(m[1][1][0], m[1][1][1], wx);
             acc += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
         }
     }
@@ -487,25 +808,19 @@ struct GradAcc {
 
 template <int MCH, int CAP, bool FUSED, bool HESS = false>
 __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
-                                    const float* __restrict__ vol3,
-                                    const float4* __restrict__ inter,
+                                    const float* __restrict__ mu,
                                     const float* __restrict__ gin,
                                     float* __restrict__ proj_out,
                                     float* __restrict__ partials, int v, int tile, int tiles,
                                     float* lds, TileShared& sh)
 {
-    // FUSED: vol3 holds four planes (mu, Gx, Gy, Gz), gin is the target image
-    // y, and the ray also integrates mu: l is written to proj_out and the
-    // SSD weight w = 2 (l - y) is applied to the gradient sums at the end.
-    // Otherwise vol3 holds (Gx, Gy, Gz) and gin is dL/dl.  inter holds the
-    // same padded values interleaved per voxel as (mu, Gx, Gy, Gz); tiles
-    // whose chunk boxes do not fit the LDS gather from it directly.
+    // FUSED: gin is the target image y, and the ray also integrates mu: l is
+    // written to proj_out and the SSD weight w = 2 (l - y) is applied to the
+    // gradient sums at the end.  Otherwise gin is dL/dl.  The chunk boxes
+    // hold (mu, Gx, Gy, Gz) (FUSED) or (Gx, Gy, Gz) per voxel, formed from
+    // mu while loading; tiles whose boxes do not fit the LDS form the same
+    // values per trilinear corner from mu directly.
     constexpr int C = FUSED ? 4 : 3;
-    const size_t plane = (size_t)(s.nx + 2 * kPadV) * (s.ny + 2 * kPadV) * (s.nz + 2 * kPadV);
-    const float* __restrict__ mu = vol3;
-    const float* __restrict__ gx = vol3 + (FUSED ? plane : 0);
-    const float* __restrict__ gy = gx + plane;
-    const float* __restrict__ gz = gy + plane;
     int a, b, a0, b0;
     rd_pixel(s, tile, a, b, a0, b0);
     const bool inside = a < s.nu && b < s.nv;
@@ -521,7 +836,6 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     float margin;
     tile_setup(s, r, inside, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
     const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
-    const int NXY = NX * NY;
     const float step = (float)s.step;
     // Padded index of the grid centre: P_a(j) = I_a(j) - centre_a.
     const float ccx = 0.5f * (s.nx - 1) + kPadV, ccy = 0.5f * (s.ny - 1) + kPadV,
@@ -534,14 +848,8 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
         for (int K = Kmin, ci = 0; K <= Kmax; K += M, ++ci) {
             const int Ke = min(K + M - 1, Kmax);
             const Box bx = planned_box(sh, ci);
-            __syncthreads();
-            if (FUSED) {
-                const float* src[4] = {mu, gx, gy, gz};
-                load_box<4, 3>(bx, src, lds, NX, NXY);
-            } else {
-                const float* src[3] = {gx, gy, gz};
-                load_box<3, 4>(bx, src, lds, NX, NXY);
-            }
+            __syncthreads();  // the previous chunk's readers are done
+            load_box<C>(bx, mu, s.nx, s.ny, s.nz, lds);
             __syncthreads();
             const int kb = max(K, klo), ke = min(Ke, khi);
             const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
@@ -590,7 +898,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
             const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
             const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-            const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
+            const int I = (int)fx, J = (int)fy, Kz = (int)fz;
             float3 q[2][2][2];
             float m[2][2][2];
 #pragma unroll
@@ -599,7 +907,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                 for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                     for (int dx = 0; dx < 2; ++dx) {
-                        const float4 t = inter[(size_t)idx + dz * NXY + dy * NX + dx];
+                        const float4 t = mug_at(mu, s.nx, s.ny, s.nz, I + dx, J + dy, Kz + dz);
                         m[dz][dy][dx] = t.x;
                         q[dz][dy][dx] = make_float3(t.y, t.z, t.w);
                     }
@@ -625,7 +933,9 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
         acc[kRdChannels] = res * res;  // SSD of this ray
     }
     if (active) {
-        const float ws = w * step;
+        // the staged G is twice the gradient field: its 1/2 enters here
+        const float hstep = 0.5f * step;
+        const float ws = w * hstep;
         acc[0] = G.Bx * ws; acc[1] = G.By * ws; acc[2] = G.Bz * ws;
         acc[3] = G.Txy * ws; acc[4] = G.Txz * ws; acc[5] = G.Tyx * ws;
         acc[6] = G.Tyz * ws; acc[7] = G.Tzx * ws; acc[8] = G.Tzy * ws;
@@ -635,10 +945,10 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             // sums; then the 21 products of 2 J J^T (Gauss-Newton matrix of
             // the SSD), accumulated in channels kRdChannels + 1 ...
             const float hx = (float)s.vx, hy = (float)s.vy, hz = (float)s.vz;
-            const float b3[3] = {G.Bx * step / hx, G.By * step / hy, G.Bz * step / hz};
-            const float t3[3] = {(hy / hz * G.Tyz - hz / hy * G.Tzy) * step,
-                                 (hz / hx * G.Tzx - hx / hz * G.Txz) * step,
-                                 (hx / hy * G.Txy - hy / hx * G.Tyx) * step};
+            const float b3[3] = {G.Bx * hstep / hx, G.By * hstep / hy, G.Bz * hstep / hz};
+            const float t3[3] = {(hy / hz * G.Tyz - hz / hy * G.Tzy) * hstep,
+                                 (hz / hx * G.Tzx - hx / hz * G.Txz) * hstep,
+                                 (hx / hy * G.Txy - hy / hx * G.Tyx) * hstep};
             float J[6];
 #pragma unroll
             for (int r3 = 0; r3 < 3; ++r3)
@@ -666,25 +976,24 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
 template <int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
                                                             const ViewGeo* __restrict__ views,
-                                                            const float* __restrict__ volp,
+                                                            const float* __restrict__ mu,
                                                             float* __restrict__ proj)
 {
     __shared__ float lds[CAP];
     __shared__ TileShared sh;
-    rd_fwd_tile<MCH, CAP>(s, views, volp, proj, blockIdx.y, blockIdx.x, lds, sh);
+    rd_fwd_tile<MCH, CAP>(s, views, mu, proj, blockIdx.y, blockIdx.x, lds, sh);
 }
 
 template <int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                                                              const ViewGeo* __restrict__ views,
-                                                             const float* __restrict__ vol3,
-                                                             const float4* __restrict__ inter,
+                                                             const float* __restrict__ mu,
                                                              const float* __restrict__ grad_proj,
                                                              float* __restrict__ partials)
 {
     __shared__ float lds[3 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, false>(s, views, vol3, inter, grad_proj, nullptr, partials, blockIdx.y,
+    rd_grad_tile<MCH, CAP, false>(s, views, mu, grad_proj, nullptr, partials, blockIdx.y,
                                   blockIdx.x, gridDim.x, lds, sh);
 }
 
@@ -693,15 +1002,14 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
 template <int MCH, int CAP, bool HESS>
 __global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
                                                               const ViewGeo* __restrict__ views,
-                                                              const float* __restrict__ vol4,
-                                                              const float4* __restrict__ inter,
+                                                              const float* __restrict__ mu,
                                                               const float* __restrict__ target,
                                                               float* __restrict__ proj,
                                                               float* __restrict__ partials)
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, true, HESS>(s, views, vol4, inter, target, proj, partials, blockIdx.y,
+    rd_grad_tile<MCH, CAP, true, HESS>(s, views, mu, target, proj, partials, blockIdx.y,
                                        blockIdx.x, gridDim.x, lds, sh);
 }
 
@@ -737,7 +1045,7 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.inter, it.gin, nullptr, it.out,
+    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.gin, nullptr, it.out,
                                   local / it.tiles, local % it.tiles, it.tiles, lds, sh);
 }
 
@@ -750,59 +1058,58 @@ __global__ __launch_bounds__(kRdThreads) void rd_fused_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP, true, true>(it.s, it.views, it.vol, it.inter, it.gin, it.proj, it.out,
+    rd_grad_tile<MCH, CAP, true, true>(it.s, it.views, it.vol, it.gin, it.proj, it.out,
                                        local / it.tiles, local % it.tiles, it.tiles, lds, sh);
 }
 
-void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* volp,
+void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
                    float* proj, int variant, hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     prof_begin(DP_K_RD_FWD, st);
     switch (variant) {
-    case 0: rd_fwd_kernel<16, 4096><<<grid, kRdThreads, 0, st>>>(s, views, volp, proj); break;
-    case 2: rd_fwd_kernel<64, 12288><<<grid, kRdThreads, 0, st>>>(s, views, volp, proj); break;
-    default: rd_fwd_kernel<32, 8192><<<grid, kRdThreads, 0, st>>>(s, views, volp, proj); break;
+    case 0: rd_fwd_kernel<16, 4096><<<grid, kRdThreads, 0, st>>>(s, views, mu, proj); break;
+    case 2: rd_fwd_kernel<64, 12288><<<grid, kRdThreads, 0, st>>>(s, views, mu, proj); break;
+    default: rd_fwd_kernel<32, 8192><<<grid, kRdThreads, 0, st>>>(s, views, mu, proj); break;
     }
     prof_end(DP_K_RD_FWD, st);
 }
 
-void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* vol3,
-                    const float4* inter, const float* grad_proj, float* partials, int variant,
-                    hipStream_t st)
+void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
+                    const float* grad_proj, float* partials, int variant, hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     prof_begin(DP_K_RD_GRAD, st);
     switch (variant) {
-    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, vol3, inter, grad_proj, partials); break;
-    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, vol3, inter, grad_proj, partials); break;
-    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, vol3, inter, grad_proj, partials); break;
+    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, mu, grad_proj, partials); break;
+    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, mu, grad_proj, partials); break;
+    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, mu, grad_proj, partials); break;
     }
     prof_end(DP_K_RD_GRAD, st);
 }
 
 template <bool HESS>
-static void launch_rd_fused_t(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                              const float4* inter, const float* target, float* proj,
-                              float* partials, int variant, hipStream_t st)
+static void launch_rd_fused_t(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
+                              const float* target, float* proj, float* partials, int variant,
+                              hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     switch (variant) {
-    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, inter, target, proj, partials); break;
-    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, inter, target, proj, partials); break;
-    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, vol4, inter, target, proj, partials); break;
+    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, target, proj, partials); break;
+    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, target, proj, partials); break;
+    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, target, proj, partials); break;
     }
 }
 
-void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* vol4,
-                     const float4* inter, const float* target, float* proj, float* partials,
-                     bool hess, int variant, hipStream_t st)
+void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
+                     const float* target, float* proj, float* partials, bool hess, int variant,
+                     hipStream_t st)
 {
     prof_begin(DP_K_RD_FUSED, st);
     if (hess)
-        launch_rd_fused_t<true>(s, V, views, vol4, inter, target, proj, partials, variant, st);
+        launch_rd_fused_t<true>(s, V, views, mu, target, proj, partials, variant, st);
     else
-        launch_rd_fused_t<false>(s, V, views, vol4, inter, target, proj, partials, variant, st);
+        launch_rd_fused_t<false>(s, V, views, mu, target, proj, partials, variant, st);
     prof_end(DP_K_RD_FUSED, st);
 }
 

@@ -480,8 +480,9 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s
     }
 }
 
+// Views [v0, v0 + Vc); proj4 holds this chunk's detector gradient images.
 template <int KIND>
-__global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s, int V,
+__global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s, int v0, int Vc,
                                                                    const ViewGeo* __restrict__ views,
                                                                    const float4* __restrict__ proj4,
                                                                    const float* __restrict__ grad_vol,
@@ -500,11 +501,12 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s,
     for (int kk = 0; kk < kSfCol; ++kk)
         e[kk] = (active && kb + kk < s.nz) ? grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
     const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
-    for (int v = 0; v < V; ++v) {
+    for (int vv = 0; vv < Vc; ++vv) {
+        const int v = v0 + vv;
         const ViewGeo& g = views[v];
         double src[3];
         const int dom = sf_source(g, s, src);
-        const float4* img = proj4 + (size_t)v * NU * NV;
+        const float4* img = proj4 + (size_t)vv * NU * NV;
         float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
         const SfColumn col = sf_column<KIND>(g, s, src, dom, i, j, kb + kSfCol / 2);
 #pragma unroll
@@ -610,11 +612,12 @@ void launch_sf_fwd_grad(const GeoScalars& s, int V, const ViewGeo* views, const 
     prof_end(DP_K_SF, st);
 }
 
-void launch_sf_bp_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
-                       const float* grad_vol, float* partials, int kind, hipStream_t st)
+void launch_sf_bp_grad(const GeoScalars& s, int v0, int Vc, const ViewGeo* views,
+                       const float4* proj4, const float* grad_vol, float* partials, int kind,
+                       hipStream_t st)
 {
     prof_begin(DP_K_SF, st);
-    DP_FP_LAUNCH(sf_bp_grad_kernel, s, V, views, proj4, grad_vol, partials);
+    DP_FP_LAUNCH(sf_bp_grad_kernel, s, v0, Vc, views, proj4, grad_vol, partials);
     prof_end(DP_K_SF, st);
 }
 #undef DP_FP_LAUNCH

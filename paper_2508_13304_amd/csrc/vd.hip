@@ -26,11 +26,35 @@
 // an algebraic identity of the projective division.  The bilinear weights
 // thus carry errors of ~1e-6 pixel instead of the ~3e-5 pixel that FP32
 // pixel coordinates of magnitude ~500 would carry.
+#include <algorithm>
+
 #include "dp_internal.h"
+
+// Voxels per batch of tap loads and the occupancy target (waves per SIMD)
+// of the two kernels; measured at 512^3 / 360 views (build-time choices).
+#ifndef VD_BP_NB
+#define VD_BP_NB 8
+#endif
+#ifndef VD_GRAD_NB
+#define VD_GRAD_NB 2
+#endif
+#ifndef VD_BP_WPE
+#define VD_BP_WPE 3
+#endif
+#ifndef VD_GRAD_WPE
+#define VD_GRAD_WPE 3
+#endif
 
 namespace dp {
 
 __device__ inline float lerp_f(float a, float b, float w) { return fmaf(w, b - a, a); }
+
+// Largest distance (pixels, per detector axis) from the detector centre at
+// which a column's FP64 anchor may project: two detector widths and a margin.
+__host__ __device__ inline double anchor_limit(const GeoScalars& s)
+{
+    return 2.0 * (double)(s.nu > s.nv ? s.nu : s.nv) + 64.0;
+}
 
 // FP64 anchor of one voxel column for one view.
 struct ColumnAnchor {
@@ -70,8 +94,11 @@ __device__ inline ColumnAnchor column_anchor(const ViewGeo& g, const GeoScalars&
     const double iw0 = 1.0 / W0;
     const double ap = U0 * iw0, bp = V0 * iw0;
     // an anchor projecting far outside the detector (or a non-finite one) is
-    // no reference for the offsets of the other voxels of its column
-    if (!(fabs(ap) <= 65536.0 && fabs(bp) <= 65536.0)) c.exact = true;
+    // no reference for the offsets of the other voxels of its column: those
+    // that land on the detector would carry FP32 offsets of the anchor's
+    // magnitude
+    const double lim = anchor_limit(s);
+    if (!(fabs(ap) <= lim && fabs(bp) <= lim)) c.exact = true;
     const double a0 = c.exact ? 0.0 : ap + s.cu + kPadD;
     const double b0 = c.exact ? 0.0 : bp + s.cv + kPadD;
     const double A0 = floor(a0), B0 = floor(b0);
@@ -83,10 +110,12 @@ __device__ inline ColumnAnchor column_anchor(const ViewGeo& g, const GeoScalars&
     c.nv = (float)((g.PVd[2] * W0 - g.PWd[2] * V0) * iw0);
     c.w0 = (float)W0;
     c.ka = (float)ka;
-    c.alo = (float)(kPadD - 1.5 - A0);
-    c.ahi = (float)(s.nu + kPadD + 0.5 - A0);
-    c.blo = (float)(kPadD - 1.5 - B0);
-    c.bhi = (float)(s.nv + kPadD + 0.5 - B0);
+    // small integers and halves: exact in FP32 (no FP64 constants to keep live)
+    const float fA0 = (float)A0, fB0 = (float)B0;
+    c.alo = ((float)kPadD - 1.5f) - fA0;
+    c.ahi = ((float)(s.nu + kPadD) + 0.5f) - fA0;
+    c.blo = ((float)kPadD - 1.5f) - fB0;
+    c.bhi = ((float)(s.nv + kPadD) + 0.5f) - fB0;
     c.apc = (float)ap;
     c.bpc = (float)bp;
     return c;
@@ -110,31 +139,44 @@ __device__ inline float clampf(float x, float lo, float hi) { return fminf(fmaxf
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const f32x4 global_float4;
 
+// The taps of NB consecutive voxels are gathered before any of them is
+// used, so NB loads are in flight per wavefront.
 template <int MODE, int K, bool FRONT>
 __device__ inline void bp_column(const ColumnAnchor& c, float pw2, global_float4* __restrict__ img,
                                  int NU, float (&acc)[K])
 {
-    float dk = -c.ka;  // kk - ka, exact: small integers
+    constexpr int NB = VD_BP_NB;
+    static_assert(K % NB == 0, "column length must be a multiple of the batch");
 #pragma unroll
-    for (int kk = 0; kk < K; ++kk, dk += 1.0f) {
-        const float W = fmaf(dk, pw2, c.w0);
-        const bool front = FRONT || W > 0.0f;  // voxels at or behind the source get no ray
-        const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
-        float A = fmaf(dk * c.nu, iw, c.a0f);
-        const float B0 = fmaf(dk * c.nv, iw, c.b0f);
-        if (!FRONT) A = front ? A : -1.0e9f;
-        A = __builtin_amdgcn_fmed3f(A, c.alo, c.ahi);
-        const float B = __builtin_amdgcn_fmed3f(B0, c.blo, c.bhi);
-        const int ia = floor_to_int(A), ib = floor_to_int(B);
-        const float wa = __builtin_amdgcn_fractf(A), wb = __builtin_amdgcn_fractf(B);
-        const f32x4 q = img[ib * NU + ia];
-        const float t0 = lerp_f(q.x, q.y, wa);
-        const float t1 = lerp_f(q.z, q.w, wa);
-        const float val = lerp_f(t0, t1, wb);
-        if (MODE == DP_W_FDK)
-            acc[kk] = fmaf(iw * iw, val, acc[kk]);
-        else
-            acc[kk] += val;
+    for (int k0 = 0; k0 < K; k0 += NB) {
+        f32x4 q[NB];
+        float wa[NB], wb[NB], iw[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const float dk = (float)(k0 + u) - c.ka;  // kk - ka, exact: small integers
+            const float W = fmaf(dk, pw2, c.w0);
+            const bool front = FRONT || W > 0.0f;  // voxels at or behind the source get no ray
+            iw[u] = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
+            float A = fmaf(dk * c.nu, iw[u], c.a0f);
+            const float B0 = fmaf(dk * c.nv, iw[u], c.b0f);
+            if (!FRONT) A = front ? A : -1.0e9f;
+            A = __builtin_amdgcn_fmed3f(A, c.alo, c.ahi);
+            const float B = __builtin_amdgcn_fmed3f(B0, c.blo, c.bhi);
+            const int ia = floor_to_int(A), ib = floor_to_int(B);
+            wa[u] = __builtin_amdgcn_fractf(A);
+            wb[u] = __builtin_amdgcn_fractf(B);
+            q[u] = img[ib * NU + ia];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const float t0 = lerp_f(q[u].x, q[u].y, wa[u]);
+            const float t1 = lerp_f(q[u].z, q[u].w, wa[u]);
+            const float val = lerp_f(t0, t1, wb[u]);
+            if (MODE == DP_W_FDK)
+                acc[k0 + u] = fmaf(iw[u] * iw[u], val, acc[k0 + u]);
+            else
+                acc[k0 + u] += val;
+        }
     }
 }
 
@@ -194,30 +236,39 @@ __device__ inline void bp_column_exact(const ViewGeo& g, const GeoScalars& s, in
     }
 }
 
+// One launch covers the views [v0, v0 + Vc) of the detector images in
+// `projq` (this chunk's footprint copy).  The column sums run in view order
+// and are carried between launches in `vol` unscaled (FIRST: start from
+// zero; LAST: apply the FDK constant), so a chunked back-projection is
+// bit-identical to a single launch over all views.
 template <int MODE, int K>
-__global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int V,
+__global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(VD_BP_WPE))) void vd_bp_kernel(GeoScalars s, int v0, int Vc,
                                                               const ViewGeo* __restrict__ views,
                                                               const float4* __restrict__ projq,
-                                                              float* __restrict__ vol)
+                                                              float* __restrict__ vol, int first,
+                                                              int last)
 {
     const int i = blockIdx.x * kVdBx + threadIdx.x;
     const int j = blockIdx.y * kVdBy + threadIdx.y;
     const int kb = blockIdx.z * K;
     const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
     const float D2 = (float)(s.sad * s.sad);
+    const bool active = i < s.nx && j < s.ny;
     float acc[K];
 #pragma unroll
-    for (int kk = 0; kk < K; ++kk) acc[kk] = 0.0f;
-    for (int v = 0; v < V; ++v) {
-        const ViewGeo& g = views[v];
+    for (int kk = 0; kk < K; ++kk)
+        acc[kk] = (!first && active && kb + kk < s.nz) ? vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i]
+                                                        : 0.0f;
+    for (int vv = 0; vv < Vc; ++vv) {
+        const ViewGeo& g = views[v0 + vv];
         const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
         const float pw2 = g.PW[2];
         if (c.exact) {
-            bp_column_exact<MODE, K>(g, s, i, j, kb, (global_float4*)(projq + (long long)v * NU * NV),
+            bp_column_exact<MODE, K>(g, s, i, j, kb, (global_float4*)(projq + (long long)vv * NU * NV),
                                      NU, acc);
             continue;
         }
-        const float4* base = projq + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
+        const float4* base = projq + ((long long)vv * NU * NV + c.off);  // anchor pixel of this view
         // one 64-bit base per view and column (kept whole, in global memory's
         // address space), so each update adds only its 32-bit pixel offset
         asm volatile("" : "+v"(base));
@@ -227,58 +278,72 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_bp_kernel(GeoScalars s, int 
         else
             bp_column<MODE, K, false>(c, pw2, img, NU, acc);
     }
-    if (i < s.nx && j < s.ny) {
+    if (active) {
+        const float scale = (MODE == DP_W_FDK && last) ? D2 : 1.0f;
 #pragma unroll
         for (int kk = 0; kk < K; ++kk)
             if (kb + kk < s.nz)
-                vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] = MODE == DP_W_FDK ? D2 * acc[kk] : acc[kk];
+                vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] = scale == 1.0f ? acc[kk] : scale * acc[kk];
     }
 }
 
 // One view's gradient sums over a column of K voxels (FRONT as in bp_column):
 // A_k += e c_k and Z_k += e c_k (k - centre_z) for k = u, v, w.
 template <int MODE, int K, bool FRONT>
-__device__ inline void grad_column(const ColumnAnchor& c, float pw2, const float4* __restrict__ img,
+__device__ inline void grad_column(const ColumnAnchor& c, float pw2, const DetTap3* __restrict__ img,
                                    int NU, const float (&e)[K], float pk0, float kappa, float& A1,
                                    float& A2, float& A3, float& Z1, float& Z2, float& Z3)
 {
-    float dk = -c.ka;  // kk - ka, exact: small integers
+    constexpr int NB = VD_GRAD_NB;  // voxels whose three taps are in flight together
+    static_assert(K % NB == 0, "column length must be a multiple of the batch");
 #pragma unroll
-    for (int kk = 0; kk < K; ++kk, dk += 1.0f) {
-        const float W = fmaf(dk, pw2, c.w0);
-        const bool front = FRONT || W > 0.0f;  // voxels at or behind the source get no ray
-        const float iw = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
-        const float da = dk * c.nu * iw, db = dk * c.nv * iw;
-        const float ap = c.apc + da, bp = c.bpc + db;  // offsets from the detector centre
-        float A = c.a0f + da;
-        if (!FRONT) A = front ? A : -1.0e9f;
-        A = __builtin_amdgcn_fmed3f(A, c.alo, c.ahi);
-        const float B = __builtin_amdgcn_fmed3f(c.b0f + db, c.blo, c.bhi);
-        const int ia = floor_to_int(A), ib = floor_to_int(B);
-        const float wa = __builtin_amdgcn_fractf(A), wb = __builtin_amdgcn_fractf(B);
-        const float4* p = img + (ib * NU + ia);
-        const float4 p00 = p[0], p10 = p[1], p01 = p[NU], p11 = p[NU + 1];
-        const float l = lerp_f(lerp_f(p00.x, p10.x, wa), lerp_f(p01.x, p11.x, wa), wb);
-        const float la = lerp_f(lerp_f(p00.y, p10.y, wa), lerp_f(p01.y, p11.y, wa), wb);
-        const float lb = lerp_f(lerp_f(p00.z, p10.z, wa), lerp_f(p01.z, p11.z, wa), wb);
-        // e * W / w' (FDK: e D^2 / w'^3, with D^2 folded into e)
-        const float ec = MODE == DP_W_FDK ? e[kk] * (iw * iw) * iw : e[kk] * iw;
-        const float c1 = ec * la, c2 = ec * lb;
-        const float c3 = -ec * fmaf(la, ap, fmaf(lb, bp, kappa * l));
-        const float pk = pk0 + (float)kk;
-        A1 += c1; A2 += c2; A3 += c3;
-        Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
+    for (int k0 = 0; k0 < K; k0 += NB) {
+        float4 ql[NB], qa[NB], qb[NB];
+        float wa[NB], wb[NB], iw[NB], ap[NB], bp[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const float dk = (float)(k0 + u) - c.ka;  // kk - ka, exact: small integers
+            const float W = fmaf(dk, pw2, c.w0);
+            const bool front = FRONT || W > 0.0f;  // voxels at or behind the source get no ray
+            iw[u] = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
+            const float da = dk * c.nu * iw[u], db = dk * c.nv * iw[u];
+            ap[u] = c.apc + da;  // offsets from the detector centre
+            bp[u] = c.bpc + db;
+            float A = c.a0f + da;
+            if (!FRONT) A = front ? A : -1.0e9f;
+            A = __builtin_amdgcn_fmed3f(A, c.alo, c.ahi);
+            const float B = __builtin_amdgcn_fmed3f(c.b0f + db, c.blo, c.bhi);
+            const int ia = floor_to_int(A), ib = floor_to_int(B);
+            wa[u] = __builtin_amdgcn_fractf(A);
+            wb[u] = __builtin_amdgcn_fractf(B);
+            const DetTap3* p = img + (ib * NU + ia);
+            ql[u] = p->l;
+            qa[u] = p->a;
+            qb[u] = p->b;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const float l = lerp_f(lerp_f(ql[u].x, ql[u].y, wa[u]), lerp_f(ql[u].z, ql[u].w, wa[u]), wb[u]);
+            const float la = lerp_f(lerp_f(qa[u].x, qa[u].y, wa[u]), lerp_f(qa[u].z, qa[u].w, wa[u]), wb[u]);
+            const float lb = lerp_f(lerp_f(qb[u].x, qb[u].y, wa[u]), lerp_f(qb[u].z, qb[u].w, wa[u]), wb[u]);
+            // e * W / w' (FDK: e D^2 / w'^3, with D^2 folded into e)
+            const float ec = MODE == DP_W_FDK ? e[k0 + u] * (iw[u] * iw[u]) * iw[u] : e[k0 + u] * iw[u];
+            const float c1 = ec * la, c2 = ec * lb;
+            const float c3 = -ec * fmaf(la, ap[u], fmaf(lb, bp[u], kappa * l));
+            const float pk = pk0 + (float)(k0 + u);
+            A1 += c1; A2 += c2; A3 += c3;
+            Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
+        }
     }
 }
 
-// Sum 12 channels over the wavefront and store (ADD: add) them to out[12].
-// Channel-halving butterfly: at the xor-32 and xor-16 steps each lane keeps
-// half of the channels and receives the partner's sums of them, so the 12
-// channels take 6 + 3 + 4 x 3 = 21 cross-lane exchanges instead of 72.  Lane
-// 16 q (q = 0..3) ends with channels 3 q .. 3 q + 2 of the whole wavefront;
-// each wavefront owns its partials (no block barrier, fixed summation order).
-template <bool ADD>
-__device__ inline void wave_partials(const float (&r)[kVdChannels], int lane, float* __restrict__ out)
+// Sum 12 channels over the wavefront and add them to out[12] (this
+// wavefront's LDS slice for one view).  Channel-halving butterfly: at the
+// xor-32 and xor-16 steps each lane keeps half of the channels and receives
+// the partner's sums of them, so the 12 channels take 6 + 3 + 4 x 3 = 21
+// cross-lane exchanges instead of 72.  Lane 16 q (q = 0..3) ends with
+// channels 3 q .. 3 q + 2 of the whole wavefront.
+__device__ inline void wave_partials(const float (&r)[kVdChannels], int lane, float* out)
 {
     const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
     float s6[6], s3[3];
@@ -299,152 +364,198 @@ __device__ inline void wave_partials(const float (&r)[kVdChannels], int lane, fl
     if ((lane & 15) == 0) {
         float* o = out + (lane >> 4) * 3;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) o[t] = ADD ? o[t] + s3[t] : s3[t];
+        for (int t = 0; t < 3; ++t) o[t] += s3[t];
     }
 }
 
-template <int MODE, int K>
-__global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(4))) void vd_grad_kernel(GeoScalars s, int V,
-                                                                const ViewGeo* __restrict__ views,
-                                                                const float4* __restrict__ proj4,
-                                                                const float* __restrict__ grad_vol,
-                                                                float* __restrict__ partials,
-                                                                int* __restrict__ exact_views)
+// Per-block partial sums of one view chunk: each wavefront accumulates its
+// per-view channel sums over the block's column groups in its own LDS slice;
+// the block then adds the four slices in a fixed order and writes (ADD:
+// adds) one partial set per view, partials[v][blk][kVdChannels].
+struct VdGradShared {
+    float acc[kVdBy][kVdMaxChunk][kVdChannels];
+};
+
+__device__ inline void vd_shared_zero(VdGradShared& sh, int Vc)
 {
+    float* a = &sh.acc[0][0][0];
+    for (int t = threadIdx.y * kVdBx + threadIdx.x; t < kVdBy * kVdMaxChunk * kVdChannels; t += kVdBx * kVdBy)
+        a[t] = 0.0f;
+    (void)Vc;
+    __syncthreads();
+}
+
+template <bool ADD>
+__device__ inline void vd_shared_store(const VdGradShared& sh, int v0, int Vc, int blk, int nblk,
+                                       const int* __restrict__ only, float* __restrict__ partials)
+{
+    __syncthreads();
+    for (int t = threadIdx.y * kVdBx + threadIdx.x; t < Vc * kVdChannels; t += kVdBx * kVdBy) {
+        const int vv = t / kVdChannels, c = t - vv * kVdChannels;
+        if (only && only[v0 + vv] == 0) continue;
+        const float sum = ((sh.acc[0][vv][c] + sh.acc[1][vv][c]) + sh.acc[2][vv][c]) + sh.acc[3][vv][c];
+        float* o = partials + ((size_t)(v0 + vv) * nblk + blk) * kVdChannels + c;
+        *o = ADD ? *o + sum : sum;
+    }
+}
+
+// Block (bx, by, bz) covers the voxel columns of x block bx, y block by and
+// the zpb consecutive column groups of K voxels starting at group bz * zpb.
+template <int MODE, int K>
+__global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(VD_GRAD_WPE))) void vd_grad_kernel(
+    GeoScalars s, int v0, int Vc, int zpb, const ViewGeo* __restrict__ views,
+    const DetTap3* __restrict__ det, const float* __restrict__ grad_vol,
+    float* __restrict__ partials, int* __restrict__ exact_views)
+{
+    __shared__ VdGradShared sh;
     const int i = blockIdx.x * kVdBx + threadIdx.x;
     const int j = blockIdx.y * kVdBy + threadIdx.y;
-    const int kb = blockIdx.z * K;
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    // one partial set per wavefront (threadIdx.y), [V][blocks * kVdBy][kVdChannels]
-    const int wv = blk * kVdBy + (int)threadIdx.y;
-    const int nwv = gridDim.x * gridDim.y * gridDim.z * kVdBy;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
     const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
     const float D2 = (float)(s.sad * s.sad);
     const float kappa = MODE == DP_W_FDK ? 2.0f : 0.0f;
     const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
-    const float pk0 = (float)kb - 0.5f * (s.nz - 1);
-    // dL/dmu of this thread's voxel column, kept in registers for all views.
-    float e[K];
     const bool active = i < s.nx && j < s.ny;
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk) {
-        const bool in = active && kb + kk < s.nz;
-        e[kk] = in ? grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
-        if (MODE == DP_W_FDK) e[kk] *= D2;
-    }
     const int lane = threadIdx.x;  // kVdBx = 64: one wavefront per threadIdx.y
-    for (int v = 0; v < V; ++v) {
-        const ViewGeo& g = views[v];
-        const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
-        const float pw2 = g.PW[2];
-        float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
-        const float4* img = proj4 + ((long long)v * NU * NV + c.off);  // anchor pixel of this view
-        if (c.exact) {
-            // no usable anchor: vd_grad_exact_kernel adds this column's sums
-            exact_views[v] = 1;
-        } else if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
-            grad_column<MODE, K, true>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
-        else
-            grad_column<MODE, K, false>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
-        const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
-                                      pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
-        wave_partials<false>(r, lane, partials + ((size_t)v * nwv + wv) * kVdChannels);
+    float* mine = &sh.acc[threadIdx.y][0][0];
+    vd_shared_zero(sh, Vc);
+    for (int zg = 0; zg < zpb; ++zg) {
+        const int kb = ((int)blockIdx.z * zpb + zg) * K;
+        if (kb >= s.nz) break;  // uniform over the block
+        const float pk0 = (float)kb - 0.5f * (s.nz - 1);
+        // dL/dmu of this thread's voxel column, kept in registers for all views.
+        float e[K];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            const bool in = active && kb + kk < s.nz;
+            e[kk] = in ? grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
+            if (MODE == DP_W_FDK) e[kk] *= D2;
+        }
+        for (int vv = 0; vv < Vc; ++vv) {
+            const ViewGeo& g = views[v0 + vv];
+            const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
+            const float pw2 = g.PW[2];
+            float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
+            const DetTap3* img = det + ((long long)vv * NU * NV + c.off);  // anchor pixel of this view
+            if (c.exact) {
+                // no usable anchor: vd_grad_exact_kernel adds this column's sums
+                exact_views[v0 + vv] = 1;
+            } else if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
+                grad_column<MODE, K, true>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
+            else
+                grad_column<MODE, K, false>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
+            const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
+                                          pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
+            wave_partials(r, lane, mine + vv * kVdChannels);
+        }
     }
+    vd_shared_store<false>(sh, v0, Vc, blk, nblk, nullptr, partials);
 }
 
 // Columns with no usable FP64 anchor (every voxel within 1 mm of the source
-// plane, or an anchor projecting beyond 65536 pixels; only with the source
-// inside or next to the volume), which vd_grad_kernel leaves out and flags
-// per view: their voxels are projected one by one in FP64 and their sums
-// added to the same per-wavefront partials.  Views without a flag are
-// skipped; in the others a conservative FP32 test of the column ends skips
-// every column that cannot be such a column: if the depth keeps its sign and exceeds 2 mm at both
-// ends, it exceeds 1 mm along the whole column, so the middle voxel is the
-// anchor, and its projection lies between those of the ends (the projective
-// map has no pole in between), so it is within 65536 pixels when both ends
-// are within 60000.
+// plane, or an anchor projecting more than anchor_limit() pixels from the
+// detector centre; only with the source inside or next to the volume), which
+// vd_grad_kernel leaves out and flags per view: their voxels are projected
+// one by one in FP64 and their block sums added to the same per-block
+// partials (same blocks, same column groups, same fixed order).  Views
+// without a flag are skipped; in the others a conservative FP32 test of the
+// column ends skips every column that cannot be such a column: if the depth
+// keeps its sign and exceeds 2 mm at both ends, it exceeds 1 mm along the
+// whole column, so the middle voxel is the anchor, and its projection lies
+// between those of the ends (the projective map has no pole in between), so
+// it is within the limit when both ends are within 0.9 of it.
 template <int MODE, int K>
-__global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(GeoScalars s, int V,
-                                                                      const ViewGeo* __restrict__ views,
-                                                                      const float4* __restrict__ proj4,
-                                                                      const float* __restrict__ grad_vol,
-                                                                      float* __restrict__ partials,
-                                                                      const int* __restrict__ exact_views)
+__global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(
+    GeoScalars s, int v0, int Vc, int zpb, const ViewGeo* __restrict__ views,
+    const DetTap3* __restrict__ det, const float* __restrict__ grad_vol,
+    float* __restrict__ partials, const int* __restrict__ exact_views)
 {
+    // uniform over the launch: nothing to do unless a view of the chunk is flagged
+    bool any = false;
+    for (int vv = 0; vv < Vc; ++vv) any = any || exact_views[v0 + vv] != 0;
+    if (!any) return;
+    __shared__ VdGradShared sh;
     const int i = blockIdx.x * kVdBx + threadIdx.x;
     const int j = blockIdx.y * kVdBy + threadIdx.y;
-    const int kb = blockIdx.z * K;
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    const int wv = blk * kVdBy + (int)threadIdx.y;
-    const int nwv = gridDim.x * gridDim.y * gridDim.z * kVdBy;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
     const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
     const float escale = MODE == DP_W_FDK ? (float)(s.sad * s.sad) : 1.0f;
     const float kappa = MODE == DP_W_FDK ? 2.0f : 0.0f;
     const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
-    const float pk0 = (float)kb - 0.5f * (s.nz - 1);
     const int lane = threadIdx.x;
-    const float fi = (float)i, fj = (float)j, flo = (float)kb, fhi = (float)(kb + K - 1);
-    for (int v = 0; v < V; ++v) {
-        if (exact_views[v] == 0) continue;  // no column of this view was left out
-        const ViewGeo& g = views[v];
-        const float wij = fmaf(g.PW[0], fi, fmaf(g.PW[1], fj, g.PW[3]));
-        const float uij = fmaf(g.PU[0], fi, fmaf(g.PU[1], fj, g.PU[3]));
-        const float vij = fmaf(g.PV[0], fi, fmaf(g.PV[1], fj, g.PV[3]));
-        const float wlo = fmaf(g.PW[2], flo, wij), whi = fmaf(g.PW[2], fhi, wij);
-        const float ulo = fmaf(g.PU[2], flo, uij), uhi = fmaf(g.PU[2], fhi, uij);
-        const float vlo = fmaf(g.PV[2], flo, vij), vhi = fmaf(g.PV[2], fhi, vij);
-        const bool safe = (wlo > 2.0f && whi > 2.0f) || (wlo < -2.0f && whi < -2.0f);
-        const float lim_lo = 60000.0f * fabsf(wlo), lim_hi = 60000.0f * fabsf(whi);
-        const bool cand = !(safe && fabsf(ulo) < lim_lo && fabsf(uhi) < lim_hi &&
-                            fabsf(vlo) < lim_lo && fabsf(vhi) < lim_hi);
-        if (__ballot(cand) == 0) continue;  // wave-uniform: no column of this wavefront
-        float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
-        if (cand && column_anchor(g, s, i, j, kb, K).exact) {
-            const float4* view = proj4 + (long long)v * NU * NV;
-            double U, V, W;
-            exact_rows(g, i, j, kb, U, V, W);
-            for (int kk = 0; kk < K; ++kk, U += g.PUd[2], V += g.PVd[2], W += g.PWd[2]) {
-                const bool in = i < s.nx && j < s.ny && kb + kk < s.nz;
-                const float ek = in ? escale * grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
-                const ExactVoxel x = exact_voxel(s, U, V, W);
-                const int ia = floor_to_int(x.A), ib = floor_to_int(x.B);
-                const float wa = __builtin_amdgcn_fractf(x.A), wb = __builtin_amdgcn_fractf(x.B);
-                const float4* p = view + (ib * NU + ia);
-                const float4 p00 = p[0], p10 = p[1], p01 = p[NU], p11 = p[NU + 1];
-                const float l = lerp_f(lerp_f(p00.x, p10.x, wa), lerp_f(p01.x, p11.x, wa), wb);
-                const float la = lerp_f(lerp_f(p00.y, p10.y, wa), lerp_f(p01.y, p11.y, wa), wb);
-                const float lb = lerp_f(lerp_f(p00.z, p10.z, wa), lerp_f(p01.z, p11.z, wa), wb);
-                const float ec = MODE == DP_W_FDK ? ek * (x.iw * x.iw) * x.iw : ek * x.iw;
-                const float c1 = ec * la, c2 = ec * lb;
-                const float c3 = -ec * fmaf(la, x.ap, fmaf(lb, x.bp, kappa * l));
-                const float pk = pk0 + (float)kk;
-                A1 += c1; A2 += c2; A3 += c3;
-                Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
+    const float lim = 0.9f * (float)anchor_limit(s);
+    float* mine = &sh.acc[threadIdx.y][0][0];
+    vd_shared_zero(sh, Vc);
+    for (int zg = 0; zg < zpb; ++zg) {
+        const int kb = ((int)blockIdx.z * zpb + zg) * K;
+        if (kb >= s.nz) break;  // uniform over the block
+        const float pk0 = (float)kb - 0.5f * (s.nz - 1);
+        const float fi = (float)i, fj = (float)j, flo = (float)kb, fhi = (float)(kb + K - 1);
+        for (int vv = 0; vv < Vc; ++vv) {
+            if (exact_views[v0 + vv] == 0) continue;  // no column of this view was left out
+            const ViewGeo& g = views[v0 + vv];
+            const float wij = fmaf(g.PW[0], fi, fmaf(g.PW[1], fj, g.PW[3]));
+            const float uij = fmaf(g.PU[0], fi, fmaf(g.PU[1], fj, g.PU[3]));
+            const float vij = fmaf(g.PV[0], fi, fmaf(g.PV[1], fj, g.PV[3]));
+            const float wlo = fmaf(g.PW[2], flo, wij), whi = fmaf(g.PW[2], fhi, wij);
+            const float ulo = fmaf(g.PU[2], flo, uij), uhi = fmaf(g.PU[2], fhi, uij);
+            const float vlo = fmaf(g.PV[2], flo, vij), vhi = fmaf(g.PV[2], fhi, vij);
+            const bool safe = (wlo > 2.0f && whi > 2.0f) || (wlo < -2.0f && whi < -2.0f);
+            const float lim_lo = lim * fabsf(wlo), lim_hi = lim * fabsf(whi);
+            const bool cand = !(safe && fabsf(ulo) < lim_lo && fabsf(uhi) < lim_hi &&
+                                fabsf(vlo) < lim_lo && fabsf(vhi) < lim_hi);
+            if (__ballot(cand) == 0) continue;  // wave-uniform: no column of this wavefront
+            float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
+            if (cand && column_anchor(g, s, i, j, kb, K).exact) {
+                const DetTap3* view = det + (long long)vv * NU * NV;
+                double U, V, W;
+                exact_rows(g, i, j, kb, U, V, W);
+                for (int kk = 0; kk < K; ++kk, U += g.PUd[2], V += g.PVd[2], W += g.PWd[2]) {
+                    const bool in = i < s.nx && j < s.ny && kb + kk < s.nz;
+                    const float ek = in ? escale * grad_vol[((size_t)(kb + kk) * s.ny + j) * s.nx + i] : 0.0f;
+                    const ExactVoxel x = exact_voxel(s, U, V, W);
+                    const int ia = floor_to_int(x.A), ib = floor_to_int(x.B);
+                    const float wa = __builtin_amdgcn_fractf(x.A), wb = __builtin_amdgcn_fractf(x.B);
+                    const DetTap3* p = view + (ib * NU + ia);
+                    const float4 ql = p->l, qa = p->a, qb = p->b;
+                    const float l = lerp_f(lerp_f(ql.x, ql.y, wa), lerp_f(ql.z, ql.w, wa), wb);
+                    const float la = lerp_f(lerp_f(qa.x, qa.y, wa), lerp_f(qa.z, qa.w, wa), wb);
+                    const float lb = lerp_f(lerp_f(qb.x, qb.y, wa), lerp_f(qb.z, qb.w, wa), wb);
+                    const float ec = MODE == DP_W_FDK ? ek * (x.iw * x.iw) * x.iw : ek * x.iw;
+                    const float c1 = ec * la, c2 = ec * lb;
+                    const float c3 = -ec * fmaf(la, x.ap, fmaf(lb, x.bp, kappa * l));
+                    const float pk = pk0 + (float)kk;
+                    A1 += c1; A2 += c2; A3 += c3;
+                    Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
+                }
             }
+            const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
+                                          pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
+            wave_partials(r, lane, mine + vv * kVdChannels);
         }
-        const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
-                                      pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
-        wave_partials<true>(r, lane, partials + ((size_t)v * nwv + wv) * kVdChannels);
     }
+    vd_shared_store<true>(sh, v0, Vc, blk, nblk, exact_views, partials);
 }
 
 template <int MODE>
-static void vd_bp_dispatch(const GeoScalars& s, int V, const ViewGeo* views, const float4* projq,
-                           float* vol, hipStream_t st)
+static void vd_bp_dispatch(const GeoScalars& s, int v0, int Vc, const ViewGeo* views,
+                           const float4* projq, float* vol, bool first, bool last, hipStream_t st)
 {
     dim3 block(kVdBx, kVdBy);
     dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy, (s.nz + kVdBpCol - 1) / kVdBpCol);
-    vd_bp_kernel<MODE, kVdBpCol><<<grid, block, 0, st>>>(s, V, views, projq, vol);
+    vd_bp_kernel<MODE, kVdBpCol><<<grid, block, 0, st>>>(s, v0, Vc, views, projq, vol, first, last);
 }
 
-void launch_vd_bp(const GeoScalars& s, int V, const ViewGeo* views, const float4* projq, float* vol,
-                  int weight_mode, hipStream_t st)
+void launch_vd_bp(const GeoScalars& s, int v0, int Vc, const ViewGeo* views, const float4* projq,
+                  float* vol, int weight_mode, bool first, bool last, hipStream_t st)
 {
     prof_begin(DP_K_VD_BP, st);
     if (weight_mode == DP_W_FDK)
-        vd_bp_dispatch<DP_W_FDK>(s, V, views, projq, vol, st);
+        vd_bp_dispatch<DP_W_FDK>(s, v0, Vc, views, projq, vol, first, last, st);
     else
-        vd_bp_dispatch<DP_W_NONE>(s, V, views, projq, vol, st);
+        vd_bp_dispatch<DP_W_NONE>(s, v0, Vc, views, projq, vol, first, last, st);
     prof_end(DP_K_VD_BP, st);
 }
 
@@ -454,30 +565,47 @@ __global__ __launch_bounds__(256) void fill_zero_i32_kernel(int* __restrict__ p,
     if (t < n) p[t] = 0;
 }
 
-template <int MODE>
-static void vd_grad_dispatch(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
-                             const float* grad_vol, float* partials, hipStream_t st)
+void launch_vd_flags_clear(int V, int* flags, hipStream_t st)
 {
-    dim3 block(kVdBx, kVdBy);
-    dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy,
-              (s.nz + kVdGradCol - 1) / kVdGradCol);
-    // the per-view flags follow the partials (one set of kVdChannels per wavefront and view)
-    int* exact_views = reinterpret_cast<int*>(partials + (size_t)V * grid.x * grid.y * grid.z * kVdBy * kVdChannels);
-    fill_zero_i32_kernel<<<(V + 255) / 256, 256, 0, st>>>(exact_views, V);
-    vd_grad_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol, partials,
-                                                             exact_views);
-    vd_grad_exact_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, V, views, proj4, grad_vol,
-                                                                   partials, exact_views);
+    fill_zero_i32_kernel<<<(V + 255) / 256, 256, 0, st>>>(flags, V);
 }
 
-void launch_vd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float4* proj4,
-                    const float* grad_vol, float* partials, int weight_mode, hipStream_t st)
+VdGradGrid vd_grad_grid(const GeoScalars& s)
+{
+    VdGradGrid g;
+    const int gx = (s.nx + kVdBx - 1) / kVdBx, gy = (s.ny + kVdBy - 1) / kVdBy;
+    const int groups = (s.nz + kVdGradCol - 1) / kVdGradCol;
+    // enough blocks to fill the chip several times over; beyond that, blocks
+    // take several column groups each (fewer partial sets to write and sum)
+    g.zpb = std::max(1, std::min(8, gx * gy * groups / kVdGradMinBlocks));
+    g.gz = (groups + g.zpb - 1) / g.zpb;
+    g.blocks = gx * gy * g.gz;
+    return g;
+}
+
+template <int MODE>
+static void vd_grad_dispatch(const GeoScalars& s, int v0, int Vc, const ViewGeo* views,
+                             const DetTap3* det, const float* grad_vol, float* partials, int* flags,
+                             hipStream_t st)
+{
+    const VdGradGrid vg = vd_grad_grid(s);
+    dim3 block(kVdBx, kVdBy);
+    dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy, vg.gz);
+    vd_grad_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, v0, Vc, vg.zpb, views, det,
+                                                             grad_vol, partials, flags);
+    vd_grad_exact_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, v0, Vc, vg.zpb, views, det,
+                                                                   grad_vol, partials, flags);
+}
+
+void launch_vd_grad(const GeoScalars& s, int v0, int Vc, const ViewGeo* views, const DetTap3* det,
+                    const float* grad_vol, float* partials, int* flags, int weight_mode,
+                    hipStream_t st)
 {
     prof_begin(DP_K_VD_GRAD, st);
     if (weight_mode == DP_W_FDK)
-        vd_grad_dispatch<DP_W_FDK>(s, V, views, proj4, grad_vol, partials, st);
+        vd_grad_dispatch<DP_W_FDK>(s, v0, Vc, views, det, grad_vol, partials, flags, st);
     else
-        vd_grad_dispatch<DP_W_NONE>(s, V, views, proj4, grad_vol, partials, st);
+        vd_grad_dispatch<DP_W_NONE>(s, v0, Vc, views, det, grad_vol, partials, flags, st);
     prof_end(DP_K_VD_GRAD, st);
 }
 

@@ -350,3 +350,14 @@ def config4_problems(device, n_problems: int = 16):
         truth = torch.tensor(random_poses(V, 5.0, 3.0, rng), dtype=torch.float64, device=device)
         out.append(dict(geom=g, vol=vol, angles=angles, truth=truth))
     return out
+
+
+def poisson_log_noise(l, photons: float, generator):
+    """Noisy line integrals of a transmission measurement: per pixel, counts
+    N ~ Poisson(photons * exp(-l)) with `photons` unattenuated photons, then
+    -log(max(N, 1) / photons).  l: torch tensor of line integrals (any shape,
+    any device); `generator` (a torch.Generator on l's device) seeds the draws."""
+    import torch
+    lam = photons * torch.exp(-l.to(torch.float64))
+    n = torch.poisson(lam, generator=generator)
+    return (-torch.log(n.clamp_min(1.0) / photons)).to(l.dtype)

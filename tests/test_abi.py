@@ -90,6 +90,10 @@ def test_invalid_arguments_rejected_before_launch(lib):
     assert _call_fwd(lib, g, ws=(1 << 24) + 8) == -1  # misaligned workspace
     big = g.replace(nx=2000, ny=2000, nz=2000)
     assert _call_fwd(lib, big) == -4
+    # a long thin volume: fewer than 2^31 padded voxels, but an x extent that
+    # 16-bit box origins cannot hold
+    assert _call_fwd(lib, g.replace(nx=65532, ny=4, nz=4, vx=0.01)) == -4
+    assert b"indexing" in lib.dp_last_error()
     gs = m.geom_struct(g)
     p = C.c_void_p(1 << 20)
     ws = m.workspace_bytes(g, 1, m.OP_BP)

@@ -44,17 +44,21 @@ def test_multi_gpu_request_exits(monkeypatch, capsys):
 
 
 def test_gather_roofline_fields(monkeypatch):
-    """The gather roofline divides the measured L2 bandwidth by 128 B per
-    sample, and takes counter figures only while the kernel hash matches."""
+    """The gather roofline divides the measured LDS read bandwidth by 128 B
+    per sample (the taps come from LDS), reports the L2 and HBM traffic
+    beside, and takes counter figures only while the kernel hash matches."""
     import bench
-    probe = {"l2_read_GBps": 32000.0, "hbm_read_GBps": 7000.0}
+    probe = {"lds_read_GBps": 127000.0, "l2_read_GBps": 32000.0, "hbm_read_GBps": 7000.0}
     fw = {"n_samples": 6.4e9, "ms_step": 20.0,
           "roofline": {"kernel": "rd_fused", "kernel_ms": 16.0, "traffic": 1.6e11,
                        "source_hash": "nomatch"}}
     g = bench.gather_roofline(fw, probe)
-    assert g["ceiling_samples_per_s"] == pytest.approx(32000e9 / 128)
-    assert g["step_frac"] == pytest.approx(round(6.4e9 / 0.02 / (32000e9 / 128), 4))
-    assert g["kernel_frac"] == pytest.approx(round(6.4e9 / 0.016 / (32000e9 / 128), 4))
+    assert g["ceiling"] == "lds"
+    assert g["ceiling_samples_per_s"] == pytest.approx(127000e9 / 128)
+    assert g["step_frac"] == pytest.approx(round(6.4e9 / 0.02 / (127000e9 / 128), 4))
+    assert g["kernel_frac"] == pytest.approx(round(6.4e9 / 0.016 / (127000e9 / 128), 4))
+    assert g["kernel_frac"] < 1.0
+    assert g["lds_GBps"] == pytest.approx(round(6.4e9 / 0.016 * 128 / 1e9, 1))
     assert g["l2_bytes_per_launch"] is None and g["l2_frac"] is None  # stale hash
     assert g["beyond_l2_GBps"] == pytest.approx(1.6e11 / 0.016 / 1e9)
     assert g["beyond_l2_frac_of_hbm_stream"] == pytest.approx(round(1.6e11 / 0.016 / 1e9 / 7000.0, 4))

@@ -165,3 +165,67 @@ def test_bias_activation_and_its_backward_are_exact(dp, relu):
     dz = pr.act_bwd(dy, y, relu=relu)
     ref_dz = torch.where(y.float() > 0, dy, torch.zeros_like(dy)) if relu else dy
     assert torch.equal(dz, ref_dz.to(torch.bfloat16))
+
+
+def _bf16_ulp(a):
+    """Spacing of bfloat16 values at |a| (8 significant bits); 0 for a == 0."""
+    a = np.abs(np.asarray(a, np.float64))
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    return np.where(a > 0, np.exp2(e - 7), 0.0)
+
+
+def _layerwise_check(net, x):
+    """Teacher-forced, element by element: every conv layer of the library is
+    fed the oracle's own BF16 input activation of that layer, and its BF16
+    output must equal the oracle's within one BF16 spacing plus the FP32
+    accumulation bound 1e-5 (|W| |x| + |b|) of each element (identical
+    operands, so the FP32 sums differ only in order, and a rounding to BF16
+    can land on the neighbouring value only where the pre-activation lies
+    within that bound of a rounding boundary); the head, fed the oracle's
+    features, within 1e-5 (|W| |f| + |b|) per sample and output.  Then the
+    end-to-end output, per sample and output, within 2^-4 of the output's
+    magnitude scale (|W| |f| + |b|): a few BF16 flips compounded over the
+    layers stay far below that, a wrong element does not."""
+    from paper_2508_13304_amd import proposal as pr
+    convs = [(W.cpu().numpy().astype(np.float64).reshape(W.shape[0], 3, 3, -1), b.cpu().numpy().astype(np.float64), s)
+             for W, b, s in net.convs]
+    Wfc = net.Wfc.cpu().numpy().astype(np.float64)
+    bfc = net.bfc.cpu().numpy().astype(np.float64)
+    ref, acts = ocnn.network_forward(x, (convs, (Wfc, bfc)))
+    worst = 0.0
+    for li, ((Wl, bl, s), (Wt, bt, _)) in enumerate(zip(convs, net.convs)):
+        h = acts[li]
+        col, Ho, Wo = pr.im2col(bf(h), s)
+        z = pr.gemm(col, Wt.to(torch.bfloat16).contiguous(), tb=True)
+        y = pr.bias_act(z, bt, relu=True).float().cpu().numpy().reshape(acts[li + 1].shape)
+        yref = acts[li + 1]
+        mag = ocnn.conv3x3_forward(np.abs(h), np.abs(ocnn.bf16(Wl)), np.abs(bl), s)
+        tol = _bf16_ulp(np.maximum(np.abs(y), np.abs(yref))) + 1e-5 * mag + 1e-30
+        err = np.abs(y - yref)
+        assert np.all(err <= tol), (li, float((err / tol).max()))
+        worst = max(worst, float((err / tol).max()))
+    feat = acts[-1].reshape(acts[-1].shape[0], -1)
+    out1 = (pr.gemm(bf(feat), net.Wfc.to(torch.bfloat16).contiguous(), tb=True) + net.bfc).cpu().numpy()
+    scale = np.abs(feat) @ np.abs(ocnn.bf16(Wfc)).T + np.abs(bfc)
+    assert np.all(np.abs(out1 - ref) <= 1e-5 * scale + 1e-30)
+    got = net.forward(bf(x)).cpu().numpy()
+    rel = np.abs(got - ref) / scale
+    assert np.all(rel <= 2.0 ** -4), float(rel.max())
+    return worst, float(rel.max())
+
+
+def test_network_elementwise_small(dp):
+    from paper_2508_13304_amd import proposal as pr
+    net = pr.ProposalNet(size=64, channels=(8, 16, 16, 32), seed=3)
+    rng = np.random.default_rng(15)
+    _layerwise_check(net, ocnn.bf16(rng.uniform(0, 1, (3, 64, 64, 2))))
+
+
+def test_network_elementwise_full_size(dp):
+    import os
+    from paper_2508_13304_amd import proposal as pr
+    if not os.path.exists(pr.WEIGHTS):
+        pytest.skip("no trained proposal weights committed")
+    net = pr.ProposalNet.load(pr.WEIGHTS)
+    rng = np.random.default_rng(17)
+    _layerwise_check(net, ocnn.bf16(rng.uniform(0, 1, (2, net.size, net.size, 2))))

@@ -192,8 +192,8 @@ def test_fused_full_launch_the_bench_times(dp, oracle):
 def test_sparse_rays_unstaged_tiles(dp, oracle, variant):
     """Rays much sparser than voxels (1.33 mm pixels at the isocentre over
     0.5 mm voxels): a 16 x 16 tile's chunk box exceeds the LDS capacity even
-    one sample deep, so every tile gathers directly from the interleaved
-    (mu, Gx, Gy, Gz) copy.  Fused SSD entry, Gauss-Newton matrix and the
+    one sample deep, so every tile forms (mu, Gx, Gy, Gz) at its trilinear
+    corners from the volume directly.  Fused SSD entry, Gauss-Newton matrix and the
     plain gradient entry against the oracle; ragged detector tail."""
     rng = synth.rng_for(214)
     g = Geom(80, 72, 64, 0.5, 0.5, 0.5, 40, 36, 2.0, 2.0, off_u=0.5)
@@ -219,3 +219,19 @@ def test_sparse_rays_unstaged_tiles(dp, oracle, variant):
     assert err.max() <= 1e-4
     check_grads(f"sparse-v{variant} grad", gp.cpu().numpy(),
                 oracle.project_fwd_grad_pose(g, angles, poses, vol, w))
+
+
+def test_fused_full_size_oracle_targets_dense(dp, oracle):
+    """Registration scale at full size (256^3 phantom, 512x512 detector) with
+    the target DRR rendered by the oracle at the true pose, as the
+    registration workload has it, and 8 candidate poses in one launch: every
+    pixel carries a residual, so dL/dl = 2 (l - y) is dense on all 8 views.
+    Whole projections (<= 1e-5), per-view SSD (<= 1e-5 relative) and pose
+    gradients (<= 1e-4, oracle gradient with dL/dl = 2 (l_ref - y))."""
+    c = synth.config2_inputs()
+    g, vol = c["geom"], c["vol"]
+    V = 8
+    angles, poses = c["angles"][:V], c["poses"][:V]
+    y1 = oracle.project_fwd(g, c["angles"][:1], c["target_pose"], vol).astype(np.float32)
+    y = np.repeat(y1, V, axis=0)
+    _fused_case(dp, oracle, g, vol, angles, poses, y, "full-size dense")

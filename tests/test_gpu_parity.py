@@ -177,15 +177,21 @@ def test_config2_full_size_sampled(dp, oracle):
 # ---------------------------------------------------------------------------
 
 def _bp_case(dp, oracle, g, proj, angles, poses, mode, e=None, name="bp"):
+    """Back-projection and its pose gradient against the oracle; returns the
+    per-view flags of columns projected voxel by voxel in FP64."""
     say(f"case {name}: vol {g.vol_shape} det {g.nv}x{g.nu} V={len(angles)} mode={mode}")
     b_gpu = dp.backproject(g, f64(angles), f64(poses), f32(proj), mode).cpu().numpy()
     b_ref = oracle.backproject(g, angles, poses, proj, mode)
     check_values(f"{name} backproject", b_gpu, b_ref)
     if e is None:
         e = np.random.default_rng(8).standard_normal(g.vol_shape).astype(np.float32)
-    g_gpu = dp.backproject_grad_pose(g, f64(angles), f64(poses), f32(proj), f32(e), mode).cpu().numpy()
+    V = len(angles)
+    ws = torch.empty(dp.workspace_bytes(g, V, dp.OP_BP_GRAD), dtype=torch.uint8, device="cuda:0")
+    g_gpu = dp.backproject_grad_pose(g, f64(angles), f64(poses), f32(proj), f32(e), mode,
+                                     ws=ws).cpu().numpy()
     g_ref = oracle.backproject_grad_pose(g, angles, poses, proj, e, mode)
     check_grads(f"{name} backproject_grad_pose", g_gpu, g_ref)
+    return dp.bp_grad_flags(g, V, ws).cpu().numpy()
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -224,7 +230,30 @@ def test_backproject_source_inside_volume(dp, oracle, mode, tilt_deg):
     angles = rng.uniform(0, 2 * math.pi, V)
     poses = synth.random_poses(V, 2.0, tilt_deg, rng)
     proj = synth.smooth_images(V, g.nv, g.nu, rng, signed=True)
-    _bp_case(dp, oracle, g, proj, angles, poses, mode, name=f"bp-source-inside-{mode}-tilt{tilt_deg:g}")
+    flags = _bp_case(dp, oracle, g, proj, angles, poses, mode,
+                     name=f"bp-source-inside-{mode}-tilt{tilt_deg:g}")
+    say(f"FP64 per-voxel views: {flags.tolist()}")
+    if tilt_deg == 3.0:
+        # whole columns within 1 mm of the source plane: the FP64 pass ran
+        assert flags.any()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backproject_source_inside_volume_config_detector(dp, oracle, mode):
+    """Source inside the volume with a config-scale detector (SDD 1500 mm,
+    0.776 mm pixels, S / du ~ 1900): columns passing close to the source
+    plane have middle voxels projecting tens of thousands of pixels off the
+    detector while their other voxels land on it; those columns go to the
+    FP64 per-voxel pass (anchor limit of a few detector widths)."""
+    rng = synth.rng_for(207)
+    g = Geom(24, 24, 24, 2.0, 2.0, 2.0, 96, 80, 0.776, 0.776, sad=20.0, sdd=1500.0)
+    V = 3
+    angles = rng.uniform(0, 2 * math.pi, V)
+    poses = synth.random_poses(V, 2.0, 3.0, rng)
+    proj = synth.smooth_images(V, g.nv, g.nu, rng, signed=True)
+    flags = _bp_case(dp, oracle, g, proj, angles, poses, mode, name=f"bp-source-inside-c3det-{mode}")
+    say(f"FP64 per-voxel views: {flags.tolist()}")
+    assert flags.any()
 
 
 def test_backproject_tiny(dp, oracle):
@@ -296,3 +325,30 @@ def test_non_default_stream_and_outputs_overwritten(dp, oracle):
     s.synchronize()
     ref = oracle.project_fwd(g, angles, poses, vol)
     check_values("stream project_fwd", out.cpu().numpy(), ref)
+
+
+def test_config3_dense_sharpness_gradient(dp, oracle):
+    """Config 3 sizes and launch (512^3 recon, all 360 views of 512x384, FDK
+    weight, sinusoidal motion) with a dense dL/dmu: the gradient of the
+    image-sharpness loss (negative sum of squared forward differences, the
+    oracle's own) of a 512^3 ellipsoid volume with noise, non-zero on every
+    voxel.  The pose gradient of each view depends only on that view's image
+    and dL/dmu, so the oracle evaluates 12 of the 360 views (every 30th) and
+    the GPU's values for those views are compared (<= 1e-4)."""
+    from oracle import fdk
+    g = synth.geom_c3_recon()
+    m = synth.config3_motion()
+    angles, poses = m["angles"], m["poses"]
+    V = len(angles)
+    rng = np.random.default_rng(19)
+    proj = synth.smooth_images(V, g.nv, g.nu, rng, n_blobs=4, signed=True)
+    vol = synth.ellipsoid_phantom(g.nx, g.vx, 20, rng).astype(np.float64)
+    vol += rng.normal(0.0, 1e-3, vol.shape)
+    e = fdk.sharpness_grad(vol).astype(np.float32)
+    del vol
+    assert np.count_nonzero(e) > 0.99 * e.size
+    say(f"config3 dense-e: |e| max {np.abs(e).max():.3e}")
+    g_gpu = dp.backproject_grad_pose(g, f64(angles), f64(poses), f32(proj), f32(e), 1).cpu().numpy()
+    sub = np.arange(0, V, 30)
+    g_ref = oracle.backproject_grad_pose(g, angles[sub], poses[sub], proj[sub], e, 1)
+    check_grads("config3 dense-e backproject_grad_pose", g_gpu[sub], g_ref)

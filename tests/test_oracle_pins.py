@@ -490,3 +490,58 @@ def test_count_samples_consistent(oracle):
     # integer), so x = -16.5 .. 16.5: 67 samples.
     c0 = oracle.count_samples_per_ray(Geom(16, 16, 16, 2.0, 2.0, 2.0, 21, 21, 3.0, 3.0), [0.0], np.zeros(6))
     assert c0[0, 10, 10] == 67
+
+
+# ---------------------------------------------------------------------------
+# Sampled entry points: the id -> (view, row, column) and id -> (i, j, k)
+# decoding of the per-ray and per-voxel checkers used at full size
+# ---------------------------------------------------------------------------
+
+def test_project_fwd_rays_equals_full_projection(oracle):
+    """project_fwd_rays at ray id v*nv*nu + b*nu + a returns exactly the full
+    projection's l_v[b][a] (bit-equal), on a ragged grid with nu != nv and
+    several views, for every id including the first and the last."""
+    g = Geom(13, 11, 9, 2.0, 1.7, 2.3, 23, 17, 3.0, 2.6)
+    rng = synth.rng_for(120)
+    vol = rng.uniform(0.0, 1.0, (g.nz, g.ny, g.nx))
+    angles = np.array([0.2, 1.9, 4.0])
+    poses = synth.random_poses(3, 5.0, 5.0, rng)
+    full = oracle.project_fwd(g, angles, poses, vol)
+    assert full.shape == (3, g.nv, g.nu)
+    order = rng.permutation(np.arange(full.size, dtype=np.int64))
+    got = oracle.project_fwd_rays(g, angles, poses, vol, order)
+    back = np.empty_like(got)
+    back[order] = got
+    assert np.array_equal(back, full.ravel())
+    # a hand-picked id decodes to (v, b, a) = (2, 16, 22), the last pixel
+    last = oracle.project_fwd_rays(g, angles, poses, vol, np.array([2 * 17 * 23 + 16 * 23 + 22]))
+    assert last[0] == full[2, 16, 22]
+    # (v, b, a) = (1, 3, 5): transposed decoding (b <-> a) would pick (1, 5, 3)
+    one = oracle.project_fwd_rays(g, angles, poses, vol, np.array([1 * 17 * 23 + 3 * 23 + 5]))
+    assert one[0] == full[1, 3, 5] and full[1, 3, 5] != full[1, 5, 3]
+    assert np.any(full != 0.0)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backproject_voxels_equals_full_backprojection(oracle, mode):
+    """backproject_voxels at voxel id (k*ny + j)*nx + i returns exactly the
+    full back-projection's mu[k][j][i] (bit-equal), on a ragged grid
+    (nx, ny, nz all different) with several views and both weights."""
+    g = Geom(9, 7, 5, 2.0, 2.5, 1.5, 21, 15, 3.0, 3.0)
+    rng = synth.rng_for(121)
+    angles = np.array([0.4, 2.2, 3.9])
+    poses = synth.random_poses(3, 5.0, 5.0, rng)
+    proj = rng.uniform(0.0, 1.0, (3, g.nv, g.nu))
+    full = oracle.backproject(g, angles, poses, proj, mode)
+    assert full.shape == (g.nz, g.ny, g.nx)
+    order = rng.permutation(np.arange(full.size, dtype=np.int64))
+    got = oracle.backproject_voxels(g, angles, poses, proj, order, mode)
+    back = np.empty_like(got)
+    back[order] = got
+    assert np.array_equal(back, full.ravel())
+    # (i, j, k) = (8, 6, 4) is the last voxel; (i, j, k) = (2, 5, 1) would be
+    # (5, 2, 1) under an i <-> j mix-up
+    last = oracle.backproject_voxels(g, angles, poses, proj, np.array([(4 * 7 + 6) * 9 + 8]), mode)
+    assert last[0] == full[4, 6, 8]
+    one = oracle.backproject_voxels(g, angles, poses, proj, np.array([(1 * 7 + 5) * 9 + 2]), mode)
+    assert one[0] == full[1, 5, 2] and full[1, 5, 2] != full[1, 2, 5]

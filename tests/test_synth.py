@@ -48,3 +48,17 @@ def test_torch_phantom_matches_numpy_recipe():
     a = synth.ellipsoid_phantom_torch(40, 2.0, 8, synth.rng_for(9, 3), "cpu", shell=True)
     b = synth.ellipsoid_phantom(40, 2.0, 8, synth.rng_for(9, 3), shell=True)
     assert np.abs(a.numpy() - b).max() < 1e-6
+
+
+def test_poisson_log_noise_statistics():
+    """Counts are Poisson with mean photons * exp(-l): the re-logged values
+    average l (to first order) with variance exp(l) / photons."""
+    import torch
+    gen = torch.Generator().manual_seed(1)
+    l = torch.full((200000,), 2.0, dtype=torch.float64)
+    y = synth.poisson_log_noise(l, 1e5, gen)
+    assert abs(float(y.mean()) - 2.0) < 1e-3
+    assert abs(float(y.var()) / (np.exp(2.0) / 1e5) - 1.0) < 0.02
+    # zero counts clamp to one photon: finite values
+    y0 = synth.poisson_log_noise(torch.full((10,), 40.0, dtype=torch.float64), 1e5, gen)
+    assert torch.isfinite(y0).all() and float(y0.max()) <= np.log(1e5) + 1e-9
