@@ -120,6 +120,23 @@ int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t n_views, const double
                                  float* proj, double* loss, double* grad_pose,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/* As dp_project_fwd_ssd_grad_pose, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no workspace argument and no allocation of any kind.
+ * The workspace is a 16 MiB array in the library's device memory, one per
+ * GPU, held until the process ends and shared by every call on that GPU; it
+ * holds the per-view setup and the per-tile partial sums, so calls with
+ * dp_workspace_bytes(g, n_views, DP_OP_FWD_SSD) > 16 MiB return
+ * DP_ERR_UNSUPPORTED (at 512 x 512 pixels this allows about 390 views per
+ * call).  Calls that overlap on one GPU (concurrent streams or threads) race
+ * on that array; the kernels overwrite everything they read from it, so
+ * nothing needs clearing between calls.  Arguments, outputs and errors as
+ * dp_project_fwd_ssd_grad_pose. */
+int dp_project_fwd_ssd_grad_pose_noalloc(const dp_geom* g, int32_t n_views, const double* angles,
+                                         const double* poses, const float* vol,
+                                         const float* target, float* proj, double* loss,
+                                         double* grad_pose, void* stream);
+
 /* As dp_project_fwd_ssd_grad_pose, plus the Gauss-Newton matrix of each
  * view's SSD: with J_p = dl_p/dtheta the per-ray pose Jacobian (the sums of
  * Eqs. final_forward / dis_forward for a unit weight on one ray),

@@ -37,7 +37,7 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
            "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16",
            "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update", "dp_read_probe",
-           "dp_bp_grad_flags_offset", "dp_lds_probe")
+           "dp_bp_grad_flags_offset", "dp_lds_probe", "dp_project_fwd_ssd_grad_pose_noalloc")
 MAX_BATCH = 16
 N_VARIANTS = 3
 
@@ -109,6 +109,8 @@ def load(path: str | None = None):
     lib.dp_read_probe.restype = C.c_int
     lib.dp_lds_probe.argtypes = [i32, i32, vp, vp]
     lib.dp_lds_probe.restype = C.c_int
+    lib.dp_project_fwd_ssd_grad_pose_noalloc.argtypes = [g, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.dp_project_fwd_ssd_grad_pose_noalloc.restype = C.c_int
     lib.dp_autotune.argtypes = [i32, g, i32, vp, vp, vp, vp, vp, vp, sz, vp, i32,
                                 C.POINTER(i32), C.POINTER(C.c_float)]
     lib.dp_autotune.restype = C.c_int
@@ -305,6 +307,32 @@ def backproject(geom, angles, poses, proj, weight_mode=W_NONE, out=None, ws=None
                                _stream(stream))
     _check(rc, "dp_backproject")
     return out
+
+
+def project_fwd_ssd_grad_pose_noalloc(geom, angles, poses, vol, target, proj=None, loss=None,
+                                      grad=None, stream=None):
+    """As project_fwd_ssd_grad_pose, through the entry point that allocates
+    nothing (its workspace is the library's fixed device array).  Outputs are
+    allocated here only when not given."""
+    import torch
+    V = _views(angles, poses)
+    dev = vol.device
+    if proj is None:
+        proj = torch.empty((V, geom.nv, geom.nu), dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(V, dtype=torch.float64, device=dev)
+    if grad is None:
+        grad = torch.empty((V, 6), dtype=torch.float64, device=dev)
+    rc = load().dp_project_fwd_ssd_grad_pose_noalloc(
+        C.byref(geom_struct(geom)), V, _dev(angles, torch.float64, "angles"),
+        _dev(poses, torch.float64, "poses"),
+        _dev(vol, torch.float32, "vol", (geom.nz, geom.ny, geom.nx)),
+        _dev(target, torch.float32, "target", (V, geom.nv, geom.nu)),
+        _dev(proj, torch.float32, "proj", (V, geom.nv, geom.nu)),
+        _dev(loss, torch.float64, "loss", (V,)), _dev(grad, torch.float64, "grad", (V, 6)),
+        _stream(stream))
+    _check(rc, "dp_project_fwd_ssd_grad_pose_noalloc")
+    return proj, loss, grad
 
 
 def bp_grad_flags(geom, n_views: int, ws):

@@ -336,6 +336,36 @@ static int fwd_ssd(const dp_geom* g, int32_t V, const double* angles, const doub
     return check_launch(name);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free variant of dp_project_fwd_ssd_grad_pose: its workspace is a
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code never uses the array's name as an address: the device address is
+// taken once per device with hipGetSymbolAddress and kept per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;  // device ordinal -> address of its scratch
+
+static int scratch_for_current_device(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(DP_ERR_HIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DP_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return DP_OK;
+}
+
 int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
                                  const double* poses, const float* vol, const float* target,
                                  float* proj, double* loss, double* grad_pose, void* ws,
@@ -343,6 +373,25 @@ int dp_project_fwd_ssd_grad_pose(const dp_geom* g, int32_t V, const double* angl
 {
     return fwd_ssd(g, V, angles, poses, vol, target, proj, loss, grad_pose, nullptr, ws, ws_bytes,
                    stream, "dp_project_fwd_ssd_grad_pose");
+}
+
+int dp_project_fwd_ssd_grad_pose_noalloc(const dp_geom* g, int32_t V, const double* angles,
+                                         const double* poses, const float* vol,
+                                         const float* target, float* proj, double* loss,
+                                         double* grad_pose, void* stream)
+{
+    int rc = check_geom(g, V);
+    if (rc) return rc;
+    const size_t need = layout(*g, V, DP_OP_FWD_SSD).total;
+    if (need > kScratchBytes)
+        return fail(DP_ERR_UNSUPPORTED,
+                    "dp_project_fwd_ssd_grad_pose_noalloc: needs %zu bytes of scratch, the "
+                    "library holds %zu (fewer views or a smaller detector per call)",
+                    need, kScratchBytes);
+    void* ws = nullptr;
+    if ((rc = scratch_for_current_device(&ws))) return rc;
+    return fwd_ssd(g, V, angles, poses, vol, target, proj, loss, grad_pose, nullptr, ws,
+                   kScratchBytes, stream, "dp_project_fwd_ssd_grad_pose_noalloc");
 }
 
 int dp_project_fwd_ssd_gauss_newton(const dp_geom* g, int32_t V, const double* angles,
