@@ -426,8 +426,10 @@ int32_t dp_version(void);
  *   dp_profile_collect() waits for the recorded events and accumulates
  *   their durations per kernel;
  *   dp_profile_read(k, &ms, &n) returns the accumulated time and launch
- *   count of kernel k (DP_K_*) and resets them.  DP_K_VOL_PREP keeps its
- *   number but is no longer launched: the ray-driven kernels read the
+ *   count of kernel k (DP_K_*) and resets them.  DP_K_VOL_PREP times the
+ *   (mu, gradient) copy that the gradient calls make only for geometries
+ *   whose rays are sparse relative to the voxels (pixel footprint at the
+ *   isocentre above 0.85 voxel); otherwise the ray-driven kernels read the
  *   caller's volume and form its gradient while staging it. */
 enum {
     DP_K_SETUP = 0, DP_K_VOL_PREP = 1, DP_K_RD_FWD = 2, DP_K_RD_GRAD = 3,

@@ -37,6 +37,8 @@ struct Layout {
     size_t n_part = 0;    // partial blocks per view
     size_t spare = 0;     // FWD_SSD: [V][6] f64 pose-gradient slot used by the autotuner
     size_t flags = 0;     // BP_GRAD: [V] int, "a column of this view has no usable anchor"
+    size_t inter = 0;     // FWD_GRAD, FWD_SSD of sparse-ray geometries: padded (mu, G) float4
+    bool has_inter = false;
     int chunk = 0;        // back-projection ops: views per detector-image chunk
     size_t total = 0;
 };
@@ -81,8 +83,18 @@ Layout layout(const dp_geom& g, int V, int op)
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
+        if (sparse_rays(s)) {  // tiles that cannot stage a box gather from this copy
+            L.has_inter = true;
+            L.inter = off;
+            off = align_up(off + padded_volume_elems(g) * sizeof(float4));
+        }
         break;
     case DP_OP_FWD_SSD:
+        if (sparse_rays(s)) {
+            L.has_inter = true;
+            L.inter = off;
+            off = align_up(off + padded_volume_elems(g) * sizeof(float4));
+        }
         L.n_part = (size_t)rd_tiles(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannelsGN * sizeof(float));
@@ -305,9 +317,12 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
     float* part = (float*)(base + L.partials);
+    float4* inter = L.has_inter ? (float4*)(base + L.inter) : nullptr;
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_rd_grad(s, V, views, vol, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V), st);
+    if (inter) launch_vol_inter(s, vol, inter, st);
+    launch_rd_grad(s, V, views, vol, inter, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V),
+                   st);
     launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
     return check_launch("dp_project_fwd_grad_pose");
 }
@@ -328,9 +343,11 @@ static int fwd_ssd(const dp_geom* g, int32_t V, const double* angles, const doub
     char* base = (char*)ws;
     ViewGeo* views = (ViewGeo*)(base + L.views);
     float* part = (float*)(base + L.partials);
+    float4* inter = L.has_inter ? (float4*)(base + L.inter) : nullptr;
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
-    launch_rd_fused(s, V, views, vol, target, proj, part, hess != nullptr,
+    if (inter) launch_vol_inter(s, vol, inter, st);
+    launch_rd_fused(s, V, views, vol, inter, target, proj, part, hess != nullptr,
                     variant_for(DP_OP_FWD_SSD, *g, V), st);
     launch_finalize_fwd_ssd(s, V, views, part, (int)L.n_part, grad_pose, loss, hess, st);
     return check_launch(name);
@@ -716,10 +733,13 @@ static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t w
         char* base = (char*)ws + offs[i];
         ViewGeo* views = (ViewGeo*)(base + L.views);
         launch_view_setup(s, q.n_views, q.angles, q.poses, views, st);
+        float4* inter = op != DP_OP_FWD && L.has_inter ? (float4*)(base + L.inter) : nullptr;
+        if (inter) launch_vol_inter(s, q.vol, inter, st);
         RdBatchItem& it = bt.it[j];
         it.s = s;
         it.views = views;
         it.vol = q.vol;
+        it.inter = inter;
         it.gin = op == DP_OP_FWD ? nullptr : q.grad_proj;
         it.out = op == DP_OP_FWD ? q.proj : (float*)(base + L.partials);
         it.proj = op == DP_OP_FWD_SSD ? q.proj : nullptr;

@@ -95,8 +95,15 @@ void launch_det_tap3(const GeoScalars& s, int V, const float* proj, DetTap3* det
 // The ray-driven kernels read the caller's volume [nz][ny][nx] directly.
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
                    float* proj, int variant, hipStream_t st);
+// inter: padded (mu, Gx, Gy, Gz) copy for tiles that cannot stage a box, or NULL
 void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
-                    const float* grad_proj, float* partials, int variant, hipStream_t st);
+                    const float4* inter, const float* grad_proj, float* partials, int variant,
+                    hipStream_t st);
+// The padded (mu, Gx, Gy, Gz) copy (G: central differences, not halved), and
+// whether a geometry's rays are sparse enough relative to its voxels that the
+// gradient kernels want it.
+void launch_vol_inter(const GeoScalars& s, const float* vol, float4* inter, hipStream_t st);
+bool sparse_rays(const GeoScalars& s);
 
 // Uneven batches of ray-driven problems in one launch (descriptors by value).
 constexpr int kRdMaxBatch = 16;
@@ -108,6 +115,7 @@ struct RdBatchItem {
     GeoScalars s;
     const ViewGeo* views;
     const float* vol;   // the problem's volume [nz][ny][nx]
+    const float4* inter;  // padded (mu, Gx, Gy, Gz) for sparse-ray geometries, or NULL
     const float* gin;   // dL/dl (gradient) or the target y (single-pass SSD)
     float* out;         // DRRs (forward) or per-block partials (gradient, SSD)
     float* proj;        // DRRs of the single-pass SSD batch
@@ -120,8 +128,8 @@ struct RdBatch {
 };
 void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st);
 void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
-                     const float* target, float* proj, float* partials, bool hess, int variant,
-                     hipStream_t st);
+                     const float4* inter, const float* target, float* proj, float* partials,
+                     bool hess, int variant, hipStream_t st);
 void launch_finalize_fwd_ssd(const GeoScalars& s, int V, const ViewGeo* views,
                              const float* partials, int n_part, double* grad_pose, double* loss,
                              double* hess, hipStream_t st);

@@ -1,4 +1,5 @@
-// Elementwise detector-image preparation passes (HBM-bound, coalesced along u):
+// Elementwise preparation passes (HBM-bound, coalesced along x / u): the
+// (mu, G) interleave of sparse-ray geometries, and detector images:
 //   - per padded detector pixel, the 2x2 bilinear footprint of the
 //     zero-extended image as one float4, for the back-projection;
 //   - detector gradient field (central differences of l, Sec. II-C) stored
@@ -88,6 +89,56 @@ void launch_det_tap3(const GeoScalars& s, int V, const float* proj, DetTap3* det
     prof_begin(DP_K_DET_PREP, st);
     det_tap3_kernel<<<grid, 256, 0, st>>>(s.nu, s.nv, proj, det);
     prof_end(DP_K_DET_PREP, st);
+}
+
+__device__ inline float vox_at(const float* __restrict__ v, int nx, int ny, int nz, int i, int j,
+                               int k)
+{
+    if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz) return 0.0f;
+    return v[((size_t)k * ny + j) * nx + i];
+}
+
+// Per padded voxel (I, J, K) (pad kPadV), (mu, Gx, Gy, Gz) with G the central
+// difference of the zero-extended volume on grid voxels (the ray kernels'
+// staging convention: not halved), zero in the pad.  For the gradient
+// kernels' tiles whose rays are too sparse to stage a box: one 16-byte
+// gather per trilinear corner.
+__global__ __launch_bounds__(256) void vol_inter_kernel(int nx, int ny, int nz,
+                                                        const float* __restrict__ vol,
+                                                        float4* __restrict__ inter)
+{
+    const int NX = nx + 2 * kPadV, NY = ny + 2 * kPadV;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y, K = blockIdx.z;
+    if (I >= NX) return;
+    const int i = I - kPadV, j = J - kPadV, k = K - kPadV;
+    float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz) {
+        o.x = vol[((size_t)k * ny + j) * nx + i];
+        o.y = vox_at(vol, nx, ny, nz, i + 1, j, k) - vox_at(vol, nx, ny, nz, i - 1, j, k);
+        o.z = vox_at(vol, nx, ny, nz, i, j + 1, k) - vox_at(vol, nx, ny, nz, i, j - 1, k);
+        o.w = vox_at(vol, nx, ny, nz, i, j, k + 1) - vox_at(vol, nx, ny, nz, i, j, k - 1);
+    }
+    inter[((size_t)K * NY + J) * NX + I] = o;
+}
+
+void launch_vol_inter(const GeoScalars& s, const float* vol, float4* inter, hipStream_t st)
+{
+    const int NX = s.nx + 2 * kPadV;
+    dim3 grid((NX + 255) / 256, s.ny + 2 * kPadV, s.nz + 2 * kPadV);
+    prof_begin(DP_K_VOL_PREP, st);
+    vol_inter_kernel<<<grid, 256, 0, st>>>(s.nx, s.ny, s.nz, vol, inter);
+    prof_end(DP_K_VOL_PREP, st);
+}
+
+// A 16 x 16 tile's rays are sparse when the tile spans more than 13 voxels at
+// the isocentre (pixel footprint above 0.85 voxel): chunk boxes of oblique
+// views then outgrow the LDS even one sample deep.
+bool sparse_rays(const GeoScalars& s)
+{
+    const double pix = (s.du > s.dv ? s.du : s.dv) * s.sad / s.sdd;
+    const double h = s.vx < s.vy ? (s.vx < s.vz ? s.vx : s.vz) : (s.vy < s.vz ? s.vy : s.vz);
+    return pix > 0.85 * h;
 }
 
 void launch_det_pad(const GeoScalars& s, int V, const float* proj, float4* projq, hipStream_t st)

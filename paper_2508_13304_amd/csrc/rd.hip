@@ -618,19 +618,41 @@ __device__ inline float mu_at(const float* __restrict__ mu, int nx, int ny, int 
     return mu[((size_t)k * ny + j) * nx + i];
 }
 
-// (mu, Gx, Gy, Gz) at padded voxel (I, J, K), as the box loaders form them.
-__device__ inline float4 mug_at(const float* __restrict__ mu, int nx, int ny, int nz, int I, int J,
-                                int K)
+// mu and (Gx, Gy, Gz) at the 8 trilinear corners of base padded voxel
+// (I, J, K), as the box loaders form them, from the 32 voxels they need:
+// the 2x2x2 core and, per axis, the two voxels beyond it on the 4 core lines
+// along that axis.
+__device__ inline void corners_at(const float* __restrict__ mu, int nx, int ny, int nz, int I,
+                                  int J, int K, float (&m)[2][2][2], float3 (&q)[2][2][2])
 {
-    const int i = I - kPadV, j = J - kPadV, k = K - kPadV;
-    if ((unsigned)i >= (unsigned)nx || (unsigned)j >= (unsigned)ny || (unsigned)k >= (unsigned)nz)
-        return make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 o;
-    o.x = mu_at(mu, nx, ny, nz, I, J, K);
-    o.y = mu_at(mu, nx, ny, nz, I + 1, J, K) - mu_at(mu, nx, ny, nz, I - 1, J, K);
-    o.z = mu_at(mu, nx, ny, nz, I, J + 1, K) - mu_at(mu, nx, ny, nz, I, J - 1, K);
-    o.w = mu_at(mu, nx, ny, nz, I, J, K + 1) - mu_at(mu, nx, ny, nz, I, J, K - 1);
-    return o;
+    float xo[2][2][2], yo[2][2][2], zo[2][2][2];  // [line][line][-1 / +2 side]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) m[a][b][c] = mu_at(mu, nx, ny, nz, I + c, J + b, K + a);
+            xo[a][b][0] = mu_at(mu, nx, ny, nz, I - 1, J + b, K + a);  // [dz][dy]
+            xo[a][b][1] = mu_at(mu, nx, ny, nz, I + 2, J + b, K + a);
+            yo[a][b][0] = mu_at(mu, nx, ny, nz, I + b, J - 1, K + a);  // [dz][dx]
+            yo[a][b][1] = mu_at(mu, nx, ny, nz, I + b, J + 2, K + a);
+            zo[a][b][0] = mu_at(mu, nx, ny, nz, I + b, J + a, K - 1);  // [dy][dx]
+            zo[a][b][1] = mu_at(mu, nx, ny, nz, I + b, J + a, K + 2);
+        }
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int i = I + dx - kPadV, j = J + dy - kPadV, k = K + dz - kPadV;
+                const bool on = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny &&
+                                (unsigned)k < (unsigned)nz;
+                const float xp = dx ? xo[dz][dy][1] : m[dz][dy][1], xm = dx ? m[dz][dy][0] : xo[dz][dy][0];
+                const float yp = dy ? yo[dz][dx][1] : m[dz][1][dx], ym = dy ? m[dz][0][dx] : yo[dz][dx][0];
+                const float zp = dz ? zo[dy][dx][1] : m[1][dy][dx], zm = dz ? m[0][dy][dx] : zo[dy][dx][0];
+                q[dz][dy][dx] = on ? make_float3(xp - xm, yp - ym, zp - zm) : make_float3(0.f, 0.f, 0.f);
+            }
 }
 
 // One chunk of one ray: first local position and per-sample increment.
@@ -809,6 +831,7 @@ struct GradAcc {
 template <int MCH, int CAP, bool FUSED, bool HESS = false>
 __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
                                     const float* __restrict__ mu,
+                                    const float4* __restrict__ inter,
                                     const float* __restrict__ gin,
                                     float* __restrict__ proj_out,
                                     float* __restrict__ partials, int v, int tile, int tiles,
@@ -818,8 +841,10 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     // written to proj_out and the SSD weight w = 2 (l - y) is applied to the
     // gradient sums at the end.  Otherwise gin is dL/dl.  The chunk boxes
     // hold (mu, Gx, Gy, Gz) (FUSED) or (Gx, Gy, Gz) per voxel, formed from
-    // mu while loading; tiles whose boxes do not fit the LDS form the same
-    // values per trilinear corner from mu directly.
+    // mu while loading.  Tiles whose boxes do not fit the LDS gather the same
+    // values per trilinear corner: one float4 per corner from `inter` (a
+    // padded (mu, Gx, Gy, Gz) copy the caller makes for sparse-ray
+    // geometries, where such tiles are common), else from mu directly.
     constexpr int C = FUSED ? 4 : 3;
     int a, b, a0, b0;
     rd_pixel(s, tile, a, b, a0, b0);
@@ -898,19 +923,24 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
             const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
             const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-            const int I = (int)fx, J = (int)fy, Kz = (int)fz;
             float3 q[2][2][2];
             float m[2][2][2];
+            if (inter) {
+                const int NXY = NX * NY;
+                const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
 #pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
+                for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-                for (int dy = 0; dy < 2; ++dy)
+                    for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-                    for (int dx = 0; dx < 2; ++dx) {
-                        const float4 t = mug_at(mu, s.nx, s.ny, s.nz, I + dx, J + dy, Kz + dz);
-                        m[dz][dy][dx] = t.x;
-                        q[dz][dy][dx] = make_float3(t.y, t.z, t.w);
-                    }
+                        for (int dx = 0; dx < 2; ++dx) {
+                            const float4 t = inter[(size_t)idx + dz * NXY + dy * NX + dx];
+                            m[dz][dy][dx] = t.x;
+                            q[dz][dy][dx] = make_float3(t.y, t.z, t.w);
+                        }
+            } else {
+                corners_at(mu, s.nx, s.ny, s.nz, (int)fx, (int)fy, (int)fz, m, q);
+            }
             const float wx = X - fx, wy = Y - fy, wz = Z - fz;
             if (FUSED) {
                 const float c00 = lerpf(m[0][0][0], m[0][0][1], wx), c10 = lerpf(m[0][1][0], m[0][1][1], wx);
@@ -988,12 +1018,13 @@ template <int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                                                              const ViewGeo* __restrict__ views,
                                                              const float* __restrict__ mu,
+                                                             const float4* __restrict__ inter,
                                                              const float* __restrict__ grad_proj,
                                                              float* __restrict__ partials)
 {
     __shared__ float lds[3 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, false>(s, views, mu, grad_proj, nullptr, partials, blockIdx.y,
+    rd_grad_tile<MCH, CAP, false>(s, views, mu, inter, grad_proj, nullptr, partials, blockIdx.y,
                                   blockIdx.x, gridDim.x, lds, sh);
 }
 
@@ -1003,13 +1034,14 @@ template <int MCH, int CAP, bool HESS>
 __global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
                                                               const ViewGeo* __restrict__ views,
                                                               const float* __restrict__ mu,
+                                                              const float4* __restrict__ inter,
                                                               const float* __restrict__ target,
                                                               float* __restrict__ proj,
                                                               float* __restrict__ partials)
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, true, HESS>(s, views, mu, target, proj, partials, blockIdx.y,
+    rd_grad_tile<MCH, CAP, true, HESS>(s, views, mu, inter, target, proj, partials, blockIdx.y,
                                        blockIdx.x, gridDim.x, lds, sh);
 }
 
@@ -1045,7 +1077,7 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.gin, nullptr, it.out,
+    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.inter, it.gin, nullptr, it.out,
                                   local / it.tiles, local % it.tiles, it.tiles, lds, sh);
 }
 
@@ -1058,7 +1090,7 @@ __global__ __launch_bounds__(kRdThreads) void rd_fused_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP, true, true>(it.s, it.views, it.vol, it.gin, it.proj, it.out,
+    rd_grad_tile<MCH, CAP, true, true>(it.s, it.views, it.vol, it.inter, it.gin, it.proj, it.out,
                                        local / it.tiles, local % it.tiles, it.tiles, lds, sh);
 }
 
@@ -1076,40 +1108,41 @@ void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float
 }
 
 void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
-                    const float* grad_proj, float* partials, int variant, hipStream_t st)
+                    const float4* inter, const float* grad_proj, float* partials, int variant,
+                    hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     prof_begin(DP_K_RD_GRAD, st);
     switch (variant) {
-    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, mu, grad_proj, partials); break;
-    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, mu, grad_proj, partials); break;
-    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, mu, grad_proj, partials); break;
+    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, grad_proj, partials); break;
+    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, grad_proj, partials); break;
+    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, grad_proj, partials); break;
     }
     prof_end(DP_K_RD_GRAD, st);
 }
 
 template <bool HESS>
 static void launch_rd_fused_t(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
-                              const float* target, float* proj, float* partials, int variant,
-                              hipStream_t st)
+                              const float4* inter, const float* target, float* proj,
+                              float* partials, int variant, hipStream_t st)
 {
     dim3 grid(rd_tiles(s), V);
     switch (variant) {
-    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, target, proj, partials); break;
-    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, target, proj, partials); break;
-    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, target, proj, partials); break;
+    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, target, proj, partials); break;
+    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, target, proj, partials); break;
+    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, target, proj, partials); break;
     }
 }
 
 void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
-                     const float* target, float* proj, float* partials, bool hess, int variant,
-                     hipStream_t st)
+                     const float4* inter, const float* target, float* proj, float* partials,
+                     bool hess, int variant, hipStream_t st)
 {
     prof_begin(DP_K_RD_FUSED, st);
     if (hess)
-        launch_rd_fused_t<true>(s, V, views, mu, target, proj, partials, variant, st);
+        launch_rd_fused_t<true>(s, V, views, mu, inter, target, proj, partials, variant, st);
     else
-        launch_rd_fused_t<false>(s, V, views, mu, target, proj, partials, variant, st);
+        launch_rd_fused_t<false>(s, V, views, mu, inter, target, proj, partials, variant, st);
     prof_end(DP_K_RD_FUSED, st);
 }
 

@@ -421,7 +421,8 @@ def evaluate(net, geom, n_phantoms=8, per_phantom=16, salt=3, device="cuda:0", l
     absolute error per pose parameter, mm and deg).  `method` is the
     refinement ("lm" Levenberg-Marquardt or "bfgs"), the same for both
     pipelines.  photons: if given, the targets carry Poisson noise of a
-    transmission measurement with that many unattenuated photons per pixel."""
+    transmission measurement with that many unattenuated photons per pixel,
+    the attenuation scaled so that the largest line integral is 5."""
     import synth
     from .registration import success
     refine = _refine(method)
@@ -438,7 +439,8 @@ def evaluate(net, geom, n_phantoms=8, per_phantom=16, salt=3, device="cuda:0", l
         angles = torch.zeros(per_phantom, dtype=torch.float64, device=dev)
         targets = _project_fwd(geom, angles, truth, vol)
         if photons:
-            targets = synth.poisson_log_noise(targets, photons, gen)
+            # attenuation scaled so the largest line integral is 5 (head-like counts)
+            targets = synth.poisson_log_noise(targets, photons, gen, 5.0 / float(targets.max()))
         ref = _project_fwd(geom, angles[:1], torch.zeros_like(truth[:1]), vol)[0]
         torch.cuda.synchronize(dev)
         if i == 0:  # warm-up (library load, workspace, first launches) outside the timing

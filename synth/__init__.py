@@ -352,12 +352,14 @@ def config4_problems(device, n_problems: int = 16):
     return out
 
 
-def poisson_log_noise(l, photons: float, generator):
+def poisson_log_noise(l, photons: float, generator, scale: float = 1.0):
     """Noisy line integrals of a transmission measurement: per pixel, counts
-    N ~ Poisson(photons * exp(-l)) with `photons` unattenuated photons, then
-    -log(max(N, 1) / photons).  l: torch tensor of line integrals (any shape,
-    any device); `generator` (a torch.Generator on l's device) seeds the draws."""
+    N ~ Poisson(photons * exp(-scale * l)) with `photons` unattenuated
+    photons, returned as -log(max(N, 1) / photons) / scale (the units of l).
+    `scale` maps the line integrals to the attenuation the detector sees
+    (1: as given).  l: torch tensor (any shape, any device); `generator` (a
+    torch.Generator on l's device) seeds the draws."""
     import torch
-    lam = photons * torch.exp(-l.to(torch.float64))
+    lam = photons * torch.exp(-scale * l.to(torch.float64))
     n = torch.poisson(lam, generator=generator)
-    return (-torch.log(n.clamp_min(1.0) / photons)).to(l.dtype)
+    return (-torch.log(n.clamp_min(1.0) / photons) / scale).to(l.dtype)

@@ -205,7 +205,8 @@ def test_per_kernel_profiler(dp):
     for k, n in (("setup", 3), ("rd_fwd", 1), ("rd_fused", 1), ("finalize", 1),
                  ("det_prep", 1), ("vd_bp", 1)):
         assert got[k][1] == n and got[k][0] > 0, (k, got.get(k))
-    # the ray-driven kernels stage the volume themselves: no volume pass
+    # dense rays (1.6 mm pixels at the isocentre over 2 mm voxels): the
+    # ray-driven kernels stage the volume themselves, no volume pass
     assert "vol_prep" not in got
     assert dp.profile_collect() == {}
     dp.project_fwd(g, a, p, vol)

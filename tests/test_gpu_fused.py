@@ -192,8 +192,8 @@ def test_fused_full_launch_the_bench_times(dp, oracle):
 def test_sparse_rays_unstaged_tiles(dp, oracle, variant):
     """Rays much sparser than voxels (1.33 mm pixels at the isocentre over
     0.5 mm voxels): a 16 x 16 tile's chunk box exceeds the LDS capacity even
-    one sample deep, so every tile forms (mu, Gx, Gy, Gz) at its trilinear
-    corners from the volume directly.  Fused SSD entry, Gauss-Newton matrix and the
+    one sample deep, so every tile gathers (mu, Gx, Gy, Gz) per trilinear
+    corner from the padded copy the library makes for sparse-ray geometries.  Fused SSD entry, Gauss-Newton matrix and the
     plain gradient entry against the oracle; ragged detector tail."""
     rng = synth.rng_for(214)
     g = Geom(80, 72, 64, 0.5, 0.5, 0.5, 40, 36, 2.0, 2.0, off_u=0.5)
@@ -235,3 +235,29 @@ def test_fused_full_size_oracle_targets_dense(dp, oracle):
     y1 = oracle.project_fwd(g, c["angles"][:1], c["target_pose"], vol).astype(np.float32)
     y = np.repeat(y1, V, axis=0)
     _fused_case(dp, oracle, g, vol, angles, poses, y, "full-size dense")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_oblique_tiles_gathering_from_the_volume(dp, oracle, variant):
+    """Pixel footprint at the isocentre just below the sparse-ray threshold
+    (0.42 mm over 0.5 mm voxels: no (mu, G) copy is made) with diagonal views
+    and large rotations: the chunk boxes of a 16 x 16 tile's diagonal rays
+    outgrow the LDS even one sample deep, so those tiles form (mu, Gx, Gy,
+    Gz) at each trilinear corner from the 32 voxels around it.  Fused SSD
+    entry and the plain gradient entry against the oracle."""
+    rng = synth.rng_for(215)
+    g = Geom(40, 44, 36, 0.5, 0.5, 0.5, 60, 52, 0.63, 0.63)
+    vol = synth.ellipsoid_phantom(44, 0.5, 8, rng)[:36, :44, :40].copy()
+    V = 3
+    angles = np.radians([45.0, 135.0, 200.0])
+    poses = synth.random_poses(V, 2.0, 25.0, rng)
+    y = oracle.project_fwd(g, angles, synth.random_poses(V, 2.0, 25.0, rng), vol).astype(np.float32)
+    _fused_case(dp, oracle, g, vol, angles, poses, y, f"oblique-v{variant}", variant)
+    w = rng.standard_normal((V, g.nv, g.nu)).astype(np.float32)
+    try:
+        dp.set_variant(dp.OP_FWD_GRAD, variant)
+        gp = dp.project_fwd_grad_pose(g, f64(angles), f64(poses), f32(vol), f32(w))
+    finally:
+        dp.set_variant(dp.OP_FWD_GRAD, -1)
+    check_grads(f"oblique-v{variant} grad", gp.cpu().numpy(),
+                oracle.project_fwd_grad_pose(g, angles, poses, vol, w))

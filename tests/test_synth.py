@@ -62,3 +62,7 @@ def test_poisson_log_noise_statistics():
     # zero counts clamp to one photon: finite values
     y0 = synth.poisson_log_noise(torch.full((10,), 40.0, dtype=torch.float64), 1e5, gen)
     assert torch.isfinite(y0).all() and float(y0.max()) <= np.log(1e5) + 1e-9
+    # scaled attenuation: the noise is that of scale * l, returned in l's units
+    ys = synth.poisson_log_noise(torch.full((200000,), 10.0, dtype=torch.float64), 1e5, gen, 0.2)
+    assert abs(float(ys.mean()) - 10.0) < 5e-3
+    assert abs(float(ys.var()) / (np.exp(2.0) / 1e5 / 0.04) - 1.0) < 0.02
