@@ -655,6 +655,14 @@ __device__ inline void corners_at(const float* __restrict__ mu, int nx, int ny, 
             }
 }
 
+// LDS voxel index of a sample's base corner from its (integral) float value,
+// clamped to [0, hi] with one median-of-three (the planned box holds every
+// tap; the clamp only keeps rounding at the box faces inside the array).
+__device__ inline int lds_index(float f, float hi)
+{
+    return (int)__builtin_amdgcn_fmed3f(f, 0.0f, hi);
+}
+
 // One chunk of one ray: first local position and per-sample increment.
 struct ChunkRay {
     float X, Y, Z;     // local box coordinates of sample kb
@@ -704,12 +712,12 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
             const ChunkRay c = chunk_ray(r, kb, ke, bx, step);
             const int BX = bx.px, BXY = bx.px * bx.py;
             const float fbx = (float)bx.px, fby = (float)bx.py;
-            const int imax = CAP - 1 - (BXY + BX + 1);
+            const float fimax = (float)(CAP - 1 - (BXY + BX + 1));
             for (float j = 0.0f; j <= c.n; j += 1.0f) {
                 const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
                 const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
                 const float wx = X - fx, wy = Y - fy, wz = Z - fz;
-                const int idx = min(max((int)fmaf(fmaf(fz, fby, fy), fbx, fx), 0), imax);
+                const int idx = lds_index(fmaf(fmaf(fz, fby, fy), fbx, fx), fimax);
                 const float* p = lds + idx;
                 const float c00 = lerpf(p[0], p[1], wx);
                 const float c10 = lerpf(p[BX], p[BX + 1], wx);
@@ -768,54 +776,89 @@ __device__ inline void block_reduce_store(float (&v)[C], float* __restrict__ out
     }
 }
 
+// Trilinear weights phi[dz][dy][dx] of the 8 corners around a sample with
+// fractional offsets (wx, wy, wz), formed with 13 operations (products of
+// the y-z pair weights with wx, complements by subtraction).
+struct Tri {
+    float p[2][2][2];
+};
+
+__device__ inline Tri tri_weights(float wx, float wy, float wz)
+{
+    Tri t;
+    const float yz11 = wy * wz, yz01 = wz - yz11, yz10 = wy - yz11;  // [dy][dz]
+    const float yz00 = (1.0f - wz) - yz10;
+    const float pr[2][2] = {{yz00, yz10}, {yz01, yz11}};              // [dz][dy]
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            t.p[dz][dy][1] = pr[dz][dy] * wx;
+            t.p[dz][dy][0] = pr[dz][dy] - t.p[dz][dy][1];
+        }
+    return t;
+}
+
+// sum_j phi_j m_j (formed on its own, so that a running sum it is added to
+// takes one rounding per sample)
+__device__ inline float tri_dot(const Tri& t, const float (&m)[2][2][2])
+{
+    float v = t.p[0][0][0] * m[0][0][0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) v = fmaf(t.p[q >> 2][(q >> 1) & 1][q & 1], m[q >> 2][(q >> 1) & 1][q & 1], v);
+    return v;
+}
+
 // Per-ray gradient sums.  add() takes the 8 corner gradient vectors q (index
-// units), the trilinear weights and the base corner's index P in any frame;
-// T accumulates sum phi P_a G_c + sum phi delta_a G_c, so a frame change by
-// c (P -> P - c) is applied later as T_ac -= c_a B_c.
+// units), their trilinear weights and the base corner's index P in any
+// frame; T accumulates sum phi P_a G_c + sum phi delta_a G_c, so a frame
+// change by c (P -> P - c) is applied later as T_ac -= c_a B_c.
 struct GradAcc {
     float Bx = 0.f, By = 0.f, Bz = 0.f;
     float Txy = 0.f, Txz = 0.f, Tyx = 0.f, Tyz = 0.f, Tzx = 0.f, Tzy = 0.f;
 
-    __device__ inline void add(const float3 (&q)[2][2][2], float wx, float wy, float wz, float Px,
-                               float Py, float Pz)
+    // One channel: value v = sum phi g and the moments ma = sum_{delta_a = 1}
+    // phi g, mb = sum_{delta_b = 1} phi g over its two other axes a, b.  The
+    // weights come in four pairs by (delta_a, delta_b); the (1, 1) pair is
+    // shared by both moments.
+    __device__ static inline void channel(const float (&ph)[2][2][2], const float (&gv)[2][2][2],
+                                          float& v, float& ma, float& mb)
     {
-        // q[dz][dy][dx]
-        // Channel Gx: lerp along x first; moments along y and z.  Each moment
-        // sum_phi delta_a G_c is w_a times the upper lerp input along a; it is
-        // added to T with a second FMA instead of being formed first.
-        float Gx, Yx1, Zx1;
-        {
-            const float L00 = lerpf(q[0][0][0].x, q[0][0][1].x, wx), L10 = lerpf(q[0][1][0].x, q[0][1][1].x, wx);
-            const float L01 = lerpf(q[1][0][0].x, q[1][0][1].x, wx), L11 = lerpf(q[1][1][0].x, q[1][1][1].x, wx);
-            const float Y0 = lerpf(L00, L01, wz), Y1 = lerpf(L10, L11, wz);
-            Gx = lerpf(Y0, Y1, wy);
-            Yx1 = Y1;                       // moment along y: wy * Y1
-            Zx1 = lerpf(L01, L11, wy);      // moment along z: wz * Zx1
-        }
-        // Channel Gy: lerp along y first; moments along x and z.
-        float Gy, Xy1, Zy1;
-        {
-            const float L00 = lerpf(q[0][0][0].y, q[0][1][0].y, wy), L10 = lerpf(q[0][0][1].y, q[0][1][1].y, wy);
-            const float L01 = lerpf(q[1][0][0].y, q[1][1][0].y, wy), L11 = lerpf(q[1][0][1].y, q[1][1][1].y, wy);
-            const float X0 = lerpf(L00, L01, wz), X1 = lerpf(L10, L11, wz);
-            Gy = lerpf(X0, X1, wx);
-            Xy1 = X1;
-            Zy1 = lerpf(L01, L11, wx);
-        }
-        // Channel Gz: lerp along z first; moments along x and y.
-        float Gz, Xz1, Yz1;
-        {
-            const float L00 = lerpf(q[0][0][0].z, q[1][0][0].z, wz), L10 = lerpf(q[0][0][1].z, q[1][0][1].z, wz);
-            const float L01 = lerpf(q[0][1][0].z, q[1][1][0].z, wz), L11 = lerpf(q[0][1][1].z, q[1][1][1].z, wz);
-            const float X0 = lerpf(L00, L01, wy), X1 = lerpf(L10, L11, wy);
-            Gz = lerpf(X0, X1, wx);
-            Xz1 = X1;
-            Yz1 = lerpf(L01, L11, wx);
-        }
+        // ph, gv indexed [delta_b][delta_a][delta_c]
+        const float s11 = fmaf(ph[1][1][1], gv[1][1][1], ph[1][1][0] * gv[1][1][0]);
+        const float s01 = fmaf(ph[0][1][1], gv[0][1][1], ph[0][1][0] * gv[0][1][0]);  // a only
+        const float s10 = fmaf(ph[1][0][1], gv[1][0][1], ph[1][0][0] * gv[1][0][0]);  // b only
+        ma = s11 + s01;
+        mb = s11 + s10;
+        v = fmaf(ph[0][0][1], gv[0][0][1], fmaf(ph[0][0][0], gv[0][0][0], ma + s10));
+    }
+
+    __device__ inline void add(const float3 (&q)[2][2][2], const Tri& t, float Px, float Py,
+                               float Pz)
+    {
+        // Regroup weights and values per channel as [delta_b][delta_a][delta_c].
+        float px[2][2][2], gxv[2][2][2];  // Gx: a = y, b = z
+        float py[2][2][2], gyv[2][2][2];  // Gy: a = x, b = z
+        float pz[2][2][2], gzv[2][2][2];  // Gz: a = x, b = y
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) {
+                    const float w = t.p[dz][dy][dx];
+                    px[dz][dy][dx] = w; gxv[dz][dy][dx] = q[dz][dy][dx].x;
+                    py[dz][dx][dy] = w; gyv[dz][dx][dy] = q[dz][dy][dx].y;
+                    pz[dy][dx][dz] = w; gzv[dy][dx][dz] = q[dz][dy][dx].z;
+                }
+        float Gx, Myx, Mzx, Gy, Mxy, Mzy, Gz, Mxz, Myz;
+        channel(px, gxv, Gx, Myx, Mzx);
+        channel(py, gyv, Gy, Mxy, Mzy);
+        channel(pz, gzv, Gz, Mxz, Myz);
         Bx += Gx; By += Gy; Bz += Gz;
-        Txy = fmaf(wx, Xy1, fmaf(Px, Gy, Txy)); Txz = fmaf(wx, Xz1, fmaf(Px, Gz, Txz));
-        Tyx = fmaf(wy, Yx1, fmaf(Py, Gx, Tyx)); Tyz = fmaf(wy, Yz1, fmaf(Py, Gz, Tyz));
-        Tzx = fmaf(wz, Zx1, fmaf(Pz, Gx, Tzx)); Tzy = fmaf(wz, Zy1, fmaf(Pz, Gy, Tzy));
+        Txy = fmaf(Px, Gy, Txy) + Mxy; Txz = fmaf(Px, Gz, Txz) + Mxz;
+        Tyx = fmaf(Py, Gx, Tyx) + Myx; Tyz = fmaf(Py, Gz, Tyz) + Myz;
+        Tzx = fmaf(Pz, Gx, Tzx) + Mzx; Tzy = fmaf(Pz, Gy, Tzy) + Mzy;
     }
 
     // this += o with o's base-corner frame shifted by -c.
@@ -881,12 +924,12 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             const int BXC = C * bx.px, BXYC = C * bx.px * bx.py;
             const float fbx = (float)bx.px, fby = (float)bx.py;
             // largest base voxel whose 2x2x2 corners stay inside the box
-            const int vmax = CAP - 2 - (bx.px * bx.py + bx.px);
+            const float fvmax = (float)(CAP - 2 - (bx.px * bx.py + bx.px));
             GradAcc Gc;  // base-corner frame: local box indices
             for (float j = 0.0f; j <= c.n; j += 1.0f) {
                 const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
                 const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-                const int idx = C * min(max((int)fmaf(fmaf(fz, fby, fy), fbx, fx), 0), vmax);
+                const int idx = C * lds_index(fmaf(fmaf(fz, fby, fy), fbx, fx), fvmax);
                 const float* p = lds + idx;
                 float3 q[2][2][2];
                 float m[2][2][2];
@@ -905,23 +948,19 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                                 q[dz][dy][dx] = make_float3(o[0], o[1], o[2]);
                             }
                         }
-                const float wx = X - fx, wy = Y - fy, wz = Z - fz;
-                if (FUSED) {
-                    const float c00 = lerpf(m[0][0][0], m[0][0][1], wx), c10 = lerpf(m[0][1][0], m[0][1][1], wx);
-                    const float c01 = lerpf(m[1][0][0], m[1][0][1], wx), c11 = lerpf(m[1][1][0], m[1][1][1], wx);
-                    lsum += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
-                }
-                Gc.add(q, wx, wy, wz, fx, fy, fz);
+                const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
+                if (FUSED) lsum += tri_dot(t, m);
+                Gc.add(q, t, fx, fy, fz);
             }
             G.merge(Gc, ccx - bx.ox, ccy - bx.oy, ccz - bx.oz);
         }
     } else {
         for (int k = klo; k <= khi; ++k) {
-            const float t = fmaf((float)(k - r.k0), step, r.f);
+            const float tk = fmaf((float)(k - r.k0), step, r.f);
             const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
-            const float X = fminf(fmaxf(fmaf(t, r.dx, r.x0), 0.0f), xmax);
-            const float Y = fminf(fmaxf(fmaf(t, r.dy, r.y0), 0.0f), ymax);
-            const float Z = fminf(fmaxf(fmaf(t, r.dz, r.z0), 0.0f), zmax);
+            const float X = fminf(fmaxf(fmaf(tk, r.dx, r.x0), 0.0f), xmax);
+            const float Y = fminf(fmaxf(fmaf(tk, r.dy, r.y0), 0.0f), ymax);
+            const float Z = fminf(fmaxf(fmaf(tk, r.dz, r.z0), 0.0f), zmax);
             const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
             float3 q[2][2][2];
             float m[2][2][2];
@@ -934,20 +973,16 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                     for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                         for (int dx = 0; dx < 2; ++dx) {
-                            const float4 t = inter[(size_t)idx + dz * NXY + dy * NX + dx];
-                            m[dz][dy][dx] = t.x;
-                            q[dz][dy][dx] = make_float3(t.y, t.z, t.w);
+                            const float4 e = inter[(size_t)idx + dz * NXY + dy * NX + dx];
+                            m[dz][dy][dx] = e.x;
+                            q[dz][dy][dx] = make_float3(e.y, e.z, e.w);
                         }
             } else {
                 corners_at(mu, s.nx, s.ny, s.nz, (int)fx, (int)fy, (int)fz, m, q);
             }
-            const float wx = X - fx, wy = Y - fy, wz = Z - fz;
-            if (FUSED) {
-                const float c00 = lerpf(m[0][0][0], m[0][0][1], wx), c10 = lerpf(m[0][1][0], m[0][1][1], wx);
-                const float c01 = lerpf(m[1][0][0], m[1][0][1], wx), c11 = lerpf(m[1][1][0], m[1][1][1], wx);
-                lsum += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
-            }
-            G.add(q, wx, wy, wz, fx - ccx, fy - ccy, fz - ccz);
+            const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
+            if (FUSED) lsum += tri_dot(t, m);
+            G.add(q, t, fx - ccx, fy - ccy, fz - ccz);
         }
     }
     constexpr int NC = FUSED ? (HESS ? kRdChannelsGN : kRdChannels + 1) : kRdChannels;

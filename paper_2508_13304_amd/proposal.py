@@ -369,12 +369,24 @@ def _refine(method):
     return {"lm": register_lm, "bfgs": register_bfgs}[method]
 
 
+def transmission_noise_ssd(targets, photons, scale):
+    """Expected SSD that Poisson counting noise leaves at the true pose, per
+    target: with counts of mean photons * exp(-scale * l), the log-transformed
+    measurement has variance exp(scale * l) / (photons * scale^2) to first
+    order; the noisy target stands in for l, so no knowledge of the truth
+    enters.  targets: [B][nv][nu]; returns FP64 [B]."""
+    y = targets.to(torch.float64)
+    return (torch.exp(scale * y) / (photons * scale * scale)).reshape(y.shape[0], -1).sum(1)
+
+
 def register_learned(net, geom, vol, angles, targets, ref, fallback=True, rel_tol=1e-6,
-                     method="lm", **kw):
+                     method="lm", noise_ssd=None, **kw):
     """Propose theta0 with the network from (reference DRR, target), refine
-    with the analytic-gradient BFGS registration, and fall back to the plain
-    registration from the identity for every registration whose refined
-    loss stays above rel_tol * |target|^2 (keeping the lower loss).
+    with the analytic-gradient registration (`method`), and fall back to the
+    plain registration from the identity for every registration whose refined
+    loss stays above rel_tol * |target|^2, plus 1.1 x noise_ssd (the SSD the
+    target's noise leaves at the true pose, [B], for noisy targets), keeping
+    the lower loss.
 
     The network was trained at gantry angle 0, so `angles` must be zero;
     `ref` is the [nv][nu] DRR of `vol` at the identity pose.
@@ -395,7 +407,10 @@ def register_learned(net, geom, vol, angles, targets, ref, fallback=True, rel_to
     n_fb = 0
     if fallback:
         energy = (targets.to(torch.float64) ** 2).reshape(B, -1).sum(1)
-        bad = torch.nonzero(fl > rel_tol * energy).flatten()
+        limit = rel_tol * energy
+        if noise_ssd is not None:
+            limit = limit + 1.1 * noise_ssd.to(device=fl.device, dtype=torch.float64)
+        bad = torch.nonzero(fl > limit).flatten()
         n_fb = int(bad.numel())
         if n_fb:
             r2 = refine(geom, vol, angles[bad], targets[bad], torch.zeros_like(theta0[bad]), **kw)
@@ -438,9 +453,12 @@ def evaluate(net, geom, n_phantoms=8, per_phantom=16, salt=3, device="cuda:0", l
                              dtype=torch.float64, device=dev)
         angles = torch.zeros(per_phantom, dtype=torch.float64, device=dev)
         targets = _project_fwd(geom, angles, truth, vol)
+        noise_ssd = None
         if photons:
             # attenuation scaled so the largest line integral is 5 (head-like counts)
-            targets = synth.poisson_log_noise(targets, photons, gen, 5.0 / float(targets.max()))
+            scale = 5.0 / float(targets.max())
+            targets = synth.poisson_log_noise(targets, photons, gen, scale)
+            noise_ssd = transmission_noise_ssd(targets, photons, scale)
         ref = _project_fwd(geom, angles[:1], torch.zeros_like(truth[:1]), vol)[0]
         torch.cuda.synchronize(dev)
         if i == 0:  # warm-up (library load, workspace, first launches) outside the timing
@@ -448,7 +466,7 @@ def evaluate(net, geom, n_phantoms=8, per_phantom=16, salt=3, device="cuda:0", l
             net.predict(pair_input(ref.expand(2, -1, -1), targets[:2], net.size))
         plain = refine(geom, vol, angles, targets, torch.zeros_like(truth), **kw)
         learned, theta0, nfb = register_learned(net, geom, vol, angles, targets, ref, method=method,
-                                                **kw)
+                                                noise_ssd=noise_ssd, **kw)
         stats["plain_ok"] += int(success(plain.poses, truth).sum())
         stats["learned_ok"] += int(success(learned.poses, truth).sum())
         stats["n"] += per_phantom

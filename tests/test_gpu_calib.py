@@ -258,9 +258,10 @@ def test_calibration_batch_full_size_sampled(dp, oracle):
     """The uneven calibration batch at full size in the launch the bench
     times (16 problems of 128^3-384^3 with 256^2-768^2 detectors, 82 views,
     one batched single-pass Gauss-Newton launch), at the identity pose of the
-    first calibration iteration.  Targets equal the GPU projections except on
-    32 random rays per view, offset by N(0, 100^2), so the residual lives on
-    rays the oracle can evaluate one by one: sampled projections (<= 1e-5 of
+    first calibration iteration.  Targets equal the launch's own projections
+    (a first launch) except on 32 random rays per view, offset by
+    N(0, 100^2), so the residual lives exactly on rays the oracle can
+    evaluate one by one: sampled projections (<= 1e-5 of
     max), per-view SSD (<= 1e-5 relative) for every problem, pose gradients
     (<= 1e-4 per triplet) for four problems; the Gauss-Newton matrices are
     checked by property (symmetric positive semi-definite) and against the
@@ -272,19 +273,21 @@ def test_calibration_batch_full_size_sampled(dp, oracle):
     for q in probs:
         g, V = q["geom"], q["angles"].numel()
         poses = torch.zeros((V, 6), dtype=torch.float64, device=DEV)
-        l0 = dp.project_fwd(g, q["angles"], poses, q["vol"])
         npix = g.nu * g.nv
         sel = np.stack([rng.choice(npix, 32, replace=False) for _ in range(V)])
         ids = (sel + np.arange(V)[:, None] * npix).ravel()
-        y = l0.clone().reshape(-1)
-        y[torch.from_numpy(ids).to(DEV)] += torch.from_numpy(rng.normal(0.0, 100.0, ids.size)).float().to(DEV)
         items.append(dict(geom=g, angles=q["angles"], vol=q["vol"], poses=poses,
-                          target=y.reshape(V, g.nv, g.nu),
+                          target=dp.project_fwd(g, q["angles"], poses, q["vol"]),
                           proj=torch.empty((V, g.nv, g.nu), dtype=torch.float32, device=DEV),
                           grad_pose=torch.empty((V, 6), dtype=torch.float64, device=DEV),
                           hess=torch.empty((V, 21), dtype=torch.float64, device=DEV),
                           loss=torch.empty(V, dtype=torch.float64, device=DEV)))
         picks.append(ids)
+    dp.project_fwd_ssd_gauss_newton_batch(items)
+    for d, ids in zip(items, picks):
+        y = d["proj"].clone().reshape(-1)
+        y[torch.from_numpy(ids).to(DEV)] += torch.from_numpy(rng.normal(0.0, 100.0, ids.size)).float().to(DEV)
+        d["target"] = y.reshape(d["proj"].shape)
     dp.project_fwd_ssd_gauss_newton_batch(items)
     torch.cuda.synchronize()
     order = sorted(range(len(items)), key=lambda i: items[i]["geom"].nx * items[i]["geom"].nu)

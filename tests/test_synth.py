@@ -66,3 +66,18 @@ def test_poisson_log_noise_statistics():
     ys = synth.poisson_log_noise(torch.full((200000,), 10.0, dtype=torch.float64), 1e5, gen, 0.2)
     assert abs(float(ys.mean()) - 10.0) < 5e-3
     assert abs(float(ys.var()) / (np.exp(2.0) / 1e5 / 0.04) - 1.0) < 0.02
+
+
+def test_transmission_noise_floor_matches_the_drawn_noise():
+    """The expected SSD at the true pose that the learned pipeline's fallback
+    allows for (first-order variance exp(s l) / (N s^2), evaluated on the
+    noisy measurement) agrees with the SSD of the noise actually drawn."""
+    import torch
+    from paper_2508_13304_amd.proposal import transmission_noise_ssd
+    gen = torch.Generator().manual_seed(11)
+    l = torch.rand((3, 128, 128), dtype=torch.float64, generator=gen) * 28.0
+    for photons, scale in ((1e5, 5.0 / 28.0), (1e4, 0.1)):
+        y = synth.poisson_log_noise(l, photons, gen, scale)
+        got = transmission_noise_ssd(y, photons, scale)
+        drawn = ((y - l) ** 2).reshape(3, -1).sum(1)
+        assert torch.allclose(got, drawn, rtol=0.03), (photons, got, drawn)
