@@ -39,8 +39,9 @@ constexpr int kVdGradMinBlocks = 2048;
 #endif
 constexpr size_t kDetChunkBytes = (size_t)DP_DET_CHUNK_MIB << 20;
 
-// Per padded detector pixel (A, B): the 2x2 bilinear footprints
-// {(A, B), (A+1, B), (A, B+1), (A+1, B+1)} of l, dl/da and dl/db.
+// Per padded detector pixel (A, B): the bilinear coefficients of l, dl/da
+// and dl/db on the cell [A, A+1] x [B, B+1] (value, a-difference,
+// b-difference, mixed second difference).
 struct alignas(16) DetTap3 {
     float4 l, a, b;
 };
@@ -88,7 +89,7 @@ inline GeoScalars make_scalars(const dp_geom& g)
 // Kernel launchers (defined next to their kernels).
 void launch_view_setup(const GeoScalars& s, int V, const double* angles, const double* poses,
                        ViewGeo* views, hipStream_t st);
-// per padded pixel, the 2x2 bilinear footprint of l as one float4
+// per padded pixel, the bilinear cell coefficients of l as one float4
 void launch_det_pad(const GeoScalars& s, int V, const float* proj, float4* projq, hipStream_t st);
 void launch_det_grad(const GeoScalars& s, int V, const float* proj, float4* proj4, hipStream_t st);
 void launch_det_tap3(const GeoScalars& s, int V, const float* proj, DetTap3* det, hipStream_t st);

@@ -1,11 +1,16 @@
 // Elementwise preparation passes (HBM-bound, coalesced along x / u): the
 // (mu, G) interleave of sparse-ray geometries, and detector images:
-//   - per padded detector pixel, the 2x2 bilinear footprint of the
-//     zero-extended image as one float4, for the back-projection;
+//   - per padded detector pixel, the bilinear coefficients of the
+//     zero-extended image on the cell to its lower right as one float4, for
+//     the back-projection;
 //   - detector gradient field (central differences of l, Sec. II-C) stored
 //     as float4 (l, dl/da, dl/db, 0) in pixel-index units, zero outside
-//     (footprint projectors), or as the 2x2 bilinear footprints of the three
-//     fields (voxel-driven back-projection gradient).
+//     (footprint projectors), or as the cell coefficients of the three fields
+//     (voxel-driven back-projection gradient).
+// Cell coefficients of pixel (A, B): with v_xy the image at (A + x, B + y),
+//   (v00, v10 - v00, v01 - v00, v11 - v10 - v01 + v00),
+// so that the bilinear value at (A + wa, B + wb) is
+//   c0 + wa ca + wb cb + wa wb cab  (three FMAs per field).
 #include "dp_internal.h"
 
 namespace dp {
@@ -16,9 +21,14 @@ __device__ inline float pix_at(const float* __restrict__ img, int nu, int nv, in
     return img[(size_t)b * nu + a];
 }
 
-// Per padded pixel (A, B), the 2x2 bilinear footprint {(A, B), (A+1, B),
-// (A, B+1), (A+1, B+1)} of the zero-extended image as one float4, so that a
-// back-projection update gathers one 16-byte vector instead of two rows.
+__device__ inline float4 cell_coef(float v00, float v10, float v01, float v11)
+{
+    return make_float4(v00, v10 - v00, v01 - v00, (v11 - v10) - (v01 - v00));
+}
+
+// Per padded pixel (A, B), the cell coefficients of the zero-extended image,
+// so that a back-projection update gathers one 16-byte vector instead of two
+// rows.
 __global__ __launch_bounds__(256) void det_pad_kernel(int nu, int nv, const float* __restrict__ proj,
                                                       float4* __restrict__ projq)
 {
@@ -29,8 +39,8 @@ __global__ __launch_bounds__(256) void det_pad_kernel(int nu, int nv, const floa
     const float* img = proj + (size_t)v * nu * nv;
     const int a = A - kPadD, b = B - kPadD;
     projq[((size_t)v * NV + B) * NU + A] =
-        make_float4(pix_at(img, nu, nv, a, b), pix_at(img, nu, nv, a + 1, b),
-                    pix_at(img, nu, nv, a, b + 1), pix_at(img, nu, nv, a + 1, b + 1));
+        cell_coef(pix_at(img, nu, nv, a, b), pix_at(img, nu, nv, a + 1, b),
+                  pix_at(img, nu, nv, a, b + 1), pix_at(img, nu, nv, a + 1, b + 1));
 }
 
 __global__ __launch_bounds__(256) void det_grad_kernel(int nu, int nv, const float* __restrict__ proj,
@@ -61,9 +71,9 @@ __device__ inline float3 lgrad_at(const float* __restrict__ img, int nu, int nv,
                        0.5f * (pix_at(img, nu, nv, a, b + 1) - pix_at(img, nu, nv, a, b - 1)));
 }
 
-// Per padded pixel (A, B), the 2x2 bilinear footprints of l, dl/da and
-// dl/db, so that a back-projection gradient update gathers three 16-byte
-// vectors, every lane of them used.
+// Per padded pixel (A, B), the cell coefficients of l, dl/da and dl/db, so
+// that a back-projection gradient update gathers three 16-byte vectors,
+// every lane of them used.
 __global__ __launch_bounds__(256) void det_tap3_kernel(int nu, int nv, const float* __restrict__ proj,
                                                        DetTap3* __restrict__ det)
 {
@@ -76,9 +86,9 @@ __global__ __launch_bounds__(256) void det_tap3_kernel(int nu, int nv, const flo
     const float3 q00 = lgrad_at(img, nu, nv, a, b), q10 = lgrad_at(img, nu, nv, a + 1, b);
     const float3 q01 = lgrad_at(img, nu, nv, a, b + 1), q11 = lgrad_at(img, nu, nv, a + 1, b + 1);
     DetTap3 t;
-    t.l = make_float4(q00.x, q10.x, q01.x, q11.x);
-    t.a = make_float4(q00.y, q10.y, q01.y, q11.y);
-    t.b = make_float4(q00.z, q10.z, q01.z, q11.z);
+    t.l = cell_coef(q00.x, q10.x, q01.x, q11.x);
+    t.a = cell_coef(q00.y, q10.y, q01.y, q11.y);
+    t.b = cell_coef(q00.z, q10.z, q01.z, q11.z);
     det[((size_t)v * NV + B) * NU + A] = t;
 }
 

@@ -47,7 +47,13 @@
 
 namespace dp {
 
-__device__ inline float lerp_f(float a, float b, float w) { return fmaf(w, b - a, a); }
+// Bilinear value from a pixel's cell coefficients (c0, ca, cb, cab) at
+// fractional offsets (wa, wb), wab = wa wb.
+__device__ inline float cell_value(float c0, float ca, float cb, float cab, float wa, float wb,
+                                   float wab)
+{
+    return fmaf(wab, cab, fmaf(wb, cb, fmaf(wa, ca, c0)));
+}
 
 // Largest distance (pixels, per detector axis) from the detector centre at
 // which a column's FP64 anchor may project: two detector widths and a margin.
@@ -138,6 +144,32 @@ __device__ inline float clampf(float x, float lo, float hi) { return fminf(fmaxf
 // both ends of the column, W being linear along it), so no per-voxel test.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const f32x4 global_float4;
+typedef __attribute__((address_space(1))) const char global_bytes;
+
+// Byte offset of the tap at pixel offset (ia, ib) from a column's anchor,
+// relative to its view's image: col = the anchor's byte offset, row = bytes
+// per padded image row, BYTES per pixel.  Two 24-bit multiply-adds (every
+// operand is far below 2^23 in magnitude); 32-bit wrap-around is exact since
+// the tap itself lies inside the image.
+__device__ inline unsigned mad_i24(int a, int b, unsigned c)
+{
+    unsigned r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+template <int BYTES>
+__device__ inline unsigned tap_offset(unsigned col, int ia, int ib, int row)
+{
+    return mad_i24(ib, row, mad_i24(ia, BYTES, col));
+}
+
+// A 16-byte load at a byte offset from a wave-uniform base (the base stays
+// in scalar registers; each lane supplies only its 32-bit offset).
+__device__ inline f32x4 ld16(global_bytes* base, unsigned off)
+{
+    return *(global_float4*)(base + off);
+}
 
 // The taps of NB consecutive voxels are gathered before any of them is
 // used, so NB loads are in flight per wavefront.
@@ -167,11 +199,13 @@ __device__ inline void bp_column(const ColumnAnchor& c, float pw2, global_float4
             wb[u] = __builtin_amdgcn_fractf(B);
             q[u] = img[ib * NU + ia];
         }
+        // keep the batch whole: without this barrier the scheduler moves the
+        // first uses of the taps up between the loads, and the wavefront then
+        // waits for each load in turn (measured ~1.6x slower)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            const float t0 = lerp_f(q[u].x, q[u].y, wa[u]);
-            const float t1 = lerp_f(q[u].z, q[u].w, wa[u]);
-            const float val = lerp_f(t0, t1, wb[u]);
+            const float val = cell_value(q[u].x, q[u].y, q[u].z, q[u].w, wa[u], wb[u], wa[u] * wb[u]);
             if (MODE == DP_W_FDK)
                 acc[k0 + u] = fmaf(iw[u] * iw[u], val, acc[k0 + u]);
             else
@@ -229,7 +263,7 @@ __device__ inline void bp_column_exact(const ViewGeo& g, const GeoScalars& s, in
         const int ia = floor_to_int(x.A), ib = floor_to_int(x.B);
         const float wa = __builtin_amdgcn_fractf(x.A), wb = __builtin_amdgcn_fractf(x.B);
         const f32x4 q = view[ib * NU + ia];
-        const float val = lerp_f(lerp_f(q.x, q.y, wa), lerp_f(q.z, q.w, wa), wb);
+        const float val = cell_value(q.x, q.y, q.z, q.w, wa, wb, wa * wb);
         const float term = MODE == DP_W_FDK ? x.iw * x.iw * val : val;
 #pragma unroll
         for (int t = 0; t < K; ++t) acc[t] += t == kk ? term : 0.0f;
@@ -237,7 +271,7 @@ __device__ inline void bp_column_exact(const ViewGeo& g, const GeoScalars& s, in
 }
 
 // One launch covers the views [v0, v0 + Vc) of the detector images in
-// `projq` (this chunk's footprint copy).  The column sums run in view order
+// `projq` (this chunk's cell-coefficient images).  The column sums run in view order
 // and are carried between launches in `vol` unscaled (FIRST: start from
 // zero; LAST: apply the FDK constant), so a chunked back-projection is
 // bit-identical to a single launch over all views.
@@ -271,6 +305,8 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(V
         const float4* base = projq + ((long long)vv * NU * NV + c.off);  // anchor pixel of this view
         // one 64-bit base per view and column (kept whole, in global memory's
         // address space), so each update adds only its 32-bit pixel offset
+        // (measured faster here than a scalar view base with 32-bit offsets,
+        // which the gradient kernel uses)
         asm volatile("" : "+v"(base));
         global_float4* img = (global_float4*)base;
         if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
@@ -287,52 +323,61 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(V
     }
 }
 
-// One view's gradient sums over a column of K voxels (FRONT as in bp_column):
-// A_k += e c_k and Z_k += e c_k (k - centre_z) for k = u, v, w.
+// One view's gradient sums over a column of K voxels (FRONT as in bp_column).
+// Per voxel, with ec = e W / w' and (a', b') = (apc + da, bpc + db):
+//   c1 = ec l_a,  c2 = ec l_b,  c3 = -(apc c1 + bpc c2 + s),
+//   s = c1 da + c2 db + kappa ec l,
+// so the column keeps A1 = sum c1, A2 = sum c2, S = sum s and their moments
+// Z1', Z2', ZS' about the column's first voxel (weights kk = 0 .. K-1); the
+// caller forms A3, the third moment and the shift to the volume centre once
+// per column.
 template <int MODE, int K, bool FRONT>
-__device__ inline void grad_column(const ColumnAnchor& c, float pw2, const DetTap3* __restrict__ img,
-                                   int NU, const float (&e)[K], float pk0, float kappa, float& A1,
-                                   float& A2, float& A3, float& Z1, float& Z2, float& Z3)
+__device__ inline void grad_column(const ColumnAnchor& c, float pw2, global_bytes* __restrict__ view,
+                                   unsigned col, int NU, const float (&e)[K], float& A1, float& A2,
+                                   float& S, float& Z1, float& Z2, float& ZS)
 {
     constexpr int NB = VD_GRAD_NB;  // voxels whose three taps are in flight together
     static_assert(K % NB == 0, "column length must be a multiple of the batch");
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += NB) {
         float4 ql[NB], qa[NB], qb[NB];
-        float wa[NB], wb[NB], iw[NB], ap[NB], bp[NB];
+        float wa[NB], wb[NB], iw[NB], da[NB], db[NB];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const float dk = (float)(k0 + u) - c.ka;  // kk - ka, exact: small integers
             const float W = fmaf(dk, pw2, c.w0);
             const bool front = FRONT || W > 0.0f;  // voxels at or behind the source get no ray
             iw[u] = front ? __builtin_amdgcn_rcpf(W) : 0.0f;
-            const float da = dk * c.nu * iw[u], db = dk * c.nv * iw[u];
-            ap[u] = c.apc + da;  // offsets from the detector centre
-            bp[u] = c.bpc + db;
-            float A = c.a0f + da;
+            const float t = dk * iw[u];
+            da[u] = t * c.nu;
+            db[u] = t * c.nv;
+            float A = c.a0f + da[u];
             if (!FRONT) A = front ? A : -1.0e9f;
             A = __builtin_amdgcn_fmed3f(A, c.alo, c.ahi);
-            const float B = __builtin_amdgcn_fmed3f(c.b0f + db, c.blo, c.bhi);
+            const float B = __builtin_amdgcn_fmed3f(c.b0f + db[u], c.blo, c.bhi);
             const int ia = floor_to_int(A), ib = floor_to_int(B);
             wa[u] = __builtin_amdgcn_fractf(A);
             wb[u] = __builtin_amdgcn_fractf(B);
-            const DetTap3* p = img + (ib * NU + ia);
-            ql[u] = p->l;
-            qa[u] = p->a;
-            qb[u] = p->b;
+            const unsigned o = tap_offset<48>(col, ia, ib, 48 * NU);  // DetTap3: 48 bytes
+            const f32x4 tl = ld16(view, o), ta = ld16(view + 16, o), tb = ld16(view + 32, o);
+            ql[u] = make_float4(tl.x, tl.y, tl.z, tl.w);
+            qa[u] = make_float4(ta.x, ta.y, ta.z, ta.w);
+            qb[u] = make_float4(tb.x, tb.y, tb.z, tb.w);
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            const float l = lerp_f(lerp_f(ql[u].x, ql[u].y, wa[u]), lerp_f(ql[u].z, ql[u].w, wa[u]), wb[u]);
-            const float la = lerp_f(lerp_f(qa[u].x, qa[u].y, wa[u]), lerp_f(qa[u].z, qa[u].w, wa[u]), wb[u]);
-            const float lb = lerp_f(lerp_f(qb[u].x, qb[u].y, wa[u]), lerp_f(qb[u].z, qb[u].w, wa[u]), wb[u]);
+            const float wab = wa[u] * wb[u];
+            const float l = cell_value(ql[u].x, ql[u].y, ql[u].z, ql[u].w, wa[u], wb[u], wab);
+            const float la = cell_value(qa[u].x, qa[u].y, qa[u].z, qa[u].w, wa[u], wb[u], wab);
+            const float lb = cell_value(qb[u].x, qb[u].y, qb[u].z, qb[u].w, wa[u], wb[u], wab);
             // e * W / w' (FDK: e D^2 / w'^3, with D^2 folded into e)
             const float ec = MODE == DP_W_FDK ? e[k0 + u] * (iw[u] * iw[u]) * iw[u] : e[k0 + u] * iw[u];
             const float c1 = ec * la, c2 = ec * lb;
-            const float c3 = -ec * fmaf(la, ap[u], fmaf(lb, bp[u], kappa * l));
-            const float pk = pk0 + (float)(k0 + u);
-            A1 += c1; A2 += c2; A3 += c3;
-            Z1 = fmaf(c1, pk, Z1); Z2 = fmaf(c2, pk, Z2); Z3 = fmaf(c3, pk, Z3);
+            const float sk = MODE == DP_W_FDK ? fmaf(c1, da[u], fmaf(c2, db[u], (ec + ec) * l))
+                                              : fmaf(c1, da[u], c2 * db[u]);
+            const float kz = (float)(k0 + u);
+            A1 += c1; A2 += c2; S += sk;
+            Z1 = fmaf(c1, kz, Z1); Z2 = fmaf(c2, kz, Z2); ZS = fmaf(sk, kz, ZS);
         }
     }
 }
@@ -414,7 +459,6 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(V
     const int nblk = gridDim.x * gridDim.y * gridDim.z;
     const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
     const float D2 = (float)(s.sad * s.sad);
-    const float kappa = MODE == DP_W_FDK ? 2.0f : 0.0f;
     const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
     const bool active = i < s.nx && j < s.ny;
     const int lane = threadIdx.x;  // kVdBx = 64: one wavefront per threadIdx.y
@@ -436,15 +480,21 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(V
             const ViewGeo& g = views[v0 + vv];
             const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
             const float pw2 = g.PW[2];
-            float A1 = 0.f, A2 = 0.f, A3 = 0.f, Z1 = 0.f, Z2 = 0.f, Z3 = 0.f;
-            const DetTap3* img = det + ((long long)vv * NU * NV + c.off);  // anchor pixel of this view
+            float A1 = 0.f, A2 = 0.f, S = 0.f, Z1 = 0.f, Z2 = 0.f, ZS = 0.f;
+            global_bytes* view = (global_bytes*)(det + (long long)vv * NU * NV);
+            const unsigned col = (unsigned)c.off * 48u;  // anchor pixel of this view
             if (c.exact) {
                 // no usable anchor: vd_grad_exact_kernel adds this column's sums
                 exact_views[v0 + vv] = 1;
             } else if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
-                grad_column<MODE, K, true>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
+                grad_column<MODE, K, true>(c, pw2, view, col, NU, e, A1, A2, S, Z1, Z2, ZS);
             else
-                grad_column<MODE, K, false>(c, pw2, img, NU, e, pk0, kappa, A1, A2, A3, Z1, Z2, Z3);
+                grad_column<MODE, K, false>(c, pw2, view, col, NU, e, A1, A2, S, Z1, Z2, ZS);
+            // third channel, and moments about the volume centre (k - centre = pk0 + kk)
+            const float A3 = -fmaf(c.apc, A1, fmaf(c.bpc, A2, S));
+            const float Z3 = fmaf(pk0, A3, -fmaf(c.apc, Z1, fmaf(c.bpc, Z2, ZS)));
+            Z1 = fmaf(pk0, A1, Z1);
+            Z2 = fmaf(pk0, A2, Z2);
             const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
                                           pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
             wave_partials(r, lane, mine + vv * kVdChannels);
@@ -520,9 +570,10 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(
                     const float wa = __builtin_amdgcn_fractf(x.A), wb = __builtin_amdgcn_fractf(x.B);
                     const DetTap3* p = view + (ib * NU + ia);
                     const float4 ql = p->l, qa = p->a, qb = p->b;
-                    const float l = lerp_f(lerp_f(ql.x, ql.y, wa), lerp_f(ql.z, ql.w, wa), wb);
-                    const float la = lerp_f(lerp_f(qa.x, qa.y, wa), lerp_f(qa.z, qa.w, wa), wb);
-                    const float lb = lerp_f(lerp_f(qb.x, qb.y, wa), lerp_f(qb.z, qb.w, wa), wb);
+                    const float wab = wa * wb;
+                    const float l = cell_value(ql.x, ql.y, ql.z, ql.w, wa, wb, wab);
+                    const float la = cell_value(qa.x, qa.y, qa.z, qa.w, wa, wb, wab);
+                    const float lb = cell_value(qb.x, qb.y, qb.z, qb.w, wa, wb, wab);
                     const float ec = MODE == DP_W_FDK ? ek * (x.iw * x.iw) * x.iw : ek * x.iw;
                     const float c1 = ec * la, c2 = ec * lb;
                     const float c3 = -ec * fmaf(la, x.ap, fmaf(lb, x.bp, kappa * l));
