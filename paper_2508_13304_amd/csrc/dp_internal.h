@@ -28,10 +28,18 @@ constexpr int kVdBy = 4;
 constexpr int kVdBpCol = 32;
 constexpr int kVdGradCol = 32;
 constexpr int kVdChannels = 12;  // A (3), QX (3), QY (3), QZ (3)
+// Back-projection gradient blocks: kVgBx x kVgBy voxel columns (4
+// wavefronts), and the detector pixels per view they stage in LDS.
+constexpr int kVgBx = 16;
+constexpr int kVgBy = 16;
+constexpr int kVgStage = 640;
 // Views per back-projection gradient launch (per-view block sums held in LDS)
 // and the block count below which blocks stop taking several column groups.
 constexpr int kVdMaxChunk = 64;
-constexpr int kVdGradMinBlocks = 2048;
+#ifndef DP_VD_GRAD_MIN_BLOCKS
+#define DP_VD_GRAD_MIN_BLOCKS 8192
+#endif
+constexpr int kVdGradMinBlocks = DP_VD_GRAD_MIN_BLOCKS;
 // Detector images are staged per chunk of views, within this many bytes
 // (a build-time choice; results do not depend on it).
 #ifndef DP_DET_CHUNK_MIB

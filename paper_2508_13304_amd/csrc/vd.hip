@@ -65,6 +65,7 @@ __host__ __device__ inline double anchor_limit(const GeoScalars& s)
 // FP64 anchor of one voxel column for one view.
 struct ColumnAnchor {
     long long off;      // padded-image offset of the anchor pixel (integer part)
+    int ai, bi;         // the anchor pixel's padded column and row
     float a0f, b0f;     // fractional part of the anchor's pixel coordinates
     float nu, nv;       // N_u, N_v of the offset formula
     float w0;           // depth of the anchor voxel (mm)
@@ -110,6 +111,8 @@ __device__ inline ColumnAnchor column_anchor(const ViewGeo& g, const GeoScalars&
     const double A0 = floor(a0), B0 = floor(b0);
     const int NU = s.nu + 2 * kPadD;
     c.off = (long long)B0 * NU + (long long)A0;
+    c.ai = (int)A0;
+    c.bi = (int)B0;
     c.a0f = (float)(a0 - A0);
     c.b0f = (float)(b0 - B0);
     c.nu = (float)((g.PUd[2] * W0 - g.PWd[2] * U0) * iw0);
@@ -331,9 +334,37 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(V
 // Z1', Z2', ZS' about the column's first voxel (weights kk = 0 .. K-1); the
 // caller forms A3, the third moment and the shift to the volume centre once
 // per column.
-template <int MODE, int K, bool FRONT>
-__device__ inline void grad_column(const ColumnAnchor& c, float pw2, global_bytes* __restrict__ view,
-                                   unsigned col, int NU, const float (&e)[K], float& A1, float& A2,
+// Tap sources of the gradient: the chunk's DetTap3 images in global memory
+// (a wave-uniform view base plus 32-bit byte offsets), or one view's
+// rectangle of them staged in LDS (offsets clamped to the rectangle).
+struct GlobalTaps {
+    global_bytes* view;
+    int row;  // bytes per padded image row
+    __device__ inline void load(unsigned o, float4& l, float4& a, float4& b) const
+    {
+        const f32x4 tl = ld16(view, o), ta = ld16(view + 16, o), tb = ld16(view + 32, o);
+        l = make_float4(tl.x, tl.y, tl.z, tl.w);
+        a = make_float4(ta.x, ta.y, ta.z, ta.w);
+        b = make_float4(tb.x, tb.y, tb.z, tb.w);
+    }
+};
+
+struct LdsTaps {
+    const DetTap3* stage;  // the staged rectangle, row-major
+    int row;               // bytes per staged row
+    unsigned hi;           // byte offset of its last pixel
+    __device__ inline void load(unsigned o, float4& l, float4& a, float4& b) const
+    {
+        const DetTap3& t = *(const DetTap3*)((const char*)stage + min(o, hi));
+        l = t.l;
+        a = t.a;
+        b = t.b;
+    }
+};
+
+template <int MODE, int K, bool FRONT, class Taps>
+__device__ inline void grad_column(const ColumnAnchor& c, float pw2, const Taps& taps,
+                                   unsigned col, const float (&e)[K], float& A1, float& A2,
                                    float& S, float& Z1, float& Z2, float& ZS)
 {
     constexpr int NB = VD_GRAD_NB;  // voxels whose three taps are in flight together
@@ -358,11 +389,7 @@ __device__ inline void grad_column(const ColumnAnchor& c, float pw2, global_byte
             const int ia = floor_to_int(A), ib = floor_to_int(B);
             wa[u] = __builtin_amdgcn_fractf(A);
             wb[u] = __builtin_amdgcn_fractf(B);
-            const unsigned o = tap_offset<48>(col, ia, ib, 48 * NU);  // DetTap3: 48 bytes
-            const f32x4 tl = ld16(view, o), ta = ld16(view + 16, o), tb = ld16(view + 32, o);
-            ql[u] = make_float4(tl.x, tl.y, tl.z, tl.w);
-            qa[u] = make_float4(ta.x, ta.y, ta.z, ta.w);
-            qb[u] = make_float4(tb.x, tb.y, tb.z, tb.w);
+            taps.load(tap_offset<48>(col, ia, ib, taps.row), ql[u], qa[u], qb[u]);  // DetTap3: 48 B
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -417,16 +444,15 @@ __device__ inline void wave_partials(const float (&r)[kVdChannels], int lane, fl
 // per-view channel sums over the block's column groups in its own LDS slice;
 // the block then adds the four slices in a fixed order and writes (ADD:
 // adds) one partial set per view, partials[v][blk][kVdChannels].
+constexpr int kVgWaves = kVgBx * kVgBy / 64;
 struct VdGradShared {
-    float acc[kVdBy][kVdMaxChunk][kVdChannels];
+    float acc[kVgWaves][kVdMaxChunk][kVdChannels];
 };
 
-__device__ inline void vd_shared_zero(VdGradShared& sh, int Vc)
+__device__ inline void vd_shared_zero(VdGradShared& sh)
 {
     float* a = &sh.acc[0][0][0];
-    for (int t = threadIdx.y * kVdBx + threadIdx.x; t < kVdBy * kVdMaxChunk * kVdChannels; t += kVdBx * kVdBy)
-        a[t] = 0.0f;
-    (void)Vc;
+    for (int t = threadIdx.x; t < kVgWaves * kVdMaxChunk * kVdChannels; t += kVgBx * kVgBy) a[t] = 0.0f;
     __syncthreads();
 }
 
@@ -434,8 +460,9 @@ template <bool ADD>
 __device__ inline void vd_shared_store(const VdGradShared& sh, int v0, int Vc, int blk, int nblk,
                                        const int* __restrict__ only, float* __restrict__ partials)
 {
+    static_assert(kVgWaves == 4, "fixed-order sum of four wavefront slices");
     __syncthreads();
-    for (int t = threadIdx.y * kVdBx + threadIdx.x; t < Vc * kVdChannels; t += kVdBx * kVdBy) {
+    for (int t = threadIdx.x; t < Vc * kVdChannels; t += kVgBx * kVgBy) {
         const int vv = t / kVdChannels, c = t - vv * kVdChannels;
         if (only && only[v0 + vv] == 0) continue;
         const float sum = ((sh.acc[0][vv][c] + sh.acc[1][vv][c]) + sh.acc[2][vv][c]) + sh.acc[3][vv][c];
@@ -444,26 +471,113 @@ __device__ inline void vd_shared_store(const VdGradShared& sh, int v0, int Vc, i
     }
 }
 
-// Block (bx, by, bz) covers the voxel columns of x block bx, y block by and
-// the zpb consecutive column groups of K voxels starting at group bz * zpb.
+// Thread t of a gradient block owns voxel column (x0 + t % kVgBx, y0 + t / kVgBx).
+__device__ inline int vg_col_i() { return blockIdx.x * kVgBx + (int)(threadIdx.x % kVgBx); }
+__device__ inline int vg_col_j() { return blockIdx.y * kVgBy + (int)(threadIdx.x / kVgBx); }
+
+// Staged detector rectangle of one view: padded pixels [a0, a0 + w) x
+// [b0, b0 + h); w = 0 when the block's taps are gathered from global memory.
+struct StageRect {
+    int a0, b0, w, h;
+};
+
+// The rectangle that holds every tap of the block's voxel region (kVgBx x
+// kVgBy columns of K voxels from kb, grid faces ignored) for one view, from
+// the FP64 projections of the region's 8 corner voxels (the projective map
+// is monotone along every segment in front of the source, so the region's
+// image lies in the hull of theirs), window-clamped like the voxels, plus a
+// safety margin.  Wavefront 0 computes it; w = 0 unless every corner lies at
+// least 1 mm in front of the source and the rectangle fits kVgStage pixels.
+__device__ inline void stage_rect(const ViewGeo& g, const GeoScalars& s, int kb, int K,
+                                  StageRect& out)
+{
+    const int q = threadIdx.x;  // lanes 0 .. 7 of wavefront 0: the corners
+    double amin = 1.0e300, amax = -1.0e300, bmin = 1.0e300, bmax = -1.0e300;
+    int ok = 1;
+    if (q < 8) {
+        const double ci = blockIdx.x * kVgBx + (q & 1) * (kVgBx - 1);
+        const double cj = blockIdx.y * kVgBy + ((q >> 1) & 1) * (kVgBy - 1);
+        const double ck = kb + (q >> 2) * (K - 1);
+        const double U = fma(g.PUd[0], ci, fma(g.PUd[1], cj, fma(g.PUd[2], ck, g.PUd[3])));
+        const double V = fma(g.PVd[0], ci, fma(g.PVd[1], cj, fma(g.PVd[2], ck, g.PVd[3])));
+        const double W = fma(g.PWd[0], ci, fma(g.PWd[1], cj, fma(g.PWd[2], ck, g.PWd[3])));
+        ok = W >= 1.0;
+        const double iw = ok ? 1.0 / W : 0.0;
+        const double a = fmin(fmax(U * iw + s.cu + kPadD, kPadD - 1.5), s.nu + kPadD + 0.5);
+        const double b = fmin(fmax(V * iw + s.cv + kPadD, kPadD - 1.5), s.nv + kPadD + 0.5);
+        amin = amax = a;
+        bmin = bmax = b;
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        amin = fmin(amin, __shfl_xor(amin, off));
+        amax = fmax(amax, __shfl_xor(amax, off));
+        bmin = fmin(bmin, __shfl_xor(bmin, off));
+        bmax = fmax(bmax, __shfl_xor(bmax, off));
+        ok &= __shfl_xor(ok, off);
+    }
+    if (q == 0) {
+        const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
+        const int a0 = max(0, (int)floor(amin - 1.0e-3)), a1 = min(NU - 1, (int)floor(amax + 1.0e-3) + 1);
+        const int b0 = max(0, (int)floor(bmin - 1.0e-3)), b1 = min(NV - 1, (int)floor(bmax + 1.0e-3) + 1);
+        const int w = a1 - a0 + 1, h = b1 - b0 + 1;
+        const bool fits = ok && w > 0 && h > 0 && w * h <= kVgStage;
+        out.a0 = a0;
+        out.b0 = b0;
+        out.w = fits ? w : 0;
+        out.h = fits ? h : 0;
+    }
+}
+
+// Copy the rectangle's DetTap3 pixels into LDS (row-major, w per row): every
+// thread issues its (at most 8) 16-byte loads before its first store.
+__device__ inline void stage_copy(const StageRect& r, global_bytes* view, int NU, DetTap3* stage)
+{
+    constexpr int kPer = (3 * kVgStage + kVgBx * kVgBy - 1) / (kVgBx * kVgBy);
+    const int n16 = 3 * r.w * r.h;
+    const float invw = 1.0f / (float)r.w;
+    f32x4 buf[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int q = (int)threadIdx.x + u * kVgBx * kVgBy;
+        if (q < n16) {
+            const int p = q / 3, part = q - 3 * p;
+            const int row = (int)(((float)p + 0.5f) * invw), cl = p - row * r.w;
+            buf[u] = ld16(view, (unsigned)(((r.b0 + row) * NU + r.a0 + cl) * 48 + part * 16));
+        }
+    }
+    f32x4* dst = (f32x4*)stage;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int q = (int)threadIdx.x + u * kVgBx * kVgBy;
+        if (q < n16) dst[q] = buf[u];
+    }
+}
+
+// Block (bx, by, bz) covers kVgBx x kVgBy voxel columns and the zpb
+// consecutive column groups of K voxels starting at group bz * zpb.  Per
+// view, the detector rectangle under the block's region is staged in LDS
+// when it fits (every tap then an LDS read); otherwise the taps come from
+// global memory.
 template <int MODE, int K>
-__global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(VD_GRAD_WPE))) void vd_grad_kernel(
+__global__ __launch_bounds__(kVgBx * kVgBy) __attribute__((amdgpu_waves_per_eu(VD_GRAD_WPE))) void vd_grad_kernel(
     GeoScalars s, int v0, int Vc, int zpb, const ViewGeo* __restrict__ views,
     const DetTap3* __restrict__ det, const float* __restrict__ grad_vol,
     float* __restrict__ partials, int* __restrict__ exact_views)
 {
     __shared__ VdGradShared sh;
-    const int i = blockIdx.x * kVdBx + threadIdx.x;
-    const int j = blockIdx.y * kVdBy + threadIdx.y;
+    __shared__ DetTap3 stage[kVgStage];
+    __shared__ StageRect rect;
+    const int i = vg_col_i(), j = vg_col_j();
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int nblk = gridDim.x * gridDim.y * gridDim.z;
     const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
     const float D2 = (float)(s.sad * s.sad);
     const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
     const bool active = i < s.nx && j < s.ny;
-    const int lane = threadIdx.x;  // kVdBx = 64: one wavefront per threadIdx.y
-    float* mine = &sh.acc[threadIdx.y][0][0];
-    vd_shared_zero(sh, Vc);
+    const int lane = threadIdx.x & 63;
+    float* mine = &sh.acc[threadIdx.x >> 6][0][0];
+    vd_shared_zero(sh);
     for (int zg = 0; zg < zpb; ++zg) {
         const int kb = ((int)blockIdx.z * zpb + zg) * K;
         if (kb >= s.nz) break;  // uniform over the block
@@ -478,26 +592,39 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(V
         }
         for (int vv = 0; vv < Vc; ++vv) {
             const ViewGeo& g = views[v0 + vv];
+            global_bytes* view = (global_bytes*)(det + (long long)vv * NU * NV);
+            if (threadIdx.x < 64) stage_rect(g, s, kb, K, rect);
+            __syncthreads();  // rect visible; every reader of the previous view's stage is done
+            const StageRect r = rect;
+            if (r.w > 0) stage_copy(r, view, NU, stage);
+            __syncthreads();  // stage visible (rect is read by everyone before this point)
             const ColumnAnchor c = column_anchor(g, s, i, j, kb, K);
             const float pw2 = g.PW[2];
             float A1 = 0.f, A2 = 0.f, S = 0.f, Z1 = 0.f, Z2 = 0.f, ZS = 0.f;
-            global_bytes* view = (global_bytes*)(det + (long long)vv * NU * NV);
-            const unsigned col = (unsigned)c.off * 48u;  // anchor pixel of this view
             if (c.exact) {
                 // no usable anchor: vd_grad_exact_kernel adds this column's sums
                 exact_views[v0 + vv] = 1;
-            } else if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
-                grad_column<MODE, K, true>(c, pw2, view, col, NU, e, A1, A2, S, Z1, Z2, ZS);
-            else
-                grad_column<MODE, K, false>(c, pw2, view, col, NU, e, A1, A2, S, Z1, Z2, ZS);
+            } else if (r.w > 0) {
+                // every voxel of the region lies in front of the source
+                const LdsTaps t{stage, 48 * r.w, (unsigned)(48 * (r.w * r.h - 1))};
+                const unsigned col = (unsigned)(((c.bi - r.b0) * r.w + (c.ai - r.a0)) * 48);
+                grad_column<MODE, K, true>(c, pw2, t, col, e, A1, A2, S, Z1, Z2, ZS);
+            } else {
+                const GlobalTaps t{view, 48 * NU};
+                const unsigned col = (unsigned)c.off * 48u;  // anchor pixel of this view
+                if (fmaf(-c.ka, pw2, c.w0) > 0.0f && fmaf((float)(K - 1) - c.ka, pw2, c.w0) > 0.0f)
+                    grad_column<MODE, K, true>(c, pw2, t, col, e, A1, A2, S, Z1, Z2, ZS);
+                else
+                    grad_column<MODE, K, false>(c, pw2, t, col, e, A1, A2, S, Z1, Z2, ZS);
+            }
             // third channel, and moments about the volume centre (k - centre = pk0 + kk)
             const float A3 = -fmaf(c.apc, A1, fmaf(c.bpc, A2, S));
             const float Z3 = fmaf(pk0, A3, -fmaf(c.apc, Z1, fmaf(c.bpc, Z2, ZS)));
             Z1 = fmaf(pk0, A1, Z1);
             Z2 = fmaf(pk0, A2, Z2);
-            const float r[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
-                                          pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
-            wave_partials(r, lane, mine + vv * kVdChannels);
+            const float rr[kVdChannels] = {A1, A2, A3, pi * A1, pi * A2, pi * A3,
+                                           pj * A1, pj * A2, pj * A3, Z1, Z2, Z3};
+            wave_partials(rr, lane, mine + vv * kVdChannels);
         }
     }
     vd_shared_store<false>(sh, v0, Vc, blk, nblk, nullptr, partials);
@@ -516,7 +643,7 @@ __global__ __launch_bounds__(kVdBx * kVdBy) __attribute__((amdgpu_waves_per_eu(V
 // between those of the ends (the projective map has no pole in between), so
 // it is within the limit when both ends are within 0.9 of it.
 template <int MODE, int K>
-__global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(
+__global__ __launch_bounds__(kVgBx * kVgBy) void vd_grad_exact_kernel(
     GeoScalars s, int v0, int Vc, int zpb, const ViewGeo* __restrict__ views,
     const DetTap3* __restrict__ det, const float* __restrict__ grad_vol,
     float* __restrict__ partials, const int* __restrict__ exact_views)
@@ -526,18 +653,17 @@ __global__ __launch_bounds__(kVdBx * kVdBy) void vd_grad_exact_kernel(
     for (int vv = 0; vv < Vc; ++vv) any = any || exact_views[v0 + vv] != 0;
     if (!any) return;
     __shared__ VdGradShared sh;
-    const int i = blockIdx.x * kVdBx + threadIdx.x;
-    const int j = blockIdx.y * kVdBy + threadIdx.y;
+    const int i = vg_col_i(), j = vg_col_j();
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int nblk = gridDim.x * gridDim.y * gridDim.z;
     const int NU = s.nu + 2 * kPadD, NV = s.nv + 2 * kPadD;
     const float escale = MODE == DP_W_FDK ? (float)(s.sad * s.sad) : 1.0f;
     const float kappa = MODE == DP_W_FDK ? 2.0f : 0.0f;
     const float pi = (float)i - 0.5f * (s.nx - 1), pj = (float)j - 0.5f * (s.ny - 1);
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const float lim = 0.9f * (float)anchor_limit(s);
-    float* mine = &sh.acc[threadIdx.y][0][0];
-    vd_shared_zero(sh, Vc);
+    float* mine = &sh.acc[threadIdx.x >> 6][0][0];
+    vd_shared_zero(sh);
     for (int zg = 0; zg < zpb; ++zg) {
         const int kb = ((int)blockIdx.z * zpb + zg) * K;
         if (kb >= s.nz) break;  // uniform over the block
@@ -624,7 +750,7 @@ void launch_vd_flags_clear(int V, int* flags, hipStream_t st)
 VdGradGrid vd_grad_grid(const GeoScalars& s)
 {
     VdGradGrid g;
-    const int gx = (s.nx + kVdBx - 1) / kVdBx, gy = (s.ny + kVdBy - 1) / kVdBy;
+    const int gx = (s.nx + kVgBx - 1) / kVgBx, gy = (s.ny + kVgBy - 1) / kVgBy;
     const int groups = (s.nz + kVdGradCol - 1) / kVdGradCol;
     // enough blocks to fill the chip several times over; beyond that, blocks
     // take several column groups each (fewer partial sets to write and sum)
@@ -640,8 +766,8 @@ static void vd_grad_dispatch(const GeoScalars& s, int v0, int Vc, const ViewGeo*
                              hipStream_t st)
 {
     const VdGradGrid vg = vd_grad_grid(s);
-    dim3 block(kVdBx, kVdBy);
-    dim3 grid((s.nx + kVdBx - 1) / kVdBx, (s.ny + kVdBy - 1) / kVdBy, vg.gz);
+    dim3 block(kVgBx * kVgBy);
+    dim3 grid((s.nx + kVgBx - 1) / kVgBx, (s.ny + kVgBy - 1) / kVgBy, vg.gz);
     vd_grad_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, v0, Vc, vg.zpb, views, det,
                                                              grad_vol, partials, flags);
     vd_grad_exact_kernel<MODE, kVdGradCol><<<grid, block, 0, st>>>(s, v0, Vc, vg.zpb, views, det,
