@@ -34,23 +34,25 @@ import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec (packed FMA)
-# Algorithmic FP32 operations per in-support sample (FMA counted as 2):
-#   forward : sample position 8, fractions 3, trilinear 7 lerps x 3 = 21, sum 1
-#   gradient: position 8, fractions 3, 3 channels x 8 lerps x 3 = 72, moments 6,
-#             centre offsets 3, accumulation of B (3) and T (6 x 3)
-#   fused   : the gradient's 113 plus the mu trilinear (21) and its sum (1)
-FLOPS_PER_SAMPLE = {"rd_fwd": 33, "rd_grad": 113, "rd_fused": 135}
+# Algorithmic FP32 operations of the method per unit of work (FMA counted as 2),
+# fixed counts that do not depend on how a kernel arranges its arithmetic:
+#   per in-support ray sample: forward ~30 (position, fractions, trilinear
+#   interpolation, sum), pose gradient ~120 (position, fractions, the three
+#   gradient channels' trilinear interpolation with their moments, the nine
+#   per-ray sums); the fused SSD pass does both on one march (150);
+#   per voxel-view update: back-projection ~25 (depth, reciprocal, pixel
+#   coordinates, bilinear tap, weight), its pose gradient ~90 (the same plus
+#   three bilinear fields, the detector-Jacobian row and twelve sums).
+FLOPS_PER_SAMPLE = {"rd_fwd": 30, "rd_grad": 120, "rd_fused": 150}
 # bytes one forward + gradient sample gathers: 8 trilinear corners x (mu, Gx, Gy, Gz) x 4 B
 GATHER_BYTES_PER_SAMPLE = 128
-# bytes one voxel-view update gathers: 4 bilinear taps of l (back-projection), of
-# (l, dl/da, dl/db) (its pose gradient)
+# bytes one voxel-view update gathers: the bilinear cell of l (back-projection),
+# of (l, dl/da, dl/db) (its pose gradient), and where the taps come from: the
+# back-projection gathers through the cache hierarchy (L2 ceiling), the
+# gradient from the detector rectangle each block stages in LDS (LDS ceiling)
 VD_GATHER_BYTES_PER_UPDATE = {"vd_bp": 16, "vd_grad": 48}
-# Algorithmic FP32 operations per voxel-view update (FMA counted as 2):
-#   vd_bp  : depth 2, reciprocal 1, two pixel coordinates 3 + 3, bilinear 3 lerps x 3,
-#            FDK weight 3                                                     = 21
-#   vd_grad: depth 2, reciprocal 1, pixel offsets 4, centre offsets 2, coordinates 2,
-#            3 bilinears x 9, e W / w' 3, c1 c2 c3 8, moment position 1, A and Z sums 9 = 59
-VD_FLOPS_PER_UPDATE = {"vd_bp": 21, "vd_grad": 59}
+VD_TAP_SOURCE = {"vd_bp": "l2", "vd_grad": "lds"}
+VD_FLOPS_PER_UPDATE = {"vd_bp": 25, "vd_grad": 90}
 
 
 def log(*a):
@@ -332,11 +334,11 @@ def gather_roofline(fw, probe):
 def vd_rooflines(bp, probe):
     """Both ceilings of each back-projector kernel: the FP32 arithmetic
     ceiling (published FP32 vector peak over the algorithmic operations per
-    update) and the gather ceiling (the measured L2 read bandwidth over the
-    bytes an update gathers: its taps come through the cache hierarchy).
-    Each kernel is graded against the lower ceiling; the texture-addresser
-    busy fraction (rocprofv3, while the kernel source is unchanged) is
-    reported beside."""
+    update) and the gather ceiling (the measured read bandwidth of where its
+    taps come from, L2 or LDS, over the bytes an update gathers).  Each
+    kernel is graded against the lower ceiling; the texture-addresser busy
+    fraction (rocprofv3, while the kernel source is unchanged) is reported
+    beside."""
     h = _kernel_hash("vd.hip", "dp_internal.h")
     out = {}
     for k, nbytes in VD_GATHER_BYTES_PER_UPDATE.items():
@@ -344,12 +346,13 @@ def vd_rooflines(bp, probe):
         if not ms:
             continue
         rate = bp["voxel_view_updates"] / (ms * 1e-3)
-        gather = probe["l2_read_GBps"] * 1e9 / nbytes
+        src = VD_TAP_SOURCE[k]
+        gather = probe[src + "_read_GBps"] * 1e9 / nbytes
         flops = VD_FLOPS_PER_UPDATE[k]
         alu = VALU_PEAK_TFLOPS * 1e12 / flops
         bound = "alu" if alu < gather else "gather"
         ceiling = min(gather, alu)
-        out[k] = {"updates_per_s": rate, "gather_bytes_per_update": nbytes,
+        out[k] = {"updates_per_s": rate, "gather_bytes_per_update": nbytes, "taps_from": src,
                   "gather_ceiling_updates_per_s": gather, "gather_frac": round(rate / gather, 4),
                   "flops_per_update": flops, "tflops": round(rate * flops / 1e12, 2),
                   "alu_ceiling_updates_per_s": alu, "alu_frac": round(rate / alu, 4),

@@ -96,3 +96,23 @@ def test_oracle_thread_count_changes_only_the_timing():
         oracle.set_num_threads(n)
     assert oracle.num_threads() == n
     assert np.array_equal(ref, one)
+
+
+def test_vd_rooflines_take_each_kernels_tap_source():
+    """The back-projection is graded against the L2 gather ceiling (its taps
+    come through the cache hierarchy), its gradient against the LDS ceiling
+    (taps from the staged rectangle), each against the arithmetic ceiling
+    too, whichever is lower."""
+    import bench
+    probe = {"lds_read_GBps": 120000.0, "l2_read_GBps": 30000.0, "hbm_read_GBps": 7000.0}
+    bp = {"voxel_view_updates": 4.8e10, "kernels_ms": {"vd_bp": 30.0, "vd_grad": 60.0}}
+    r = bench.vd_rooflines(bp, probe)
+    assert r["vd_bp"]["taps_from"] == "l2" and r["vd_grad"]["taps_from"] == "lds"
+    assert r["vd_bp"]["gather_ceiling_updates_per_s"] == pytest.approx(30000e9 / 16)
+    assert r["vd_grad"]["gather_ceiling_updates_per_s"] == pytest.approx(120000e9 / 48)
+    for k in ("vd_bp", "vd_grad"):
+        d = r[k]
+        ceiling = min(d["gather_ceiling_updates_per_s"], d["alu_ceiling_updates_per_s"])
+        assert d["frac"] == pytest.approx(round(d["updates_per_s"] / ceiling, 4))
+        assert d["graded_against"] == ("alu" if d["alu_ceiling_updates_per_s"] < d["gather_ceiling_updates_per_s"]
+                                       else "gather")
