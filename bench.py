@@ -679,6 +679,58 @@ def run_learned(args, dp, torch):
     return res
 
 
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA, MI355X
+
+
+def proposal_train_flops(net, batch):
+    """Algorithmic FLOPs of one training step (FMA counted as 2): per
+    convolution, 2 M K Co for the forward product and again for the weight
+    gradient and (all but the first layer) the input gradient, with
+    M = batch Ho Wo and K = 9 Ci; the same three for the linear head."""
+    total, hw = 0, net.size
+    for li, (W, _, s) in enumerate(net.convs):
+        hw = (hw - 1) // s + 1
+        f = 2 * batch * hw * hw * W.shape[1] * W.shape[0]
+        total += f * (2 if li == 0 else 3)
+    return total + 3 * 2 * batch * net.Wfc.shape[1] * net.Wfc.shape[0]
+
+
+def run_proposal_training(args, dp, torch, steps=10, batch=256):
+    """One training step of the pose-proposal CNN at batch 256 (256x256 pair
+    images, forward + backward + Adam, every product on the BF16 MFMA GEMM),
+    on seeded synthetic inputs and labels; time per step against the dense
+    BF16 peak."""
+    from paper_2508_13304_amd import proposal as pr
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(11)
+    net = pr.ProposalNet(size=256, device=dev, seed=1)
+    x = torch.rand((batch, net.size, net.size, 2), generator=gen, device=dev).to(torch.bfloat16)
+    y = torch.rand((batch, 6), generator=gen, device=dev) * 2 - 1
+
+    def step():
+        out, cache = net.forward(x, keep=True)
+        d = out - y
+        grads, head = net.backward(cache, (2.0 / d.numel()) * d)
+        net.adam_step(grads, head, lr=1e-4)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    flops = proposal_train_flops(net, batch)
+    tf = flops / (ms * 1e-3) / 1e12
+    res = {"batch": batch, "ms_per_step": round(ms, 3), "flops_per_step": flops,
+           "tflops": round(tf, 2), "bf16_peak_tflops": BF16_PEAK_TFLOPS,
+           "frac": round(tf / BF16_PEAK_TFLOPS, 4),
+           "what": "ProposalNet(256x256x2, channels 32-64-128-256-256-256, stride 2) forward + backward + Adam"}
+    log(f"[bench] proposal training step: {res}")
+    return res
+
+
 PAPER_LADDER = [(128, 192), (256, 384), (384, 572), (512, 768)]
 # The paper's own cost tables (RTX 4090; context, not targets): seconds for
 # 100 iterations of a differentiable forward projection of 1 view, and for
@@ -876,6 +928,9 @@ def main():
     ap.add_argument("--probe-calib", action="store_true",
                     help="only run one L2 and one HBM read-probe launch (L2 counter calibration) and exit")
     ap.add_argument("--no-probe", action="store_true", help="skip the L2 / HBM read-bandwidth probe")
+    ap.add_argument("--no-train", action="store_true", help="skip the proposal-network training step")
+    ap.add_argument("--train-only", action="store_true",
+                    help="only time the proposal-network training step (profiling runs) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -903,6 +958,9 @@ def main():
         print(json.dumps({"l2_probe_bytes": 2048 * 32 * l2.numel() * 4,
                           "hbm_probe_bytes": hbm.numel() * 4}), flush=True)
         return
+    if args.train_only:
+        print(json.dumps({"proposal_training": run_proposal_training(args, dp, torch)}), flush=True)
+        return
     if args.no_fwd:
         bp = run_backproject(args, dp, torch)
         print(json.dumps({"backprojector": bp}), flush=True)
@@ -914,6 +972,7 @@ def main():
     regr_noisy = None if args.no_reg else run_registration_paper(args, dp, torch, fw)
     learned = None if args.no_reg else run_learned(args, dp, torch)
     calib = None if args.no_batch else run_calibration_batch(args, dp, torch)
+    training = None if args.no_train else run_proposal_training(args, dp, torch)
     ladder = None if args.no_ladder else run_paper_ladder(args, dp, torch)
     cpu = None if args.no_cpu else run_cpu_baseline(fw)
     value = fw["n_samples"] / (fw["ms_step"] * 1e-3)
@@ -958,6 +1017,7 @@ def main():
         "registration": regr,
         "registration_noisy": regr_noisy,
         "learned_proposal": learned,
+        "proposal_training": training,
         "calibration_batch": calib,
         "projector_ladder": ladder,
     }

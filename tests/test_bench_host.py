@@ -116,3 +116,16 @@ def test_vd_rooflines_take_each_kernels_tap_source():
         assert d["frac"] == pytest.approx(round(d["updates_per_s"] / ceiling, 4))
         assert d["graded_against"] == ("alu" if d["alu_ceiling_updates_per_s"] < d["gather_ceiling_updates_per_s"]
                                        else "gather")
+
+
+def test_proposal_training_flops():
+    """Training-step FLOPs: three products per layer (two for the first,
+    which needs no input gradient), counted from the layer shapes."""
+    import bench
+    from paper_2508_13304_amd import proposal as pr
+    net = pr.ProposalNet(size=32, channels=(4, 8), device="cpu")
+    # conv0: 32 -> 16, K = 18, Co 4; conv1: 16 -> 8, K = 36, Co 8; head 8*8*8 -> 6
+    f0 = 2 * 2 * 16 * 16 * 18 * 4
+    f1 = 2 * 2 * 8 * 8 * 36 * 8
+    fc = 2 * 2 * 512 * 6
+    assert bench.proposal_train_flops(net, 2) == 2 * f0 + 3 * f1 + 3 * fc
