@@ -360,7 +360,7 @@ def vd_rooflines(bp, probe):
                   "valu_busy": _traffic(k + "_reconstruction_scale", h, "valu_busy"),
                   "ta_busy": _traffic(k + "_reconstruction_scale", h, "ta_busy"),
                   "l2_hit_rate": _traffic(k + "_reconstruction_scale", h, "l2_hit_rate")}
-        l2b = _traffic(k + "_reconstruction_scale", h, "l2_bytes_per_launch")
+        l2b = _traffic(k + "_reconstruction_scale", h, "l2_bytes_per_call")  # the call's launches
         out[k]["l2_GBps"] = round(l2b / (ms * 1e-3) / 1e9, 1) if l2b else None
         out[k]["l2_frac"] = round(l2b / (ms * 1e-3) / 1e9 / probe["l2_read_GBps"], 4) if l2b else None
     return out
