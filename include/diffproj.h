@@ -273,14 +273,45 @@ int32_t dp_get_variant(const dp_geom* g, int32_t n_views, int32_t op);
 int dp_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
                  const void* A, int32_t lda, const void* B, int32_t ldb, float* C,
                  int32_t ldc, int32_t accumulate, void* stream);
+/* The same product with split-K partial sums in a caller workspace of
+ * dp_gemm_bf16_ws_bytes(M, N, K) bytes (0: none needed) for few output
+ * tiles and a long reduction (weight gradients), reduced in split order, so
+ * the result does not depend on block timing; dp_gemm_bf16 runs such
+ * products in one pass.  Error DP_ERR_ARG if the workspace is too small. */
+size_t dp_gemm_bf16_ws_bytes(int32_t M, int32_t N, int32_t K);
+int dp_gemm_bf16_ws(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                    const void* A, int32_t lda, const void* B, int32_t ldb, float* C, int32_t ldc,
+                    int32_t accumulate, void* ws, size_t ws_bytes, void* stream);
+/* Forward convolution product with its epilogue: Y [M][N] BF16 (row stride
+ * ldy) = act(A B^T + bias), A [M][K] and B [N][K] BF16, FP32 accumulation,
+ * bias of output column n at bias[n * bias_stride] (FP32), act = ReLU if
+ * relu else identity, rounded to BF16 once. */
+int dp_gemm_bias_act_bf16(int32_t M, int32_t N, int32_t K, const void* A, int32_t lda,
+                          const void* B, int32_t ldb, const float* bias, int32_t bias_stride,
+                          int32_t relu, void* Y, int32_t ldy, void* stream);
 /* col [N Ho Wo][9 C] BF16 from x [N][H][W][C] BF16; K index (ky, kx, c).
  * N Ho Wo 9 C and N H W C must stay below 2^31 (DP_ERR_UNSUPPORTED otherwise;
  * split the batch).  The same limit holds for dp_col2im3x3. */
 int dp_im2col3x3_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
                       const void* x, void* col, void* stream);
+/* As dp_im2col3x3_bf16 with rows of ld >= 9 C (+ 1) entries: the 9 C window
+ * values, then 1 in column 9 C if ones (the product dz^T col then carries
+ * the column sums of dz, the bias gradient, in that column), zeros after. */
+int dp_im2col3x3_ld_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
+                         const void* x, void* col, int32_t ld, int32_t ones, void* stream);
 /* dx [N][H][W][C] FP32 = adjoint of im2col applied to dcol [N Ho Wo][9 C] FP32. */
 int dp_col2im3x3(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
                  const float* dcol, float* dx, void* stream);
+/* The same adjoint followed by the activation backward of the layer below:
+ * dz [N][H][W][C] BF16 = dx * (y > 0) if relu else dx, y [N][H][W][C] BF16
+ * that layer's output (one rounding to BF16). */
+int dp_col2im3x3_act_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
+                          const float* dcol, const void* y, int32_t relu, void* dz, void* stream);
+/* One Adam step over n parameters in flat FP32 buffers: m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, p -= lr (m / c1) / (sqrt(v / c2) + eps), and p
+ * rounded to BF16 into p_bf16 [n].  c1, c2 > 0: the bias corrections. */
+int dp_adam_f32(int64_t n, float* p, const float* g, float* m, float* v, void* p_bf16, float lr,
+                float beta1, float beta2, float eps, float c1, float c2, void* stream);
 /* y [rows][C] BF16 = act(z + bias), act = ReLU if relu else identity. */
 int dp_bias_act_bf16(int64_t rows, int32_t C, const float* z, const float* bias,
                      int32_t relu, void* y, void* stream);

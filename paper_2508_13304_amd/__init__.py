@@ -35,7 +35,9 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_fp_project_grad_pose", "dp_fp_backproject_grad_pose", "dp_fdk_filter", "dp_sharpness",
            "dp_sharpness_workspace_bytes", "dp_gradient_entropy",
            "dp_gradient_entropy_workspace_bytes", "dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3",
-           "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16",
+           "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16", "dp_gemm_bf16_ws_bytes",
+           "dp_gemm_bf16_ws", "dp_gemm_bias_act_bf16", "dp_im2col3x3_ld_bf16",
+           "dp_col2im3x3_act_bf16", "dp_adam_f32",
            "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update", "dp_read_probe",
            "dp_bp_grad_flags_offset", "dp_lds_probe", "dp_project_fwd_ssd_grad_pose_noalloc")
 MAX_BATCH = 16

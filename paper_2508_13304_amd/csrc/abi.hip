@@ -868,8 +868,49 @@ int dp_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t
     if ((N + 63) / 64 > 65535) return fail(DP_ERR_UNSUPPORTED, "gemm: N above 65535 tiles of 64");
     (void)hipGetLastError();
     launch_gemm_bf16(trans_a != 0, trans_b != 0, M, N, K, A, lda, B, ldb, C, ldc, accumulate != 0,
-                     (hipStream_t)stream);
+                     nullptr, 0, (hipStream_t)stream);
     return check_launch("dp_gemm_bf16");
+}
+
+size_t dp_gemm_bf16_ws_bytes(int32_t M, int32_t N, int32_t K)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    return gemm_ws_bytes(M, N, K);
+}
+
+int dp_gemm_bf16_ws(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                    const void* A, int32_t lda, const void* B, int32_t ldb, float* C, int32_t ldc,
+                    int32_t accumulate, void* ws, size_t ws_bytes, void* stream)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return fail(DP_ERR_ARG, "gemm sizes must be positive");
+    if (!A || !B || !C) return fail(DP_ERR_ARG, "gemm: NULL operand");
+    if (lda < (trans_a ? M : K) || ldb < (trans_b ? K : N) || ldc < N)
+        return fail(DP_ERR_ARG, "gemm: leading dimension too small");
+    if ((size_t)M * ldc >= ((size_t)1 << 40)) return fail(DP_ERR_UNSUPPORTED, "gemm too large");
+    if ((N + 63) / 64 > 65535) return fail(DP_ERR_UNSUPPORTED, "gemm: N above 65535 tiles of 64");
+    const size_t need = gemm_ws_bytes(M, N, K);
+    if (need && (!ws || ws_bytes < need))
+        return fail(DP_ERR_ARG, "gemm: workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    (void)hipGetLastError();
+    launch_gemm_bf16(trans_a != 0, trans_b != 0, M, N, K, A, lda, B, ldb, C, ldc, accumulate != 0,
+                     (float*)ws, ws_bytes, (hipStream_t)stream);
+    return check_launch("dp_gemm_bf16_ws");
+}
+
+int dp_gemm_bias_act_bf16(int32_t M, int32_t N, int32_t K, const void* A, int32_t lda,
+                          const void* B, int32_t ldb, const float* bias, int32_t bias_stride,
+                          int32_t relu, void* Y, int32_t ldy, void* stream)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return fail(DP_ERR_ARG, "gemm sizes must be positive");
+    if (!A || !B || !bias || !Y) return fail(DP_ERR_ARG, "gemm_bias_act: NULL pointer");
+    if (lda < K || ldb < K || ldy < N || bias_stride < 1)
+        return fail(DP_ERR_ARG, "gemm_bias_act: leading dimension or bias stride too small");
+    if ((size_t)M * ldy >= ((size_t)1 << 40)) return fail(DP_ERR_UNSUPPORTED, "gemm too large");
+    if ((N + 63) / 64 > 65535) return fail(DP_ERR_UNSUPPORTED, "gemm: N above 65535 tiles of 64");
+    (void)hipGetLastError();
+    launch_gemm_bias_act(M, N, K, A, lda, B, ldb, bias, bias_stride, relu != 0, Y, ldy,
+                         (hipStream_t)stream);
+    return check_launch("dp_gemm_bias_act_bf16");
 }
 
 static int conv_dims(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride)
@@ -891,8 +932,23 @@ int dp_im2col3x3_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride
     if (!x || !col) return fail(DP_ERR_ARG, "im2col: NULL pointer");
     const int Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
     (void)hipGetLastError();
-    launch_im2col(N, H, W, C, stride, Ho, Wo, x, col, (hipStream_t)stream);
+    launch_im2col(N, H, W, C, stride, Ho, Wo, x, col, 9 * C, false, (hipStream_t)stream);
     return check_launch("dp_im2col3x3_bf16");
+}
+
+int dp_im2col3x3_ld_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
+                         const void* x, void* col, int32_t ld, int32_t ones, void* stream)
+{
+    int rc = conv_dims(N, H, W, C, stride);
+    if (rc) return rc;
+    if (!x || !col) return fail(DP_ERR_ARG, "im2col: NULL pointer");
+    if (ld < 9 * C + (ones ? 1 : 0)) return fail(DP_ERR_ARG, "im2col: row stride %d too small", ld);
+    const int Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
+    if ((int64_t)N * Ho * Wo * ld >= ((int64_t)1 << 31))
+        return fail(DP_ERR_UNSUPPORTED, "im2col: N x Ho x Wo x ld exceeds 2^31 elements; split the batch");
+    (void)hipGetLastError();
+    launch_im2col(N, H, W, C, stride, Ho, Wo, x, col, ld, ones != 0, (hipStream_t)stream);
+    return check_launch("dp_im2col3x3_ld_bf16");
 }
 
 int dp_col2im3x3(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride, const float* dcol,
@@ -903,8 +959,30 @@ int dp_col2im3x3(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride, con
     if (!dcol || !dx) return fail(DP_ERR_ARG, "col2im: NULL pointer");
     const int Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
     (void)hipGetLastError();
-    launch_col2im(N, H, W, C, stride, Ho, Wo, dcol, dx, (hipStream_t)stream);
+    launch_col2im(N, H, W, C, stride, Ho, Wo, dcol, dx, nullptr, false, nullptr, (hipStream_t)stream);
     return check_launch("dp_col2im3x3");
+}
+
+int dp_col2im3x3_act_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
+                          const float* dcol, const void* y, int32_t relu, void* dz, void* stream)
+{
+    int rc = conv_dims(N, H, W, C, stride);
+    if (rc) return rc;
+    if (!dcol || !y || !dz) return fail(DP_ERR_ARG, "col2im_act: NULL pointer");
+    const int Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
+    (void)hipGetLastError();
+    launch_col2im(N, H, W, C, stride, Ho, Wo, dcol, nullptr, y, relu != 0, dz, (hipStream_t)stream);
+    return check_launch("dp_col2im3x3_act_bf16");
+}
+
+int dp_adam_f32(int64_t n, float* p, const float* g, float* m, float* v, void* p_bf16, float lr,
+                float beta1, float beta2, float eps, float c1, float c2, void* stream)
+{
+    if (n <= 0 || !p || !g || !m || !v || !p_bf16) return fail(DP_ERR_ARG, "adam: bad argument");
+    if (!(c1 > 0.0f) || !(c2 > 0.0f)) return fail(DP_ERR_ARG, "adam: bias corrections must be positive");
+    (void)hipGetLastError();
+    launch_adam((size_t)n, p, g, m, v, p_bf16, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream);
+    return check_launch("dp_adam_f32");
 }
 
 int dp_bias_act_bf16(int64_t rows, int32_t C, const float* z, const float* bias, int32_t relu,

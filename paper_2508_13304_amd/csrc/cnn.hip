@@ -82,19 +82,34 @@ __device__ inline void stage_tile(const __bf16* __restrict__ P, int ld, int rows
     }
 }
 
-template <bool TA, bool TB, bool VEC>
+// Output modes of the GEMM kernel: FP32 C (+ C if accumulating); this
+// block's split-K partial tile into a workspace slice; or act(C + bias) to
+// BF16 (the forward convolution's epilogue).
+enum { kOutF32 = 0, kOutPartial = 1, kOutBiasAct = 2 };
+
+struct GemmOut {
+    float* C;            // kOutF32: C; kOutPartial: the workspace [splits][M][N]
+    int ldc;
+    int accumulate;
+    const float* bias;   // kOutBiasAct: bias of column n at bias[n * bias_stride]
+    int bias_stride;
+    int relu;
+    __bf16* Y;           // kOutBiasAct: BF16 output, row stride ldy
+    int ldy;
+};
+
+template <bool TA, bool TB, bool VEC, int OUT>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
                                                         const __bf16* __restrict__ A, int lda,
                                                         const __bf16* __restrict__ B, int ldb,
-                                                        float* __restrict__ C, int ldc,
-                                                        int accumulate)
+                                                        GemmOut o)
 {
     // As[m][k] and Bs[n][k]: both k-contiguous so a lane reads 8 k at once.
     __shared__ __attribute__((aligned(16))) __bf16 As[kGT][kGK + kGPad];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[kGT][kGK + kGPad];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT;
-    // split-K: block z covers k in [kbeg, kend); partial sums are added atomically
+    // split-K: block z covers k in [kbeg, kend) and writes its own partial tile
     const int ksplit = (K + (int)gridDim.z - 1) / (int)gridDim.z;
     const int kbeg = (int)blockIdx.z * ((ksplit + kGK - 1) / kGK * kGK);
     const int kend = min(K, kbeg + (ksplit + kGK - 1) / kGK * kGK);
@@ -108,7 +123,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
         // A stored [M][K] (k-contiguous) unless TA; B stored [N][K] if TB
         stage_tile<!TA, VEC>(A, lda, M, m0, k0, kend, As, tid);
         stage_tile<TB, VEC>(B, ldb, N, n0, k0, kend, Bs, tid);
-    __syncthreads();
+        __syncthreads();
         const int kq = (lane >> 4) * 8;
         bf16x8 a[2], b[2];
 #pragma unroll
@@ -131,55 +146,116 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
                 const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
                 const int n = n0 + wn + j * 16 + (lane & 15);
                 if (m < M && n < N) {
-                    float* c = C + (size_t)m * ldc + n;
-                    if (gridDim.z > 1)
-                        atomicAdd(c, acc[i][j][q]);
-                    else
-                        *c = accumulate ? *c + acc[i][j][q] : acc[i][j][q];
+                    const float v = acc[i][j][q];
+                    if constexpr (OUT == kOutPartial) {
+                        o.C[((size_t)blockIdx.z * M + m) * N + n] = v;
+                    } else if constexpr (OUT == kOutBiasAct) {
+                        float y = v + o.bias[(size_t)n * o.bias_stride];
+                        if (o.relu) y = fmaxf(y, 0.f);
+                        o.Y[(size_t)m * o.ldy + n] = to_bf16(y);
+                    } else {
+                        float* c = o.C + (size_t)m * o.ldc + n;
+                        *c = o.accumulate ? *c + v : v;
+                    }
                 }
             }
 }
 
-__global__ __launch_bounds__(256) void fill_rows_kernel(int M, int N, float* __restrict__ C, int ldc)
+// C (+)= the sum of the split-K partial tiles, in split order (the result
+// does not depend on which block finished first).
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(int M, int N, int S,
+                                                            const float* __restrict__ ws,
+                                                            float* __restrict__ C, int ldc,
+                                                            int accumulate)
 {
     const size_t total = (size_t)M * N;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x)
-        C[(i / N) * ldc + i % N] = 0.0f;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        for (int z = 0; z < S; ++z) v += ws[(size_t)z * total + i];
+        float* c = C + (i / N) * ldc + i % N;
+        *c = accumulate ? *c + v : v;
+    }
 }
 
-void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int lda, const void* B,
-                      int ldb, float* C, int ldc, bool accumulate, hipStream_t st)
+// Split-K for few output tiles and a long reduction (the weight gradients):
+// about 1024 blocks, each reducing at least 1024 rows.
+static int gemm_splits(int M, int N, int K)
 {
-    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
-    // few output tiles and a long reduction (the weight gradients): split K so
-    // that about 1024 blocks run, each reducing at least 1024 rows
-    int splits = 1;
-    const long long tiles = (long long)tm * tn;
+    const long long tiles = (long long)((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
     if (tiles < 512 && K >= 2048)
-        splits = (int)std::max<long long>(1, std::min<long long>((1024 + tiles - 1) / tiles, K / 1024));
-    if (splits > 1 && !accumulate) {
-        const size_t total = (size_t)M * N;
-        const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-        fill_rows_kernel<<<blocks, 256, 0, st>>>(M, N, C, ldc);
-    }
-    dim3 grid(tm, tn, splits);
-    const __bf16* a = (const __bf16*)A;
-    const __bf16* b = (const __bf16*)B;
-    const int acc = accumulate ? 1 : 0;
-    const bool vec = lda % 8 == 0 && ldb % 8 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+        return (int)std::max<long long>(1, std::min<long long>((1024 + tiles - 1) / tiles, K / 1024));
+    return 1;
+}
+
+size_t gemm_ws_bytes(int M, int N, int K)
+{
+    const int s = gemm_splits(M, N, K);
+    return s > 1 ? (size_t)s * M * N * sizeof(float) : 0;
+}
+
+template <int OUT>
+static void gemm_dispatch(bool ta, bool tb, bool vec, dim3 grid, int M, int N, int K,
+                          const __bf16* a, int lda, const __bf16* b, int ldb, const GemmOut& o,
+                          hipStream_t st)
+{
 #define DP_GEMM(TA_, TB_)                                                                          \
     do {                                                                                           \
         if (vec)                                                                                   \
-            gemm_bf16_kernel<TA_, TB_, true><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc); \
+            gemm_bf16_kernel<TA_, TB_, true, OUT><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, o); \
         else                                                                                       \
-            gemm_bf16_kernel<TA_, TB_, false><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, C, ldc, acc); \
+            gemm_bf16_kernel<TA_, TB_, false, OUT><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, o); \
     } while (0)
     if (!ta && !tb) DP_GEMM(false, false);
     else if (!ta && tb) DP_GEMM(false, true);
     else if (ta && !tb) DP_GEMM(true, false);
     else DP_GEMM(true, true);
 #undef DP_GEMM
+}
+
+static bool gemm_vec(int lda, int ldb, const void* A, const void* B)
+{
+    return lda % 8 == 0 && ldb % 8 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+}
+
+void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int lda, const void* B,
+                      int ldb, float* C, int ldc, bool accumulate, float* ws, size_t ws_bytes,
+                      hipStream_t st)
+{
+    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
+    int splits = gemm_splits(M, N, K);
+    if (splits > 1 && (!ws || ws_bytes < gemm_ws_bytes(M, N, K))) splits = 1;  // no workspace: one pass
+    const __bf16* a = (const __bf16*)A;
+    const __bf16* b = (const __bf16*)B;
+    const bool vec = gemm_vec(lda, ldb, A, B);
+    GemmOut o{};
+    if (splits > 1) {
+        o.C = ws;
+        gemm_dispatch<kOutPartial>(ta, tb, vec, dim3(tm, tn, splits), M, N, K, a, lda, b, ldb, o, st);
+        const size_t total = (size_t)M * N;
+        const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+        splitk_reduce_kernel<<<blocks, 256, 0, st>>>(M, N, splits, ws, C, ldc, accumulate ? 1 : 0);
+    } else {
+        o.C = C;
+        o.ldc = ldc;
+        o.accumulate = accumulate ? 1 : 0;
+        gemm_dispatch<kOutF32>(ta, tb, vec, dim3(tm, tn, 1), M, N, K, a, lda, b, ldb, o, st);
+    }
+}
+
+void launch_gemm_bias_act(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
+                          const float* bias, int bias_stride, bool relu, void* Y, int ldy,
+                          hipStream_t st)
+{
+    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
+    GemmOut o{};
+    o.bias = bias;
+    o.bias_stride = bias_stride;
+    o.relu = relu ? 1 : 0;
+    o.Y = (__bf16*)Y;
+    o.ldy = ldy;
+    gemm_dispatch<kOutBiasAct>(false, true, gemm_vec(lda, ldb, A, B), dim3(tm, tn, 1), M, N, K,
+                               (const __bf16*)A, lda, (const __bf16*)B, ldb, o, st);
 }
 
 // im2col of a 3x3 convolution (stride s, padding 1) on NHWC BF16 input:
@@ -190,7 +266,7 @@ void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int 
 template <int G>
 __global__ __launch_bounds__(256) void im2col_kernel(int N, int H, int W, int C, int s, int Ho,
                                                      int Wo, const __bf16* __restrict__ x,
-                                                     __bf16* __restrict__ col)
+                                                     __bf16* __restrict__ col, int ld)
 {
     const unsigned groups = (unsigned)(C / G);
     const unsigned total = (unsigned)N * Ho * Wo * 9u * groups;
@@ -202,7 +278,7 @@ __global__ __launch_bounds__(256) void im2col_kernel(int N, int H, int W, int C,
         const int yo = (int)(q % (unsigned)Ho), n = (int)(q / (unsigned)Ho);
         const int ky = (int)t / 3, kx = (int)t - 3 * ky;
         const int yi = yo * s + ky - 1, xi = xo * s + kx - 1;
-        __bf16* dst = col + (size_t)m * 9 * C + t * C + g * G;
+        __bf16* dst = col + (size_t)m * ld + t * C + g * G;
         const bool in = yi >= 0 && yi < H && xi >= 0 && xi < W;
         const __bf16* src = x + (((size_t)n * H + yi) * W + xi) * C + g * G;
         if constexpr (G == 8) {
@@ -214,13 +290,31 @@ __global__ __launch_bounds__(256) void im2col_kernel(int N, int H, int W, int C,
     }
 }
 
+// Columns [9 C, ld) of each im2col row: 1 in column 9 C when `ones` (so that
+// the weight-gradient product dz^T col also yields the bias gradient, the
+// column sums of dz), 0 elsewhere.
+__global__ __launch_bounds__(256) void col_tail_kernel(unsigned rows, int K9, int ld, int ones,
+                                                       __bf16* __restrict__ col)
+{
+    const unsigned w = (unsigned)(ld - K9), total = rows * w;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const unsigned m = i / w, c = i - m * w;
+        col[(size_t)m * ld + K9 + c] = to_bf16(ones && c == 0 ? 1.f : 0.f);
+    }
+}
+
 // dx = col2im(dcol): each input element gathers the window entries that read
 // it (taps in ky, kx order).  One thread per (n, yi, xi, group of G
 // channels); G = 4 moves float4.
-template <int G>
+// ACT: the result is the gradient of the layer below's BF16 activation y, and
+// the kernel applies that layer's ReLU backward and writes the BF16 operand
+// dz = dx * (y > 0) instead of FP32 dx.
+template <int G, bool ACT>
 __global__ __launch_bounds__(256) void col2im_kernel(int N, int H, int W, int C, int s, int Ho,
                                                      int Wo, const float* __restrict__ dcol,
-                                                     float* __restrict__ dx)
+                                                     float* __restrict__ dx,
+                                                     const __bf16* __restrict__ y, int relu,
+                                                     __bf16* __restrict__ dz)
 {
     const unsigned groups = (unsigned)(C / G);
     const unsigned total = (unsigned)N * H * W * groups;
@@ -253,12 +347,19 @@ __global__ __launch_bounds__(256) void col2im_kernel(int N, int H, int W, int C,
                 }
             }
         }
-        float* dst = dx + (size_t)p * C + g * G;
-        if constexpr (G == 4) {
-            *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        } else {
+        if constexpr (ACT) {
+            const size_t o = (size_t)p * C + g * G;
 #pragma unroll
-            for (int c = 0; c < G; ++c) dst[c] = acc[c];
+            for (int c = 0; c < G; ++c)
+                dz[o + c] = to_bf16(relu ? ((float)y[o + c] > 0.f ? acc[c] : 0.f) : acc[c]);
+        } else {
+            float* dst = dx + (size_t)p * C + g * G;
+            if constexpr (G == 4) {
+                *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < G; ++c) dst[c] = acc[c];
+            }
         }
     }
 }
@@ -324,6 +425,28 @@ __global__ __launch_bounds__(256) void colsum_kernel(int M, int C, const __bf16*
     }
 }
 
+// One Adam step over a flat parameter buffer (every layer at once): moments
+// m, v and the FP32 master p updated in place, and p rounded to BF16 for the
+// next products.  c1, c2: the bias corrections 1 - beta^t.
+__global__ __launch_bounds__(256) void adam_kernel(size_t n, float* __restrict__ p,
+                                                   const float* __restrict__ g, float* __restrict__ m,
+                                                   float* __restrict__ v, __bf16* __restrict__ pb,
+                                                   float lr, float b1, float b2, float eps, float c1,
+                                                   float c2)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+        const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        pb[i] = to_bf16(pi);
+    }
+}
+
 __global__ __launch_bounds__(256) void fill_zero_kernel(int n, float* __restrict__ p)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,27 +460,49 @@ static int grid_for(size_t total)
 }
 
 void launch_im2col(int N, int H, int W, int C, int s, int Ho, int Wo, const void* x, void* col,
-                   hipStream_t st)
+                   int ld, bool ones, hipStream_t st)
 {
-    const bool vec = C % 8 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)col % 16 == 0;
+    const bool vec = C % 8 == 0 && ld % 8 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)col % 16 == 0;
     const size_t total = (size_t)N * Ho * Wo * 9 * (vec ? C / 8 : C);
     if (vec)
         im2col_kernel<8><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, (const __bf16*)x,
-                                                          (__bf16*)col);
+                                                          (__bf16*)col, ld);
     else
         im2col_kernel<1><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, (const __bf16*)x,
-                                                          (__bf16*)col);
+                                                          (__bf16*)col, ld);
+    if (ld > 9 * C) {
+        const unsigned rows = (unsigned)N * Ho * Wo;
+        col_tail_kernel<<<grid_for((size_t)rows * (ld - 9 * C)), 256, 0, st>>>(rows, 9 * C, ld, ones ? 1 : 0,
+                                                                              (__bf16*)col);
+    }
 }
 
 void launch_col2im(int N, int H, int W, int C, int s, int Ho, int Wo, const float* dcol, float* dx,
-                   hipStream_t st)
+                   const void* y, bool relu, void* dz, hipStream_t st)
 {
-    const bool vec = C % 4 == 0 && (uintptr_t)dcol % 16 == 0 && (uintptr_t)dx % 16 == 0;
+    const bool act = y != nullptr;
+    const bool vec = C % 4 == 0 && (uintptr_t)dcol % 16 == 0 && (act || (uintptr_t)dx % 16 == 0);
     const size_t total = (size_t)N * H * W * (vec ? C / 4 : C);
-    if (vec)
-        col2im_kernel<4><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx);
-    else
-        col2im_kernel<1><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx);
+    const __bf16* yb = (const __bf16*)y;
+    __bf16* dzb = (__bf16*)dz;
+    const int r = relu ? 1 : 0;
+    if (act) {
+        if (vec)
+            col2im_kernel<4, true><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx, yb, r, dzb);
+        else
+            col2im_kernel<1, true><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx, yb, r, dzb);
+    } else {
+        if (vec)
+            col2im_kernel<4, false><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx, yb, r, dzb);
+        else
+            col2im_kernel<1, false><<<grid_for(total), 256, 0, st>>>(N, H, W, C, s, Ho, Wo, dcol, dx, yb, r, dzb);
+    }
+}
+
+void launch_adam(size_t n, float* p, const float* g, float* m, float* v, void* pb, float lr,
+                 float b1, float b2, float eps, float c1, float c2, hipStream_t st)
+{
+    adam_kernel<<<grid_for(n), 256, 0, st>>>(n, p, g, m, v, (__bf16*)pb, lr, b1, b2, eps, c1, c2);
 }
 
 void launch_bias_relu(size_t total, int C, const float* z, const float* b, bool relu, void* y,

@@ -164,12 +164,25 @@ void launch_finalize_bp(const GeoScalars& s, int V, const ViewGeo* views, const 
                         int n_part, double* grad_pose, hipStream_t st);
 
 // Learned-proposal CNN primitives (cnn.hip).
+// ws (may be NULL): split-K partials for few output tiles and a long
+// reduction, gemm_ws_bytes(M, N, K) bytes; without it the product runs in one
+// pass.  Either way the result does not depend on block timing.
+size_t gemm_ws_bytes(int M, int N, int K);
 void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int lda, const void* B,
-                      int ldb, float* C, int ldc, bool accumulate, hipStream_t st);
+                      int ldb, float* C, int ldc, bool accumulate, float* ws, size_t ws_bytes,
+                      hipStream_t st);
+// Y [M][N] BF16 (row stride ldy) = act(A B^T + bias), A [M][K], B [N][K] BF16.
+void launch_gemm_bias_act(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
+                          const float* bias, int bias_stride, bool relu, void* Y, int ldy,
+                          hipStream_t st);
+// col rows of ld >= 9 C entries: the 9 C window values, then 1 (ones) and zeros.
 void launch_im2col(int N, int H, int W, int C, int s, int Ho, int Wo, const void* x, void* col,
-                   hipStream_t st);
+                   int ld, bool ones, hipStream_t st);
+// y == NULL: FP32 dx; else the BF16 dz = dx * (y > 0) (relu) or dx of the layer below.
 void launch_col2im(int N, int H, int W, int C, int s, int Ho, int Wo, const float* dcol, float* dx,
-                   hipStream_t st);
+                   const void* y, bool relu, void* dz, hipStream_t st);
+void launch_adam(size_t n, float* p, const float* g, float* m, float* v, void* pb, float lr,
+                 float b1, float b2, float eps, float c1, float c2, hipStream_t st);
 void launch_bias_relu(size_t total, int C, const float* z, const float* b, bool relu, void* y,
                       hipStream_t st);
 void launch_relu_bwd(size_t total, const float* dy, const void* y, bool relu, void* dz,

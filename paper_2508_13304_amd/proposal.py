@@ -43,15 +43,24 @@ def label_scale(device) -> torch.Tensor:
 def _lib():
     lib = load()
     if not getattr(lib, "_cnn_ready", False):
-        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        vp, i32, i64, f32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
         lib.dp_gemm_bf16.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, vp, i32, i32, vp]
+        lib.dp_gemm_bf16_ws_bytes.argtypes = [i32, i32, i32]
+        lib.dp_gemm_bf16_ws_bytes.restype = sz
+        lib.dp_gemm_bf16_ws.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, vp, i32, i32, vp,
+                                        sz, vp]
+        lib.dp_gemm_bias_act_bf16.argtypes = [i32, i32, i32, vp, i32, vp, i32, vp, i32, i32, vp, i32, vp]
         lib.dp_im2col3x3_bf16.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp]
+        lib.dp_im2col3x3_ld_bf16.argtypes = [i32, i32, i32, i32, i32, vp, vp, i32, i32, vp]
         lib.dp_col2im3x3.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp]
+        lib.dp_col2im3x3_act_bf16.argtypes = [i32, i32, i32, i32, i32, vp, vp, i32, vp, vp]
         lib.dp_bias_act_bf16.argtypes = [i64, i32, vp, vp, i32, vp, vp]
         lib.dp_act_bwd_bf16.argtypes = [i64, vp, vp, i32, vp, vp]
         lib.dp_colsum_bf16.argtypes = [i32, i32, vp, vp, vp]
-        for f in ("dp_gemm_bf16", "dp_im2col3x3_bf16", "dp_col2im3x3", "dp_bias_act_bf16",
-                  "dp_act_bwd_bf16", "dp_colsum_bf16"):
+        lib.dp_adam_f32.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, f32, f32, vp]
+        for f in ("dp_gemm_bf16", "dp_gemm_bf16_ws", "dp_gemm_bias_act_bf16", "dp_im2col3x3_bf16",
+                  "dp_im2col3x3_ld_bf16", "dp_col2im3x3", "dp_col2im3x3_act_bf16",
+                  "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16", "dp_adam_f32"):
             getattr(lib, f).restype = C.c_int
         lib._cnn_ready = True
     return lib
@@ -61,30 +70,73 @@ def _p(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _ld(t):
+    """Row stride of a 2-D tensor whose rows are contiguous."""
+    assert t.dim() == 2 and (t.stride(1) == 1 or t.shape[1] == 1)
+    return t.stride(0)
+
+
+_WS = {}
+
+
+def _workspace(device, nbytes):
+    """Split-K workspace, one per device, grown on demand (calls on one
+    stream use it in turn)."""
+    ws = _WS.get(device)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+        _WS[device] = ws
+    return ws
+
+
 def gemm(a, b, ta=False, tb=False, out=None, accumulate=False):
-    """FP32 out = op(a) @ op(b) with BF16 operands (2-D, contiguous)."""
+    """FP32 out = op(a) @ op(b) with BF16 operands (2-D, rows contiguous;
+    split-K partials in a workspace, so the result is repeatable)."""
     M, K = (a.shape[1], a.shape[0]) if ta else (a.shape[0], a.shape[1])
     N = b.shape[0] if tb else b.shape[1]
     assert a.dtype == torch.bfloat16 and b.dtype == torch.bfloat16
     assert (b.shape[1] if tb else b.shape[0]) == K
     if out is None:
         out = torch.empty((M, N), dtype=torch.float32, device=a.device)
-    rc = _lib().dp_gemm_bf16(int(ta), int(tb), M, N, K, _p(a), a.shape[1], _p(b), b.shape[1],
-                             _p(out), out.shape[1], int(accumulate), _stream(None))
-    _check(rc, "dp_gemm_bf16")
+    lib = _lib()
+    need = lib.dp_gemm_bf16_ws_bytes(M, N, K)
+    ws = _workspace(a.device, need) if need else None
+    rc = lib.dp_gemm_bf16_ws(int(ta), int(tb), M, N, K, _p(a), _ld(a), _p(b), _ld(b), _p(out),
+                             _ld(out), int(accumulate), _p(ws) if ws is not None else None,
+                             ws.numel() if ws is not None else 0, _stream(None))
+    _check(rc, "dp_gemm_bf16_ws")
     return out
 
 
-def im2col(x, stride):
+def gemm_bias_act(a, b, K, bias, relu=True):
+    """BF16 act(a[:, :K] @ b[:, :K]^T + bias) with a [M][>=K], b [N][>=K] BF16 and
+    bias a 1-D FP32 view of N values (any stride)."""
+    M, N = a.shape[0], b.shape[0]
+    y = torch.empty((M, N), dtype=torch.bfloat16, device=a.device)
+    _check(_lib().dp_gemm_bias_act_bf16(M, N, K, _p(a), _ld(a), _p(b), _ld(b), _p(bias),
+                                        bias.stride(0), int(relu), _p(y), N, _stream(None)),
+           "dp_gemm_bias_act_bf16")
+    return y
+
+
+def im2col(x, stride, ld=None, ones=False):
+    """col [N Ho Wo][ld] BF16: the 9 Ci window values, then (ones) a 1 and zeros."""
+    x = x.contiguous()
     N, H, W, Ci = x.shape
     Ho, Wo = (H - 1) // stride + 1, (W - 1) // stride + 1
-    col = torch.empty((N * Ho * Wo, 9 * Ci), dtype=torch.bfloat16, device=x.device)
-    _check(_lib().dp_im2col3x3_bf16(N, H, W, Ci, stride, _p(x), _p(col), _stream(None)),
-           "dp_im2col3x3_bf16")
+    ld = 9 * Ci if ld is None else ld
+    col = torch.empty((N * Ho * Wo, ld), dtype=torch.bfloat16, device=x.device)
+    if ld == 9 * Ci and not ones:
+        rc = _lib().dp_im2col3x3_bf16(N, H, W, Ci, stride, _p(x), _p(col), _stream(None))
+    else:
+        rc = _lib().dp_im2col3x3_ld_bf16(N, H, W, Ci, stride, _p(x), _p(col), ld, int(ones),
+                                         _stream(None))
+    _check(rc, "dp_im2col3x3_bf16")
     return col, Ho, Wo
 
 
 def col2im(dcol, shape, stride):
+    dcol = dcol.contiguous()
     N, H, W, Ci = shape
     dx = torch.empty(shape, dtype=torch.float32, device=dcol.device)
     _check(_lib().dp_col2im3x3(N, H, W, Ci, stride, _p(dcol), _p(dx), _stream(None)),
@@ -92,7 +144,18 @@ def col2im(dcol, shape, stride):
     return dx
 
 
+def col2im_act(dcol, shape, stride, y, relu=True):
+    """BF16 dz = col2im(dcol) * (y > 0) for the layer below's BF16 output y."""
+    N, H, W, Ci = shape
+    dcol, y = dcol.contiguous(), y.contiguous()
+    dz = torch.empty(shape, dtype=torch.bfloat16, device=dcol.device)
+    _check(_lib().dp_col2im3x3_act_bf16(N, H, W, Ci, stride, _p(dcol), _p(y), int(relu), _p(dz),
+                                        _stream(None)), "dp_col2im3x3_act_bf16")
+    return dz
+
+
 def bias_act(z, bias, relu=True):
+    z, bias = z.contiguous(), bias.contiguous()
     y = torch.empty(z.shape, dtype=torch.bfloat16, device=z.device)
     _check(_lib().dp_bias_act_bf16(z.shape[0], z.shape[1], _p(z), _p(bias), int(relu), _p(y),
                                    _stream(None)), "dp_bias_act_bf16")
@@ -100,6 +163,7 @@ def bias_act(z, bias, relu=True):
 
 
 def act_bwd(dy, y, relu=True):
+    dy, y = dy.contiguous(), y.contiguous()
     dz = torch.empty(dy.shape, dtype=torch.bfloat16, device=dy.device)
     _check(_lib().dp_act_bwd_bf16(dy.numel(), _p(dy), _p(y), int(relu), _p(dz), _stream(None)),
            "dp_act_bwd_bf16")
@@ -107,31 +171,74 @@ def act_bwd(dy, y, relu=True):
 
 
 def colsum(dz):
+    dz = dz.contiguous()
     db = torch.empty(dz.shape[1], dtype=torch.float32, device=dz.device)
     _check(_lib().dp_colsum_bf16(dz.shape[0], dz.shape[1], _p(dz), _p(db), _stream(None)),
            "dp_colsum_bf16")
     return db
 
 
+def adam(p, g, m, v, pb, lr, betas, eps, c1, c2):
+    """One fused Adam step over flat FP32 buffers; pb receives p in BF16."""
+    _check(_lib().dp_adam_f32(p.numel(), _p(p), _p(g), _p(m), _p(v), _p(pb), lr, betas[0], betas[1],
+                              eps, c1, c2, _stream(None)), "dp_adam_f32")
+
+
+def _row_len(ci):
+    """Row length of a layer's parameter block: 9 Ci weights, the bias, zero
+    padding to a multiple of 8 (16-byte rows for the BF16 products)."""
+    return (9 * ci + 1 + 7) // 8 * 8
+
+
 class ProposalNet:
-    """Strided CNN + linear head; parameters in FP32, operands in BF16."""
+    """Strided CNN + linear head; parameters in FP32, operands in BF16.
+
+    All parameters live in one flat FP32 buffer P (gradients in G of the same
+    layout, a BF16 copy in Pb): per conv layer a [Co][row] block whose row
+    holds the 9 Ci weights, the bias and zero padding, then the head's
+    weights [6][F] and bias [6].  The forward product reads the BF16 weights
+    with the FP32 bias in its epilogue; the weight-gradient product of the
+    im2col matrix with a ones column writes the layer's weight and bias
+    gradients straight into its block of G; Adam is one launch over P."""
 
     def __init__(self, size=256, in_ch=2, channels=CHANNELS, device="cuda:0", seed=0):
         self.size = size
         self.device = torch.device(device)
         g = torch.Generator(device="cpu").manual_seed(seed)
-        self.convs = []   # (W [Co][9 Ci], b [Co], stride)
-        ci, hw = in_ch, size
+        shapes, ci, hw = [], in_ch, size
         for co in channels:
-            std = math.sqrt(2.0 / (9 * ci))
-            W = (torch.randn(co, 9 * ci, generator=g) * std).to(self.device)
-            self.convs.append([W, torch.zeros(co, device=self.device), 2])
+            shapes.append((ci, co, _row_len(ci)))
             ci, hw = co, (hw - 1) // 2 + 1
         self.feat_hw, self.feat_c = hw, ci
         F = hw * hw * ci
-        self.Wfc = (torch.randn(6, F, generator=g) * math.sqrt(1.0 / F)).to(self.device)
-        self.bfc = torch.zeros(6, device=self.device)
+        n = sum(co * r for _, co, r in shapes) + 6 * F + 6
+        self.P = torch.zeros(n, device=self.device)
+        self.G = torch.zeros(n, device=self.device)
+        self.Pb = torch.zeros(n, dtype=torch.bfloat16, device=self.device)
+        self.blocks, self.gblocks, self.bblocks, self.convs = [], [], [], []
+        off = 0
+        for ci, co, r in shapes:
+            blk = self.P[off:off + co * r].view(co, r)
+            std = math.sqrt(2.0 / (9 * ci))
+            blk[:, :9 * ci] = (torch.randn(co, 9 * ci, generator=g) * std).to(self.device)
+            self.blocks.append(blk)
+            self.gblocks.append(self.G[off:off + co * r].view(co, r))
+            self.bblocks.append(self.Pb[off:off + co * r].view(co, r))
+            self.convs.append([blk[:, :9 * ci], blk[:, 9 * ci], 2])
+            off += co * r
+        self.Wfc = self.P[off:off + 6 * F].view(6, F)
+        self.Wfc.copy_((torch.randn(6, F, generator=g) * math.sqrt(1.0 / F)).to(self.device))
+        self.gWfc = self.G[off:off + 6 * F].view(6, F)
+        self.Wfc_b = self.Pb[off:off + 6 * F].view(6, F)
+        off += 6 * F
+        self.bfc = self.P[off:off + 6]
+        self.gbfc = self.G[off:off + 6]
+        self.sync_bf16()
         self._adam = None
+
+    def sync_bf16(self):
+        """Refresh the BF16 copy after the FP32 parameters were changed."""
+        self.Pb.copy_(self.P)
 
     def params(self):
         ps = []
@@ -143,54 +250,53 @@ class ProposalNet:
         """x: [N][H][W][2] BF16 (NHWC).  Returns FP32 [N][6] (and the cache)."""
         cache = []
         h = x.contiguous()
-        for W, b, s in self.convs:
-            col, Ho, Wo = im2col(h, s)
-            z = gemm(col, W.to(torch.bfloat16).contiguous(), tb=True)
-            y = bias_act(z, b, relu=True)
+        for li, (W, b, s) in enumerate(self.convs):
+            K = W.shape[1]
+            col, Ho, Wo = im2col(h, s, ld=self.blocks[li].shape[1], ones=keep)
+            y = gemm_bias_act(col, self.bblocks[li], K, b, relu=True)
             if keep:
                 cache.append((h.shape, col, y, s))
             h = y.view(h.shape[0], Ho, Wo, W.shape[0])
         feat = h.reshape(h.shape[0], -1)
-        out = gemm(feat, self.Wfc.to(torch.bfloat16).contiguous(), tb=True) + self.bfc
+        out = gemm(feat, self.Wfc_b, tb=True) + self.bfc
         return (out, (cache, feat)) if keep else out
 
     def backward(self, cache, dout):
-        """Gradients of sum(dout * forward(x)) for every parameter (FP32)."""
+        """Gradients of sum(dout * forward(x)) for every parameter (FP32),
+        written into G; returns views of it: per layer (dW, db), and the head's."""
         convs_cache, feat = cache
         d = dout.to(torch.bfloat16).contiguous()
-        dWfc = gemm(d, feat, ta=True)
-        dbfc = dout.to(torch.bfloat16).float().sum(0)
-        dh = gemm(d, self.Wfc.to(torch.bfloat16).contiguous())   # [N][F] FP32
+        gemm(d, feat, ta=True, out=self.gWfc)
+        self.gbfc.copy_(d.float().sum(0))
+        dh = gemm(d, self.Wfc_b)                                   # [N][F] FP32
+        _, _, y_top, _ = convs_cache[-1]
+        dz = act_bwd(dh.reshape(y_top.shape).contiguous(), y_top, relu=True)
         grads = [None] * len(self.convs)
         for li in range(len(self.convs) - 1, -1, -1):
             W, b, s = self.convs[li]
             xshape, col, y, _ = convs_cache[li]
-            dz = act_bwd(dh.reshape(y.shape).contiguous(), y, relu=True)
-            dW = gemm(dz, col, ta=True)                          # [Co][9 Ci]
-            db = colsum(dz)
+            gemm(dz, col, ta=True, out=self.gblocks[li])            # [Co][row]: dW | db | 0
+            K = W.shape[1]
             if li > 0:
-                dcol = gemm(dz, W.to(torch.bfloat16).contiguous())  # [M][9 Ci]
-                dh = col2im(dcol, xshape, s)
-            grads[li] = (dW, db)
-        return grads, (dWfc, dbfc)
+                dcol = gemm(dz, self.bblocks[li][:, :K])             # [M][9 Ci]
+                y_below = convs_cache[li - 1][2]
+                dz = col2im_act(dcol, xshape, s, y_below, relu=True).view(-1, xshape[3])
+            grads[li] = (self.gblocks[li][:, :K], self.gblocks[li][:, K])
+        return grads, (self.gWfc, self.gbfc)
 
     def adam_step(self, grads, head, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, wd=0.0):
-        flat = []
-        for dW, db in grads:
-            flat += [dW, db]
-        flat += list(head)
-        ps = self.params()
+        """One Adam step on every parameter; `grads` and `head` must be the
+        views of G that backward() returned (the step reads G as a whole)."""
+        assert head[0].data_ptr() == self.gWfc.data_ptr()
         if self._adam is None:
-            self._adam = [(torch.zeros_like(p), torch.zeros_like(p)) for p in ps]
+            self._adam = (torch.zeros_like(self.P), torch.zeros_like(self.P))
             self._t = 0
         self._t += 1
-        c1, c2 = 1 - betas[0] ** self._t, 1 - betas[1] ** self._t
-        for p, g, (m, v) in zip(ps, flat, self._adam):
-            if wd:
-                g = g + wd * p
-            m.mul_(betas[0]).add_(g, alpha=1 - betas[0])
-            v.mul_(betas[1]).addcmul_(g, g, value=1 - betas[1])
-            p.sub_(lr * (m / c1) / ((v / c2).sqrt() + eps))
+        if wd:
+            self.G.add_(self.P, alpha=wd)
+        m, v = self._adam
+        adam(self.P, self.G, m, v, self.Pb, lr, betas, eps, 1 - betas[0] ** self._t,
+             1 - betas[1] ** self._t)
 
     def tensors(self) -> dict:
         """Flat name -> FP32 CPU tensor map (safetensors layout)."""
@@ -218,10 +324,11 @@ class ProposalNet:
         chans = tuple(int(c) for c in meta["channels"].split(","))
         net = cls(size=int(meta["size"]), channels=chans, device=device)
         for i, conv in enumerate(net.convs):
-            conv[0] = t[f"conv{i}.weight"].to(net.device).contiguous()
-            conv[1] = t[f"conv{i}.bias"].to(net.device).contiguous()
-        net.Wfc = t["fc.weight"].to(net.device).contiguous()
-        net.bfc = t["fc.bias"].to(net.device).contiguous()
+            conv[0].copy_(t[f"conv{i}.weight"].to(net.device))
+            conv[1].copy_(t[f"conv{i}.bias"].to(net.device))
+        net.Wfc.copy_(t["fc.weight"].to(net.device))
+        net.bfc.copy_(t["fc.bias"].to(net.device))
+        net.sync_bf16()
         net.meta = meta
         return net
 

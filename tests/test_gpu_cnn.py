@@ -229,3 +229,99 @@ def test_network_elementwise_full_size(dp):
     net = pr.ProposalNet.load(pr.WEIGHTS)
     rng = np.random.default_rng(17)
     _layerwise_check(net, ocnn.bf16(rng.uniform(0, 1, (2, net.size, net.size, 2))))
+
+
+def test_fused_forward_epilogue_equals_separate_passes(dp):
+    """The forward product with its bias + ReLU epilogue writes exactly what
+    the FP32 product followed by the separate bias / activation pass writes
+    (same MFMA accumulation, one rounding to BF16), for a row-padded operand
+    with the bias read through a strided view."""
+    from paper_2508_13304_amd import proposal as pr
+    g = torch.Generator(device=DEV).manual_seed(31)
+    M, N, K, row = 1000, 70, 45, 56
+    a = (torch.randn((M, row), device=DEV, generator=g)).to(torch.bfloat16)
+    blk = torch.randn((N, row), device=DEV, generator=g)
+    b = blk[:, K]                       # bias column of the parameter block
+    y = pr.gemm_bias_act(a, blk.to(torch.bfloat16), K, b, relu=True)
+    z = pr.gemm(a[:, :K].contiguous(), blk[:, :K].to(torch.bfloat16).contiguous(), tb=True)
+    assert torch.equal(y, pr.bias_act(z, b.contiguous(), relu=True))
+
+
+def test_col2im_with_activation_backward_equals_separate_passes(dp):
+    from paper_2508_13304_amd import proposal as pr
+    g = torch.Generator(device=DEV).manual_seed(32)
+    for (N, H, W, C, s) in ((2, 13, 10, 8, 2), (1, 9, 7, 5, 1)):
+        Ho, Wo = (H - 1) // s + 1, (W - 1) // s + 1
+        dcol = torch.randn((N * Ho * Wo, 9 * C), device=DEV, generator=g)
+        y = torch.randn((N, H, W, C), device=DEV, generator=g).to(torch.bfloat16)
+        dz = pr.col2im_act(dcol, (N, H, W, C), s, y, relu=True)
+        dx = pr.col2im(dcol, (N, H, W, C), s)
+        assert torch.equal(dz, pr.act_bwd(dx.reshape(-1, C), y.reshape(-1, C), relu=True).view(N, H, W, C))
+
+
+def test_im2col_row_stride_and_ones_column(dp):
+    from paper_2508_13304_amd import proposal as pr
+    g = torch.Generator(device=DEV).manual_seed(33)
+    for C, ld in ((2, 24), (8, 80)):
+        x = torch.randn((2, 11, 9, C), device=DEV, generator=g).to(torch.bfloat16)
+        col, Ho, Wo = pr.im2col(x, 2)
+        colp, _, _ = pr.im2col(x, 2, ld=ld, ones=True)
+        assert torch.equal(colp[:, :9 * C], col)
+        assert torch.all(colp[:, 9 * C] == 1) and torch.all(colp[:, 9 * C + 1:] == 0)
+
+
+def test_split_k_product_is_repeatable_and_matches_oracle(dp):
+    """Weight-gradient shaped product (few output tiles, long reduction):
+    split-K partials reduced in split order, so two launches agree bit for
+    bit, and the result meets the elementwise FP32-accumulation bound."""
+    from paper_2508_13304_amd import proposal as pr
+    rng = np.random.default_rng(34)
+    M, N, K = 64, 200, 60000
+    A = ocnn.bf16(rng.standard_normal((K, M)))
+    B = ocnn.bf16(rng.standard_normal((K, N)))
+    C1 = pr.gemm(bf(A), bf(B), ta=True)
+    C2 = pr.gemm(bf(A), bf(B), ta=True)
+    assert torch.equal(C1, C2)
+    ref = A.T @ B
+    assert np.all(np.abs(C1.cpu().numpy() - ref) <= 1e-5 * (np.abs(A.T) @ np.abs(B)))
+
+
+def test_fused_adam_matches_the_update_rule(dp):
+    from paper_2508_13304_amd import proposal as pr
+    g = torch.Generator(device=DEV).manual_seed(35)
+    n = 100003
+    p = torch.randn(n, device=DEV, generator=g)
+    gr = torch.randn(n, device=DEV, generator=g)
+    m = torch.randn(n, device=DEV, generator=g) * 0.1
+    v = torch.rand(n, device=DEV, generator=g) * 0.01
+    pb = torch.empty(n, dtype=torch.bfloat16, device=DEV)
+    b1, b2, lr, eps, c1, c2 = 0.9, 0.999, 1e-3, 1e-8, 1 - 0.9 ** 3, 1 - 0.999 ** 3
+    # the kernel takes FP32 constants: the reference uses the same values
+    f = lambda a: float(np.float32(a))  # noqa: E731
+    b1f, b2f, lrf, epsf, c1f, c2f = map(f, (b1, b2, lr, eps, c1, c2))
+    m_ref = b1f * m.double() + f(1 - b1f) * gr.double()
+    v_ref = b2f * v.double() + f(1 - b2f) * gr.double() ** 2
+    p_ref = p.double() - lrf * (m_ref / c1f) / ((v_ref / c2f).sqrt() + epsf)
+    mag_m = b1f * m.double().abs() + gr.double().abs() * 0.1
+    mag_v = b2f * v.double() + gr.double() ** 2 * 1e-3
+    pr.adam(p, gr, m, v, pb, lr, (b1, b2), eps, c1, c2)
+    assert torch.all((m.double() - m_ref).abs() <= 4e-7 * mag_m)
+    assert torch.all((v.double() - v_ref).abs() <= 4e-7 * mag_v)
+    assert torch.allclose(p.double(), p_ref, rtol=1e-6, atol=1e-7)
+    assert torch.equal(pb, p.to(torch.bfloat16))
+
+
+def test_network_training_step_is_repeatable(dp):
+    """Two networks from the same seed, one training step each on the same
+    batch: bit-identical parameters afterwards (no atomics in any product or
+    sum of the step)."""
+    from paper_2508_13304_amd import proposal as pr
+    x = torch.rand((8, 64, 64, 2), device=DEV, generator=torch.Generator(device=DEV).manual_seed(36))
+    x = x.to(torch.bfloat16)
+    y = torch.randn((8, 6), device=DEV, generator=torch.Generator(device=DEV).manual_seed(37))
+    nets = [pr.ProposalNet(size=64, channels=(8, 16, 32), seed=4) for _ in range(2)]
+    for net in nets:
+        out, cache = net.forward(x, keep=True)
+        grads, head = net.backward(cache, 2.0 * (out - y) / out.numel())
+        net.adam_step(grads, head, lr=1e-3)
+    assert torch.equal(nets[0].P, nets[1].P)
