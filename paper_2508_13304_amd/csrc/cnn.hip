@@ -120,7 +120,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int k0 = kbeg; k0 < kend; k0 += kGK) {
-        // A stored [M][K] (k-contiguous) unless TA; B stored [N][K] if TB
+        // A stored [M][K] (k-contiguous) unless TA; B stored [N][K] if TB.
+        // (Prefetching the next step's tiles into registers during the
+        // products measured slower: a step's products are too short to hide
+        // the loads.)
         stage_tile<!TA, VEC>(A, lda, M, m0, k0, kend, As, tid);
         stage_tile<TB, VEC>(B, ldb, N, n0, k0, kend, Bs, tid);
         __syncthreads();
@@ -349,9 +352,18 @@ __global__ __launch_bounds__(256) void col2im_kernel(int N, int H, int W, int C,
         }
         if constexpr (ACT) {
             const size_t o = (size_t)p * C + g * G;
+            union { uint2 u; __bf16 h[4]; } yv, dv;
+            if constexpr (G == 4) {
+                yv.u = *reinterpret_cast<const uint2*>(y + o);
 #pragma unroll
-            for (int c = 0; c < G; ++c)
-                dz[o + c] = to_bf16(relu ? ((float)y[o + c] > 0.f ? acc[c] : 0.f) : acc[c]);
+                for (int c = 0; c < 4; ++c)
+                    dv.h[c] = to_bf16(relu ? ((float)yv.h[c] > 0.f ? acc[c] : 0.f) : acc[c]);
+                *reinterpret_cast<uint2*>(dz + o) = dv.u;
+            } else {
+#pragma unroll
+                for (int c = 0; c < G; ++c)
+                    dz[o + c] = to_bf16(relu ? ((float)y[o + c] > 0.f ? acc[c] : 0.f) : acc[c]);
+            }
         } else {
             float* dst = dx + (size_t)p * C + g * G;
             if constexpr (G == 4) {
@@ -481,7 +493,8 @@ void launch_col2im(int N, int H, int W, int C, int s, int Ho, int Wo, const floa
                    const void* y, bool relu, void* dz, hipStream_t st)
 {
     const bool act = y != nullptr;
-    const bool vec = C % 4 == 0 && (uintptr_t)dcol % 16 == 0 && (act || (uintptr_t)dx % 16 == 0);
+    const bool vec = C % 4 == 0 && (uintptr_t)dcol % 16 == 0 &&
+                     (act ? ((uintptr_t)y % 8 == 0 && (uintptr_t)dz % 8 == 0) : (uintptr_t)dx % 16 == 0);
     const size_t total = (size_t)N * H * W * (vec ? C / 4 : C);
     const __bf16* yb = (const __bf16*)y;
     __bf16* dzb = (__bf16*)dz;
