@@ -22,7 +22,11 @@ pose-gradient launch for the whole batch.  Two optimisers:
 * ``register_lm`` -- Levenberg-Marquardt for the SSD: the single-pass kernel
   also returns the Gauss-Newton matrix 2 sum J J^T built from the per-ray
   pose Jacobians (the gradient's sums before weighting), so each iteration
-  is one launch and converges quadratically near the optimum.
+  is one launch and converges quadratically near the optimum.  Optionally
+  coarse to fine: the same iterations first on a resolution pyramid
+  (`coarsen`: volume averaged over 2x2x2 voxels, targets binned 2x2, an
+  eighth of the samples per level), the full-resolution problem only for
+  the last few steps.
 
 Losses: SSD, or NCC (the paper's registration loss), per view.
 """
@@ -31,6 +35,7 @@ from __future__ import annotations
 import dataclasses
 import math
 import time
+import types
 
 import torch
 
@@ -64,6 +69,7 @@ class RegistrationResult:
     launches: int                # forward + gradient launch pairs
     ncc: torch.Tensor | None = None     # [B] NCC at the last evaluation (stop="paper")
     failed: torch.Tensor | None = None  # [B] NCC < 0.99 at the end (stop="paper")
+    level_launches: list | None = None  # launches per pyramid level, finest first
 
 
 def pose_errors(est: torch.Tensor, truth: torch.Tensor):
@@ -270,8 +276,35 @@ def register_bfgs(geom, vol, angles, targets, init_poses, loss="ssd", iters=150,
                               seconds=time.perf_counter() - t0, launches=launches)
 
 
+def coarsen(geom, vol, targets):
+    """One level down a resolution pyramid: the volume averaged over 2x2x2
+    voxels, every target averaged over 2x2 pixels (detector binning: the mean
+    of four line integrals stands for the one through the binned pixel's
+    centre), and the geometry with doubled voxel and pixel sizes, halved
+    detector offsets (in pixels) and a doubled march step.  Voxel and pixel
+    centres of the coarse grids are the centroids of the fine cells they
+    replace, so both levels describe the same object and detector.  Every
+    grid dimension must be even.  Returns (geom, vol, targets)."""
+    from . import DPGeom
+    dims = (geom.nx, geom.ny, geom.nz, geom.nu, geom.nv)
+    if any(n % 2 or n < 2 for n in dims):
+        raise ValueError(f"coarsen needs even grid sizes, got {dims}")
+    fields = {f: getattr(geom, f) for f, _ in DPGeom._fields_}
+    fields.update(nx=geom.nx // 2, ny=geom.ny // 2, nz=geom.nz // 2, vx=2 * geom.vx,
+                  vy=2 * geom.vy, vz=2 * geom.vz, nu=geom.nu // 2, nv=geom.nv // 2,
+                  du=2 * geom.du, dv=2 * geom.dv, off_u=geom.off_u / 2, off_v=geom.off_v / 2,
+                  step=2 * geom.step)
+    gc = (dataclasses.replace(geom, **fields) if dataclasses.is_dataclass(geom)
+          else types.SimpleNamespace(**fields))
+    F = torch.nn.functional
+    vc = F.avg_pool3d(vol[None, None], 2)[0, 0].contiguous()
+    yc = F.avg_pool2d(targets[:, None], 2)[:, 0].contiguous()
+    return gc, vc, yc
+
+
 def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=4.0, down=3.0,
-                tol=1e-4, lam_max=1e10, rule="step") -> RegistrationResult:
+                tol=1e-4, lam_max=1e10, rule="step", levels=0,
+                coarse_tol=None) -> RegistrationResult:
     """Batched Levenberg-Marquardt registration on the SSD.
 
     Each launch evaluates, at one point per registration, the DRR, the SSD
@@ -286,10 +319,34 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
     rule="newton", once the undamped Gauss-Newton step -H^-1 g at the
     accepted point is below tol in every scaled parameter (near the optimum
     that step is the remaining distance, so the evaluation that would only
-    confirm convergence is skipped).
+    confirm convergence is skipped; the rule is also applied at the starting
+    point).
+
+    levels > 0 runs coarse to fine: the same method first on the problem
+    `coarsen`ed `levels` times (stopping with coarse_tol, default tol), each
+    finer level starting from the coarser level's poses.  The coarse optimum
+    is biased by the lost detail, so only the full-resolution stage decides
+    the result; it starts close to it and needs a launch or two.  The
+    result's time and launches cover every level (level_launches splits
+    them, finest first).
     """
     if rule not in ("step", "newton"):
         raise ValueError(f"unknown stopping rule {rule}")
+    if levels > 0:
+        t0 = time.perf_counter()
+        gc, vc, yc = coarsen(geom, vol, targets)
+        ct = tol if coarse_tol is None else coarse_tol
+        c = register_lm(gc, vc, angles, yc, init_poses, iters, lam0, up, down, ct, lam_max, rule,
+                        levels - 1, coarse_tol)
+        r = register_lm(geom, vol, angles, targets, c.poses, iters, lam0, up, down, tol, lam_max,
+                        rule)
+        if init_poses.device.type == "cuda":
+            torch.cuda.synchronize(init_poses.device)
+        return RegistrationResult(poses=r.poses, iterations=r.iterations + c.iterations,
+                                  converged=r.converged, final_loss=r.final_loss,
+                                  seconds=time.perf_counter() - t0,
+                                  launches=r.launches + c.launches,
+                                  level_launches=[r.launches] + c.level_launches)
     from . import project_fwd_ssd_gauss_newton
     B = init_poses.shape[0]
     dev = init_poses.device
@@ -303,6 +360,12 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
                                                   targets[idx].contiguous())
         return L, g * D, H * DD
 
+    eye = torch.eye(6, dtype=f64, device=dev)
+
+    def newton_small(Hn, gn):
+        reg = 1e-12 * (torch.diagonal(Hn, dim1=1, dim2=2)[:, :, None] + 1.0) * eye
+        return torch.linalg.solve(Hn + reg, -gn).abs().max(dim=1).values < tol
+
     t0 = time.perf_counter()
     z = (init_poses.detach().to(f64) / D).clone()
     allidx = torch.arange(B, device=dev)
@@ -311,8 +374,9 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
     lam = torch.full((B,), lam0, dtype=f64, device=dev)
     its = torch.zeros(B, dtype=torch.int64, device=dev)
     done = torch.zeros(B, dtype=torch.bool, device=dev)
-    eye = torch.eye(6, dtype=f64, device=dev)
-    active = allidx.clone()
+    if rule == "newton":
+        done = newton_small(H, g)
+    active = allidx[~done]
     for _ in range(iters):
         if active.numel() == 0:
             break
@@ -334,17 +398,15 @@ def register_lm(geom, vol, angles, targets, init_poses, iters=60, lam0=1e-3, up=
             if rule == "step":
                 small = acc & (d.abs().max(dim=1).values < tol)
             else:
-                Hn = H[active]
-                reg = 1e-12 * (torch.diagonal(Hn, dim1=1, dim2=2)[:, :, None] + 1.0) * eye
-                dn = torch.linalg.solve(Hn + reg, -g[active])
-                small = dn.abs().max(dim=1).values < tol
+                small = newton_small(H[active], g[active])
             stop = small | (lam[active] > lam_max)
             done[active] = stop
             active = active[~stop]
     if dev.type == "cuda":
         torch.cuda.synchronize(dev)
     return RegistrationResult(poses=z * D, iterations=its, converged=done, final_loss=f,
-                              seconds=time.perf_counter() - t0, launches=launches)
+                              seconds=time.perf_counter() - t0, launches=launches,
+                              level_launches=[launches])
 
 
 class BatchLM:

@@ -153,6 +153,27 @@ def test_levenberg_marquardt_newton_stopping_rule(dp):
         reg.register_lm(g, vol, angles, targets, torch.zeros_like(truth), rule="never")
 
 
+def test_coarse_to_fine_levenberg_marquardt(dp):
+    """One and two pyramid levels (48^3 / 96^2 and 24^3 / 48^2 below the
+    96^3 / 192^2 problem), coarse levels stopping at 0.1 mm / 0.1 deg: every
+    registration still reaches 0.1 mm / 0.1 deg at full resolution, with
+    fewer full-resolution launches than starting there."""
+    from paper_2508_13304_amd import registration as reg
+    g, vol, truth, angles, targets = _registration_case(dp)
+    flat = reg.register_lm(g, vol, angles, targets, torch.zeros_like(truth), tol=1e-2,
+                           rule="newton")
+    for levels in (1, 2):
+        res = reg.register_lm(g, vol, angles, targets, torch.zeros_like(truth), tol=1e-2,
+                              rule="newton", levels=levels, coarse_tol=0.1)
+        _report(reg, res, truth)
+        print("levels", levels, "launches per level", res.level_launches, "flat", flat.launches,
+              flush=True)
+        assert len(res.level_launches) == levels + 1
+        assert sum(res.level_launches) == res.launches
+        assert bool(reg.success(res.poses, truth).all()) and bool(res.converged.all())
+        assert res.level_launches[0] < flat.launches
+
+
 def test_batched_adam_registration_reduces_error(dp):
     """The Adam driver (fixed step sizes) recovers the rotations and shrinks
     the translation error by an order of magnitude on the same case."""
