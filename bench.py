@@ -760,8 +760,8 @@ def run_paper_ladder(args, dp, torch):
     """Every projector type at the paper's cost-table shapes: (128n)^3
     volumes at 256/(128n) mm, (192n)^2 detectors (572 at n = 3) at
     384/(192n) mm.  Forward: one view, time of 100 iterations of projection +
-    pose gradient (RD: the single-pass SSD kernel; SF, DD: projection then
-    gradient).  Back-projection: 256 views over 360 deg, one back-projection
+    pose gradient (RD: the single-pass SSD kernel, with the default and with
+    the autotuned variant; SF, DD: projection then gradient).  Back-projection: 256 views over 360 deg, one back-projection
     + pose gradient.  Peak device memory per case and projector type (GB,
     torch's allocator peak over the projector's own step: inputs, outputs and
     the library workspace)."""
@@ -804,6 +804,12 @@ def run_paper_ladder(args, dp, torch):
         reset()
         res["rd"] = timed(lambda: dp.project_fwd_ssd_grad_pose(g, a1, p1, vol, y1), 10) * 100
         peak["rd"] = peak_gb()
+        # the same step with the variant (tile shape x chunk class) the
+        # autotuner picks for this shape (it keeps it for later calls)
+        res["rd_variant"], _ = dp.autotune(dp.OP_FWD_SSD, g, a1, p1, vol, torch.empty_like(y1),
+                                           grad_proj=y1, reps=3)
+        res["rd_autotuned"] = timed(lambda: dp.project_fwd_ssd_grad_pose(g, a1, p1, vol, y1),
+                                    10) * 100
         for kind in ("sf", "dd"):
             def step(kind=kind):
                 l = dp.fp_project(g, a1, p1, vol, kind)

@@ -241,8 +241,12 @@ int dp_lm_update(int32_t n, double* trial, const double* loss, const double* gra
                  double* state_h, double* lam, int32_t* done, double tol, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Kernel variants of the ray-driven kernels (chunk length and LDS budget:
- * 0, 1 = default, 2).  dp_autotune times every variant of `op` (DP_OP_FWD,
+ * Kernel variants of the ray-driven kernels: DP_RD_VARIANTS = 9, variant =
+ * 3 * tile shape + chunk class.  Tile shapes (detector pixels per block,
+ * u x v): 0 = 16 x 16, 1 = 32 x 8, 2 = 8 x 32; chunk classes (chunk length
+ * before adaptation and LDS budget): 0, 1, 2.  Variant 1 (16 x 16, class 1)
+ * is the default.  Every variant computes the same result up to FP32
+ * summation order.  dp_autotune times every variant of `op` (DP_OP_FWD,
  * DP_OP_FWD_GRAD or DP_OP_FWD_SSD) on the given inputs (reps timed calls
  * each, after one warm-up; `out` is proj for FWD and FWD_SSD, grad_pose for
  * FWD_GRAD; grad_proj is dL/dl for FWD_GRAD and the target image for
@@ -253,10 +257,11 @@ int dp_lm_update(int32_t n, double* trial, const double* loss, const double* gra
  * dp_get_variant returns the variant a call of `op` on this shape would use
  * (-1 for another op or a NULL geometry).
  * ------------------------------------------------------------------------- */
+#define DP_RD_VARIANTS 9
 int dp_autotune(int32_t op, const dp_geom* g, int32_t n_views, const double* angles,
                 const double* poses, const float* vol, const float* grad_proj, void* out,
                 void* ws, size_t ws_bytes, void* stream, int32_t reps, int32_t* best,
-                float* ms_per_variant /* [3] or NULL */);
+                float* ms_per_variant /* [DP_RD_VARIANTS] or NULL */);
 int dp_set_variant(int32_t op, int32_t variant);
 int32_t dp_get_variant(const dp_geom* g, int32_t n_views, int32_t op);
 

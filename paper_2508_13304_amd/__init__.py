@@ -41,7 +41,7 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update", "dp_read_probe",
            "dp_bp_grad_flags_offset", "dp_lds_probe", "dp_project_fwd_ssd_grad_pose_noalloc")
 MAX_BATCH = 16
-N_VARIANTS = 3
+N_VARIANTS = 9  # ray-driven kernel variants: 3 * tile shape (16x16, 32x8, 8x32) + chunk class
 
 
 class DPGeom(C.Structure):

@@ -80,7 +80,8 @@ Layout layout(const dp_geom& g, int V, int op)
     case DP_OP_FWD:
         break;
     case DP_OP_FWD_GRAD:
-        L.n_part = (size_t)rd_tiles(s);
+        // per-block partials, sized for the tile shape with the most tiles
+        L.n_part = (size_t)rd_tiles_max(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannels * sizeof(float));
         if (sparse_rays(s)) {  // tiles that cannot stage a box gather from this copy
@@ -95,7 +96,7 @@ Layout layout(const dp_geom& g, int V, int op)
             L.inter = off;
             off = align_up(off + padded_volume_elems(g) * sizeof(float4));
         }
-        L.n_part = (size_t)rd_tiles(s);
+        L.n_part = (size_t)rd_tiles_max(s);
         L.partials = off;
         off = align_up(off + (size_t)V * L.n_part * kRdChannelsGN * sizeof(float));
         L.spare = off;
@@ -321,9 +322,9 @@ int dp_project_fwd_grad_pose(const dp_geom* g, int32_t V, const double* angles,
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
     if (inter) launch_vol_inter(s, vol, inter, st);
-    launch_rd_grad(s, V, views, vol, inter, grad_proj, part, variant_for(DP_OP_FWD_GRAD, *g, V),
-                   st);
-    launch_finalize_fwd(s, V, views, part, (int)L.n_part, grad_pose, st);
+    const int var = variant_for(DP_OP_FWD_GRAD, *g, V);
+    launch_rd_grad(s, V, views, vol, inter, grad_proj, part, var, st);
+    launch_finalize_fwd(s, V, views, part, rd_tiles(s, rd_variant_shape(var)), grad_pose, st);
     return check_launch("dp_project_fwd_grad_pose");
 }
 
@@ -347,9 +348,10 @@ static int fwd_ssd(const dp_geom* g, int32_t V, const double* angles, const doub
     (void)hipGetLastError();
     launch_view_setup(s, V, angles, poses, views, st);
     if (inter) launch_vol_inter(s, vol, inter, st);
-    launch_rd_fused(s, V, views, vol, inter, target, proj, part, hess != nullptr,
-                    variant_for(DP_OP_FWD_SSD, *g, V), st);
-    launch_finalize_fwd_ssd(s, V, views, part, (int)L.n_part, grad_pose, loss, hess, st);
+    const int var = variant_for(DP_OP_FWD_SSD, *g, V);
+    launch_rd_fused(s, V, views, vol, inter, target, proj, part, hess != nullptr, var, st);
+    launch_finalize_fwd_ssd(s, V, views, part, rd_tiles(s, rd_variant_shape(var)), grad_pose,
+                            loss, hess, st);
     return check_launch(name);
 }
 
@@ -718,7 +720,9 @@ static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t w
     bt.n = n;
     size_t off = 0;
     long long blocks = 0;
-    int big = order[0];
+    const int big = order[0];
+    const int var = variant >= 0 ? variant : variant_for(op, pr[big].geom, pr[big].n_views);
+    const int shape = rd_variant_shape(var);
     std::vector<size_t> offs(n);
     for (int i = 0; i < n; ++i) {
         offs[i] = off;
@@ -743,12 +747,11 @@ static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t w
         it.gin = op == DP_OP_FWD ? nullptr : q.grad_proj;
         it.out = op == DP_OP_FWD ? q.proj : (float*)(base + L.partials);
         it.proj = op == DP_OP_FWD_SSD ? q.proj : nullptr;
-        it.tiles = rd_tiles(s);
+        it.tiles = rd_tiles(s, shape);
         it.first = (int)blocks;
         blocks += (long long)it.tiles * q.n_views;
     }
     if (blocks >= (1LL << 31)) return fail(DP_ERR_UNSUPPORTED, "batch too large for one launch");
-    const int var = variant >= 0 ? variant : variant_for(op, pr[big].geom, pr[big].n_views);
     if (op == DP_OP_FWD) {
         launch_rd_fwd_batch(bt, (int)blocks, var, st);
     } else {
@@ -763,12 +766,13 @@ static int run_batch(const dp_problem* pr, int32_t n, int op, void* ws, size_t w
             char* base = (char*)ws + offs[i];
             const ViewGeo* views = (ViewGeo*)(base + L.views);
             const float* part = (float*)(base + L.partials);
+            const GeoScalars s = make_scalars(q.geom);
+            const int tiles = rd_tiles(s, shape);
             if (op == DP_OP_FWD_GRAD)
-                launch_finalize_fwd(make_scalars(q.geom), q.n_views, views, part, (int)L.n_part,
-                                    q.grad_pose, st);
+                launch_finalize_fwd(s, q.n_views, views, part, tiles, q.grad_pose, st);
             else
-                launch_finalize_fwd_ssd(make_scalars(q.geom), q.n_views, views, part,
-                                        (int)L.n_part, q.grad_pose, q.loss, q.hess, st);
+                launch_finalize_fwd_ssd(s, q.n_views, views, part, tiles, q.grad_pose, q.loss,
+                                        q.hess, st);
         }
     }
     return check_launch(op == DP_OP_FWD        ? "dp_project_fwd_batch"

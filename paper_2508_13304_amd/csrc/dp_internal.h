@@ -14,10 +14,17 @@ namespace dp {
 constexpr int kPadV = 2;
 constexpr int kPadD = 2;
 
-// Ray-driven launch shape: one block = 16x16 detector pixels = 4 wavefronts,
-// each wavefront an 8x8 pixel tile (compact footprint in the volume).
-constexpr int kRdTile = 16;
+// Ray-driven launch shape: one block = 256 detector pixels = 4 wavefronts,
+// each wavefront an 8x8 pixel tile (compact footprint in the volume).  The
+// block's tile is 16x16 (shape 0), 32x8 (shape 1) or 8x32 (shape 2) pixels
+// (u x v), its wavefront sub-tiles laid out along u first.
 constexpr int kRdThreads = 256;
+constexpr int kRdShapes = 3;
+__host__ __device__ constexpr int rd_tile_w(int shape)
+{
+    return shape == 1 ? 32 : shape == 2 ? 8 : 16;
+}
+__host__ __device__ constexpr int rd_tile_h(int shape) { return kRdThreads / rd_tile_w(shape); }
 constexpr int kRdChannels = 9;   // B (3) and T (6) accumulators of the pose gradient
 
 // Voxel-driven launch shape: 64 (x) x 4 (y) threads, each thread owns a
@@ -116,7 +123,12 @@ bool sparse_rays(const GeoScalars& s);
 
 // Uneven batches of ray-driven problems in one launch (descriptors by value).
 constexpr int kRdMaxBatch = 16;
-constexpr int kRdVariants = 3;
+// Compiled variants: tile shape (above) x chunk class (chunk length before
+// adaptation and LDS budget, three per kernel); variant = shape * 3 + class.
+constexpr int kRdChunkClasses = 3;
+constexpr int kRdVariants = kRdShapes * kRdChunkClasses;
+static_assert(kRdVariants == DP_RD_VARIANTS, "variant count of the public header");
+inline int rd_variant_shape(int variant) { return variant / kRdChunkClasses; }
 // fused SSD kernel with the Gauss-Newton matrix: 9 gradient sums, the SSD,
 // and the 21 upper-triangle entries of 2 J J^T
 constexpr int kRdChannelsGN = kRdChannels + 1 + 21;
@@ -214,9 +226,18 @@ size_t gradient_entropy_ws_doubles(int nx, int ny, int nz);
 void launch_gradient_entropy(int nx, int ny, int nz, float eps, const float* vol, float* grad,
                              double* loss, double* ws, hipStream_t st);
 
-inline int rd_tiles(const GeoScalars& s)
+inline int rd_tiles(const GeoScalars& s, int shape)
 {
-    return ((s.nu + kRdTile - 1) / kRdTile) * ((s.nv + kRdTile - 1) / kRdTile);
+    const int tw = rd_tile_w(shape), th = rd_tile_h(shape);
+    return ((s.nu + tw - 1) / tw) * ((s.nv + th - 1) / th);
+}
+
+// Tiles of the shape with the most (per-block partial buffers are sized for it).
+inline int rd_tiles_max(const GeoScalars& s)
+{
+    int m = 0;
+    for (int sh = 0; sh < kRdShapes; ++sh) m = m > rd_tiles(s, sh) ? m : rd_tiles(s, sh);
+    return m;
 }
 
 

@@ -35,6 +35,8 @@
 // its first sample of the chunk, X(kb) = X0 + (f + (kb - k0) step) D; the
 // chunk's samples are then X(kb) + j (step D) for j < M.  No absolute
 // position of ~1000 mm is ever formed in FP32.
+#include <type_traits>
+
 #include "dp_internal.h"
 
 namespace dp {
@@ -42,10 +44,9 @@ namespace dp {
 // LDS budgets: forward = one float per voxel; gradient = (Gx, Gy, Gz)
 // interleaved per voxel, so the x-neighbour pairs of all three channels are
 // reachable from one address with the 8-bit offsets of ds_read2.
-// Compiled variants (chunk length before adaptation, LDS voxels); the
-// autotuner picks one per shape class, variant 1 is the default.
-//   forward : (16, 4096) (32, 8192) (64, 12288)
-//   gradient: ( 8, 2048) (16, 3072) (32, 5120)
+// Compiled variants: tile shape x chunk class (chunk length before
+// adaptation, LDS voxels; listed with the launchers); the autotuner picks
+// one per shape class, variant 1 (16x16 tiles, middle class) is the default.
 constexpr int kMaxChunks = kRdThreads;  // one chunk box planned per thread
 // 16-byte row loads for interior boxes of volumes with aligned rows (a
 // build-time switch for measurements; 1 in the library)
@@ -114,16 +115,19 @@ __device__ inline RayState ray_setup(const GeoScalars& s, const ViewGeo& g, int 
     return r;
 }
 
-// Lane -> detector pixel: 4 wavefronts per block, each an 8x8 pixel tile.
+// Lane -> detector pixel: 4 wavefronts per block, each an 8x8 pixel tile,
+// in a block tile TW pixels wide (u) and 256 / TW high (v).
+template <int TW>
 __device__ inline void rd_pixel(const GeoScalars& s, int tile, int& a, int& b, int& a0, int& b0)
 {
-    const int tiles_u = (s.nu + kRdTile - 1) / kRdTile;
+    constexpr int TH = kRdThreads / TW, WU = TW / 8;
+    const int tiles_u = (s.nu + TW - 1) / TW;
     const int tu = tile % tiles_u, tv = tile / tiles_u;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    a0 = tu * kRdTile;
-    b0 = tv * kRdTile;
-    a = a0 + (wave & 1) * 8 + (lane & 7);
-    b = b0 + (wave >> 1) * 8 + (lane >> 3);
+    a0 = tu * TW;
+    b0 = tv * TH;
+    a = a0 + (wave % WU) * 8 + (lane & 7);
+    b = b0 + (wave / WU) * 8 + (lane >> 3);
 }
 
 __device__ inline float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
@@ -153,6 +157,7 @@ struct TileShared {
 // the margin that covers the spherical cap between them (voxel units).
 // `active` rays define the sample range; every in-detector corner lane
 // publishes its ray geometry (whether or not it carries samples).
+template <int TW>
 __device__ inline void tile_setup(const GeoScalars& s, const RayState& r, bool inside, bool active,
                                   int a, int b, int a0, int b0, TileShared& sh, int& Kmin,
                                   int& Kmax, float& margin)
@@ -169,7 +174,7 @@ __device__ inline void tile_setup(const GeoScalars& s, const RayState& r, bool i
         sh.khi[wave] = hi;
     }
     // corner rays: first / last valid pixel of the tile in each direction
-    const int a1 = min(a0 + kRdTile - 1, s.nu - 1), b1 = min(b0 + kRdTile - 1, s.nv - 1);
+    const int a1 = min(a0 + TW - 1, s.nu - 1), b1 = min(b0 + kRdThreads / TW - 1, s.nv - 1);
     // a degenerate tile (one column or row) has coincident corners: every
     // owner writes the same values
     if (inside && (a == a0 || a == a1) && (b == b0 || b == b1)) {
@@ -682,19 +687,19 @@ __device__ inline ChunkRay chunk_ray(const RayState& r, int kb, int ke, const Bo
     return c;
 }
 
-template <int MCH, int CAP>
+template <int TW, int MCH, int CAP>
 __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
                                    const float* __restrict__ mu, float* __restrict__ proj,
                                    int v, int tile, float* lds, TileShared& sh)
 {
     int a, b, a0, b0;
-    rd_pixel(s, tile, a, b, a0, b0);
+    rd_pixel<TW>(s, tile, a, b, a0, b0);
     const bool active = a < s.nu && b < s.nv;
     const ViewGeo& g = views[v];
     const RayState r = ray_setup(s, g, min(a, s.nu - 1), min(b, s.nv - 1));
     int Kmin, Kmax;
     float margin;
-    tile_setup(s, r, active, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
+    tile_setup<TW>(s, r, active, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
     const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
     const float step = (float)s.step;
     const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
@@ -871,7 +876,7 @@ struct GradAcc {
     }
 };
 
-template <int MCH, int CAP, bool FUSED, bool HESS = false>
+template <int TW, int MCH, int CAP, bool FUSED, bool HESS = false>
 __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restrict__ views,
                                     const float* __restrict__ mu,
                                     const float4* __restrict__ inter,
@@ -890,7 +895,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     // geometries, where such tiles are common), else from mu directly.
     constexpr int C = FUSED ? 4 : 3;
     int a, b, a0, b0;
-    rd_pixel(s, tile, a, b, a0, b0);
+    rd_pixel<TW>(s, tile, a, b, a0, b0);
     const bool inside = a < s.nu && b < s.nv;
     const size_t pix = ((size_t)v * s.nv + min(b, s.nv - 1)) * s.nu + min(a, s.nu - 1);
     const float gpix = inside ? gin[pix] : 0.0f;
@@ -902,7 +907,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     float lsum = 0.0f;
     int Kmin, Kmax;
     float margin;
-    tile_setup(s, r, inside, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
+    tile_setup<TW>(s, r, inside, active, a, b, a0, b0, sh, Kmin, Kmax, margin);
     const int NX = s.nx + 2 * kPadV, NY = s.ny + 2 * kPadV, NZ = s.nz + 2 * kPadV;
     const float step = (float)s.step;
     // Padded index of the grid centre: P_a(j) = I_a(j) - centre_a.
@@ -1038,7 +1043,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     block_reduce_store<NC>(acc, partials + ((size_t)v * tiles + tile) * NC);
 }
 
-template <int MCH, int CAP>
+template <int TW, int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
                                                             const ViewGeo* __restrict__ views,
                                                             const float* __restrict__ mu,
@@ -1046,10 +1051,10 @@ __global__ __launch_bounds__(kRdThreads) void rd_fwd_kernel(GeoScalars s,
 {
     __shared__ float lds[CAP];
     __shared__ TileShared sh;
-    rd_fwd_tile<MCH, CAP>(s, views, mu, proj, blockIdx.y, blockIdx.x, lds, sh);
+    rd_fwd_tile<TW, MCH, CAP>(s, views, mu, proj, blockIdx.y, blockIdx.x, lds, sh);
 }
 
-template <int MCH, int CAP>
+template <int TW, int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                                                              const ViewGeo* __restrict__ views,
                                                              const float* __restrict__ mu,
@@ -1059,13 +1064,13 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
 {
     __shared__ float lds[3 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, false>(s, views, mu, inter, grad_proj, nullptr, partials, blockIdx.y,
-                                  blockIdx.x, gridDim.x, lds, sh);
+    rd_grad_tile<TW, MCH, CAP, false>(s, views, mu, inter, grad_proj, nullptr, partials,
+                                      blockIdx.y, blockIdx.x, gridDim.x, lds, sh);
 }
 
 // Forward projection, SSD loss and its pose gradient in one march (HESS:
 // also the per-view Gauss-Newton matrix of the SSD).
-template <int MCH, int CAP, bool HESS>
+template <int TW, int MCH, int CAP, bool HESS>
 __global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
                                                               const ViewGeo* __restrict__ views,
                                                               const float* __restrict__ mu,
@@ -1076,8 +1081,8 @@ __global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
-    rd_grad_tile<MCH, CAP, true, HESS>(s, views, mu, inter, target, proj, partials, blockIdx.y,
-                                       blockIdx.x, gridDim.x, lds, sh);
+    rd_grad_tile<TW, MCH, CAP, true, HESS>(s, views, mu, inter, target, proj, partials,
+                                           blockIdx.y, blockIdx.x, gridDim.x, lds, sh);
 }
 
 // Uneven batch: one launch covers every (problem, view, tile) of up to
@@ -1092,7 +1097,7 @@ __device__ inline int batch_problem(const RdBatch& bt)
     return p;
 }
 
-template <int MCH, int CAP>
+template <int TW, int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_fwd_batch_kernel(RdBatch bt)
 {
     __shared__ float lds[CAP];
@@ -1100,11 +1105,11 @@ __global__ __launch_bounds__(kRdThreads) void rd_fwd_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_fwd_tile<MCH, CAP>(it.s, it.views, it.vol, it.out, local / it.tiles, local % it.tiles, lds,
-                          sh);
+    rd_fwd_tile<TW, MCH, CAP>(it.s, it.views, it.vol, it.out, local / it.tiles,
+                              local % it.tiles, lds, sh);
 }
 
-template <int MCH, int CAP>
+template <int TW, int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
 {
     __shared__ float lds[3 * CAP];
@@ -1112,12 +1117,12 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP, false>(it.s, it.views, it.vol, it.inter, it.gin, nullptr, it.out,
-                                  local / it.tiles, local % it.tiles, it.tiles, lds, sh);
+    rd_grad_tile<TW, MCH, CAP, false>(it.s, it.views, it.vol, it.inter, it.gin, nullptr, it.out,
+                                      local / it.tiles, local % it.tiles, it.tiles, lds, sh);
 }
 
 // Single-pass SSD with the Gauss-Newton matrix over an uneven batch.
-template <int MCH, int CAP>
+template <int TW, int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_fused_batch_kernel(RdBatch bt)
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
@@ -1125,20 +1130,56 @@ __global__ __launch_bounds__(kRdThreads) void rd_fused_batch_kernel(RdBatch bt)
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
     const int local = (int)blockIdx.x - it.first;
-    rd_grad_tile<MCH, CAP, true, true>(it.s, it.views, it.vol, it.inter, it.gin, it.proj, it.out,
-                                       local / it.tiles, local % it.tiles, it.tiles, lds, sh);
+    rd_grad_tile<TW, MCH, CAP, true, true>(it.s, it.views, it.vol, it.inter, it.gin, it.proj,
+                                           it.out, local / it.tiles, local % it.tiles, it.tiles,
+                                           lds, sh);
+}
+
+// Chunk classes (chunk length before adaptation, LDS voxels) per kernel kind:
+//   forward : (16, 4096) (32, 8192) (64, 12288)
+//   gradient: ( 8, 2048) (16, 3072) (32, 5120)
+//   fused   : ( 8, 2048) (16, 3072) (32, 4096)  (four channels per voxel)
+struct FwdClasses {
+    static constexpr int mch[3] = {16, 32, 64}, cap[3] = {4096, 8192, 12288};
+};
+struct GradClasses {
+    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 3072, 5120};
+};
+struct FusedClasses {
+    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 3072, 4096};
+};
+
+template <int N>
+using IntC = std::integral_constant<int, N>;
+
+// Calls f(IntC<tile width>, IntC<chunk class>) for a variant in
+// [0, kRdVariants) (anything else: the default, 16x16 tiles and class 1).
+template <class F>
+static void rd_dispatch(int variant, F&& f)
+{
+    switch (variant) {
+    case 0: f(IntC<16>(), IntC<0>()); break;
+    case 2: f(IntC<16>(), IntC<2>()); break;
+    case 3: f(IntC<32>(), IntC<0>()); break;
+    case 4: f(IntC<32>(), IntC<1>()); break;
+    case 5: f(IntC<32>(), IntC<2>()); break;
+    case 6: f(IntC<8>(), IntC<0>()); break;
+    case 7: f(IntC<8>(), IntC<1>()); break;
+    case 8: f(IntC<8>(), IntC<2>()); break;
+    default: f(IntC<16>(), IntC<1>()); break;
+    }
 }
 
 void launch_rd_fwd(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
                    float* proj, int variant, hipStream_t st)
 {
-    dim3 grid(rd_tiles(s), V);
+    const dim3 grid(rd_tiles(s, rd_variant_shape(variant)), V);
     prof_begin(DP_K_RD_FWD, st);
-    switch (variant) {
-    case 0: rd_fwd_kernel<16, 4096><<<grid, kRdThreads, 0, st>>>(s, views, mu, proj); break;
-    case 2: rd_fwd_kernel<64, 12288><<<grid, kRdThreads, 0, st>>>(s, views, mu, proj); break;
-    default: rd_fwd_kernel<32, 8192><<<grid, kRdThreads, 0, st>>>(s, views, mu, proj); break;
-    }
+    rd_dispatch(variant, [&](auto tw, auto cl) {
+        constexpr int c = decltype(cl)::value;
+        rd_fwd_kernel<decltype(tw)::value, FwdClasses::mch[c], FwdClasses::cap[c]>
+            <<<grid, kRdThreads, 0, st>>>(s, views, mu, proj);
+    });
     prof_end(DP_K_RD_FWD, st);
 }
 
@@ -1146,71 +1187,65 @@ void launch_rd_grad(const GeoScalars& s, int V, const ViewGeo* views, const floa
                     const float4* inter, const float* grad_proj, float* partials, int variant,
                     hipStream_t st)
 {
-    dim3 grid(rd_tiles(s), V);
+    const dim3 grid(rd_tiles(s, rd_variant_shape(variant)), V);
     prof_begin(DP_K_RD_GRAD, st);
-    switch (variant) {
-    case 0: rd_grad_kernel<8, 2048><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, grad_proj, partials); break;
-    case 2: rd_grad_kernel<32, 5120><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, grad_proj, partials); break;
-    default: rd_grad_kernel<16, 3072><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, grad_proj, partials); break;
-    }
+    rd_dispatch(variant, [&](auto tw, auto cl) {
+        constexpr int c = decltype(cl)::value;
+        rd_grad_kernel<decltype(tw)::value, GradClasses::mch[c], GradClasses::cap[c]>
+            <<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, grad_proj, partials);
+    });
     prof_end(DP_K_RD_GRAD, st);
-}
-
-template <bool HESS>
-static void launch_rd_fused_t(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
-                              const float4* inter, const float* target, float* proj,
-                              float* partials, int variant, hipStream_t st)
-{
-    dim3 grid(rd_tiles(s), V);
-    switch (variant) {
-    case 0: rd_fused_kernel<8, 2048, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, target, proj, partials); break;
-    case 2: rd_fused_kernel<32, 4096, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, target, proj, partials); break;
-    default: rd_fused_kernel<16, 3072, HESS><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter, target, proj, partials); break;
-    }
 }
 
 void launch_rd_fused(const GeoScalars& s, int V, const ViewGeo* views, const float* mu,
                      const float4* inter, const float* target, float* proj, float* partials,
                      bool hess, int variant, hipStream_t st)
 {
+    const dim3 grid(rd_tiles(s, rd_variant_shape(variant)), V);
     prof_begin(DP_K_RD_FUSED, st);
-    if (hess)
-        launch_rd_fused_t<true>(s, V, views, mu, inter, target, proj, partials, variant, st);
-    else
-        launch_rd_fused_t<false>(s, V, views, mu, inter, target, proj, partials, variant, st);
+    rd_dispatch(variant, [&](auto tw, auto cl) {
+        constexpr int t = decltype(tw)::value, c = decltype(cl)::value;
+        constexpr int m = FusedClasses::mch[c], cap = FusedClasses::cap[c];
+        if (hess)
+            rd_fused_kernel<t, m, cap, true><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter,
+                                                                         target, proj, partials);
+        else
+            rd_fused_kernel<t, m, cap, false><<<grid, kRdThreads, 0, st>>>(s, views, mu, inter,
+                                                                          target, proj, partials);
+    });
     prof_end(DP_K_RD_FUSED, st);
 }
 
 void launch_rd_fwd_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)
 {
     prof_begin(DP_K_RD_FWD, st);
-    switch (variant) {
-    case 0: rd_fwd_batch_kernel<16, 4096><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    case 2: rd_fwd_batch_kernel<64, 12288><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    default: rd_fwd_batch_kernel<32, 8192><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    }
+    rd_dispatch(variant, [&](auto tw, auto cl) {
+        constexpr int c = decltype(cl)::value;
+        rd_fwd_batch_kernel<decltype(tw)::value, FwdClasses::mch[c], FwdClasses::cap[c]>
+            <<<blocks, kRdThreads, 0, st>>>(bt);
+    });
     prof_end(DP_K_RD_FWD, st);
 }
 
 void launch_rd_fused_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)
 {
     prof_begin(DP_K_RD_FUSED, st);
-    switch (variant) {
-    case 0: rd_fused_batch_kernel<8, 2048><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    case 2: rd_fused_batch_kernel<32, 4096><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    default: rd_fused_batch_kernel<16, 3072><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    }
+    rd_dispatch(variant, [&](auto tw, auto cl) {
+        constexpr int c = decltype(cl)::value;
+        rd_fused_batch_kernel<decltype(tw)::value, FusedClasses::mch[c], FusedClasses::cap[c]>
+            <<<blocks, kRdThreads, 0, st>>>(bt);
+    });
     prof_end(DP_K_RD_FUSED, st);
 }
 
 void launch_rd_grad_batch(const RdBatch& bt, int blocks, int variant, hipStream_t st)
 {
     prof_begin(DP_K_RD_GRAD, st);
-    switch (variant) {
-    case 0: rd_grad_batch_kernel<8, 2048><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    case 2: rd_grad_batch_kernel<32, 5120><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    default: rd_grad_batch_kernel<16, 3072><<<blocks, kRdThreads, 0, st>>>(bt); break;
-    }
+    rd_dispatch(variant, [&](auto tw, auto cl) {
+        constexpr int c = decltype(cl)::value;
+        rd_grad_batch_kernel<decltype(tw)::value, GradClasses::mch[c], GradClasses::cap[c]>
+            <<<blocks, kRdThreads, 0, st>>>(bt);
+    });
     prof_end(DP_K_RD_GRAD, st);
 }
 

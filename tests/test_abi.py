@@ -148,7 +148,11 @@ def test_newer_entries_validate_before_launch(lib):
                                    None) == -1  # misaligned workspace
     # kernel variants: every ray-driven op, including the single-pass SSD
     for op in (m.OP_FWD, m.OP_FWD_GRAD, m.OP_FWD_SSD):
-        assert lib.dp_get_variant(C.byref(gs), 1, op) in (0, 1, 2)
+        assert lib.dp_get_variant(C.byref(gs), 1, op) in range(m.N_VARIANTS)
+        assert lib.dp_set_variant(op, m.N_VARIANTS) == -1
+        assert lib.dp_set_variant(op, m.N_VARIANTS - 1) == 0
+        assert lib.dp_get_variant(C.byref(gs), 1, op) == m.N_VARIANTS - 1
+        assert lib.dp_set_variant(op, -1) == 0
     assert lib.dp_get_variant(C.byref(gs), 1, m.OP_BP) == -1
     assert lib.dp_set_variant(m.OP_BP, 0) == -1
     # CNN helpers: 32-bit index spaces
@@ -174,7 +178,7 @@ def test_batch_ssd_and_lm_update_validate_before_launch(lib):
     assert need == m.workspace_bytes(g1, 3, m.OP_FWD_SSD) + m.workspace_bytes(g2, 5, m.OP_FWD_SSD)
     ws = C.c_void_p(1 << 24)
     assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 2, ws, need - 256, -1, None) == -2
-    assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 2, ws, need, 3, None) == -1
+    assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 2, ws, need, m.N_VARIANTS, None) == -1
     assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 17, ws, need, -1, None) == -4
     arr[1].hess = None
     assert lib.dp_project_fwd_ssd_gauss_newton_batch(arr, 2, ws, need, -1, None) == -1

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import synth
+from paper_2508_13304_amd import N_VARIANTS
 from synth import Geom
 
 pytestmark = pytest.mark.gpu
@@ -70,7 +71,7 @@ def test_batch_of_more_than_sixteen_problems(dp):
         assert torch.equal(d["proj"], ref)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
 def test_every_variant_meets_oracle_tolerance(dp, oracle, variant):
     rng = synth.rng_for(502)
     g = Geom(56, 48, 40, 1.2, 1.3, 1.4, 70, 50, 1.6, 1.8)

@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import synth
+from paper_2508_13304_amd import N_VARIANTS
 from synth import Geom
 
 pytestmark = pytest.mark.gpu
@@ -54,7 +55,7 @@ def _with_outputs(probs, poses):
     return out
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
 def test_ssd_batch_equals_single_launches(dp, oracle, variant):
     """Every problem of the batch gets bit for bit what the single-problem
     entry gives with the same kernel variant (same tiles, same block sums),

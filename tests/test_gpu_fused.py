@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import synth
+from paper_2508_13304_amd import N_VARIANTS
 from synth import Geom
 from test_gpu_parity import check_grads, check_values, f32, f64, say
 
@@ -44,7 +45,7 @@ def test_fused_config1(dp, oracle):
     _fused_case(dp, oracle, g, c["vol"], c["angles"], c["poses"], y, "config1")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
 def test_fused_ragged_multiview_every_variant(dp, oracle, variant):
     rng = synth.rng_for(210)
     g = Geom(37, 29, 23, 1.3, 1.1, 1.7, 45, 27, 1.9, 2.3, off_u=1.25, off_v=-0.75)
@@ -187,7 +188,7 @@ def test_fused_full_launch_the_bench_times(dp, oracle):
     check_grads("full launch fused gradient", gp.cpu().numpy(), g_ref)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
 def test_sparse_rays_unstaged_tiles(dp, oracle, variant):
     """Rays much sparser than voxels (1.33 mm pixels at the isocentre over
     0.5 mm voxels): a 16 x 16 tile's chunk box exceeds the LDS capacity even
@@ -236,7 +237,7 @@ def test_fused_full_size_oracle_targets_dense(dp, oracle):
     _fused_case(dp, oracle, g, vol, angles, poses, y, "full-size dense")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
 def test_oblique_tiles_gathering_from_the_volume(dp, oracle, variant):
     """Pixel footprint at the isocentre just below the sparse-ray threshold
     (0.42 mm over 0.5 mm voxels: no (mu, G) copy is made) with diagonal views
