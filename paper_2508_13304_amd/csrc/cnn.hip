@@ -32,40 +32,48 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 64;   // block tile (M and N)
 constexpr int kGK = 32;   // K step
-constexpr int kGPad = 8;  // LDS row padding (bf16 elements) against bank conflicts
+constexpr int kGPad = 8;  // k-major tile: row padding (bf16) against bank conflicts
+// row-major tile: pitch 80 bf16 = 40 dwords, so the four k rows one 16-lane
+// group of a transpose read touches start 8 banks apart
+constexpr int kTPad = 16;
+constexpr int kSK = kGK + kGPad;  // pitch of a k-major tile S[row][k]
+constexpr int kST = kGT + kTPad;  // pitch of a row-major tile T[k][row]
+constexpr int kTileElems = kGT * kSK > kGK * kST ? kGT * kSK : kGK * kST;
 
 __device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
 
-// Stage a 64 x 32 (rows x k) tile of one operand into LDS S[row][k].
-// KC: the operand is stored k-contiguous (element (r, k) at P[r * ld + k]),
-// else row-contiguous (at P[k * ld + r]).  VEC: ld is a multiple of 8 and P
-// 16-byte aligned, so each thread moves 8 contiguous elements with one
-// 16-byte load (ragged edges fall back to guarded element loads).
+// Stage a 64 x 32 (rows x k) tile of one operand into LDS.
+// KC: the operand is stored k-contiguous (element (r, k) at P[r * ld + k])
+// and lands in S[row][k] (pitch kSK); else it is row-contiguous (at
+// P[k * ld + r]) and keeps that layout, T[k][row] (pitch kST): the
+// transpose happens when the fragments are read.  VEC: ld is a multiple of 8
+// and P 16-byte aligned, so each thread moves 8 contiguous elements with one
+// 16-byte load and one 16-byte store (ragged edges fall back to guarded
+// element loads).
 template <bool KC, bool VEC>
 __device__ inline void stage_tile(const __bf16* __restrict__ P, int ld, int rows, int row0, int k0,
-                                  int kend, __bf16 (*S)[kGK + kGPad], int tid)
+                                  int kend, __bf16* S, int tid)
 {
     if (VEC) {
         if (KC) {
             const int r = tid >> 2, c = (tid & 3) * 8, row = row0 + r, k = k0 + c;
             if (row < rows && k + 8 <= kend) {
-                *(uint4*)&S[r][c] = *(const uint4*)(P + (size_t)row * ld + k);
+                *(uint4*)&S[r * kSK + c] = *(const uint4*)(P + (size_t)row * ld + k);
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    S[r][c + j] = (row < rows && k + j < kend) ? P[(size_t)row * ld + k + j] : to_bf16(0.f);
+                    S[r * kSK + c + j] =
+                        (row < rows && k + j < kend) ? P[(size_t)row * ld + k + j] : to_bf16(0.f);
             }
         } else {
             const int kk = tid >> 3, c = (tid & 7) * 8, k = k0 + kk, row = row0 + c;
             if (k < kend && row + 8 <= rows) {
-                union { uint4 u; __bf16 h[8]; } v;
-                v.u = *(const uint4*)(P + (size_t)k * ld + row);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) S[c + j][kk] = v.h[j];
+                *(uint4*)&S[kk * kST + c] = *(const uint4*)(P + (size_t)k * ld + row);
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    S[c + j][kk] = (k < kend && row + j < rows) ? P[(size_t)k * ld + row + j] : to_bf16(0.f);
+                    S[kk * kST + c + j] =
+                        (k < kend && row + j < rows) ? P[(size_t)k * ld + row + j] : to_bf16(0.f);
             }
         }
         return;
@@ -77,8 +85,36 @@ __device__ inline void stage_tile(const __bf16* __restrict__ P, int ld, int rows
         if (KC) { r = idx >> 5; c = idx & 31; }  // coalesced along k
         else    { r = idx & 63; c = idx >> 6; }  // coalesced along rows
         const int row = row0 + r, k = k0 + c;
-        S[r][c] = (row < rows && k < kend) ? (KC ? P[(size_t)row * ld + k] : P[(size_t)k * ld + row])
-                                           : to_bf16(0.f);
+        const __bf16 v = (row < rows && k < kend)
+                             ? (KC ? P[(size_t)row * ld + k] : P[(size_t)k * ld + row])
+                             : to_bf16(0.f);
+        S[KC ? r * kSK + c : c * kST + r] = v;
+    }
+}
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+// MFMA operand fragment of rows rb .. rb + 15: lane l gets row rb + (l % 16),
+// k = 8 (l / 16) .. + 7.  From a k-major tile that is one 16-byte read.
+// From a row-major tile it is two transpose reads (ds_read_b64_tr_b16):
+// within each 16-lane group, the lane i' = 4 j + q addresses the four rows
+// 4 q .. 4 q + 3 at one k (8 bytes) and lane i receives, as element j, the
+// element i % 4 of lane 4 j + i / 4's four; so lane i gets row i at the four
+// k the group's lanes addressed.
+template <bool KC>
+__device__ inline bf16x8 load_frag(const __bf16* S, int rb, int lane)
+{
+    if constexpr (KC) {
+        return *(const bf16x8*)&S[(rb + (lane & 15)) * kSK + (lane >> 4) * 8];
+    } else {
+        const int i = lane & 15, k = (lane >> 4) * 8 + (i >> 2);
+        typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+        const __bf16* p = S + k * kST + rb + 4 * (i & 3);
+        const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)p);
+        const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)(p + 4 * kST));
+        const i16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        return __builtin_bit_cast(bf16x8, v);
     }
 }
 
@@ -104,9 +140,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
                                                         const __bf16* __restrict__ B, int ldb,
                                                         GemmOut o)
 {
-    // As[m][k] and Bs[n][k]: both k-contiguous so a lane reads 8 k at once.
-    __shared__ __attribute__((aligned(16))) __bf16 As[kGT][kGK + kGPad];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[kGT][kGK + kGPad];
+    // A is k-major in LDS unless stored transposed (TA), B k-major if TB.
+    constexpr bool AK = !TA, BK = TB;
+    __shared__ __attribute__((aligned(16))) __bf16 As[kTileElems];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[kTileElems];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT;
     // split-K: block z covers k in [kbeg, kend) and writes its own partial tile
@@ -124,15 +161,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
         // (Prefetching the next step's tiles into registers during the
         // products measured slower: a step's products are too short to hide
         // the loads.)
-        stage_tile<!TA, VEC>(A, lda, M, m0, k0, kend, As, tid);
-        stage_tile<TB, VEC>(B, ldb, N, n0, k0, kend, Bs, tid);
+        stage_tile<AK, VEC>(A, lda, M, m0, k0, kend, As, tid);
+        stage_tile<BK, VEC>(B, ldb, N, n0, k0, kend, Bs, tid);
         __syncthreads();
-        const int kq = (lane >> 4) * 8;
         bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][kq];
+        for (int i = 0; i < 2; ++i) a[i] = load_frag<AK>(As, wm + i * 16, lane);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][kq];
+        for (int j = 0; j < 2; ++j) b[j] = load_frag<BK>(Bs, wn + j * 16, lane);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -178,6 +214,35 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int M, int N, int S,
         for (int z = 0; z < S; ++z) v += ws[(size_t)z * total + i];
         float* c = C + (i / N) * ldc + i % N;
         *c = accumulate ? *c + v : v;
+    }
+}
+
+// The same sum for many splits: a block covers 16 consecutive outputs with
+// 16 threads each; thread g sums its contiguous range of splits in order,
+// and the 16 range sums are added in range order (fixed order, so still
+// independent of block timing).
+constexpr int kRedOut = 16, kRedGroups = 16;
+__global__ __launch_bounds__(256) void splitk_reduce_grouped_kernel(int M, int N, int S,
+                                                                    const float* __restrict__ ws,
+                                                                    float* __restrict__ C, int ldc,
+                                                                    int accumulate)
+{
+    __shared__ float part[kRedGroups][kRedOut];
+    const size_t total = (size_t)M * N;
+    const int o = threadIdx.x % kRedOut, grp = threadIdx.x / kRedOut;
+    const size_t i = (size_t)blockIdx.x * kRedOut + o;
+    const int per = (S + kRedGroups - 1) / kRedGroups;
+    const int z0 = grp * per, z1 = min(S, z0 + per);
+    float v = 0.f;
+    if (i < total)
+        for (int z = z0; z < z1; ++z) v += ws[(size_t)z * total + i];
+    part[grp][o] = v;
+    __syncthreads();
+    if (grp == 0 && i < total) {
+        float t = part[0][o];
+        for (int q = 1; q < kRedGroups; ++q) t += part[q][o];
+        float* c = C + (i / N) * ldc + i % N;
+        *c = accumulate ? *c + t : t;
     }
 }
 
@@ -236,8 +301,15 @@ void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int 
         o.C = ws;
         gemm_dispatch<kOutPartial>(ta, tb, vec, dim3(tm, tn, splits), M, N, K, a, lda, b, ldb, o, st);
         const size_t total = (size_t)M * N;
-        const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-        splitk_reduce_kernel<<<blocks, 256, 0, st>>>(M, N, splits, ws, C, ldc, accumulate ? 1 : 0);
+        if (splits >= 2 * kRedGroups) {
+            const size_t blocks = (total + kRedOut - 1) / kRedOut;
+            splitk_reduce_grouped_kernel<<<(unsigned)blocks, 256, 0, st>>>(M, N, splits, ws, C, ldc,
+                                                                          accumulate ? 1 : 0);
+        } else {
+            const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+            splitk_reduce_kernel<<<blocks, 256, 0, st>>>(M, N, splits, ws, C, ldc,
+                                                         accumulate ? 1 : 0);
+        }
     } else {
         o.C = C;
         o.ldc = ldc;
