@@ -312,6 +312,39 @@ int dp_col2im3x3(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
  * that layer's output (one rounding to BF16). */
 int dp_col2im3x3_act_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t stride,
                           const float* dcol, const void* y, int32_t relu, void* dz, void* stream);
+/* Implicit-GEMM 3x3 convolutions (padding 1, stride >= 1) on NHWC BF16
+ * tensors: no im2col matrix is formed, each product gathers its operand
+ * tiles from the tensors.  Ci and Co multiples of 8, ldw a multiple of 8 and
+ * >= 9 Ci (+ 1 with ones), every pointer 16-byte aligned; N H W Ci and
+ * N Ho Wo 9 Ci below 2^31 (DP_ERR_UNSUPPORTED otherwise; split the batch).
+ * Weights w [Co][ldw] BF16, row co = the 9 Ci kernel values in (ky, kx, ci)
+ * order, further entries ignored.
+ * dp_conv3x3_fwd_bf16: y [N][Ho][Wo][Co] BF16 = act(conv(x) + bias), bias of
+ *   output channel o at bias[o * bias_stride], act = ReLU if relu.  The same
+ *   values as dp_im2col3x3_bf16 + dp_gemm_bias_act_bf16. */
+int dp_conv3x3_fwd_bf16(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co, int32_t stride,
+                        const void* x, const void* w, int32_t ldw, const float* bias,
+                        int32_t bias_stride, int32_t relu, void* y, void* stream);
+/* dp_conv3x3_wgrad_bf16: dw [Co][ldw] FP32 = dz^T . im2col(x) over the N Ho Wo
+ *   output pixels, dz [N][Ho][Wo][Co] BF16: columns < 9 Ci the weight
+ *   gradient, column 9 Ci the bias gradient (column sums of dz) if ones,
+ *   further columns zero.  Long reductions are split over a workspace of
+ *   dp_conv3x3_wgrad_ws_bytes bytes (may be 0; NULL then allowed) and
+ *   reduced in a fixed order. */
+size_t dp_conv3x3_wgrad_ws_bytes(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                                 int32_t stride, int32_t ldw);
+int dp_conv3x3_wgrad_bf16(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                          int32_t stride, const void* x, const void* dz, int32_t ldw,
+                          int32_t ones, float* dw, void* ws, size_t ws_bytes, void* stream);
+/* dp_conv3x3_dgrad_act_bf16: the input gradient dx [N][H][W][Ci] of
+ *   sum(dz . conv(x)), followed by the activation backward of the layer
+ *   below: out BF16 = dx * (y > 0) if relu (y [N][H][W][Ci] BF16, that
+ *   layer's output) else dx (y may be NULL).  Computed per parity class of
+ *   input pixels (stride^2 products, one per class, each summing exactly the
+ *   taps that reach the class), one rounding to BF16. */
+int dp_conv3x3_dgrad_act_bf16(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                              int32_t stride, const void* dz, const void* w, int32_t ldw,
+                              const void* y, int32_t relu, void* out, void* stream);
 /* One Adam step over n parameters in flat FP32 buffers: m = b1 m + (1 - b1) g,
  * v = b2 v + (1 - b2) g^2, p -= lr (m / c1) / (sqrt(v / c2) + eps), and p
  * rounded to BF16 into p_bf16 [n].  c1, c2 > 0: the bias corrections. */

@@ -39,7 +39,9 @@ EXPORTS = ("dp_workspace_bytes", "dp_project_fwd", "dp_project_fwd_grad_pose", "
            "dp_gemm_bf16_ws", "dp_gemm_bias_act_bf16", "dp_im2col3x3_ld_bf16",
            "dp_col2im3x3_act_bf16", "dp_adam_f32",
            "dp_project_fwd_ssd_gauss_newton_batch", "dp_lm_update", "dp_read_probe",
-           "dp_bp_grad_flags_offset", "dp_lds_probe", "dp_project_fwd_ssd_grad_pose_noalloc")
+           "dp_bp_grad_flags_offset", "dp_lds_probe", "dp_project_fwd_ssd_grad_pose_noalloc",
+           "dp_conv3x3_fwd_bf16", "dp_conv3x3_wgrad_ws_bytes", "dp_conv3x3_wgrad_bf16",
+           "dp_conv3x3_dgrad_act_bf16")
 MAX_BATCH = 16
 N_VARIANTS = 9  # ray-driven kernel variants: 3 * tile shape (16x16, 32x8, 8x32) + chunk class
 

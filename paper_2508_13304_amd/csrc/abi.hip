@@ -979,6 +979,85 @@ int dp_col2im3x3_act_bf16(int32_t N, int32_t H, int32_t W, int32_t C, int32_t st
     return check_launch("dp_col2im3x3_act_bf16");
 }
 
+// Shared checks of the implicit-GEMM convolutions.
+static int conv_igemm_args(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                           int32_t stride, int32_t ldw, int extra, const char* what)
+{
+    int rc = conv_dims(N, H, W, Ci, stride);
+    if (rc) return rc;
+    if (Co <= 0) return fail(DP_ERR_ARG, "%s: Co must be positive", what);
+    if (Ci % 8 || Co % 8 || ldw % 8)
+        return fail(DP_ERR_ARG, "%s: Ci, Co and ldw must be multiples of 8", what);
+    if (ldw < 9 * Ci + extra) return fail(DP_ERR_ARG, "%s: ldw %d too small", what, ldw);
+    const int64_t Ho = (H - 1) / stride + 1, Wo = (W - 1) / stride + 1;
+    if ((int64_t)N * Ho * Wo * Co >= ((int64_t)1 << 31) || (int64_t)N * H * W * Co >= ((int64_t)1 << 31) ||
+        (int64_t)Co * ldw >= ((int64_t)1 << 31))
+        return fail(DP_ERR_UNSUPPORTED, "%s: tensor above 2^31 elements; split the batch", what);
+    if ((N * Ho * Wo + 63) / 64 > 0x7FFFFFFF || (ldw + 63) / 64 > 65535 || (Ci + 63) / 64 > 65535 ||
+        (Co + 63) / 64 > 65535)
+        return fail(DP_ERR_UNSUPPORTED, "%s: too many tiles", what);
+    return DP_OK;
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+int dp_conv3x3_fwd_bf16(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co, int32_t stride,
+                        const void* x, const void* w, int32_t ldw, const float* bias,
+                        int32_t bias_stride, int32_t relu, void* y, void* stream)
+{
+    int rc = conv_igemm_args(N, H, W, Ci, Co, stride, ldw, 0, "conv3x3_fwd");
+    if (rc) return rc;
+    if (!x || !w || !bias || !y) return fail(DP_ERR_ARG, "conv3x3_fwd: NULL pointer");
+    if (bias_stride < 1) return fail(DP_ERR_ARG, "conv3x3_fwd: bias_stride must be positive");
+    if (!aligned16(x) || !aligned16(w) || !aligned16(y))
+        return fail(DP_ERR_ARG, "conv3x3_fwd: pointers must be 16-byte aligned");
+    (void)hipGetLastError();
+    launch_conv_fwd(N, H, W, Ci, Co, stride, x, w, ldw, bias, bias_stride, relu != 0, y,
+                    (hipStream_t)stream);
+    return check_launch("dp_conv3x3_fwd_bf16");
+}
+
+size_t dp_conv3x3_wgrad_ws_bytes(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                                 int32_t stride, int32_t ldw)
+{
+    if (conv_igemm_args(N, H, W, Ci, Co, stride, ldw, 0, "conv3x3_wgrad_ws_bytes")) return 0;
+    return conv_wgrad_ws_bytes(N, H, W, Ci, Co, stride, ldw);
+}
+
+int dp_conv3x3_wgrad_bf16(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                          int32_t stride, const void* x, const void* dz, int32_t ldw,
+                          int32_t ones, float* dw, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = conv_igemm_args(N, H, W, Ci, Co, stride, ldw, ones ? 1 : 0, "conv3x3_wgrad");
+    if (rc) return rc;
+    if (!x || !dz || !dw) return fail(DP_ERR_ARG, "conv3x3_wgrad: NULL pointer");
+    if (!aligned16(x) || !aligned16(dz))
+        return fail(DP_ERR_ARG, "conv3x3_wgrad: x and dz must be 16-byte aligned");
+    const size_t need = conv_wgrad_ws_bytes(N, H, W, Ci, Co, stride, ldw);
+    if (need && (!ws || ws_bytes < need))
+        return fail(DP_ERR_ARG, "conv3x3_wgrad: workspace of %zu bytes needed, %zu given", need,
+                    ws_bytes);
+    (void)hipGetLastError();
+    launch_conv_wgrad(N, H, W, Ci, Co, stride, x, dz, ldw, ones != 0, dw, (float*)ws, ws_bytes,
+                      (hipStream_t)stream);
+    return check_launch("dp_conv3x3_wgrad_bf16");
+}
+
+int dp_conv3x3_dgrad_act_bf16(int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                              int32_t stride, const void* dz, const void* w, int32_t ldw,
+                              const void* y, int32_t relu, void* out, void* stream)
+{
+    int rc = conv_igemm_args(N, H, W, Ci, Co, stride, ldw, 0, "conv3x3_dgrad_act");
+    if (rc) return rc;
+    if (!dz || !w || !out || (relu && !y)) return fail(DP_ERR_ARG, "conv3x3_dgrad_act: NULL pointer");
+    if (!aligned16(dz) || !aligned16(w) || !aligned16(out))
+        return fail(DP_ERR_ARG, "conv3x3_dgrad_act: pointers must be 16-byte aligned");
+    (void)hipGetLastError();
+    launch_conv_dgrad_act(N, H, W, Ci, Co, stride, dz, w, ldw, relu ? y : nullptr, relu != 0, out,
+                          (hipStream_t)stream);
+    return check_launch("dp_conv3x3_dgrad_act_bf16");
+}
+
 int dp_adam_f32(int64_t n, float* p, const float* g, float* m, float* v, void* p_bf16, float lr,
                 float beta1, float beta2, float eps, float c1, float c2, void* stream)
 {

@@ -118,35 +118,259 @@ __device__ inline bf16x8 load_frag(const __bf16* S, int rb, int lane)
     }
 }
 
-// Output modes of the GEMM kernel: FP32 C (+ C if accumulating); this
-// block's split-K partial tile into a workspace slice; or act(C + bias) to
-// BF16 (the forward convolution's epilogue).
-enum { kOutF32 = 0, kOutPartial = 1, kOutBiasAct = 2 };
-
-struct GemmOut {
-    float* C;            // kOutF32: C; kOutPartial: the workspace [splits][M][N]
-    int ldc;
-    int accumulate;
-    const float* bias;   // kOutBiasAct: bias of column n at bias[n * bias_stride]
-    int bias_stride;
-    int relu;
-    __bf16* Y;           // kOutBiasAct: BF16 output, row stride ldy
-    int ldy;
+// Exact unsigned division by a divisor fixed at launch (multiply-high and
+// shift; Granlund and Montgomery's method with a 33-bit magic number split
+// into a 32-bit multiplier and an add-and-halve step).  Valid for every
+// 32-bit dividend.
+struct FastDiv {
+    unsigned d, mul, sh;
+    FastDiv() = default;
+    explicit FastDiv(unsigned div) : d(div), mul(0), sh(0)
+    {
+        while ((1ull << sh) < div) ++sh;  // sh = ceil(log2 d)
+        if (sh > 0) mul = (unsigned)((((1ull << sh) - div) << 32) / div + 1);
+    }
+    __device__ unsigned div(unsigned n) const
+    {
+        if (sh == 0) return n;
+        const unsigned t = __umulhi(n, mul);
+        return (t + ((n - t) >> 1)) >> (sh - 1);
+    }
 };
 
-template <bool TA, bool TB, bool VEC, int OUT>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
-                                                        const __bf16* __restrict__ A, int lda,
-                                                        const __bf16* __restrict__ B, int ldb,
-                                                        GemmOut o)
+// ---------------------------------------------------------------------------
+// Operand sources.  A source stages the 64 x 32 (rows x k) tile of its
+// operand at (row0, k0) into LDS, zero outside [0, rows) x [k0, kend): S[row][k]
+// if KC, else T[k][row].  init() computes what a thread can keep over the
+// K loop.
+// ---------------------------------------------------------------------------
+
+// A dense BF16 matrix (k-contiguous if KC).
+template <bool KC_, bool VEC>
+struct DenseSrc {
+    static constexpr bool KC = KC_;
+    const __bf16* P;
+    int ld, rows;
+    struct St {};
+    __device__ St init(int, int) const { return {}; }
+    __device__ void stage(const St&, __bf16* S, int row0, int k0, int kend, int tid) const
+    {
+        stage_tile<KC, VEC>(P, ld, rows, row0, k0, kend, S, tid);
+    }
+};
+
+// 3x3 convolution geometry (padding 1, stride s) on NHWC BF16 input with C
+// channels, C a multiple of 8: output pixel m = (n, yo, xo), column
+// k = (3 ky + kx) C + ci of the implicit im2col matrix; column 9 C is the
+// ones column if `ones`, further columns are zero.
+struct ConvGeo {
+    int H, W, C, s, Ho, Wo, M;  // M = N Ho Wo output pixels
+    int ones;
+    FastDiv hw, w, c;            // by Ho Wo, Wo, C
+};
+
+// 8 consecutive columns k .. k + 7 (k a multiple of 8) of im2col row m.
+__device__ inline uint4 im2col8(const __bf16* __restrict__ x, const ConvGeo& g, int n, int yo,
+                                int xo, int k)
 {
-    // A is k-major in LDS unless stored transposed (TA), B k-major if TB.
-    constexpr bool AK = !TA, BK = TB;
+    const int K9 = 9 * g.C;
+    if (k >= K9) {
+        uint4 z = make_uint4(0u, 0u, 0u, 0u);
+        if (g.ones && k == K9) z.x = 0x3F80u;  // BF16 1.0 in the low half
+        return z;
+    }
+    const unsigned t = g.c.div((unsigned)k), ci = (unsigned)k - t * (unsigned)g.C;
+    const int ky = (int)t / 3, kx = (int)t - 3 * ky;
+    const int y = yo * g.s + ky - 1, xx = xo * g.s + kx - 1;
+    if ((unsigned)y >= (unsigned)g.H || (unsigned)xx >= (unsigned)g.W)
+        return make_uint4(0u, 0u, 0u, 0u);
+    return *(const uint4*)(x + ((size_t)((n * g.H + y) * g.W + xx)) * g.C + ci);
+}
+
+// The im2col matrix of the input x as the GEMM's A (rows = output pixels,
+// KC): each thread keeps its row's pixel over the K loop.
+struct Im2colA {
+    static constexpr bool KC = true;
+    const __bf16* x;
+    ConvGeo g;
+    struct St { int n, yo, xo; bool ok; };
+    __device__ St init(int row0, int tid) const
+    {
+        const int m = row0 + (tid >> 2);
+        St st;
+        st.ok = m < g.M;
+        const unsigned n = g.hw.div((unsigned)m), r = (unsigned)m - n * (unsigned)(g.Ho * g.Wo);
+        st.n = (int)n;
+        st.yo = (int)g.w.div(r);
+        st.xo = (int)r - st.yo * g.Wo;
+        return st;
+    }
+    __device__ void stage(const St& st, __bf16* S, int, int k0, int kend, int tid) const
+    {
+        const int r = tid >> 2, c = (tid & 3) * 8, k = k0 + c;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (st.ok && k < kend) v = im2col8(x, g, st.n, st.yo, st.xo, k);  // kend % 8 == 0
+        *(uint4*)&S[r * kSK + c] = v;
+    }
+};
+
+// The im2col matrix as the B of the weight gradient dW = dz^T . col: rows =
+// im2col columns (the GEMM's N), k = output pixels (row-major tile T[k][row]).
+struct Im2colB {
+    static constexpr bool KC = false;
+    const __bf16* x;
+    ConvGeo g;
+    int ncols;  // columns of the product (row length of dW)
+    struct St {};
+    __device__ St init(int, int) const { return {}; }
+    __device__ void stage(const St&, __bf16* S, int row0, int k0, int kend, int tid) const
+    {
+        const int kk = tid >> 3, c = (tid & 7) * 8, m = k0 + kk, col = row0 + c;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (m < kend && col < ncols) {  // ncols % 8 == 0
+            const unsigned n = g.hw.div((unsigned)m), r = (unsigned)m - n * (unsigned)(g.Ho * g.Wo);
+            const int yo = (int)g.w.div(r), xo = (int)r - yo * g.Wo;
+            v = im2col8(x, g, (int)n, yo, xo, col);
+        }
+        *(uint4*)&S[kk * kST + c] = v;
+    }
+};
+
+// Input gradient of a 3x3 convolution, one parity class (py, px) of input
+// pixels y = s y' + py, x = s x' + px at a time: such a pixel receives tap
+// (ky, kx) exactly when s divides py + 1 - ky and px + 1 - kx, from output
+// pixel (y' + (py + 1 - ky) / s, x' + (px + 1 - kx) / s).  So the class is
+// the product dx[m'][ci] = sum_{(t, co)} dz[pixel(m', t)][co] W[co][tap t][ci]
+// over its taps t, with no overlap between classes (no col2im).
+struct DgradClass {
+    int H, W, Ci, Co, s, Ho, Wo;
+    int py, px, Hc, Wc, M;      // class pixels: N Hc Wc
+    int nky, nkx;               // taps of the class
+    int ky[3], kx[3], dy[3], dx[3];
+    FastDiv hw, w, co, nkxd;    // by Hc Wc, Wc, Co, nkx
+};
+
+struct DgradA {
+    static constexpr bool KC = true;
+    const __bf16* dz;  // [N][Ho][Wo][Co]
+    DgradClass c;
+    struct St { int n, yc, xc; bool ok; };
+    __device__ St init(int row0, int tid) const
+    {
+        const int m = row0 + (tid >> 2);
+        St st;
+        st.ok = m < c.M;
+        const unsigned n = c.hw.div((unsigned)m), r = (unsigned)m - n * (unsigned)(c.Hc * c.Wc);
+        st.n = (int)n;
+        st.yc = (int)c.w.div(r);
+        st.xc = (int)r - st.yc * c.Wc;
+        return st;
+    }
+    __device__ void stage(const St& st, __bf16* S, int, int k0, int kend, int tid) const
+    {
+        const int r = tid >> 2, q = (tid & 3) * 8, k = k0 + q;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (st.ok && k < kend) {
+            const unsigned t = c.co.div((unsigned)k), co = (unsigned)k - t * (unsigned)c.Co;
+            const unsigned ty = c.nkxd.div(t), tx = t - ty * (unsigned)c.nkx;
+            const int yo = st.yc + c.dy[ty], xo = st.xc + c.dx[tx];
+            if ((unsigned)yo < (unsigned)c.Ho && (unsigned)xo < (unsigned)c.Wo)
+                v = *(const uint4*)(dz + ((size_t)((st.n * c.Ho + yo) * c.Wo + xo)) * c.Co + co);
+        }
+        *(uint4*)&S[r * kSK + q] = v;
+    }
+};
+
+// The weights as the class's B: element (k = (t, co), ci) = W[co][tap t][ci]
+// of the [Co][ldw] weight rows (row-major tile T[k][ci]).
+struct DgradB {
+    static constexpr bool KC = false;
+    const __bf16* w;
+    int ldw;
+    DgradClass c;
+    struct St {};
+    __device__ St init(int, int) const { return {}; }
+    __device__ void stage(const St&, __bf16* S, int row0, int k0, int kend, int tid) const
+    {
+        const int kk = tid >> 3, q = (tid & 7) * 8, k = k0 + kk, ci = row0 + q;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (k < kend && ci < c.Ci) {  // Ci % 8 == 0
+            const unsigned t = c.co.div((unsigned)k), co = (unsigned)k - t * (unsigned)c.Co;
+            const unsigned ty = c.nkxd.div(t), tx = t - ty * (unsigned)c.nkx;
+            const int tap = 3 * c.ky[ty] + c.kx[tx];
+            v = *(const uint4*)(w + (size_t)co * ldw + tap * c.Ci + ci);
+        }
+        *(uint4*)&S[kk * kST + q] = v;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Epilogues: what happens to element (m, n) of the block's FP32 tile.
+// ---------------------------------------------------------------------------
+
+// C (+ C if accumulating), FP32.
+struct EpF32 {
+    float* C;
+    int ldc, accumulate;
+    __device__ void operator()(int m, int n, float v) const
+    {
+        float* c = C + (size_t)m * ldc + n;
+        *c = accumulate ? *c + v : v;
+    }
+};
+
+// This block's split-K partial tile into the workspace [splits][M][N].
+struct EpPartial {
+    float* ws;
+    int M, N;
+    __device__ void operator()(int m, int n, float v) const
+    {
+        ws[((size_t)blockIdx.z * M + m) * N + n] = v;
+    }
+};
+
+// act(C + bias) to BF16 (the forward convolution's epilogue).
+struct EpBiasAct {
+    const float* bias;  // bias of column n at bias[n * bias_stride]
+    int bias_stride, relu;
+    __bf16* Y;
+    int ldy;
+    __device__ void operator()(int m, int n, float v) const
+    {
+        float y = v + bias[(size_t)n * bias_stride];
+        if (relu) y = fmaxf(y, 0.f);
+        Y[(size_t)m * ldy + n] = to_bf16(y);
+    }
+};
+
+// Input gradient of one parity class, with the ReLU backward of the layer
+// below applied (dz_below = dx where y_below > 0) and written as BF16 at the
+// class pixel's place in [N][H][W][Ci].
+struct EpDgradAct {
+    DgradClass c;
+    const __bf16* y;  // activation of the layer below (NULL: no activation)
+    int relu;
+    __bf16* out;
+    __device__ void operator()(int m, int n, float v) const
+    {
+        const unsigned b = c.hw.div((unsigned)m), r = (unsigned)m - b * (unsigned)(c.Hc * c.Wc);
+        const int yc = (int)c.w.div(r), xc = (int)r - yc * c.Wc;
+        const size_t p = ((size_t)((b * c.H + c.s * yc + c.py) * c.W + c.s * xc + c.px)) * c.Ci + n;
+        if (relu && !((float)y[p] > 0.f)) v = 0.f;
+        out[p] = to_bf16(v);
+    }
+};
+
+// C[M][N] = A B over k: 64 x 64 block tiles, 4 wavefronts of 32 x 32 (2 x 2
+// MFMA 16x16x32 tiles each), K advancing by 32 through LDS.  With several
+// z blocks (split-K) block z covers its own contiguous k range.
+template <class AS, class BS, class EP>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, AS as, BS bs, EP ep)
+{
     __shared__ __attribute__((aligned(16))) __bf16 As[kTileElems];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[kTileElems];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT;
-    // split-K: block z covers k in [kbeg, kend) and writes its own partial tile
     const int ksplit = (K + (int)gridDim.z - 1) / (int)gridDim.z;
     const int kbeg = (int)blockIdx.z * ((ksplit + kGK - 1) / kGK * kGK);
     const int kend = min(K, kbeg + (ksplit + kGK - 1) / kGK * kGK);
@@ -156,19 +380,20 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const auto sa = as.init(m0, tid);
+    const auto sb = bs.init(n0, tid);
     for (int k0 = kbeg; k0 < kend; k0 += kGK) {
-        // A stored [M][K] (k-contiguous) unless TA; B stored [N][K] if TB.
         // (Prefetching the next step's tiles into registers during the
         // products measured slower: a step's products are too short to hide
         // the loads.)
-        stage_tile<AK, VEC>(A, lda, M, m0, k0, kend, As, tid);
-        stage_tile<BK, VEC>(B, ldb, N, n0, k0, kend, Bs, tid);
+        as.stage(sa, As, m0, k0, kend, tid);
+        bs.stage(sb, Bs, n0, k0, kend, tid);
         __syncthreads();
         bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = load_frag<AK>(As, wm + i * 16, lane);
+        for (int i = 0; i < 2; ++i) a[i] = load_frag<AS::KC>(As, wm + i * 16, lane);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = load_frag<BK>(Bs, wn + j * 16, lane);
+        for (int j = 0; j < 2; ++j) b[j] = load_frag<BS::KC>(Bs, wn + j * 16, lane);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -184,19 +409,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
             for (int q = 0; q < 4; ++q) {
                 const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
                 const int n = n0 + wn + j * 16 + (lane & 15);
-                if (m < M && n < N) {
-                    const float v = acc[i][j][q];
-                    if constexpr (OUT == kOutPartial) {
-                        o.C[((size_t)blockIdx.z * M + m) * N + n] = v;
-                    } else if constexpr (OUT == kOutBiasAct) {
-                        float y = v + o.bias[(size_t)n * o.bias_stride];
-                        if (o.relu) y = fmaxf(y, 0.f);
-                        o.Y[(size_t)m * o.ldy + n] = to_bf16(y);
-                    } else {
-                        float* c = o.C + (size_t)m * o.ldc + n;
-                        *c = o.accumulate ? *c + v : v;
-                    }
-                }
+                if (m < M && n < N) ep(m, n, acc[i][j][q]);
             }
 }
 
@@ -262,44 +475,18 @@ size_t gemm_ws_bytes(int M, int N, int K)
     return s > 1 ? (size_t)s * M * N * sizeof(float) : 0;
 }
 
-template <int OUT>
-static void gemm_dispatch(bool ta, bool tb, bool vec, dim3 grid, int M, int N, int K,
-                          const __bf16* a, int lda, const __bf16* b, int ldb, const GemmOut& o,
-                          hipStream_t st)
-{
-#define DP_GEMM(TA_, TB_)                                                                          \
-    do {                                                                                           \
-        if (vec)                                                                                   \
-            gemm_bf16_kernel<TA_, TB_, true, OUT><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, o); \
-        else                                                                                       \
-            gemm_bf16_kernel<TA_, TB_, false, OUT><<<grid, 256, 0, st>>>(M, N, K, a, lda, b, ldb, o); \
-    } while (0)
-    if (!ta && !tb) DP_GEMM(false, false);
-    else if (!ta && tb) DP_GEMM(false, true);
-    else if (ta && !tb) DP_GEMM(true, false);
-    else DP_GEMM(true, true);
-#undef DP_GEMM
-}
-
-static bool gemm_vec(int lda, int ldb, const void* A, const void* B)
-{
-    return lda % 8 == 0 && ldb % 8 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
-}
-
-void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int lda, const void* B,
-                      int ldb, float* C, int ldc, bool accumulate, float* ws, size_t ws_bytes,
-                      hipStream_t st)
+// Runs C (+)= A B with the split-K decision of gemm_splits: the partial
+// tiles go to ws and are reduced in split order (one pass if ws is too
+// small or NULL).
+template <class AS, class BS>
+static void run_gemm_f32(int M, int N, int K, const AS& as, const BS& bs, float* C, int ldc,
+                         bool accumulate, float* ws, size_t ws_bytes, hipStream_t st)
 {
     const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
     int splits = gemm_splits(M, N, K);
-    if (splits > 1 && (!ws || ws_bytes < gemm_ws_bytes(M, N, K))) splits = 1;  // no workspace: one pass
-    const __bf16* a = (const __bf16*)A;
-    const __bf16* b = (const __bf16*)B;
-    const bool vec = gemm_vec(lda, ldb, A, B);
-    GemmOut o{};
+    if (splits > 1 && (!ws || ws_bytes < gemm_ws_bytes(M, N, K))) splits = 1;
     if (splits > 1) {
-        o.C = ws;
-        gemm_dispatch<kOutPartial>(ta, tb, vec, dim3(tm, tn, splits), M, N, K, a, lda, b, ldb, o, st);
+        gemm_kernel<<<dim3(tm, tn, splits), 256, 0, st>>>(M, N, K, as, bs, EpPartial{ws, M, N});
         const size_t total = (size_t)M * N;
         if (splits >= 2 * kRedGroups) {
             const size_t blocks = (total + kRedOut - 1) / kRedOut;
@@ -311,26 +498,129 @@ void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int 
                                                          accumulate ? 1 : 0);
         }
     } else {
-        o.C = C;
-        o.ldc = ldc;
-        o.accumulate = accumulate ? 1 : 0;
-        gemm_dispatch<kOutF32>(ta, tb, vec, dim3(tm, tn, 1), M, N, K, a, lda, b, ldb, o, st);
+        gemm_kernel<<<dim3(tm, tn, 1), 256, 0, st>>>(M, N, K, as, bs,
+                                                     EpF32{C, ldc, accumulate ? 1 : 0});
     }
+}
+
+static bool gemm_vec(int lda, int ldb, const void* A, const void* B)
+{
+    return lda % 8 == 0 && ldb % 8 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+}
+
+// Dense operands: A stored [M][K] unless ta ([K][M]), B stored [K][N] unless
+// tb ([N][K]); VEC when both take 16-byte moves.
+template <bool VEC, class F>
+static void with_dense(bool ta, bool tb, const __bf16* a, int lda, int M, const __bf16* b, int ldb,
+                       int N, F&& f)
+{
+    if (!ta && !tb) f(DenseSrc<true, VEC>{a, lda, M}, DenseSrc<false, VEC>{b, ldb, N});
+    else if (!ta && tb) f(DenseSrc<true, VEC>{a, lda, M}, DenseSrc<true, VEC>{b, ldb, N});
+    else if (ta && !tb) f(DenseSrc<false, VEC>{a, lda, M}, DenseSrc<false, VEC>{b, ldb, N});
+    else f(DenseSrc<false, VEC>{a, lda, M}, DenseSrc<true, VEC>{b, ldb, N});
+}
+
+void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int lda, const void* B,
+                      int ldb, float* C, int ldc, bool accumulate, float* ws, size_t ws_bytes,
+                      hipStream_t st)
+{
+    const __bf16* a = (const __bf16*)A;
+    const __bf16* b = (const __bf16*)B;
+    auto go = [&](const auto& as, const auto& bs) {
+        run_gemm_f32(M, N, K, as, bs, C, ldc, accumulate, ws, ws_bytes, st);
+    };
+    if (gemm_vec(lda, ldb, A, B)) with_dense<true>(ta, tb, a, lda, M, b, ldb, N, go);
+    else with_dense<false>(ta, tb, a, lda, M, b, ldb, N, go);
 }
 
 void launch_gemm_bias_act(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
                           const float* bias, int bias_stride, bool relu, void* Y, int ldy,
                           hipStream_t st)
 {
-    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
-    GemmOut o{};
-    o.bias = bias;
-    o.bias_stride = bias_stride;
-    o.relu = relu ? 1 : 0;
-    o.Y = (__bf16*)Y;
-    o.ldy = ldy;
-    gemm_dispatch<kOutBiasAct>(false, true, gemm_vec(lda, ldb, A, B), dim3(tm, tn, 1), M, N, K,
-                               (const __bf16*)A, lda, (const __bf16*)B, ldb, o, st);
+    const dim3 grid((M + kGT - 1) / kGT, (N + kGT - 1) / kGT, 1);
+    const EpBiasAct ep{bias, bias_stride, relu ? 1 : 0, (__bf16*)Y, ldy};
+    const __bf16* a = (const __bf16*)A;
+    const __bf16* b = (const __bf16*)B;
+    if (gemm_vec(lda, ldb, A, B))
+        gemm_kernel<<<grid, 256, 0, st>>>(M, N, K, DenseSrc<true, true>{a, lda, M},
+                                          DenseSrc<true, true>{b, ldb, N}, ep);
+    else
+        gemm_kernel<<<grid, 256, 0, st>>>(M, N, K, DenseSrc<true, false>{a, lda, M},
+                                          DenseSrc<true, false>{b, ldb, N}, ep);
+}
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM 3x3 convolutions (C a multiple of 8; no im2col matrix)
+// ---------------------------------------------------------------------------
+
+static ConvGeo conv_geo(int N, int H, int W, int C, int s, bool ones)
+{
+    ConvGeo g;
+    g.H = H; g.W = W; g.C = C; g.s = s;
+    g.Ho = (H - 1) / s + 1;
+    g.Wo = (W - 1) / s + 1;
+    g.M = N * g.Ho * g.Wo;
+    g.ones = ones ? 1 : 0;
+    g.hw = FastDiv((unsigned)(g.Ho * g.Wo));
+    g.w = FastDiv((unsigned)g.Wo);
+    g.c = FastDiv((unsigned)C);
+    return g;
+}
+
+void launch_conv_fwd(int N, int H, int W, int Ci, int Co, int s, const void* x, const void* w,
+                     int ldw, const float* bias, int bias_stride, bool relu, void* y, hipStream_t st)
+{
+    const ConvGeo g = conv_geo(N, H, W, Ci, s, false);
+    const dim3 grid((g.M + kGT - 1) / kGT, (Co + kGT - 1) / kGT, 1);
+    gemm_kernel<<<grid, 256, 0, st>>>(g.M, Co, 9 * Ci, Im2colA{(const __bf16*)x, g},
+                                      DenseSrc<true, true>{(const __bf16*)w, ldw, Co},
+                                      EpBiasAct{bias, bias_stride, relu ? 1 : 0, (__bf16*)y, Co});
+}
+
+size_t conv_wgrad_ws_bytes(int N, int H, int W, int Ci, int Co, int s, int ldw)
+{
+    const ConvGeo g = conv_geo(N, H, W, Ci, s, false);
+    return gemm_ws_bytes(Co, ldw, g.M);
+}
+
+void launch_conv_wgrad(int N, int H, int W, int Ci, int Co, int s, const void* x, const void* dz,
+                       int ldw, bool ones, float* dw, float* ws, size_t ws_bytes, hipStream_t st)
+{
+    const ConvGeo g = conv_geo(N, H, W, Ci, s, ones);
+    run_gemm_f32(Co, ldw, g.M, DenseSrc<false, true>{(const __bf16*)dz, Co, Co},
+                 Im2colB{(const __bf16*)x, g, ldw}, dw, ldw, false, ws, ws_bytes, st);
+}
+
+void launch_conv_dgrad_act(int N, int H, int W, int Ci, int Co, int s, const void* dz,
+                           const void* w, int ldw, const void* y, bool relu, void* out,
+                           hipStream_t st)
+{
+    DgradClass c{};
+    c.H = H; c.W = W; c.Ci = Ci; c.Co = Co; c.s = s;
+    c.Ho = (H - 1) / s + 1;
+    c.Wo = (W - 1) / s + 1;
+    c.co = FastDiv((unsigned)Co);
+    for (int py = 0; py < s && py < H; ++py)
+        for (int px = 0; px < s && px < W; ++px) {
+            c.py = py; c.px = px;
+            c.Hc = (H - py + s - 1) / s;
+            c.Wc = (W - px + s - 1) / s;
+            c.M = N * c.Hc * c.Wc;
+            c.nky = c.nkx = 0;
+            for (int k = 0; k < 3; ++k) {
+                if ((py + 1 - k) % s == 0) { c.ky[c.nky] = k; c.dy[c.nky++] = (py + 1 - k) / s; }
+                if ((px + 1 - k) % s == 0) { c.kx[c.nkx] = k; c.dx[c.nkx++] = (px + 1 - k) / s; }
+            }
+            c.hw = FastDiv((unsigned)(c.Hc * c.Wc));
+            c.w = FastDiv((unsigned)c.Wc);
+            c.nkxd = FastDiv((unsigned)c.nkx);
+            const int K = c.nky * c.nkx * Co;
+            const dim3 grid((c.M + kGT - 1) / kGT, (Ci + kGT - 1) / kGT, 1);
+            gemm_kernel<<<grid, 256, 0, st>>>(c.M, Ci, K, DgradA{(const __bf16*)dz, c},
+                                              DgradB{(const __bf16*)w, ldw, c},
+                                              EpDgradAct{c, (const __bf16*)y, relu ? 1 : 0,
+                                                         (__bf16*)out});
+        }
 }
 
 // im2col of a 3x3 convolution (stride s, padding 1) on NHWC BF16 input:

@@ -187,6 +187,24 @@ void launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const void* A, int 
 void launch_gemm_bias_act(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
                           const float* bias, int bias_stride, bool relu, void* Y, int ldy,
                           hipStream_t st);
+// Implicit-GEMM 3x3 convolutions (padding 1, stride s) on NHWC BF16 tensors
+// with Ci and Co multiples of 8, weights w [Co][ldw] BF16 (9 Ci per row,
+// (ky, kx, ci) order; ldw a multiple of 8), 16-byte aligned pointers.
+// Forward: y [N][Ho][Wo][Co] = act(conv(x) + bias).
+void launch_conv_fwd(int N, int H, int W, int Ci, int Co, int s, const void* x, const void* w,
+                     int ldw, const float* bias, int bias_stride, bool relu, void* y, hipStream_t st);
+// Weight gradient dw [Co][ldw] FP32 = dz^T . im2col(x) (column 9 Ci: the
+// bias gradient if `ones`; further columns zero); split-K workspace as for
+// the GEMM.
+size_t conv_wgrad_ws_bytes(int N, int H, int W, int Ci, int Co, int s, int ldw);
+void launch_conv_wgrad(int N, int H, int W, int Ci, int Co, int s, const void* x, const void* dz,
+                       int ldw, bool ones, float* dw, float* ws, size_t ws_bytes, hipStream_t st);
+// Input gradient, per parity class of input pixels, with the ReLU backward
+// of the layer below: out [N][H][W][Ci] BF16 = dx (y == NULL or !relu) or
+// dx * (y > 0).
+void launch_conv_dgrad_act(int N, int H, int W, int Ci, int Co, int s, const void* dz,
+                           const void* w, int ldw, const void* y, bool relu, void* out,
+                           hipStream_t st);
 // col rows of ld >= 9 C entries: the 9 C window values, then 1 (ones) and zeros.
 void launch_im2col(int N, int H, int W, int C, int s, int Ho, int Wo, const void* x, void* col,
                    int ld, bool ones, hipStream_t st);

@@ -58,9 +58,15 @@ def _lib():
         lib.dp_act_bwd_bf16.argtypes = [i64, vp, vp, i32, vp, vp]
         lib.dp_colsum_bf16.argtypes = [i32, i32, vp, vp, vp]
         lib.dp_adam_f32.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, f32, f32, vp]
+        lib.dp_conv3x3_fwd_bf16.argtypes = [i32] * 6 + [vp, vp, i32, vp, i32, i32, vp, vp]
+        lib.dp_conv3x3_wgrad_ws_bytes.argtypes = [i32] * 7
+        lib.dp_conv3x3_wgrad_ws_bytes.restype = sz
+        lib.dp_conv3x3_wgrad_bf16.argtypes = [i32] * 6 + [vp, vp, i32, i32, vp, vp, sz, vp]
+        lib.dp_conv3x3_dgrad_act_bf16.argtypes = [i32] * 6 + [vp, vp, i32, vp, i32, vp, vp]
         for f in ("dp_gemm_bf16", "dp_gemm_bf16_ws", "dp_gemm_bias_act_bf16", "dp_im2col3x3_bf16",
                   "dp_im2col3x3_ld_bf16", "dp_col2im3x3", "dp_col2im3x3_act_bf16",
-                  "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16", "dp_adam_f32"):
+                  "dp_bias_act_bf16", "dp_act_bwd_bf16", "dp_colsum_bf16", "dp_adam_f32",
+                  "dp_conv3x3_fwd_bf16", "dp_conv3x3_wgrad_bf16", "dp_conv3x3_dgrad_act_bf16"):
             getattr(lib, f).restype = C.c_int
         lib._cnn_ready = True
     return lib
@@ -154,6 +160,53 @@ def col2im_act(dcol, shape, stride, y, relu=True):
     return dz
 
 
+def conv_fwd(x, w, stride, bias, relu=True):
+    """Implicit-GEMM convolution: BF16 y [N][Ho][Wo][Co] = act(conv3x3(x) +
+    bias) for x [N][H][W][Ci] BF16 (Ci a multiple of 8) and weight rows w
+    [Co][>= 9 Ci] BF16 ((ky, kx, ci) order); bias a 1-D FP32 view (any stride)."""
+    x = x.contiguous()
+    N, H, W, Ci = x.shape
+    Co = w.shape[0]
+    Ho, Wo = (H - 1) // stride + 1, (W - 1) // stride + 1
+    y = torch.empty((N, Ho, Wo, Co), dtype=torch.bfloat16, device=x.device)
+    _check(_lib().dp_conv3x3_fwd_bf16(N, H, W, Ci, Co, stride, _p(x), _p(w), _ld(w), _p(bias),
+                                      bias.stride(0), int(relu), _p(y), _stream(None)),
+           "dp_conv3x3_fwd_bf16")
+    return y
+
+
+def conv_wgrad(x, dz, stride, out, ones=True):
+    """FP32 out [Co][ld] = dz^T . im2col(x) without the im2col matrix (column
+    9 Ci: the bias gradient if ones; columns after it zero)."""
+    x, dz = x.contiguous(), dz.contiguous()
+    N, H, W, Ci = x.shape
+    Co, ld = out.shape
+    assert out.stride(1) == 1 and out.stride(0) == ld
+    lib = _lib()
+    need = lib.dp_conv3x3_wgrad_ws_bytes(N, H, W, Ci, Co, stride, ld)
+    ws = _workspace(x.device, need) if need else None
+    rc = lib.dp_conv3x3_wgrad_bf16(N, H, W, Ci, Co, stride, _p(x), _p(dz), ld, int(ones), _p(out),
+                                   _p(ws) if ws is not None else None,
+                                   ws.numel() if ws is not None else 0, _stream(None))
+    _check(rc, "dp_conv3x3_wgrad_bf16")
+    return out
+
+
+def conv_dgrad_act(dz, w, shape, stride, y=None, relu=True):
+    """BF16 input gradient of a 3x3 convolution for dz [N][Ho][Wo][Co], weight
+    rows w [Co][>= 9 Ci], times (y > 0) for the layer below's output y if
+    relu: computed per parity class of input pixels, no col2im."""
+    dz = dz.contiguous()
+    N, H, W, Ci = shape
+    Co = w.shape[0]
+    out = torch.empty(shape, dtype=torch.bfloat16, device=dz.device)
+    yp = _p(y.contiguous()) if (relu and y is not None) else None
+    _check(_lib().dp_conv3x3_dgrad_act_bf16(N, H, W, Ci, Co, stride, _p(dz), _p(w), _ld(w), yp,
+                                            int(relu and y is not None), _p(out), _stream(None)),
+           "dp_conv3x3_dgrad_act_bf16")
+    return out
+
+
 def bias_act(z, bias, relu=True):
     z, bias = z.contiguous(), bias.contiguous()
     y = torch.empty(z.shape, dtype=torch.bfloat16, device=z.device)
@@ -196,10 +249,14 @@ class ProposalNet:
     All parameters live in one flat FP32 buffer P (gradients in G of the same
     layout, a BF16 copy in Pb): per conv layer a [Co][row] block whose row
     holds the 9 Ci weights, the bias and zero padding, then the head's
-    weights [6][F] and bias [6].  The forward product reads the BF16 weights
-    with the FP32 bias in its epilogue; the weight-gradient product of the
-    im2col matrix with a ones column writes the layer's weight and bias
-    gradients straight into its block of G; Adam is one launch over P."""
+    weights [6][F] and bias [6].  Layers with a multiple of 8 input channels
+    run as implicit GEMMs (operand tiles gathered from the activations, no
+    im2col matrix; the input gradient per parity class of input pixels, no
+    col2im), the 2-channel input layer through an explicit im2col.  The
+    forward product reads the BF16 weights with the FP32 bias in its
+    epilogue; the weight-gradient product (with an implicit or explicit ones
+    column) writes the layer's weight and bias gradients straight into its
+    block of G; Adam is one launch over P."""
 
     def __init__(self, size=256, in_ch=2, channels=CHANNELS, device="cuda:0", seed=0):
         self.size = size
@@ -252,11 +309,20 @@ class ProposalNet:
         h = x.contiguous()
         for li, (W, b, s) in enumerate(self.convs):
             K = W.shape[1]
-            col, Ho, Wo = im2col(h, s, ld=self.blocks[li].shape[1], ones=keep)
-            y = gemm_bias_act(col, self.bblocks[li], K, b, relu=True)
+            if h.shape[3] % 8 == 0:
+                # implicit GEMM: the products gather their operand tiles from h
+                y = conv_fwd(h, self.bblocks[li], s, b, relu=True)
+                col = None
+            else:
+                # few input channels (the 2-channel input layer): im2col rows
+                # padded to the parameter row, with a ones column for the
+                # bias gradient
+                col, Ho, Wo = im2col(h, s, ld=self.blocks[li].shape[1], ones=keep)
+                y = gemm_bias_act(col, self.bblocks[li], K, b, relu=True)
+                y = y.view(h.shape[0], Ho, Wo, W.shape[0])
             if keep:
-                cache.append((h.shape, col, y, s))
-            h = y.view(h.shape[0], Ho, Wo, W.shape[0])
+                cache.append((h, col, y, s))
+            h = y
         feat = h.reshape(h.shape[0], -1)
         out = gemm(feat, self.Wfc_b, tb=True) + self.bfc
         return (out, (cache, feat)) if keep else out
@@ -274,13 +340,21 @@ class ProposalNet:
         grads = [None] * len(self.convs)
         for li in range(len(self.convs) - 1, -1, -1):
             W, b, s = self.convs[li]
-            xshape, col, y, _ = convs_cache[li]
-            gemm(dz, col, ta=True, out=self.gblocks[li])            # [Co][row]: dW | db | 0
+            x_in, col, y, _ = convs_cache[li]
+            dz = dz.reshape(-1, W.shape[0])
             K = W.shape[1]
+            # [Co][row]: dW | db | 0
+            if col is None:
+                conv_wgrad(x_in, dz, s, out=self.gblocks[li], ones=True)
+            else:
+                gemm(dz, col, ta=True, out=self.gblocks[li])
             if li > 0:
-                dcol = gemm(dz, self.bblocks[li][:, :K])             # [M][9 Ci]
                 y_below = convs_cache[li - 1][2]
-                dz = col2im_act(dcol, xshape, s, y_below, relu=True).view(-1, xshape[3])
+                if col is None:
+                    dz = conv_dgrad_act(dz, self.bblocks[li], tuple(x_in.shape), s, y_below)
+                else:
+                    dcol = gemm(dz, self.bblocks[li][:, :K])         # [M][9 Ci]
+                    dz = col2im_act(dcol, tuple(x_in.shape), s, y_below, relu=True)
             grads[li] = (self.gblocks[li][:, :K], self.gblocks[li][:, K])
         return grads, (self.gWfc, self.gbfc)
 

@@ -155,6 +155,17 @@ def test_newer_entries_validate_before_launch(lib):
         assert lib.dp_set_variant(op, -1) == 0
     assert lib.dp_get_variant(C.byref(gs), 1, m.OP_BP) == -1
     assert lib.dp_set_variant(m.OP_BP, 0) == -1
+    # implicit-GEMM convolutions: channel multiples of 8, row length, NULL,
+    # alignment (all refused before any launch)
+    a16 = C.c_void_p(1 << 20)
+    assert lib.dp_conv3x3_fwd_bf16(2, 8, 8, 6, 16, 2, a16, a16, 56, a16, 1, 1, a16, None) == -1
+    assert lib.dp_conv3x3_fwd_bf16(2, 8, 8, 8, 16, 2, a16, a16, 64, a16, 1, 1, a16, None) == -1
+    assert lib.dp_conv3x3_fwd_bf16(2, 8, 8, 8, 16, 2, a16, None, 72, a16, 1, 1, a16, None) == -1
+    assert lib.dp_conv3x3_fwd_bf16(2, 8, 8, 8, 16, 2, C.c_void_p((1 << 20) + 8), a16, 72, a16, 1,
+                                   1, a16, None) == -1
+    assert lib.dp_conv3x3_wgrad_bf16(2, 8, 8, 8, 16, 2, a16, a16, 72, 1, a16, None, 0, None) == -1
+    assert lib.dp_conv3x3_wgrad_ws_bytes(2, 8, 8, 8, 16, 2, 72) == 0
+    assert lib.dp_conv3x3_dgrad_act_bf16(2, 8, 8, 8, 16, 2, a16, a16, 72, None, 1, a16, None) == -1
     # CNN helpers: 32-bit index spaces
     assert lib.dp_im2col3x3_bf16(512, 256, 256, 64, 1, p, p, None) == -4
     assert lib.dp_col2im3x3(512, 256, 256, 64, 1, p, p, None) == -4

@@ -325,3 +325,54 @@ def test_network_training_step_is_repeatable(dp):
         grads, head = net.backward(cache, 2.0 * (out - y) / out.numel())
         net.adam_step(grads, head, lr=1e-3)
     assert torch.equal(nets[0].P, nets[1].P)
+
+
+@pytest.mark.parametrize("N,H,W,Ci,Co,s", [(2, 13, 10, 8, 16, 2), (1, 9, 7, 16, 8, 1),
+                                           (2, 16, 16, 32, 64, 2), (3, 7, 11, 64, 24, 2)])
+def test_implicit_gemm_convolution_against_oracle(dp, N, H, W, Ci, Co, s):
+    """The implicit-GEMM convolution entry points (operand tiles gathered from
+    NHWC tensors: no im2col matrix, input gradient per parity class of input
+    pixels: no col2im) against the FP64 oracle on ragged and odd sizes, both
+    strides.  Forward (BF16 out, before ReLU) and input gradient (BF16 out,
+    times the ReLU mask of a layer below): within one BF16 rounding plus the
+    FP32 accumulation bound; weight and bias gradients (FP32): 1e-5 of the
+    largest entry.  Forward and weight gradient are also bit-equal to the
+    explicit im2col products (same MFMA accumulation order)."""
+    from paper_2508_13304_amd import proposal as pr
+    rng = np.random.default_rng(100 * Ci + Co + s)
+    x = ocnn.bf16(rng.standard_normal((N, H, W, Ci)))
+    Wt = ocnn.bf16(rng.standard_normal((Co, 3, 3, Ci)))
+    b = rng.standard_normal(Co).astype(np.float32).astype(np.float64)
+    row = pr._row_len(Ci)
+    blk = torch.zeros((Co, row), dtype=torch.float32, device=DEV)
+    blk[:, :9 * Ci] = torch.tensor(Wt.reshape(Co, -1), dtype=torch.float32, device=DEV)
+    blk[:, 9 * Ci] = torch.tensor(b, dtype=torch.float32, device=DEV)
+    wb = blk.to(torch.bfloat16)
+    xb = bf(x)
+    y = pr.conv_fwd(xb, wb, s, blk[:, 9 * Ci], relu=False)
+    zref = ocnn.conv3x3_forward(x, Wt, b, s)
+    got = y.float().cpu().numpy()
+    tol = 2.0 ** -8 * np.abs(zref) + 1e-5 * np.abs(zref).max()
+    assert np.all(np.abs(got - zref) <= tol)
+    col, Ho, Wo = pr.im2col(xb, s, ld=row, ones=True)
+    assert torch.equal(y.view(-1, Co), pr.gemm_bias_act(col, wb, 9 * Ci, blk[:, 9 * Ci], relu=False))
+
+    dz = ocnn.bf16(rng.standard_normal(zref.shape))
+    dzb = bf(dz.reshape(-1, Co))
+    dw = torch.empty((Co, row), dtype=torch.float32, device=DEV)
+    pr.conv_wgrad(xb, dzb, s, out=dw, ones=True)
+    dx_r, dW_r, db_r = ocnn.conv3x3_backward(x, Wt, dz, s)
+    dwn = dw.cpu().numpy()
+    assert np.abs(dwn[:, :9 * Ci] - dW_r.reshape(Co, -1)).max() <= 1e-5 * np.abs(dW_r).max()
+    assert np.abs(dwn[:, 9 * Ci] - db_r).max() <= 1e-5 * np.abs(db_r).max()
+    assert np.all(dwn[:, 9 * Ci + 1:] == 0)
+    assert torch.equal(dw, pr.gemm(dzb, col, ta=True))
+
+    yb = ocnn.bf16(rng.standard_normal((N, H, W, Ci)))
+    out = pr.conv_dgrad_act(dzb, wb, (N, H, W, Ci), s, bf(yb), relu=True)
+    ref = dx_r * (yb > 0)
+    got = out.float().cpu().numpy()
+    tol = 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(dx_r).max()
+    assert np.all(np.abs(got - ref) <= tol)
+    plain = pr.conv_dgrad_act(dzb, wb, (N, H, W, Ci), s, relu=False).float().cpu().numpy()
+    assert np.all(np.abs(plain - dx_r) <= 2.0 ** -8 * np.abs(dx_r) + 1e-5 * np.abs(dx_r).max())
