@@ -305,17 +305,29 @@ struct DgradB {
 };
 
 // ---------------------------------------------------------------------------
-// Epilogues: what happens to element (m, n) of the block's FP32 tile.
+// Epilogues: store4(m, n, v, N) receives v[q] = C[m][n + q] for the four
+// consecutive columns n .. n + 3 (n a multiple of 4, n < N) a lane holds.
 // ---------------------------------------------------------------------------
 
-// C (+ C if accumulating), FP32.
+// C (+ C if accumulating), FP32; v4: rows 16-byte aligned (one vector store).
 struct EpF32 {
     float* C;
-    int ldc, accumulate;
-    __device__ void operator()(int m, int n, float v) const
+    int ldc, accumulate, v4;
+    __device__ void store4(int m, int n, const f32x4& v, int N) const
     {
         float* c = C + (size_t)m * ldc + n;
-        *c = accumulate ? *c + v : v;
+        if (v4 && n + 3 < N) {
+            float4 o = make_float4(v[0], v[1], v[2], v[3]);
+            if (accumulate) {
+                const float4 a = *(const float4*)c;
+                o.x += a.x; o.y += a.y; o.z += a.z; o.w += a.w;
+            }
+            *(float4*)c = o;
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (n + q < N) c[q] = accumulate ? c[q] + v[q] : v[q];
     }
 };
 
@@ -323,41 +335,73 @@ struct EpF32 {
 struct EpPartial {
     float* ws;
     int M, N;
-    __device__ void operator()(int m, int n, float v) const
+    __device__ void store4(int m, int n, const f32x4& v, int) const
     {
-        ws[((size_t)blockIdx.z * M + m) * N + n] = v;
+        float* c = ws + ((size_t)blockIdx.z * M + m) * N + n;
+        if ((N & 3) == 0) {
+            *(float4*)c = make_float4(v[0], v[1], v[2], v[3]);
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (n + q < N) c[q] = v[q];
     }
 };
 
-// act(C + bias) to BF16 (the forward convolution's epilogue).
+__device__ inline void store_bf16x4(__bf16* p, const float (&y)[4], bool vec, int count)
+{
+    if (vec && count == 4) {
+        union { uint2 u; __bf16 h[4]; } o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o.h[q] = to_bf16(y[q]);
+        *(uint2*)p = o.u;
+        return;
+    }
+    for (int q = 0; q < count; ++q) p[q] = to_bf16(y[q]);
+}
+
+// act(C + bias) to BF16 (the forward convolution's epilogue); v4: rows of Y
+// 8-byte aligned.
 struct EpBiasAct {
     const float* bias;  // bias of column n at bias[n * bias_stride]
     int bias_stride, relu;
     __bf16* Y;
-    int ldy;
-    __device__ void operator()(int m, int n, float v) const
+    int ldy, v4;
+    __device__ void store4(int m, int n, const f32x4& v, int N) const
     {
-        float y = v + bias[(size_t)n * bias_stride];
-        if (relu) y = fmaxf(y, 0.f);
-        Y[(size_t)m * ldy + n] = to_bf16(y);
+        const int cnt = min(4, N - n);
+        float y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            y[q] = q < cnt ? v[q] + bias[(size_t)(n + q) * bias_stride] : 0.f;
+            if (relu) y[q] = fmaxf(y[q], 0.f);
+        }
+        store_bf16x4(Y + (size_t)m * ldy + n, y, v4 != 0, cnt);
     }
 };
 
 // Input gradient of one parity class, with the ReLU backward of the layer
 // below applied (dz_below = dx where y_below > 0) and written as BF16 at the
-// class pixel's place in [N][H][W][Ci].
+// class pixel's place in [N][H][W][Ci] (Ci a multiple of 8: 8-byte groups).
 struct EpDgradAct {
     DgradClass c;
     const __bf16* y;  // activation of the layer below (NULL: no activation)
     int relu;
     __bf16* out;
-    __device__ void operator()(int m, int n, float v) const
+    __device__ void store4(int m, int n, const f32x4& v, int) const
     {
         const unsigned b = c.hw.div((unsigned)m), r = (unsigned)m - b * (unsigned)(c.Hc * c.Wc);
         const int yc = (int)c.w.div(r), xc = (int)r - yc * c.Wc;
         const size_t p = ((size_t)((b * c.H + c.s * yc + c.py) * c.W + c.s * xc + c.px)) * c.Ci + n;
-        if (relu && !((float)y[p] > 0.f)) v = 0.f;
-        out[p] = to_bf16(v);
+        float o[4] = {v[0], v[1], v[2], v[3]};
+        if (relu) {
+            union { uint2 u; __bf16 h[4]; } a;
+            a.u = *(const uint2*)(y + p);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (!((float)a.h[q] > 0.f)) o[q] = 0.f;
+        }
+        store_bf16x4(out + p, o, true, 4);
     }
 };
 
@@ -398,19 +442,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, AS as, B
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                // B's fragment as the instruction's first operand: the
+                // result is the transposed tile, so a lane holds four
+                // consecutive columns n of one row m (vector stores)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
-                const int n = n0 + wn + j * 16 + (lane & 15);
-                if (m < M && n < N) ep(m, n, acc[i][j][q]);
-            }
+        for (int j = 0; j < 2; ++j) {
+            const int m = m0 + wm + i * 16 + (lane & 15);
+            const int n = n0 + wn + j * 16 + (lane >> 4) * 4;
+            if (m < M && n < N) ep.store4(m, n, acc[i][j], N);
+        }
 }
 
 // C (+)= the sum of the split-K partial tiles, in split order (the result
@@ -484,7 +529,9 @@ static void run_gemm_f32(int M, int N, int K, const AS& as, const BS& bs, float*
 {
     const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
     int splits = gemm_splits(M, N, K);
-    if (splits > 1 && (!ws || ws_bytes < gemm_ws_bytes(M, N, K))) splits = 1;
+    // (partial tiles take 16-byte stores: the workspace must be aligned)
+    if (splits > 1 && (!ws || ws_bytes < gemm_ws_bytes(M, N, K) || ((uintptr_t)ws & 15)))
+        splits = 1;
     if (splits > 1) {
         gemm_kernel<<<dim3(tm, tn, splits), 256, 0, st>>>(M, N, K, as, bs, EpPartial{ws, M, N});
         const size_t total = (size_t)M * N;
@@ -498,8 +545,9 @@ static void run_gemm_f32(int M, int N, int K, const AS& as, const BS& bs, float*
                                                          accumulate ? 1 : 0);
         }
     } else {
+        const int v4 = ldc % 4 == 0 && ((uintptr_t)C & 15) == 0;
         gemm_kernel<<<dim3(tm, tn, 1), 256, 0, st>>>(M, N, K, as, bs,
-                                                     EpF32{C, ldc, accumulate ? 1 : 0});
+                                                     EpF32{C, ldc, accumulate ? 1 : 0, v4});
     }
 }
 
@@ -538,7 +586,8 @@ void launch_gemm_bias_act(int M, int N, int K, const void* A, int lda, const voi
                           hipStream_t st)
 {
     const dim3 grid((M + kGT - 1) / kGT, (N + kGT - 1) / kGT, 1);
-    const EpBiasAct ep{bias, bias_stride, relu ? 1 : 0, (__bf16*)Y, ldy};
+    const EpBiasAct ep{bias, bias_stride, relu ? 1 : 0, (__bf16*)Y, ldy,
+                       ldy % 4 == 0 && ((uintptr_t)Y & 7) == 0};
     const __bf16* a = (const __bf16*)A;
     const __bf16* b = (const __bf16*)B;
     if (gemm_vec(lda, ldb, A, B))
@@ -574,7 +623,8 @@ void launch_conv_fwd(int N, int H, int W, int Ci, int Co, int s, const void* x, 
     const dim3 grid((g.M + kGT - 1) / kGT, (Co + kGT - 1) / kGT, 1);
     gemm_kernel<<<grid, 256, 0, st>>>(g.M, Co, 9 * Ci, Im2colA{(const __bf16*)x, g},
                                       DenseSrc<true, true>{(const __bf16*)w, ldw, Co},
-                                      EpBiasAct{bias, bias_stride, relu ? 1 : 0, (__bf16*)y, Co});
+                                      EpBiasAct{bias, bias_stride, relu ? 1 : 0, (__bf16*)y, Co,
+                                                Co % 4 == 0 && ((uintptr_t)y & 7) == 0});
 }
 
 size_t conv_wgrad_ws_bytes(int N, int H, int W, int Ci, int Co, int s, int ldw)
