@@ -34,6 +34,11 @@ import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TFLOPS = 157.3       # fp32 vector, MI355X spec (packed FMA)
+# The same chip without packed FP32 (this build keeps it off): 256 CUs x 4
+# SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.  Reported beside the peak; the
+# counters show the kernels issuing above it (VALU busy > 100 % of the
+# 4-cycle wave64 model), so it is not a hard ceiling either.
+VALU_UNPACKED_TFLOPS = 78.6
 # Algorithmic FP32 operations of the method per unit of work (FMA counted as 2),
 # fixed counts that do not depend on how a kernel arranges its arithmetic:
 #   per in-support ray sample: forward ~30 (position, fractions, trilinear
@@ -223,6 +228,8 @@ def run_forward(args, dp, torch):
                         "traffic": _traffic(k + "_registration_scale", src_hash)}
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                "unpacked_fp32_peak": VALU_UNPACKED_TFLOPS,
+                "frac_of_unpacked": round(achieved / VALU_UNPACKED_TFLOPS, 4),
                 "traffic": _traffic(dominant + "_registration_scale", src_hash),
                 "kernel": dominant, "kernel_ms": dom_ms, "flops_per_sample": flops,
                 "source_hash": src_hash, "other": other}
@@ -356,6 +363,7 @@ def vd_rooflines(bp, probe):
                   "gather_ceiling_updates_per_s": gather, "gather_frac": round(rate / gather, 4),
                   "flops_per_update": flops, "tflops": round(rate * flops / 1e12, 2),
                   "alu_ceiling_updates_per_s": alu, "alu_frac": round(rate / alu, 4),
+                  "alu_frac_of_unpacked": round(rate * flops / (VALU_UNPACKED_TFLOPS * 1e12), 4),
                   "graded_against": bound, "frac": round(rate / ceiling, 4),
                   "valu_busy": _traffic(k + "_reconstruction_scale", h, "valu_busy"),
                   "ta_busy": _traffic(k + "_reconstruction_scale", h, "ta_busy"),
