@@ -47,7 +47,10 @@ namespace dp {
 // Compiled variants: tile shape x chunk class (chunk length before
 // adaptation, LDS voxels; listed with the launchers); the autotuner picks
 // one per shape class, variant 1 (16x16 tiles, middle class) is the default.
-constexpr int kMaxChunks = kRdThreads;  // one chunk box planned per thread
+// At most 128 chunks per tile (one box planned per thread of the first two
+// wavefronts): 1.5 KB of box records, which lets the fused kernel's middle
+// class (38 KB of boxes) run four blocks per compute unit.
+constexpr int kMaxChunks = 128;
 // 16-byte row loads for interior boxes of volumes with aligned rows (a
 // build-time switch for measurements; 1 in the library)
 #ifndef RD_VEC_ROWS
@@ -237,7 +240,9 @@ __device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step,
 
 // Plan every chunk of the tile at once (thread i plans chunk i) and return
 // the chunk length M for which all boxes fit `cap` voxels, or 0 if none
-// does (the tile then reads its taps from global memory).
+// does (the tile then reads its taps from global memory).  M shrinks in
+// steps of max(2, M / 8) (16 -> 14 -> 12 ...): a tile whose widest box
+// overflows by a few percent keeps most of its chunk length.
 __device__ inline int plan_chunks(TileShared& sh, int Kmin, int Kmax, int Mmax, int cap,
                                   float step, float margin, int NX, int NY, int NZ)
 {
@@ -261,7 +266,7 @@ __device__ inline int plan_chunks(TileShared& sh, int Kmin, int Kmax, int Mmax, 
         __syncthreads();
         if (vmax <= cap) return M;
         if (M == 1) return 0;
-        M = (M + 1) >> 1;
+        M = max(1, M - max(2, M >> 3));
     }
 }
 
@@ -469,6 +474,10 @@ __device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
     const unsigned dslot = (unsigned)(C * b.py * b.px);
     // LDS index of segment voxel e at the item's first z (only for 0 <= lx0 + e < bx)
     const int slot0 = C * (((int)z0 * b.py + (int)ly) * b.px + lx0);
+    // which segment voxels lie in the box (the same at every z of the item)
+    bool inb[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) inb[e] = (unsigned)(lx0 + e) < (unsigned)b.bx;
     if constexpr (C == 1) {
         float4 v[kVecSeg];
 #pragma unroll
@@ -478,8 +487,7 @@ __device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
             if (q >= cnt) break;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (lx0 + e >= 0 && lx0 + e < b.bx)
-                    dst[slot0 + (int)(q * dslot) + C * e] = f4at(v[q], e);
+                if (inb[e]) dst[slot0 + (int)(q * dslot) + C * e] = f4at(v[q], e);
         }
     } else {
         // x neighbours of the segment: clamped onto the segment at the row ends
@@ -504,7 +512,7 @@ __device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
             const float4 c = zc[q + 1], zm = zc[q], zp = zc[q + 2];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if (lx0 + e < 0 || lx0 + e >= b.bx) continue;
+                if (!inb[e]) continue;
                 const float right = e < 3 ? f4at(c, e + 1) : xr[q];
                 const float left = e > 0 ? f4at(c, e - 1) : xl[q];
                 box_store<C>(dst, (unsigned)(slot0 + (int)(q * dslot) + C * e), f4at(c, e),
@@ -815,9 +823,9 @@ __device__ inline float tri_dot(const Tri& t, const float (&m)[2][2][2])
 }
 
 // Per-ray gradient sums.  add() takes the 8 corner gradient vectors q (index
-// units), their trilinear weights and the base corner's index P in any
-// frame; T accumulates sum phi P_a G_c + sum phi delta_a G_c, so a frame
-// change by c (P -> P - c) is applied later as T_ac -= c_a B_c.
+// units), their trilinear weights and the base corner's index P in some
+// frame; T accumulates sum phi P_a G_c + sum phi delta_a G_c.  A change of
+// frame P -> P + d moves the sums with T_ac += d_a B_c (shift()).
 struct GradAcc {
     float Bx = 0.f, By = 0.f, Bz = 0.f;
     float Txy = 0.f, Txz = 0.f, Tyx = 0.f, Tyz = 0.f, Tzx = 0.f, Tzy = 0.f;
@@ -866,13 +874,12 @@ struct GradAcc {
         Tzx = fmaf(Pz, Gx, Tzx) + Mzx; Tzy = fmaf(Pz, Gy, Tzy) + Mzy;
     }
 
-    // this += o with o's base-corner frame shifted by -c.
-    __device__ inline void merge(const GradAcc& o, float cx, float cy, float cz)
+    // Re-express the sums in the frame P + d.
+    __device__ inline void shift(float dx, float dy, float dz)
     {
-        Bx += o.Bx; By += o.By; Bz += o.Bz;
-        Txy += fmaf(-cx, o.By, o.Txy); Txz += fmaf(-cx, o.Bz, o.Txz);
-        Tyx += fmaf(-cy, o.Bx, o.Tyx); Tyz += fmaf(-cy, o.Bz, o.Tyz);
-        Tzx += fmaf(-cz, o.Bx, o.Tzx); Tzy += fmaf(-cz, o.By, o.Tzy);
+        Txy = fmaf(dx, By, Txy); Txz = fmaf(dx, Bz, Txz);
+        Tyx = fmaf(dy, Bx, Tyx); Tyz = fmaf(dy, Bz, Tyz);
+        Tzx = fmaf(dz, Bx, Tzx); Tzy = fmaf(dz, By, Tzy);
     }
 };
 
@@ -918,9 +925,15 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     const int M = Kmin <= Kmax ? plan_chunks(sh, Kmin, Kmax, MCH, CAP, step, margin, NX, NY, NZ)
                                : 1;
     if (M > 0) {
+        // G runs through the chunks in the base-corner frame of the current
+        // chunk's box (P = local box index); it moves to the next box's
+        // frame at each chunk and to the grid-centred frame at the end.
+        int fox = 0, foy = 0, foz = 0;  // origin of G's frame (G is zero at first)
         for (int K = Kmin, ci = 0; K <= Kmax; K += M, ++ci) {
             const int Ke = min(K + M - 1, Kmax);
             const Box bx = planned_box(sh, ci);
+            G.shift((float)(fox - bx.ox), (float)(foy - bx.oy), (float)(foz - bx.oz));
+            fox = bx.ox; foy = bx.oy; foz = bx.oz;
             __syncthreads();  // the previous chunk's readers are done
             load_box<C>(bx, mu, s.nx, s.ny, s.nz, lds);
             __syncthreads();
@@ -930,7 +943,6 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             const float fbx = (float)bx.px, fby = (float)bx.py;
             // largest base voxel whose 2x2x2 corners stay inside the box
             const float fvmax = (float)(CAP - 2 - (bx.px * bx.py + bx.px));
-            GradAcc Gc;  // base-corner frame: local box indices
             for (float j = 0.0f; j <= c.n; j += 1.0f) {
                 const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
                 const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
@@ -955,10 +967,10 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                         }
                 const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
                 if (FUSED) lsum += tri_dot(t, m);
-                Gc.add(q, t, fx, fy, fz);
+                G.add(q, t, fx, fy, fz);
             }
-            G.merge(Gc, ccx - bx.ox, ccy - bx.oy, ccz - bx.oz);
         }
+        G.shift((float)fox - ccx, (float)foy - ccy, (float)foz - ccz);
     } else {
         for (int k = klo; k <= khi; ++k) {
             const float tk = fmaf((float)(k - r.k0), step, r.f);
@@ -1138,7 +1150,9 @@ __global__ __launch_bounds__(kRdThreads) void rd_fused_batch_kernel(RdBatch bt)
 // Chunk classes (chunk length before adaptation, LDS voxels) per kernel kind:
 //   forward : (16, 4096) (32, 8192) (64, 12288)
 //   gradient: ( 8, 2048) (16, 3072) (32, 5120)
-//   fused   : ( 8, 2048) (16, 3072) (32, 4096)  (four channels per voxel)
+//   fused   : ( 8, 2048) (16, 2432) (32, 4096)  (four channels per voxel)
+// The fused kernel's first two classes stay within 40 KB of LDS per block,
+// four blocks (16 wavefronts) per compute unit; the third runs two.
 struct FwdClasses {
     static constexpr int mch[3] = {16, 32, 64}, cap[3] = {4096, 8192, 12288};
 };
@@ -1146,7 +1160,7 @@ struct GradClasses {
     static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 3072, 5120};
 };
 struct FusedClasses {
-    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 3072, 4096};
+    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 2432, 4096};
 };
 
 template <int N>
