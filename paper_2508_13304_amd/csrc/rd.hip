@@ -416,13 +416,25 @@ __device__ inline bool box_interior(const Box& b, int nx, int ny, int nz)
 }
 
 // Interior box, volume rows 16-byte aligned (nx a multiple of 4 and an
-// aligned base): the box is covered by aligned 4-voxel x segments, and item
-// i is one segment of one box row over up to VSEG consecutive z (segment
-// fastest, so a wavefront's loads are contiguous 16-byte pieces of a row).
-// Per z step an item loads the +z, -y and +y rows as 16-byte vectors and the
-// two x neighbours of the segment as scalars: 5 loads for 4 voxels instead
-// of 20.  Segment voxels outside the box (at most 3 at either end of a row)
-// are loaded and not stored.
+// aligned base), at least kVecSeg voxels deep: the box is covered by aligned
+// 4-voxel x segments, and item i is one segment of one box row over kVecSeg
+// consecutive z (segment fastest, so a wavefront's loads are contiguous
+// 16-byte pieces of a row).  The last z run of a column starts at
+// bz - kVecSeg and overlaps the one before it (those voxels are stored
+// twice, with the same values), so every item spans kVecSeg planes inside
+// the box.  Per z step an item loads the +z, -y and +y rows as 16-byte
+// vectors and the two x neighbours of the segment as scalars: 5 loads for 4
+// voxels instead of 20.  Segment voxels outside the box (at most 3 at either
+// end of a row) are loaded and not stored.
+//
+// The loads are raw buffer loads over the volume: one per-lane offset per
+// item (three with the x neighbours) and the plane and row steps as
+// wavefront-uniform offsets, so no per-load address arithmetic.  Every
+// address is inside the volume: the box keeps a one-voxel margin to the
+// grid faces, and an aligned segment of a row containing a box voxel ends
+// inside the row (nx is a multiple of 4); at the row ends the x neighbour
+// falls back onto the segment voxel itself, which the margin keeps out of
+// the box.
 constexpr int kVecSeg = 4;
 
 struct VecItems {
@@ -445,9 +457,20 @@ __device__ inline VecItems vec_items(const Box& b)
     return vi;
 }
 
-__device__ inline float4 ldv4(const float* __restrict__ mu, unsigned boff)
+// Raw buffer over the volume (gfx9 descriptor: 32-bit data, no swizzle).
+__device__ inline __amdgpu_buffer_rsrc_t vol_rsrc(const float* __restrict__ mu, unsigned bytes)
 {
-    return *(const float4*)((const char*)mu + boff);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)mu, (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ inline float4 bload4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+__device__ inline float bload1(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
 __device__ inline float f4at(const float4& v, int e)
@@ -457,7 +480,7 @@ __device__ inline float f4at(const float4& v, int e)
 
 template <int C>
 __device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
-                                const float* __restrict__ mu, int nx, int ny, float* dst)
+                                __amdgpu_buffer_rsrc_t vr, int nx, int ny, float* dst)
 {
     const unsigned t = vi.nxs > 1 ? __umulhi(it, vi.mxs) : it;
     const unsigned xs = it - t * vi.nxs;
@@ -465,12 +488,10 @@ __device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
     const unsigned ly = t - zs * (unsigned)b.by;
     const int gxs = (int)(vi.s0 + xs) * 4;        // grid x of the segment's first voxel
     const int lx0 = gxs - vi.gx0;                 // its box x (may be negative)
-    const unsigned z0 = zs * kVecSeg;
-    const int cnt = min(kVecSeg, b.bz - (int)z0);
+    const unsigned z0 = min(zs * kVecSeg, (unsigned)b.bz - kVecSeg);
     const unsigned nx4 = 4u * (unsigned)nx, nxy4 = nx4 * (unsigned)ny;
     const unsigned j = (unsigned)b.oy + ly - kPadV, k0 = (unsigned)b.oz + z0 - kPadV;
     const unsigned o0 = ((k0 * (unsigned)ny + j) * (unsigned)nx + (unsigned)gxs) * 4u;
-    const unsigned olast = o0 + (unsigned)(cnt - 1) * nxy4;
     const unsigned dslot = (unsigned)(C * b.py * b.px);
     // LDS index of segment voxel e at the item's first z (only for 0 <= lx0 + e < bx)
     const int slot0 = C * (((int)z0 * b.py + (int)ly) * b.px + lx0);
@@ -481,42 +502,43 @@ __device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
     if constexpr (C == 1) {
         float4 v[kVecSeg];
 #pragma unroll
-        for (int q = 0; q < kVecSeg; ++q) v[q] = ldv4(mu, min(o0 + (unsigned)q * nxy4, olast));
+        for (int q = 0; q < kVecSeg; ++q) v[q] = bload4(vr, o0, (unsigned)q * nxy4);
+        unsigned sq = (unsigned)slot0;
 #pragma unroll
-        for (int q = 0; q < kVecSeg; ++q) {
-            if (q >= cnt) break;
+        for (int q = 0; q < kVecSeg; ++q, sq += dslot)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (inb[e]) dst[slot0 + (int)(q * dslot) + C * e] = f4at(v[q], e);
-        }
+                if (inb[e]) dst[sq + (unsigned)e] = f4at(v[q], e);
     } else {
-        // x neighbours of the segment: clamped onto the segment at the row ends
-        // (those voxels are never stored: an interior box keeps a margin)
-        const unsigned dl = gxs > 0 ? 4u : 0u, dr = gxs + 4 < nx ? 16u : 12u;
+        // base: the item's first voxel one plane down (k0 >= 1 in an interior box)
+        const unsigned vb = o0 - nxy4;
+        const unsigned vl = vb - (gxs > 0 ? 4u : 0u), vrt = vb + (gxs + 4 < nx ? 16u : 12u);
         float4 zc[kVecSeg + 2], ym[kVecSeg], yp[kVecSeg];
         float xl[kVecSeg], xr[kVecSeg];
-        zc[0] = ldv4(mu, o0 - nxy4);
-        zc[1] = ldv4(mu, o0);
+        zc[0] = bload4(vr, vb, 0u);
+        zc[1] = bload4(vr, vb, nxy4);
 #pragma unroll
         for (int q = 0; q < kVecSeg; ++q) {
-            const unsigned o = min(o0 + (unsigned)q * nxy4, olast);
-            zc[q + 2] = ldv4(mu, o + nxy4);
-            ym[q] = ldv4(mu, o - nx4);
-            yp[q] = ldv4(mu, o + nx4);
-            xl[q] = ldv(mu, o - dl);
-            xr[q] = ldv(mu, o + dr);
+            const unsigned pl = (unsigned)(q + 1) * nxy4;  // plane of voxel row q
+            zc[q + 2] = bload4(vr, vb, pl + nxy4);
+            ym[q] = bload4(vr, vb, pl - nx4);
+            yp[q] = bload4(vr, vb, pl + nx4);
+            xl[q] = bload1(vr, vl, pl);
+            xr[q] = bload1(vr, vrt, pl);
         }
+        // LDS index of the segment's first voxel at plane q of the item
+        // (modulo 2^32; voxels outside the box are never stored)
+        unsigned sq = (unsigned)slot0;
 #pragma unroll
-        for (int q = 0; q < kVecSeg; ++q) {
-            if (q >= cnt) break;
+        for (int q = 0; q < kVecSeg; ++q, sq += dslot) {
             const float4 c = zc[q + 1], zm = zc[q], zp = zc[q + 2];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if (!inb[e]) continue;
                 const float right = e < 3 ? f4at(c, e + 1) : xr[q];
                 const float left = e > 0 ? f4at(c, e - 1) : xl[q];
-                box_store<C>(dst, (unsigned)(slot0 + (int)(q * dslot) + C * e), f4at(c, e),
-                             right - left, f4at(yp[q], e) - f4at(ym[q], e), f4at(zp, e) - f4at(zm, e));
+                box_store<C>(dst, sq + (unsigned)(C * e), f4at(c, e), right - left,
+                             f4at(yp[q], e) - f4at(ym[q], e), f4at(zp, e) - f4at(zm, e));
             }
         }
     }
@@ -524,11 +546,12 @@ __device__ inline void vec_item(const Box& b, const VecItems& vi, unsigned it,
 
 template <int C>
 __device__ inline void load_box_vec(const Box& b, const float* __restrict__ mu, int nx, int ny,
-                                    float* dst)
+                                    unsigned vol_bytes, float* dst)
 {
     const VecItems vi = vec_items(b);
+    const __amdgpu_buffer_rsrc_t vr = vol_rsrc(mu, vol_bytes);
     for (unsigned it = threadIdx.x; it < vi.items; it += kRdThreads)
-        vec_item<C>(b, vi, it, mu, nx, ny, dst);
+        vec_item<C>(b, vi, it, vr, nx, ny, dst);
 }
 
 // Interior box staged in one go: every item loaded and stored, two items per
@@ -608,10 +631,13 @@ template <int C>
 __device__ inline void load_box(const Box& b, const float* __restrict__ mu, int nx, int ny, int nz,
                                 float* dst)
 {
-    // uniform over the block; rows of mu are 16-byte aligned when nx % 4 == 0
+    // uniform over the block; rows of mu are 16-byte aligned when nx % 4 == 0;
+    // the buffer loads cover volumes below 4 GiB
     if (box_interior<C>(b, nx, ny, nz)) {
-        if (RD_VEC_ROWS && (nx & 3) == 0 && ((uintptr_t)mu & 15) == 0)
-            load_box_vec<C>(b, mu, nx, ny, dst);
+        const size_t vol_bytes = (size_t)nx * ny * nz * sizeof(float);
+        if (RD_VEC_ROWS && (nx & 3) == 0 && ((uintptr_t)mu & 15) == 0 && b.bz >= kVecSeg &&
+            vol_bytes <= 0xFFFFFFF0u)
+            load_box_vec<C>(b, mu, nx, ny, (unsigned)vol_bytes, dst);
         else
             load_box_interior<C>(b, mu, nx, ny, dst);
     } else {
@@ -943,8 +969,9 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             const float fbx = (float)bx.px, fby = (float)bx.py;
             // largest base voxel whose 2x2x2 corners stay inside the box
             const float fvmax = (float)(CAP - 2 - (bx.px * bx.py + bx.px));
-            for (float j = 0.0f; j <= c.n; j += 1.0f) {
-                const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
+            // sample j of the chunk, its position measured from (X0, Y0, Z0)
+            auto sample = [&](float j, float X0, float Y0, float Z0) {
+                const float X = fmaf(j, c.sx, X0), Y = fmaf(j, c.sy, Y0), Z = fmaf(j, c.sz, Z0);
                 const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
                 const int idx = C * lds_index(fmaf(fmaf(fz, fby, fy), fbx, fx), fvmax);
                 const float* p = lds + idx;
@@ -968,7 +995,16 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                 const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
                 if (FUSED) lsum += tri_dot(t, m);
                 G.add(q, t, fx, fy, fz);
+            };
+            // two samples per trip (the second from the next sample's origin),
+            // then the odd one
+            const float X1 = c.X + c.sx, Y1 = c.Y + c.sy, Z1 = c.Z + c.sz, n1 = c.n - 1.0f;
+            float j = 0.0f;
+            for (; j <= n1; j += 2.0f) {
+                sample(j, c.X, c.Y, c.Z);
+                sample(j, X1, Y1, Z1);
             }
+            if (j <= c.n) sample(j, c.X, c.Y, c.Z);
         }
         G.shift((float)fox - ccx, (float)foy - ccy, (float)foz - ccz);
     } else {
