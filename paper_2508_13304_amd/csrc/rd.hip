@@ -795,23 +795,25 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
 }
 
 // Deterministic block reduction of C channels: butterfly within each
-// wavefront, then a fixed-order sum over the 4 wavefronts.
+// wavefront, then a fixed-order sum over the 4 wavefronts through `red`
+// (4 C floats of LDS; the kernels pass their box array, whose readers the
+// leading barrier waits for).
 template <int C>
-__device__ inline void block_reduce_store(float (&v)[C], float* __restrict__ out)
+__device__ inline void block_reduce_store(float (&v)[C], float* red, float* __restrict__ out)
 {
-    __shared__ float red[4][C];
 #pragma unroll
     for (int c = 0; c < C; ++c)
         for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
     if (lane == 0) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) red[wave][c] = v[c];
+        for (int c = 0; c < C; ++c) red[wave * C + c] = v[c];
     }
     __syncthreads();
     if (threadIdx.x < C) {
         const int c = threadIdx.x;
-        out[c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        out[c] = ((red[c] + red[C + c]) + red[2 * C + c]) + red[3 * C + c];
     }
 }
 
@@ -1088,7 +1090,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                 for (int j6 = i6; j6 < 6; ++j6) acc[o++] = 2.0f * J[i6] * J[j6];
         }
     }
-    block_reduce_store<NC>(acc, partials + ((size_t)v * tiles + tile) * NC);
+    block_reduce_store<NC>(acc, lds, partials + ((size_t)v * tiles + tile) * NC);
 }
 
 template <int TW, int MCH, int CAP>
@@ -1118,8 +1120,10 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
 
 // Forward projection, SSD loss and its pose gradient in one march (HESS:
 // also the per-view Gauss-Newton matrix of the SSD).
+// Both fused kernels are held to 128 VGPRs (four wavefronts per SIMD), which
+// the 40 KB LDS classes need for four blocks per compute unit.
 template <int TW, int MCH, int CAP, bool HESS>
-__global__ __launch_bounds__(kRdThreads) void rd_fused_kernel(GeoScalars s,
+__global__ __launch_bounds__(kRdThreads, 4) void rd_fused_kernel(GeoScalars s,
                                                               const ViewGeo* __restrict__ views,
                                                               const float* __restrict__ mu,
                                                               const float4* __restrict__ inter,
@@ -1171,7 +1175,7 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
 
 // Single-pass SSD with the Gauss-Newton matrix over an uneven batch.
 template <int TW, int MCH, int CAP>
-__global__ __launch_bounds__(kRdThreads) void rd_fused_batch_kernel(RdBatch bt)
+__global__ __launch_bounds__(kRdThreads, 4) void rd_fused_batch_kernel(RdBatch bt)
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
