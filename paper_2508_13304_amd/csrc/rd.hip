@@ -47,10 +47,10 @@ namespace dp {
 // Compiled variants: tile shape x chunk class (chunk length before
 // adaptation, LDS voxels; listed with the launchers); the autotuner picks
 // one per shape class, variant 1 (16x16 tiles, middle class) is the default.
-// At most 128 chunks per tile (one box planned per thread of the first two
-// wavefronts): 1.5 KB of box records, which lets the fused kernel's middle
-// class (38 KB of boxes) run four blocks per compute unit.
-constexpr int kMaxChunks = 128;
+// At most one chunk per thread of the block: thread i plans chunk i and
+// keeps its box record in registers (published to the block through a
+// two-slot LDS buffer when the chunk comes up).
+constexpr int kMaxChunks = kRdThreads;
 // 16-byte row loads for interior boxes of volumes with aligned rows (a
 // build-time switch for measurements; 1 in the library)
 #ifndef RD_VEC_ROWS
@@ -153,7 +153,13 @@ __device__ inline int lds_pitch(int n) { return n | 1; }
 struct TileShared {
     Corner corner[4];
     int klo[4], khi[4], vmax[4];
-    unsigned short box[kMaxChunks][6];
+    unsigned cur[2][3];  // box records of the current and the next chunk
+};
+
+// A chunk box packed in three words: (ox | oy << 16, oz | bx << 16,
+// by | bz << 16); every field fits 16 bits (padded extents <= 65535).
+struct BoxRec {
+    unsigned w[3];
 };
 
 // Union of the active rays' sample ranges, the tile's four corner rays and
@@ -243,8 +249,9 @@ __device__ inline Box chunk_box(const TileShared& sh, int K, int Ke, float step,
 // does (the tile then reads its taps from global memory).  M shrinks in
 // steps of max(2, M / 8) (16 -> 14 -> 12 ...): a tile whose widest box
 // overflows by a few percent keeps most of its chunk length.
+// Thread i < the chunk count leaves the record of chunk i in `rec`.
 __device__ inline int plan_chunks(TileShared& sh, int Kmin, int Kmax, int Mmax, int cap,
-                                  float step, float margin, int NX, int NY, int NZ)
+                                  float step, float margin, int NX, int NY, int NZ, BoxRec& rec)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int M = Mmax;;) {
@@ -254,9 +261,9 @@ __device__ inline int plan_chunks(TileShared& sh, int Kmin, int Kmax, int Mmax, 
         if ((int)threadIdx.x < nch) {
             const int K = Kmin + (int)threadIdx.x * M;
             const Box b = chunk_box(sh, K, min(K + M - 1, Kmax), step, margin, NX, NY, NZ);
-            unsigned short* q = sh.box[threadIdx.x];
-            q[0] = (unsigned short)b.ox; q[1] = (unsigned short)b.oy; q[2] = (unsigned short)b.oz;
-            q[3] = (unsigned short)b.bx; q[4] = (unsigned short)b.by; q[5] = (unsigned short)b.bz;
+            rec.w[0] = (unsigned)b.ox | (unsigned)b.oy << 16;
+            rec.w[1] = (unsigned)b.oz | (unsigned)b.bx << 16;
+            rec.w[2] = (unsigned)b.by | (unsigned)b.bz << 16;
             vol = lds_pitch(b.bx) * lds_pitch(b.by) * b.bz;
         }
         for (int off = 32; off > 0; off >>= 1) vol = max(vol, __shfl_xor(vol, off));
@@ -270,11 +277,26 @@ __device__ inline int plan_chunks(TileShared& sh, int Kmin, int Kmax, int Mmax, 
     }
 }
 
-__device__ inline Box planned_box(const TileShared& sh, int i)
+// Chunk records travel through the two slots of sh.cur: chunk ci is read
+// from slot ci & 1 at the start of the chunk.  Its planner writes it after
+// the first barrier of chunk ci - 1 (all reads of that slot, made at the
+// start of chunk ci - 2, are done by then) and the second barrier of chunk
+// ci - 1 publishes it; chunk 0 is written after planning, before a barrier
+// of its own.
+__device__ inline void publish_box(TileShared& sh, const BoxRec& rec, int ci)
 {
-    const unsigned short* q = sh.box[i];
+    if ((int)threadIdx.x == ci) {
+        unsigned* d = sh.cur[ci & 1];
+        d[0] = rec.w[0]; d[1] = rec.w[1]; d[2] = rec.w[2];
+    }
+}
+
+__device__ inline Box planned_box(const TileShared& sh, int ci)
+{
+    const unsigned* q = sh.cur[ci & 1];
     Box b;
-    b.ox = q[0]; b.oy = q[1]; b.oz = q[2]; b.bx = q[3]; b.by = q[4]; b.bz = q[5];
+    b.ox = q[0] & 0xFFFF; b.oy = q[0] >> 16; b.oz = q[1] & 0xFFFF;
+    b.bx = q[1] >> 16; b.by = q[2] & 0xFFFF; b.bz = q[2] >> 16;
     b.px = lds_pitch(b.bx);
     b.py = lds_pitch(b.by);
     return b;
@@ -738,13 +760,18 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
     const float step = (float)s.step;
     const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
     float acc = 0.0f;
-    const int M = Kmin <= Kmax ? plan_chunks(sh, Kmin, Kmax, MCH, CAP, step, margin, NX, NY, NZ)
+    BoxRec rec = {};
+    const int M = Kmin <= Kmax ? plan_chunks(sh, Kmin, Kmax, MCH, CAP, step, margin, NX, NY, NZ,
+                                             rec)
                                : 1;
     if (M > 0) {
+        publish_box(sh, rec, 0);
+        __syncthreads();
         for (int K = Kmin, ci = 0; K <= Kmax; K += M, ++ci) {
             const int Ke = min(K + M - 1, Kmax);
             const Box bx = planned_box(sh, ci);
             __syncthreads();  // the previous chunk's readers are done
+            publish_box(sh, rec, ci + 1);
             load_box<1>(bx, mu, s.nx, s.ny, s.nz, lds);
             __syncthreads();
             const int kb = max(K, klo), ke = min(Ke, khi);
@@ -950,9 +977,13 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                 ccz = 0.5f * (s.nz - 1) + kPadV;
     const int klo = active ? r.klo : 1, khi = active ? r.khi : 0;
     GradAcc G;
-    const int M = Kmin <= Kmax ? plan_chunks(sh, Kmin, Kmax, MCH, CAP, step, margin, NX, NY, NZ)
+    BoxRec rec = {};
+    const int M = Kmin <= Kmax ? plan_chunks(sh, Kmin, Kmax, MCH, CAP, step, margin, NX, NY, NZ,
+                                             rec)
                                : 1;
     if (M > 0) {
+        publish_box(sh, rec, 0);
+        __syncthreads();
         // G runs through the chunks in the base-corner frame of the current
         // chunk's box (P = local box index); it moves to the next box's
         // frame at each chunk and to the grid-centred frame at the end.
@@ -963,6 +994,7 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
             G.shift((float)(fox - bx.ox), (float)(foy - bx.oy), (float)(foz - bx.oz));
             fox = bx.ox; foy = bx.oy; foz = bx.oz;
             __syncthreads();  // the previous chunk's readers are done
+            publish_box(sh, rec, ci + 1);
             load_box<C>(bx, mu, s.nx, s.ny, s.nz, lds);
             __syncthreads();
             const int kb = max(K, klo), ke = min(Ke, khi);
@@ -1188,19 +1220,20 @@ __global__ __launch_bounds__(kRdThreads, 4) void rd_fused_batch_kernel(RdBatch b
 }
 
 // Chunk classes (chunk length before adaptation, LDS voxels) per kernel kind:
-//   forward : (16, 4096) (32, 8192) (64, 12288)
-//   gradient: ( 8, 2048) (16, 3072) (32, 5120)
-//   fused   : ( 8, 2048) (16, 2432) (32, 4096)  (four channels per voxel)
-// The fused kernel's first two classes stay within 40 KB of LDS per block,
-// four blocks (16 wavefronts) per compute unit; the third runs two.
+//   forward : (16, 4096) (32, 8128) (64, 12288)  (middle class: 32 KB, five blocks per CU)
+//   gradient: ( 8, 2048) (16, 3360) (32, 5120)
+//   fused   : ( 8, 2048) (16, 2520) (32, 4096)  (four channels per voxel)
+// The fused and gradient kernels' first two classes take at most 40,520
+// bytes of LDS per block, which measures as four blocks (16 wavefronts) per
+// compute unit (40,904 bytes measures as three); the third runs two.
 struct FwdClasses {
-    static constexpr int mch[3] = {16, 32, 64}, cap[3] = {4096, 8192, 12288};
+    static constexpr int mch[3] = {16, 32, 64}, cap[3] = {4096, 8128, 12288};
 };
 struct GradClasses {
-    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 3072, 5120};
+    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 3360, 5120};
 };
 struct FusedClasses {
-    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 2432, 4096};
+    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 2520, 4096};
 };
 
 template <int N>
