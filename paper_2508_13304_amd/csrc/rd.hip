@@ -41,9 +41,9 @@
 
 namespace dp {
 
-// LDS budgets: forward = one float per voxel; gradient = (Gx, Gy, Gz)
-// interleaved per voxel, so the x-neighbour pairs of all three channels are
-// reachable from one address with the 8-bit offsets of ds_read2.
+// LDS budgets: forward = one float per voxel; gradient (with or without the
+// SSD) = (mu, Gx, Gy, Gz) interleaved per voxel, one 16-byte read per
+// trilinear corner.
 // Compiled variants: tile shape x chunk class (chunk length before
 // adaptation, LDS voxels; listed with the launchers); the autotuner picks
 // one per shape class, variant 1 (16x16 tiles, middle class) is the default.
@@ -134,6 +134,12 @@ __device__ inline void rd_pixel(const GeoScalars& s, int tile, int& a, int& b, i
 }
 
 __device__ inline float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
+
+// 16-byte LDS vector with its address space explicit (LDS instructions, not
+// flat ones, whatever the pointer it is formed from)
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const v4f lds_v4f;
+typedef __attribute__((address_space(3))) const volatile v4f lds_v4f_vol;
 
 struct Corner {
     float x0, y0, z0, dx, dy, dz, f, k0;
@@ -308,9 +314,8 @@ __device__ inline Box planned_box(const TileShared& sh, int ci)
 // everything outside the grid reads as zero.  C floats per voxel, in the
 // box's own x-fastest order (LDS index = C * ((z * py + y) * px + x); the
 // pitch padding is never read):
-//   C == 1: mu;
-//   C == 3: (Gx, Gy, Gz);
-//   C == 4: (mu, Gx, Gy, Gz);
+//   C == 1: mu (forward);
+//   C == 4: (mu, Gx, Gy, Gz) (pose gradient, with or without the SSD);
 // G_c = the central difference of mu along c in index units (twice the
 // gradient field; the factor 1/2 is applied to the per-ray sums) on grid
 // voxels, mu zero-extended; G is zero off the grid.
@@ -396,10 +401,9 @@ template <int C>
 __device__ inline void box_store(float* dst, unsigned slot, float m, float gx, float gy, float gz)
 {
     float* d = dst + slot;
+    static_assert(C == 1 || C == 4, "boxes hold mu or (mu, Gx, Gy, Gz)");
     if constexpr (C == 4) {  // one 16-byte store: lanes 16 B apart, no bank conflict
         *reinterpret_cast<float4*>(d) = make_float4(m, gx, gy, gz);
-    } else if constexpr (C == 3) {
-        d[0] = gx; d[1] = gy; d[2] = gz;
     } else {
         d[0] = m;
     }
@@ -950,12 +954,13 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
     // FUSED: gin is the target image y, and the ray also integrates mu: l is
     // written to proj_out and the SSD weight w = 2 (l - y) is applied to the
     // gradient sums at the end.  Otherwise gin is dL/dl.  The chunk boxes
-    // hold (mu, Gx, Gy, Gz) (FUSED) or (Gx, Gy, Gz) per voxel, formed from
-    // mu while loading.  Tiles whose boxes do not fit the LDS gather the same
+    // hold (mu, Gx, Gy, Gz) per voxel in both modes, formed from mu while
+    // loading: one aligned 16-byte LDS read per corner (the gradient-only
+    // mode ignores mu).  Tiles whose boxes do not fit the LDS gather the same
     // values per trilinear corner: one float4 per corner from `inter` (a
     // padded (mu, Gx, Gy, Gz) copy the caller makes for sparse-ray
     // geometries, where such tiles are common), else from mu directly.
-    constexpr int C = FUSED ? 4 : 3;
+    constexpr int C = 4;
     int a, b, a0, b0;
     rd_pixel<TW>(s, tile, a, b, a0, b0);
     const bool inside = a < s.nu && b < s.nv;
@@ -1018,13 +1023,12 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
 #pragma unroll
                         for (int dx = 0; dx < 2; ++dx) {
                             const float* o = p + dz * BXYC + dy * BXC + C * dx;
-                            if (FUSED) {
-                                const float4 t = *reinterpret_cast<const float4*>(o);
-                                m[dz][dy][dx] = t.x;
-                                q[dz][dy][dx] = make_float3(t.y, t.z, t.w);
-                            } else {
-                                q[dz][dy][dx] = make_float3(o[0], o[1], o[2]);
-                            }
+                            // gradient-only mode: a volatile 16-byte read keeps the
+                            // aligned ds_read_b128 (its mu lane is unused, and a plain
+                            // load would be narrowed to two unaligned 8-byte reads)
+                            const v4f t = FUSED ? *(lds_v4f*)o : *(lds_v4f_vol*)o;
+                            m[dz][dy][dx] = t[0];
+                            q[dz][dy][dx] = make_float3(t[1], t[2], t[3]);
                         }
                 const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
                 if (FUSED) lsum += tri_dot(t, m);
@@ -1144,7 +1148,7 @@ __global__ __launch_bounds__(kRdThreads) void rd_grad_kernel(GeoScalars s,
                                                              const float* __restrict__ grad_proj,
                                                              float* __restrict__ partials)
 {
-    __shared__ float lds[3 * CAP];
+    __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
     rd_grad_tile<TW, MCH, CAP, false>(s, views, mu, inter, grad_proj, nullptr, partials,
                                       blockIdx.y, blockIdx.x, gridDim.x, lds, sh);
@@ -1196,7 +1200,7 @@ __global__ __launch_bounds__(kRdThreads) void rd_fwd_batch_kernel(RdBatch bt)
 template <int TW, int MCH, int CAP>
 __global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
 {
-    __shared__ float lds[3 * CAP];
+    __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
     const int p = batch_problem(bt);
     const RdBatchItem& it = bt.it[p];
@@ -1221,8 +1225,8 @@ __global__ __launch_bounds__(kRdThreads, 4) void rd_fused_batch_kernel(RdBatch b
 
 // Chunk classes (chunk length before adaptation, LDS voxels) per kernel kind:
 //   forward : (16, 4096) (32, 8128) (64, 12288)  (middle class: 32 KB, five blocks per CU)
-//   gradient: ( 8, 2048) (16, 3360) (32, 5120)
-//   fused   : ( 8, 2048) (16, 2520) (32, 4096)  (four channels per voxel)
+//   gradient: ( 8, 2048) (16, 2520) (32, 4096)
+//   fused   : ( 8, 2048) (16, 2520) (32, 4096)  (both: four channels per voxel)
 // The fused and gradient kernels' first two classes take at most 40,520
 // bytes of LDS per block, which measures as four blocks (16 wavefronts) per
 // compute unit (40,904 bytes measures as three); the third runs two.
@@ -1230,7 +1234,7 @@ struct FwdClasses {
     static constexpr int mch[3] = {16, 32, 64}, cap[3] = {4096, 8128, 12288};
 };
 struct GradClasses {
-    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 3360, 5120};
+    static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 2520, 4096};
 };
 struct FusedClasses {
     static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 2520, 4096};
