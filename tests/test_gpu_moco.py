@@ -76,3 +76,32 @@ def test_motion_compensation_recovers_smooth_motion(dp):
     assert res.losses[-1] < res.losses[0]
     assert e1[1] < 0.25 * e0[1]
     assert u1 < 0.25 * u0 and v1 < 0.25 * v0
+
+
+def test_motion_compensation_on_the_reconstruction_grid(dp):
+    """The same estimation on the reconstruction workload's own 512^3 grid at
+    0.375 mm (projections of the 256^3 phantom at 0.75 mm, 360 views of
+    512x384, 3 mm / 2 deg sinusoidal motion): gradient entropy lowers and
+    the demeaned rotation error and the detector-plane translation errors
+    shrink at least 4x."""
+    from paper_2508_13304_amd import moco
+    m = synth.config3_motion()
+    gp = synth.geom_c3_phantom()
+    g = synth.geom_c3_recon()
+    vol = synth.ellipsoid_phantom_torch(gp.nx, gp.vx, 40, m["rng"], DEV, shell=True)
+    angles = T(m["angles"])
+    truth = T(m["poses"])
+    q = moco.prefilter(g, dp.project_fwd(gp, angles, truth, vol))
+    del vol
+    zero = torch.zeros_like(truth)
+    e0 = moco.demeaned_rms_error(zero, truth)
+    u0, v0, _ = moco.view_frame_errors(zero, truth, angles)
+    res = moco.estimate_motion(g, angles, q, iters=120, nodes=24, lr_t=0.1, lr_r_deg=0.07,
+                               decay=0.98)
+    e1 = moco.demeaned_rms_error(res.poses, truth)
+    u1, v1, w1 = moco.view_frame_errors(res.poses, truth, angles)
+    print("512^3 GE", res.losses[0], "->", res.losses[-1], "err", e0, "->", e1,
+          "detector-plane", (u0, v0), "->", (u1, v1), "depth", w1, f"{res.seconds:.2f} s", flush=True)
+    assert res.losses[-1] < res.losses[0]
+    assert e1[1] < 0.25 * e0[1]
+    assert u1 < 0.25 * u0 and v1 < 0.25 * v0
