@@ -261,3 +261,30 @@ def test_oblique_tiles_gathering_from_the_volume(dp, oracle, variant):
         dp.set_variant(dp.OP_FWD_GRAD, -1)
     check_grads(f"oblique-v{variant} grad", gp.cpu().numpy(),
                 oracle.project_fwd_grad_pose(g, angles, poses, vol, w))
+
+
+@pytest.mark.parametrize("case", ["shallow-boxes", "aligned-rows"])
+def test_box_staging_paths(dp, oracle, case):
+    """Both staging paths of the ray kernels against the oracle, for the
+    forward, the gradient-only and the single-pass kernels, on volumes whose
+    rows are 16-byte aligned (nx a multiple of 4, the vector path's
+    condition).  shallow-boxes: 0.1 mm pixels at the isocentre over 3 mm
+    voxels, so a 16x16 tile spans about half a voxel and the interior chunk
+    boxes are 2-3 planes deep (fewer than the vector path's 4-plane items:
+    the scalar path stages them).  aligned-rows: 0.6 mm at the isocentre over
+    0.7 mm voxels, boxes many planes deep whose x range starts and ends
+    inside 4-voxel segments (the vector path, last z run overlapping)."""
+    from test_gpu_parity import _fwd_case
+    rng = synth.rng_for(230 if case == "shallow-boxes" else 231)
+    if case == "shallow-boxes":
+        g = Geom(32, 24, 16, 3.0, 3.0, 3.0, 48, 40, 0.15, 0.15, off_u=0.3, off_v=-0.2)
+        vol = synth.ellipsoid_phantom(32, 3.0, 6, rng)[:16, :24, :32].copy()
+    else:
+        g = Geom(48, 44, 40, 0.7, 0.7, 0.7, 64, 60, 0.9, 0.9, off_u=-0.4, off_v=0.6)
+        vol = synth.ellipsoid_phantom(48, 0.7, 8, rng)[:40, :44, :48].copy()
+    V = 3
+    angles = rng.uniform(0, 2 * math.pi, V)
+    poses = synth.random_poses(V, 1.0, 4.0, rng)
+    _fwd_case(dp, oracle, g, vol, angles, poses, name=case)
+    y = oracle.project_fwd(g, angles, synth.random_poses(V, 1.0, 4.0, rng), vol).astype(np.float32)
+    _fused_case(dp, oracle, g, vol, angles, poses, y, case)
