@@ -1224,14 +1224,14 @@ __global__ __launch_bounds__(kRdThreads, 4) void rd_fused_batch_kernel(RdBatch b
 }
 
 // Chunk classes (chunk length before adaptation, LDS voxels) per kernel kind:
-//   forward : (16, 4096) (32, 8128) (64, 12288)  (middle class: 32 KB, five blocks per CU)
+//   forward : (16, 4096) (32, 4928) (64, 12288)  (middle class: 19.9 KB, eight blocks per CU)
 //   gradient: ( 8, 2048) (16, 2520) (32, 4096)
 //   fused   : ( 8, 2048) (16, 2520) (32, 4096)  (both: four channels per voxel)
 // The fused and gradient kernels' first two classes take at most 40,520
 // bytes of LDS per block, which measures as four blocks (16 wavefronts) per
 // compute unit (40,904 bytes measures as three); the third runs two.
 struct FwdClasses {
-    static constexpr int mch[3] = {16, 32, 64}, cap[3] = {4096, 8128, 12288};
+    static constexpr int mch[3] = {16, 32, 64}, cap[3] = {4096, 4928, 12288};
 };
 struct GradClasses {
     static constexpr int mch[3] = {8, 16, 32}, cap[3] = {2048, 2520, 4096};
