@@ -26,9 +26,9 @@
 // spherical cap spanned by the tile (bounded per tile), so the chunk's
 // axis-aligned bounding box is loaded once, coalesced, into LDS and every
 // trilinear tap is an LDS read.  All chunk boxes of a tile are planned up
-// front, one per thread; M halves until every box fits the LDS budget, and
-// a tile whose boxes do not fit even at M = 1 reads its taps from the
-// padded volume in global memory.
+// front, one per thread; M shrinks in steps until every box fits the LDS
+// budget, and a tile whose boxes do not fit even at M = 1 (or need more
+// chunks than threads) reads its taps from global memory.
 //
 // Numerics: per-ray setup in FP64; each ray is anchored at its crossing of
 // the iso-plane (a point of small magnitude) and, per chunk, re-anchored at
@@ -1046,18 +1046,27 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
         }
         G.shift((float)fox - ccx, (float)foy - ccy, (float)foz - ccz);
     } else {
-        for (int k = klo; k <= khi; ++k) {
+        const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
+        // clamped padded position of sample k
+        auto position = [&](int k, float& X, float& Y, float& Z) {
             const float tk = fmaf((float)(k - r.k0), step, r.f);
-            const float xmax = NX - 1.001f, ymax = NY - 1.001f, zmax = NZ - 1.001f;
-            const float X = fminf(fmaxf(fmaf(tk, r.dx, r.x0), 0.0f), xmax);
-            const float Y = fminf(fmaxf(fmaf(tk, r.dy, r.y0), 0.0f), ymax);
-            const float Z = fminf(fmaxf(fmaf(tk, r.dz, r.z0), 0.0f), zmax);
+            X = fminf(fmaxf(fmaf(tk, r.dx, r.x0), 0.0f), xmax);
+            Y = fminf(fmaxf(fmaf(tk, r.dy, r.y0), 0.0f), ymax);
+            Z = fminf(fmaxf(fmaf(tk, r.dz, r.z0), 0.0f), zmax);
+        };
+        auto accumulate = [&](float X, float Y, float Z, const float (&m)[2][2][2],
+                              const float3 (&q)[2][2][2]) {
             const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-            float3 q[2][2][2];
-            float m[2][2][2];
-            if (inter) {
-                const int NXY = NX * NY;
-                const int idx = ((int)fz * NY + (int)fy) * NX + (int)fx;
+            const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
+            if (FUSED) lsum += tri_dot(t, m);
+            G.add(q, t, fx - ccx, fy - ccy, fz - ccz);
+        };
+        if (inter) {
+            // the 8 corner vectors of sample k from the padded (mu, G) copy
+            const int NXY = NX * NY;
+            auto gather = [&](float X, float Y, float Z, float (&m)[2][2][2],
+                              float3 (&q)[2][2][2]) {
+                const int idx = ((int)floorf(Z) * NY + (int)floorf(Y)) * NX + (int)floorf(X);
 #pragma unroll
                 for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
@@ -1068,12 +1077,38 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
                             m[dz][dy][dx] = e.x;
                             q[dz][dy][dx] = make_float3(e.y, e.z, e.w);
                         }
-            } else {
-                corners_at(mu, s.nx, s.ny, s.nz, (int)fx, (int)fy, (int)fz, m, q);
+            };
+            // two samples per trip: the 16 corner loads of both are in flight
+            // before either sample's arithmetic waits for them
+            int k = klo;
+            for (; k < khi; k += 2) {
+                float X0, Y0, Z0, X1, Y1, Z1;
+                position(k, X0, Y0, Z0);
+                position(k + 1, X1, Y1, Z1);
+                float m0[2][2][2], m1[2][2][2];
+                float3 q0[2][2][2], q1[2][2][2];
+                gather(X0, Y0, Z0, m0, q0);
+                gather(X1, Y1, Z1, m1, q1);
+                accumulate(X0, Y0, Z0, m0, q0);
+                accumulate(X1, Y1, Z1, m1, q1);
             }
-            const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
-            if (FUSED) lsum += tri_dot(t, m);
-            G.add(q, t, fx - ccx, fy - ccy, fz - ccz);
+            if (k == khi) {
+                float X0, Y0, Z0;
+                position(k, X0, Y0, Z0);
+                float m0[2][2][2];
+                float3 q0[2][2][2];
+                gather(X0, Y0, Z0, m0, q0);
+                accumulate(X0, Y0, Z0, m0, q0);
+            }
+        } else {
+            for (int k = klo; k <= khi; ++k) {
+                float X, Y, Z;
+                position(k, X, Y, Z);
+                float3 q[2][2][2];
+                float m[2][2][2];
+                corners_at(mu, s.nx, s.ny, s.nz, (int)floorf(X), (int)floorf(Y), (int)floorf(Z), m, q);
+                accumulate(X, Y, Z, m, q);
+            }
         }
     }
     constexpr int NC = FUSED ? (HESS ? kRdChannelsGN : kRdChannels + 1) : kRdChannels;
