@@ -139,7 +139,6 @@ __device__ inline float lerpf(float a, float b, float w) { return fmaf(w, b - a,
 // flat ones, whatever the pointer it is formed from)
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) const v4f lds_v4f;
-typedef __attribute__((address_space(3))) const volatile v4f lds_v4f_vol;
 
 struct Corner {
     float x0, y0, z0, dx, dy, dz, f, k0;
@@ -1023,16 +1022,23 @@ __device__ inline void rd_grad_tile(const GeoScalars& s, const ViewGeo* __restri
 #pragma unroll
                         for (int dx = 0; dx < 2; ++dx) {
                             const float* o = p + dz * BXYC + dy * BXC + C * dx;
-                            // gradient-only mode: a volatile 16-byte read keeps the
-                            // aligned ds_read_b128 (its mu lane is unused, and a plain
-                            // load would be narrowed to two unaligned 8-byte reads)
-                            const v4f t = FUSED ? *(lds_v4f*)o : *(lds_v4f_vol*)o;
+                            const v4f t = *(lds_v4f*)o;
                             m[dz][dy][dx] = t[0];
                             q[dz][dy][dx] = make_float3(t[1], t[2], t[3]);
                         }
                 const Tri t = tri_weights(X - fx, Y - fy, Z - fz);
                 if (FUSED) lsum += tri_dot(t, m);
                 G.add(q, t, fx, fy, fz);
+                if constexpr (!FUSED) {
+                    // The gradient-only mode has no use for mu; this empty statement
+                    // keeps its 8 lanes live to the end of the sample, so that the
+                    // reads stay whole 16-byte ds_read_b128 and their registers are
+                    // not reused while a read is still in flight (which would make
+                    // the wavefront wait for each read in turn).
+                    asm volatile("" ::"v"(m[0][0][0]), "v"(m[0][0][1]), "v"(m[0][1][0]),
+                                 "v"(m[0][1][1]), "v"(m[1][0][0]), "v"(m[1][0][1]),
+                                 "v"(m[1][1][0]), "v"(m[1][1][1]));
+                }
             };
             // two samples per trip (the second from the next sample's origin),
             // then the odd one
