@@ -782,8 +782,9 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
             const int BX = bx.px, BXY = bx.px * bx.py;
             const float fbx = (float)bx.px, fby = (float)bx.py;
             const float fimax = (float)(CAP - 1 - (BXY + BX + 1));
-            for (float j = 0.0f; j <= c.n; j += 1.0f) {
-                const float X = fmaf(j, c.sx, c.X), Y = fmaf(j, c.sy, c.Y), Z = fmaf(j, c.sz, c.Z);
+            // sample j of the chunk, its position measured from (X0, Y0, Z0)
+            auto sample = [&](float j, float X0, float Y0, float Z0) {
+                const float X = fmaf(j, c.sx, X0), Y = fmaf(j, c.sy, Y0), Z = fmaf(j, c.sz, Z0);
                 const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
                 const float wx = X - fx, wy = Y - fy, wz = Z - fz;
                 const int idx = lds_index(fmaf(fmaf(fz, fby, fy), fbx, fx), fimax);
@@ -793,7 +794,16 @@ __device__ inline void rd_fwd_tile(const GeoScalars& s, const ViewGeo* __restric
                 const float c01 = lerpf(p[BXY], p[BXY + 1], wx);
                 const float c11 = lerpf(p[BXY + BX], p[BXY + BX + 1], wx);
                 acc += lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
+            };
+            // two samples per trip (the second from the next sample's origin),
+            // then the odd one
+            const float X1 = c.X + c.sx, Y1 = c.Y + c.sy, Z1 = c.Z + c.sz, n1 = c.n - 1.0f;
+            float j = 0.0f;
+            for (; j <= n1; j += 2.0f) {
+                sample(j, c.X, c.Y, c.Z);
+                sample(j, X1, Y1, Z1);
             }
+            if (j <= c.n) sample(j, c.X, c.Y, c.Z);
         }
     } else {
         // chunk boxes too large for LDS: taps straight from the volume
