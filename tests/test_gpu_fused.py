@@ -288,3 +288,22 @@ def test_box_staging_paths(dp, oracle, case):
     _fwd_case(dp, oracle, g, vol, angles, poses, name=case)
     y = oracle.project_fwd(g, angles, synth.random_poses(V, 1.0, 4.0, rng), vol).astype(np.float32)
     _fused_case(dp, oracle, g, vol, angles, poses, y, case)
+
+
+@pytest.mark.parametrize("du", [1.8, 2.2])
+def test_many_chunks_per_tile(dp, oracle, du):
+    """Wide tiles over a deep volume (96 x 128 x 128 at 1 mm, pixels of 1.2 /
+    1.5 mm at the isocentre, rays of ~200 samples): the chunk length drops
+    to 2-6 samples (1.8 mm pixels) or to a single sample, ~195 chunks per
+    tile with the box records of all four wavefronts in use (2.2 mm; that
+    geometry's other tiles gather from the volume), for the forward, the
+    gradient-only and the single-pass kernels against the oracle."""
+    from test_gpu_parity import _fwd_case
+    rng = synth.rng_for(232)
+    g = Geom(96, 128, 128, 1.0, 1.0, 1.0, 48, 48, du, du)
+    vol = synth.ellipsoid_phantom(128, 1.0, 10, rng)[:, :, 16:112].copy()
+    angles = np.array([0.0, 0.02])
+    poses = np.array([[0.5, -0.3, 0.2, 0.01, 0.02, -0.01], [-0.4, 0.2, 0.1, -0.02, 0.01, 0.015]])
+    _fwd_case(dp, oracle, g, vol, angles, poses, name=f"many-chunks-{du}")
+    y = oracle.project_fwd(g, angles, synth.random_poses(2, 1.0, 2.0, rng), vol).astype(np.float32)
+    _fused_case(dp, oracle, g, vol, angles, poses, y, f"many-chunks-{du}")
