@@ -1249,7 +1249,7 @@ __global__ __launch_bounds__(kRdThreads) void rd_fwd_batch_kernel(RdBatch bt)
 }
 
 template <int TW, int MCH, int CAP>
-__global__ __launch_bounds__(kRdThreads) void rd_grad_batch_kernel(RdBatch bt)
+__global__ __launch_bounds__(kRdThreads, 4) void rd_grad_batch_kernel(RdBatch bt)
 {
     __shared__ __attribute__((aligned(16))) float lds[4 * CAP];
     __shared__ TileShared sh;
