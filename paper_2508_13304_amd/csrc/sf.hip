@@ -329,7 +329,7 @@ __device__ inline float sf_gather(const SfFootprint& f, const float* __restrict_
 // ones (their FP32 atomics would serialise).  The flat block index covers
 // both tilings of the (x, y) plane; each block decodes it per view.
 template <int KIND>
-__global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_kernel(GeoScalars s, int V,
+__global__ __launch_bounds__(kSfBx * kSfBy, 5) void sf_fwd_kernel(GeoScalars s, int V,
                                                                const ViewGeo* __restrict__ views,
                                                                const float* __restrict__ vol,
                                                                float* __restrict__ proj)
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_kernel(GeoScalars s, int
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_kernel(GeoScalars s, int V,
+__global__ __launch_bounds__(kSfBx * kSfBy, 4) void sf_bp_kernel(GeoScalars s, int V,
                                                               const ViewGeo* __restrict__ views,
                                                               const float* __restrict__ proj,
                                                               float* __restrict__ vol)
