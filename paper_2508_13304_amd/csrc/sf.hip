@@ -425,7 +425,7 @@ __device__ inline float vol_at(const float* __restrict__ v, const GeoScalars& s,
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s, int V,
+__global__ __launch_bounds__(kSfBx * kSfBy, KIND == kFpDD ? 4 : 1) void sf_fwd_grad_kernel(GeoScalars s, int V,
                                                                     const ViewGeo* __restrict__ views,
                                                                     const float* __restrict__ vol,
                                                                     const float* __restrict__ grad_proj,
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kSfBx * kSfBy) void sf_fwd_grad_kernel(GeoScalars s
 
 // Views [v0, v0 + Vc); proj4 holds this chunk's detector gradient images.
 template <int KIND>
-__global__ __launch_bounds__(kSfBx * kSfBy) void sf_bp_grad_kernel(GeoScalars s, int v0, int Vc,
+__global__ __launch_bounds__(kSfBx * kSfBy, KIND == kFpDD ? 4 : 1) void sf_bp_grad_kernel(GeoScalars s, int v0, int Vc,
                                                                    const ViewGeo* __restrict__ views,
                                                                    const float4* __restrict__ proj4,
                                                                    const float* __restrict__ grad_vol,
